@@ -1,0 +1,251 @@
+"""ctypes binding of libslash.so (include/slash.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device buffers are torch tensors on the current HIP device
+(uint32 data travels in int32 tensors, bit-identical); streams are torch
+streams.  Functions keep the C names.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libslash.so")
+_lib = None
+
+SLASH_OK, E_INVAL, E_NOMEM, E_DEVICE, E_CAPACITY, E_BUSY, E_CLOSED, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+FLAG_TRUSTED = 1
+EMPTY = 0xFFFFFFFF
+_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_CAPACITY", -5: "E_BUSY",
+          -6: "E_CLOSED", -7: "E_UNSUPPORTED"}
+
+
+class SlashError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what}: {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_uint32) for n in ("dim", "K", "L", "log2_buckets", "R", "cm_rows", "log2_cm_width",
+                                          "k_max", "hash_mode", "reserved")] + [("seed", C.c_uint64)]
+
+    @classmethod
+    def of(cls, **kw) -> "Params":
+        p = cls()
+        for k, v in kw.items():
+            setattr(p, k, (int(v) & (2**64 - 1)) if k == "seed" else int(v))
+        return p
+
+
+class CSR(C.Structure):
+    _fields_ = [("indptr", C.c_void_p), ("indices", C.c_void_p), ("n_rows", C.c_uint64)]
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("params", Params), ("n_items", C.c_uint64), ("table_bytes", C.c_uint64),
+                ("n_buckets", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("waves_per_query", C.c_uint32), ("queries_per_ticket", C.c_uint32),
+                ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(SO_PATH)
+        vp, u32, u64, st = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+        P = C.POINTER
+        sig = {
+            "slash_build": ([P(Params), CSR, vp, P(vp)], st),
+            "slash_insert": ([vp, CSR, u32, vp, vp], st),
+            "slash_query": ([vp, CSR, vp, u32, u32, vp, vp, vp], st),
+            "slash_query_batched": ([vp, CSR, vp, u32, u32, vp, vp, P(Schedule), vp], st),
+            "slash_autotune": ([vp, CSR, u32, P(Schedule), vp], st),
+            "slash_hash": ([vp, CSR, u32, vp, vp], st),
+            "slash_export_tables": ([vp, vp, vp, vp], st),
+            "slash_index_info_get": ([vp, P(IndexInfo)], st),
+            "slash_free": ([vp], None),
+            "slash_last_error": ([], C.c_char_p),
+            "slash_set_allocator": ([vp, vp, vp], st),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def slash_last_error() -> str:
+    return lib().slash_last_error().decode()
+
+
+def _check(rc: int, what: str):
+    if rc != SLASH_OK:
+        raise SlashError(rc, what, slash_last_error())
+
+
+def _stream(stream) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_i32(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.contiguous()
+
+
+def csr(indptr: torch.Tensor, indices: torch.Tensor) -> tuple[CSR, tuple]:
+    """CSR struct over device tensors (int64 indptr, int32 indices); returns
+    (struct, tensors to keep alive)."""
+    ip = _dev_i32(indptr)
+    ix = _dev_i32(indices)
+    if ip.dtype != torch.int64 or ix.dtype != torch.int32:
+        raise TypeError("indptr must be int64 and indices int32")
+    n = ip.numel() - 1
+    c = CSR(ip.data_ptr() if n >= 0 else 0, ix.data_ptr() if ix.numel() else ip.data_ptr(), max(n, 0))
+    return c, (ip, ix)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ---------------------------------------------------------------- calls
+
+
+def slash_build(params: Params, indptr: torch.Tensor, indices: torch.Tensor, stream=None) -> C.c_void_p:
+    c, keep = csr(indptr, indices)
+    out = C.c_void_p()
+    _check(lib().slash_build(C.byref(params), c, _stream(stream), C.byref(out)), "slash_build")
+    return out
+
+
+def slash_insert(index, indptr, indices, flags: int = 0, new_ids: torch.Tensor | None = None, stream=None):
+    c, keep = csr(indptr, indices)
+    _check(lib().slash_insert(index, c, flags, _ptr(new_ids), _stream(stream)), "slash_insert")
+
+
+def _outputs(index, n, out_ids, out_scores):
+    km = slash_index_info_get(index)["k_max"]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out_ids is None:
+        out_ids = torch.empty((n, km), dtype=torch.int32, device=dev)
+    if out_scores is None:
+        out_scores = torch.empty((n, km), dtype=torch.int32, device=dev)
+    return out_ids, out_scores
+
+
+def slash_query(index, indptr, indices, k: int, k_per_query: torch.Tensor | None = None, flags: int = 0,
+                out_ids=None, out_scores=None, stream=None):
+    """Top-k (ids, scores) as int32 tensors [n, k_max] holding uint32 bits."""
+    c, keep = csr(indptr, indices)
+    oi, osc = _outputs(index, c.n_rows, out_ids, out_scores)
+    _check(lib().slash_query(index, c, _ptr(k_per_query), k, flags, _ptr(oi), _ptr(osc), _stream(stream)),
+           "slash_query")
+    return oi, osc
+
+
+def slash_query_batched(index, indptr, indices, k: int, k_per_query=None, flags: int = 0, schedule=None,
+                        out_ids=None, out_scores=None, stream=None):
+    c, keep = csr(indptr, indices)
+    oi, osc = _outputs(index, c.n_rows, out_ids, out_scores)
+    sch = None
+    if schedule is not None:
+        sch = C.byref(Schedule(*[int(schedule.get(f, 0)) for f, _ in Schedule._fields_]))
+    _check(lib().slash_query_batched(index, c, _ptr(k_per_query), k, flags, _ptr(oi), _ptr(osc), sch,
+                                     _stream(stream)), "slash_query_batched")
+    return oi, osc
+
+
+def slash_autotune(index, indptr, indices, k: int, stream=None) -> dict:
+    c, keep = csr(indptr, indices)
+    best = Schedule()
+    _check(lib().slash_autotune(index, c, k, C.byref(best), _stream(stream)), "slash_autotune")
+    return {f: int(getattr(best, f)) for f, _ in Schedule._fields_}
+
+
+def slash_hash(index, indptr, indices, flags: int = 0, stream=None) -> torch.Tensor:
+    c, keep = csr(indptr, indices)
+    L = slash_index_info_get(index)["L"]
+    out = torch.empty((c.n_rows, L), dtype=torch.int32, device=indptr.device)
+    _check(lib().slash_hash(index, c, flags, _ptr(out), _stream(stream)), "slash_hash")
+    return out
+
+
+def slash_export_tables(index, stream=None):
+    info = slash_index_info_get(index)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ids = torch.empty((info["L"], info["n_buckets"], info["R"]), dtype=torch.int32, device=dev)
+    seen = torch.empty((info["L"], info["n_buckets"]), dtype=torch.int32, device=dev)
+    _check(lib().slash_export_tables(index, _ptr(ids), _ptr(seen), _stream(stream)), "slash_export_tables")
+    return ids, seen
+
+
+def slash_index_info_get(index) -> dict:
+    info = IndexInfo()
+    _check(lib().slash_index_info_get(index, C.byref(info)), "slash_index_info_get")
+    d = {f: int(getattr(info.params, f)) for f, _ in Params._fields_}
+    d.update(n_items=int(info.n_items), table_bytes=int(info.table_bytes), n_buckets=int(info.n_buckets))
+    return d
+
+
+def slash_free(index):
+    if index:
+        lib().slash_free(index)
+
+
+def as_u32(t: torch.Tensor) -> np.ndarray:
+    """Host numpy uint32 view of an int32 device tensor."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+class Index:
+    """Owning wrapper around a slash_index handle."""
+
+    def __init__(self, params: Params, indptr, indices, stream=None):
+        self.params = params
+        self.handle = slash_build(params, indptr, indices, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            slash_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, indptr, indices, flags=0, new_ids=None, stream=None):
+        slash_insert(self.handle, indptr, indices, flags, new_ids, stream)
+
+    def query(self, indptr, indices, k, **kw):
+        return slash_query(self.handle, indptr, indices, k, **kw)
+
+    def query_batched(self, indptr, indices, k, **kw):
+        return slash_query_batched(self.handle, indptr, indices, k, **kw)
+
+    def autotune(self, indptr, indices, k, stream=None):
+        return slash_autotune(self.handle, indptr, indices, k, stream)
+
+    def hash(self, indptr, indices, flags=0, stream=None):
+        return slash_hash(self.handle, indptr, indices, flags, stream)
+
+    def tables(self, stream=None):
+        return slash_export_tables(self.handle, stream)
+
+    def info(self):
+        return slash_index_info_get(self.handle)

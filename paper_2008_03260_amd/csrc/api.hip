@@ -1,0 +1,712 @@
+// Host side of the C ABI: parameter checks, constant derivation, device
+// memory, and the orchestration of the hash / sort / select / query kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "slash_internal.h"
+
+using namespace slash;
+
+// ----------------------------------------------------------------- errors
+
+static thread_local std::string g_err;
+
+slash_status slash::fail(slash_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                             \
+  do {                                                                                            \
+    hipError_t e__ = (expr);                                                                      \
+    if (e__ != hipSuccess) return fail(SLASH_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e__)); \
+  } while (0)
+
+extern "C" const char* slash_last_error(void) { return g_err.c_str(); }
+
+// -------------------------------------------------------------- allocator
+
+static slash_alloc_fn g_alloc = nullptr;
+static slash_free_fn g_free = nullptr;
+static void* g_alloc_ctx = nullptr;
+
+extern "C" slash_status slash_set_allocator(slash_alloc_fn a, slash_free_fn f, void* ctx) {
+  if ((a == nullptr) != (f == nullptr)) return fail(SLASH_E_INVAL, "allocator and free must both be set or both NULL");
+  g_alloc = a;
+  g_free = f;
+  g_alloc_ctx = ctx;
+  return SLASH_OK;
+}
+
+static void* dalloc(size_t bytes) {
+  if (bytes == 0) bytes = 4;
+  if (g_alloc) return g_alloc(bytes, g_alloc_ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+static void dfree(void* p) {
+  if (!p) return;
+  if (g_free)
+    g_free(p, g_alloc_ctx);
+  else
+    (void)hipFree(p);
+}
+
+// RAII device buffer for scratch.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { dfree(p); }
+  bool get(size_t b) {
+    if (b <= bytes && p) return true;
+    dfree(p);
+    p = dalloc(b);
+    bytes = p ? b : 0;
+    return p != nullptr;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+// ------------------------------------------------------------- constants
+
+// SplitMix64 (Steele, Lea, Flood 2014).
+static uint64_t sm64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// One seed gives every hash function (Section 3 "Design", Section 4
+// "Initialization").  Draw order: nonzero-hash pair(s); one direction bit per
+// bin; per table K odd multipliers then an offset; per table priority key and
+// two odd 32-bit multipliers; per count-min row an odd multiplier and an
+// offset.
+static HostConsts derive_consts(const slash_params& p) {
+  HostConsts h;
+  uint64_t s = p.seed;
+  const uint32_t M = p.K * p.L;
+  const uint32_t n_h = p.hash_mode ? p.L : 1;
+  for (uint32_t t = 0; t < n_h; ++t) {
+    h.a_h.push_back(sm64(s) | 1u);
+    h.b_h.push_back(sm64(s));
+  }
+  h.dirw.assign((M + 31) / 32 + 1, 0u);
+  for (uint32_t b = 0; b < M; ++b)
+    if (sm64(s) >> 63) h.dirw[b >> 5] |= 1u << (b & 31);
+  for (uint32_t t = 0; t < p.L; ++t) {
+    for (uint32_t j = 0; j < p.K; ++j) h.a_tj.push_back(sm64(s) | 1u);
+    h.b_t.push_back(sm64(s));
+  }
+  for (uint32_t t = 0; t < p.L; ++t) {
+    h.key_t.push_back((uint32_t)sm64(s));
+    h.m1_t.push_back((uint32_t)sm64(s) | 1u);
+    h.m2_t.push_back((uint32_t)sm64(s) | 1u);
+  }
+  for (uint32_t r = 0; r < p.cm_rows; ++r) {
+    h.a_r.push_back(sm64(s) | 1u);
+    h.b_r.push_back(sm64(s));
+  }
+  return h;
+}
+
+static slash_status check_params(const slash_params* p) {
+  if (!p) return fail(SLASH_E_INVAL, "params is NULL");
+  if (p->dim == 0) return fail(SLASH_E_INVAL, "dim must be >= 1");
+  if (p->K == 0 || p->L == 0) return fail(SLASH_E_INVAL, "K and L must be >= 1");
+  if ((uint64_t)p->K * p->L > 4096) return fail(SLASH_E_UNSUPPORTED, "K * L must be <= 4096");
+  if (p->log2_buckets < 1 || p->log2_buckets > 30) return fail(SLASH_E_INVAL, "log2_buckets must be in [1, 30]");
+  if (p->R < 1 || p->R > 256) return fail(SLASH_E_INVAL, "R must be in [1, 256]");
+  if (p->cm_rows < 1 || p->cm_rows > 16) return fail(SLASH_E_INVAL, "cm_rows must be in [1, 16]");
+  if (p->log2_cm_width > 16) return fail(SLASH_E_INVAL, "log2_cm_width must be <= 16");
+  if (p->k_max < 1 || p->k_max > 1024) return fail(SLASH_E_INVAL, "k_max must be in [1, 1024]");
+  if (p->hash_mode > 1) return fail(SLASH_E_INVAL, "hash_mode must be 0 or 1");
+  if (p->reserved != 0) return fail(SLASH_E_INVAL, "reserved must be 0");
+  if (((uint64_t)p->L << p->log2_buckets) > (1ull << 32)) return fail(SLASH_E_UNSUPPORTED, "L * 2^B must be <= 2^32");
+  if ((uint64_t)p->L * p->R > 65535) return fail(SLASH_E_UNSUPPORTED, "L * R must be <= 65535");
+  return SLASH_OK;
+}
+
+// -------------------------------------------------------------- the index
+
+struct GraphSlot {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t fill = nullptr, run = nullptr;
+  uint32_t waves = 0, per_ticket = 0, grid = 0;
+};
+
+struct slash_index {
+  slash_params p{};
+  Shape shape{};
+  HostConsts hc;
+  int device = 0;
+  int n_cu = 0;
+  uint64_t n_items = 0;
+  void* d_consts = nullptr;
+  ConstView cv{};
+  uint32_t* ids = nullptr;
+  uint32_t* seen = nullptr;
+  uint32_t* flag = nullptr;     // validation flag
+  uint32_t* tickets = nullptr;  // ring of work counters for the batched path
+  uint32_t ticket_next = 0;
+  DBuf ins_keys, ins_vals, ins_k0, ins_v0, ins_k1, ins_v1, ins_hist, ins_part, ins_seg;
+  std::mutex mu;
+  std::map<uint64_t, GraphSlot> graphs;
+  // tuned schedule per query-size class (0: nnz < 64, 1: < 256, 2: < 1024, 3: larger)
+  slash_schedule tuned[4];
+  bool has_tuned[4] = {false, false, false, false};
+};
+
+static const uint32_t kTicketRing = 256;
+
+static TablesView tables(const slash_index* ix) { return TablesView{ix->ids, ix->seen}; }
+
+static Shape make_shape(const slash_params& p) {
+  Shape s;
+  s.dim = p.dim;
+  s.K = p.K;
+  s.L = p.L;
+  s.M = p.K * p.L;
+  s.B = p.log2_buckets;
+  s.R = p.R;
+  s.d = p.cm_rows;
+  s.lw = p.log2_cm_width;
+  s.k_max = p.k_max;
+  s.mode = p.hash_mode;
+  s.nb = 1u << p.log2_buckets;
+  s.mshift = 0xFFu;
+  if ((s.M & (s.M - 1)) == 0) {
+    uint32_t m = 0;
+    while ((1u << m) < s.M) ++m;
+    s.mshift = m;
+  }
+  return s;
+}
+
+static slash_status upload_consts(slash_index* ix, hipStream_t st) {
+  const HostConsts& h = ix->hc;
+  std::vector<uint64_t> u64;
+  size_t o_ah = u64.size();
+  u64.insert(u64.end(), h.a_h.begin(), h.a_h.end());
+  size_t o_bh = u64.size();
+  u64.insert(u64.end(), h.b_h.begin(), h.b_h.end());
+  size_t o_atj = u64.size();
+  u64.insert(u64.end(), h.a_tj.begin(), h.a_tj.end());
+  size_t o_bt = u64.size();
+  u64.insert(u64.end(), h.b_t.begin(), h.b_t.end());
+  size_t o_ar = u64.size();
+  u64.insert(u64.end(), h.a_r.begin(), h.a_r.end());
+  size_t o_br = u64.size();
+  u64.insert(u64.end(), h.b_r.begin(), h.b_r.end());
+  std::vector<uint32_t> u32;
+  size_t o_dir = u32.size();
+  u32.insert(u32.end(), h.dirw.begin(), h.dirw.end());
+  size_t o_key = u32.size();
+  u32.insert(u32.end(), h.key_t.begin(), h.key_t.end());
+  size_t o_m1 = u32.size();
+  u32.insert(u32.end(), h.m1_t.begin(), h.m1_t.end());
+  size_t o_m2 = u32.size();
+  u32.insert(u32.end(), h.m2_t.begin(), h.m2_t.end());
+  size_t bytes = u64.size() * 8 + u32.size() * 4;
+  ix->d_consts = dalloc(bytes);
+  if (!ix->d_consts) return fail(SLASH_E_NOMEM, "constant table allocation failed");
+  uint8_t* base = (uint8_t*)ix->d_consts;
+  HIP_TRY(hipMemcpy(base, u64.data(), u64.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(base + u64.size() * 8, u32.data(), u32.size() * 4, hipMemcpyHostToDevice));
+  const uint64_t* d64 = (const uint64_t*)base;
+  const uint32_t* d32 = (const uint32_t*)(base + u64.size() * 8);
+  ix->cv.a_h = d64 + o_ah;
+  ix->cv.b_h = d64 + o_bh;
+  ix->cv.a_tj = d64 + o_atj;
+  ix->cv.b_t = d64 + o_bt;
+  ix->cv.a_r = d64 + o_ar;
+  ix->cv.b_r = d64 + o_br;
+  ix->cv.dirw = d32 + o_dir;
+  ix->cv.key_t = d32 + o_key;
+  ix->cv.m1_t = d32 + o_m1;
+  ix->cv.m2_t = d32 + o_m2;
+  (void)st;
+  return SLASH_OK;
+}
+
+static void destroy_index(slash_index* ix) {
+  if (!ix) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ix->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  dfree(ix->d_consts);
+  dfree(ix->ids);
+  dfree(ix->seen);
+  dfree(ix->flag);
+  dfree(ix->tickets);
+  delete ix;
+}
+
+extern "C" void slash_free(slash_index* ix) { destroy_index(ix); }
+
+// Device-side validation of rows (and per-query k); reads back one flag.
+static slash_status validate_rows(slash_index* ix, slash_csr rows, const uint32_t* kq, hipStream_t st) {
+  if (rows.n_rows == 0) return SLASH_OK;
+  if (!rows.indptr || !rows.indices) return fail(SLASH_E_INVAL, "CSR pointers are NULL");
+  int64_t ends[2];
+  HIP_TRY(hipMemcpyAsync(&ends[0], rows.indptr, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&ends[1], rows.indptr + rows.n_rows, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ends[1] < ends[0]) return fail(SLASH_E_INVAL, "indptr is decreasing");
+  HIP_TRY(launch_fill_u32(ix->flag, 0u, 1, st));
+  HIP_TRY(launch_validate(rows, ix->p.dim, kq, ix->p.k_max, ix->flag, st));
+  HIP_TRY(launch_validate_indices(rows.indices + ends[0], (uint64_t)(ends[1] - ends[0]), ix->p.dim, ix->flag, st));
+  uint32_t f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, ix->flag, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (f & 1u) return fail(SLASH_E_INVAL, "a row is empty (or indptr decreases)");
+  if (f & 2u) return fail(SLASH_E_INVAL, "a feature index is outside [0, dim)");
+  if (f & 4u) return fail(SLASH_E_INVAL, "a per-query k exceeds k_max");
+  return SLASH_OK;
+}
+
+static int ceil_log2(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+// ------------------------------------------------------------------ build
+
+static const uint32_t kHeavy = 16384;  // items one wave handles per bucket / chunk
+
+namespace {
+struct HeavyBucket {
+  uint32_t bucket, seen;
+  uint64_t off;
+  uint64_t len;
+};
+}  // namespace
+
+// Finish the buckets with more than kHeavy items: split into chunks, reduce
+// every chunk to its bottom-R, repeat on the candidate lists until a bucket's
+// candidates fit one wave, then write its reservoir.
+static slash_status finish_heavy(slash_index* ix, uint32_t t, const uint32_t* svals, std::vector<HeavyBucket> hv,
+                                 DBuf& candA, DBuf& candB, DBuf& workbuf, std::vector<std::vector<uint8_t>>& keep,
+                                 hipStream_t st) {
+  const Shape& s = ix->shape;
+  const uint32_t* src = svals;
+  bool useA = true;
+  while (!hv.empty()) {
+    std::vector<FinalWork> fin;
+    std::vector<ChunkWork> chk;
+    std::vector<HeavyBucket> next;
+    uint32_t slot = 0;
+    for (const HeavyBucket& h : hv) {
+      if (h.len <= kHeavy) {
+        fin.push_back(FinalWork{h.off, (uint32_t)h.len, h.bucket, h.seen, 0});
+        continue;
+      }
+      uint64_t nch = (h.len + kHeavy - 1) / kHeavy;
+      HeavyBucket nh{h.bucket, h.seen, (uint64_t)slot * s.R, nch * s.R};
+      for (uint64_t c = 0; c < nch; ++c) {
+        uint64_t off = h.off + c * kHeavy;
+        uint32_t len = (uint32_t)std::min<uint64_t>(kHeavy, h.off + h.len - off);
+        chk.push_back(ChunkWork{off, len, slot++});
+      }
+      next.push_back(nh);
+    }
+    size_t wbytes = fin.size() * sizeof(FinalWork) + chk.size() * sizeof(ChunkWork) + 64;
+    keep.emplace_back(wbytes);
+    uint8_t* host = keep.back().data();
+    memcpy(host, fin.data(), fin.size() * sizeof(FinalWork));
+    size_t chk_off = (fin.size() * sizeof(FinalWork) + 15) & ~(size_t)15;
+    memcpy(host + chk_off, chk.data(), chk.size() * sizeof(ChunkWork));
+    // work descriptors live in their own buffer per round
+    DBuf* wb = new DBuf();
+    if (!wb->get(wbytes)) {
+      delete wb;
+      return fail(SLASH_E_NOMEM, "heavy-bucket work list allocation failed");
+    }
+    HIP_TRY(hipMemcpyAsync(wb->p, host, wbytes, hipMemcpyHostToDevice, st));
+    const FinalWork* dfin = (const FinalWork*)wb->p;
+    const ChunkWork* dchk = (const ChunkWork*)((uint8_t*)wb->p + chk_off);
+    slash_status rs = SLASH_OK;
+    if (!fin.empty()) {
+      hipError_t e = launch_select_final(s, ix->cv, t, src, dfin, (uint32_t)fin.size(), tables(ix), st);
+      if (e != hipSuccess) rs = fail(SLASH_E_DEVICE, "select_final: %s", hipGetErrorString(e));
+    }
+    if (rs == SLASH_OK && !chk.empty()) {
+      DBuf& dst = useA ? candA : candB;
+      if (!dst.get((size_t)slot * s.R * 4)) rs = fail(SLASH_E_NOMEM, "candidate buffer allocation failed");
+      if (rs == SLASH_OK) {
+        hipError_t e = launch_select_chunks(s, ix->cv, t, src, dchk, (uint32_t)chk.size(), dst.as<uint32_t>(), st);
+        if (e != hipSuccess) rs = fail(SLASH_E_DEVICE, "select_chunks: %s", hipGetErrorString(e));
+      }
+      src = dst.as<uint32_t>();
+      useA = !useA;
+    }
+    // the round's descriptors must outlive its kernels
+    hipError_t e = hipStreamSynchronize(st);
+    delete wb;
+    if (rs != SLASH_OK) return rs;
+    if (e != hipSuccess) return fail(SLASH_E_DEVICE, "heavy round: %s", hipGetErrorString(e));
+    hv.swap(next);
+    (void)workbuf;
+  }
+  return SLASH_OK;
+}
+
+static slash_status alloc_tables(slash_index* ix) {
+  const Shape& s = ix->shape;
+  size_t n_ids = (size_t)s.L * s.nb * s.R;
+  ix->ids = (uint32_t*)dalloc(n_ids * 4);
+  ix->seen = (uint32_t*)dalloc((size_t)s.L * s.nb * 4);
+  ix->flag = (uint32_t*)dalloc(64);
+  ix->tickets = (uint32_t*)dalloc(kTicketRing * 4);
+  if (!ix->ids || !ix->seen || !ix->flag || !ix->tickets) return fail(SLASH_E_NOMEM, "table allocation failed (%zu bytes)", n_ids * 4);
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_build(const slash_params* params, slash_csr data, void* stream, slash_index** out) {
+  if (!out) return fail(SLASH_E_INVAL, "out is NULL");
+  slash_status rs = check_params(params);
+  if (rs != SLASH_OK) return rs;
+  if (data.n_rows > 0xFFFFFFFEull) return fail(SLASH_E_CAPACITY, "more than 2^32-2 rows");
+  hipStream_t st = (hipStream_t)stream;
+  slash_index* ix = new (std::nothrow) slash_index();
+  if (!ix) return fail(SLASH_E_NOMEM, "host allocation failed");
+  ix->p = *params;
+  ix->shape = make_shape(*params);
+  ix->hc = derive_consts(*params);
+  HIP_TRY(hipGetDevice(&ix->device));
+  HIP_TRY(hipDeviceGetAttribute(&ix->n_cu, hipDeviceAttributeMultiprocessorCount, ix->device));
+  auto bail = [&](slash_status s) {
+    destroy_index(ix);
+    return s;
+  };
+  if ((rs = upload_consts(ix, st)) != SLASH_OK) return bail(rs);
+  if ((rs = alloc_tables(ix)) != SLASH_OK) return bail(rs);
+  if ((rs = validate_rows(ix, data, nullptr, st)) != SLASH_OK) return bail(rs);
+  const Shape& s = ix->shape;
+  const uint64_t n = data.n_rows;
+  {
+    hipError_t e = launch_fill_u32(ix->ids, SL_EMPTY, (uint64_t)s.L * s.nb * s.R, st);
+    if (e == hipSuccess) e = launch_fill_u32(ix->seen, 0u, (uint64_t)s.L * s.nb, st);
+    if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table init: %s", hipGetErrorString(e)));
+  }
+  if (n > 0) {
+    DBuf keys, k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, candA, candB, workbuf;
+    size_t hist_n = sort_hist_entries(n);
+    size_t part_n = std::max(sort_part_entries(hist_n), sort_part_entries(n)) + 16;
+    if (!keys.get((size_t)s.L * n * 4) || !k0.get(n * 4) || !v0.get(n * 4) || !k1.get(n * 4) || !v1.get(n * 4) ||
+        !hist.get(hist_n * 4) || !part.get(part_n * 4) || !start.get((size_t)s.nb * 4) ||
+        !end.get((size_t)s.nb * 4) || !heavy.get((size_t)s.nb * 12) || !heavy_n.get(4))
+      return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
+    hipError_t e = launch_hash_rows(s, ix->cv, data, keys.as<uint32_t>(), n, 0, st);
+    if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "hash: %s", hipGetErrorString(e)));
+    SortBuffers sb{k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), hist.as<uint32_t>(),
+                   part.as<uint32_t>()};
+    std::vector<std::vector<uint8_t>> keep;
+    for (uint32_t t = 0; t < s.L; ++t) {
+      uint32_t *sk = nullptr, *sv = nullptr;
+      e = radix_sort(keys.as<uint32_t>() + (uint64_t)t * n, nullptr, n, (int)s.B, sb, &sk, &sv, st);
+      if (e == hipSuccess) e = launch_fill_u32(start.as<uint32_t>(), 0u, s.nb, st);
+      if (e == hipSuccess) e = launch_fill_u32(end.as<uint32_t>(), 0u, s.nb, st);
+      if (e == hipSuccess) e = launch_fill_u32(heavy_n.as<uint32_t>(), 0u, 1, st);
+      if (e == hipSuccess) e = launch_segment_bounds(sk, n, start.as<uint32_t>(), end.as<uint32_t>(), st);
+      if (e == hipSuccess)
+        e = launch_select_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
+                                heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
+      if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build table %u: %s", t, hipGetErrorString(e)));
+      uint32_t nh = 0;
+      e = hipMemcpyAsync(&nh, heavy_n.p, 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build table %u: %s", t, hipGetErrorString(e)));
+      if (nh) {
+        std::vector<uint32_t> hl((size_t)nh * 3);
+        e = hipMemcpy(hl.data(), heavy.p, hl.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "heavy list: %s", hipGetErrorString(e)));
+        std::vector<HeavyBucket> hv;
+        for (uint32_t i = 0; i < nh; ++i) hv.push_back(HeavyBucket{hl[3 * i], hl[3 * i + 2], hl[3 * i + 1], hl[3 * i + 2]});
+        std::sort(hv.begin(), hv.end(), [](const HeavyBucket& a, const HeavyBucket& b) { return a.bucket < b.bucket; });
+        rs = finish_heavy(ix, t, sv, hv, candA, candB, workbuf, keep, st);
+        if (rs != SLASH_OK) return bail(rs);
+      }
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build: %s", hipGetErrorString(e)));
+  }
+  ix->n_items = n;
+  *out = ix;
+  return SLASH_OK;
+}
+
+// ----------------------------------------------------------------- insert
+
+extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev,
+                                     void* stream) {
+  if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t n = rows.n_rows;
+  if (n == 0) return SLASH_OK;
+  if (ix->n_items + n > 0xFFFFFFFFull) return fail(SLASH_E_CAPACITY, "ids would exceed 0xFFFFFFFE");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  slash_status rs;
+  if (!(flags & SLASH_FLAG_TRUSTED) && (rs = validate_rows(ix, rows, nullptr, st)) != SLASH_OK) return rs;
+  const Shape& s = ix->shape;
+  const uint64_t items = n * s.L;
+  if (items >= 0xFFFFFFFFull) return fail(SLASH_E_UNSUPPORTED, "insert batch too large");
+  size_t hist_n = sort_hist_entries(items);
+  size_t part_n = std::max(sort_part_entries(hist_n), sort_part_entries(items)) + 16;
+  if (!ix->ins_keys.get(items * 4) || !ix->ins_vals.get(items * 4) || !ix->ins_k0.get(items * 4) ||
+      !ix->ins_v0.get(items * 4) || !ix->ins_k1.get(items * 4) || !ix->ins_v1.get(items * 4) ||
+      !ix->ins_hist.get(hist_n * 4) || !ix->ins_part.get(part_n * 4) || !ix->ins_seg.get((2 * items + 4) * 4))
+    return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
+  const uint32_t first = (uint32_t)ix->n_items;
+  HIP_TRY(launch_hash_rows(s, ix->cv, rows, ix->ins_keys.as<uint32_t>(), n, 1, st));
+  HIP_TRY(launch_item_ids(ix->ins_vals.as<uint32_t>(), first, n, items, st));
+  SortBuffers sb{ix->ins_k0.as<uint32_t>(), ix->ins_v0.as<uint32_t>(), ix->ins_k1.as<uint32_t>(),
+                 ix->ins_v1.as<uint32_t>(), ix->ins_hist.as<uint32_t>(), ix->ins_part.as<uint32_t>()};
+  uint32_t *sk = nullptr, *sv = nullptr;
+  int bits = (int)s.B + ceil_log2(s.L);
+  HIP_TRY(radix_sort(ix->ins_keys.as<uint32_t>(), ix->ins_vals.as<uint32_t>(), items, bits, sb, &sk, &sv, st));
+  HIP_TRY(launch_insert_merge(s, ix->cv, sk, sv, items, ix->ins_seg.as<uint32_t>(), ix->ins_part.as<uint32_t>(),
+                              tables(ix), st));
+  if (new_ids_dev) HIP_TRY(launch_iota_u32(new_ids_dev, first, n, st));
+  ix->n_items += n;
+  return SLASH_OK;
+}
+
+// ------------------------------------------------------------------ query
+
+static slash_status query_prelude(const slash_index* ix, slash_csr q, const uint32_t* kq, uint32_t k, uint32_t flags,
+                                  uint32_t* ids, uint32_t* scores, hipStream_t st) {
+  if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
+  if (q.n_rows && (!ids || !scores)) return fail(SLASH_E_INVAL, "output pointers are NULL");
+  if (!kq && k > ix->p.k_max) return fail(SLASH_E_INVAL, "k (%u) exceeds k_max (%u)", k, ix->p.k_max);
+  if (!query_supported(ix->shape)) return fail(SLASH_E_UNSUPPORTED, "query shape not supported (count-min too large for LDS)");
+  if (!(flags & SLASH_FLAG_TRUSTED))
+    return validate_rows(const_cast<slash_index*>(ix), q, kq, st);
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_query(const slash_index* ix, slash_csr q, const uint32_t* kq, uint32_t k, uint32_t flags,
+                                    uint32_t* ids, uint32_t* scores, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  slash_status rs = query_prelude(ix, q, kq, k, flags, ids, scores, st);
+  if (rs != SLASH_OK) return rs;
+  if (q.n_rows == 0) return SLASH_OK;
+  QueryArgs a{q, kq, k, 1, ids, scores};
+  HIP_TRY(launch_query(ix->shape, ix->cv, tables(ix), a, st));
+  return SLASH_OK;
+}
+
+static uint32_t size_class(double mean_nnz) {
+  if (mean_nnz < 64) return 0;
+  if (mean_nnz < 256) return 1;
+  if (mean_nnz < 1024) return 2;
+  return 3;
+}
+
+static slash_schedule default_schedule(const slash_index* ix) {
+  slash_schedule sc{query_default_waves(ix->shape), 1, 0, 0};
+  return sc;
+}
+
+// Graph = [reset work counter, persistent query kernel]; the kernel node's
+// arguments are updated per call.
+static slash_status run_batched(slash_index* ix, const QueryArgs& a, const slash_schedule& sc, hipStream_t st) {
+  const Shape& s = ix->shape;
+  uint32_t waves = sc.waves_per_query;
+  if (!query_supported(s, waves)) return fail(SLASH_E_UNSUPPORTED, "schedule with %u waves/query not supported", waves);
+  int occ = 0;
+  HIP_TRY(query_occupancy(s, waves, &occ));
+  if (occ < 1) occ = 1;
+  uint32_t per_cu = sc.groups_per_cu ? std::min<uint32_t>(sc.groups_per_cu, (uint32_t)occ) : (uint32_t)occ;
+  uint32_t grid = per_cu * (uint32_t)ix->n_cu;
+  uint64_t max_grid = (a.q.n_rows + std::max(1u, sc.queries_per_ticket) - 1) / std::max(1u, sc.queries_per_ticket);
+  if (grid > max_grid) grid = (uint32_t)std::max<uint64_t>(1, max_grid);
+  uint32_t per_ticket = std::max(1u, sc.queries_per_ticket);
+  std::lock_guard<std::mutex> lk(ix->mu);
+  uint32_t* ticket = ix->tickets + (ix->ticket_next++ % kTicketRing);
+  uint64_t gkey = ((uint64_t)waves << 48) | ((uint64_t)per_ticket << 32) | grid;
+  GraphSlot& g = ix->graphs[gkey];
+  Shape sh = s;
+  ConstView cv = ix->cv;
+  TablesView tv = tables(ix);
+  QueryArgs qa = a;
+  uint32_t zero = 0;
+  uint64_t one = 1;
+  void* run_args[] = {&sh, &cv, &tv, &qa, &per_ticket, &ticket};
+  uint32_t* tk = ticket;
+  void* fill_args[] = {&tk, &zero, &one};
+  hipKernelNodeParams rp{};
+  rp.func = persistent_query_kernel(waves);
+  rp.gridDim = dim3(grid);
+  rp.blockDim = dim3(waves * SL_WAVE);
+  rp.sharedMemBytes = (unsigned)query_lds_bytes(s, waves);
+  rp.kernelParams = run_args;
+  hipKernelNodeParams fp{};
+  fp.func = fill_kernel_ptr();
+  fp.gridDim = dim3(1);
+  fp.blockDim = dim3(64);
+  fp.sharedMemBytes = 0;
+  fp.kernelParams = fill_args;
+  if (!g.exec) {
+    HIP_TRY(hipGraphCreate(&g.graph, 0));
+    HIP_TRY(hipGraphAddKernelNode(&g.fill, g.graph, nullptr, 0, &fp));
+    HIP_TRY(hipGraphAddKernelNode(&g.run, g.graph, &g.fill, 1, &rp));
+    HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  } else {
+    HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.fill, &fp));
+    HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.run, &rp));
+  }
+  HIP_TRY(hipGraphLaunch(g.exec, st));
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q, const uint32_t* kq, uint32_t k,
+                                            uint32_t flags, uint32_t* ids, uint32_t* scores,
+                                            const slash_schedule* sched, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  slash_status rs = query_prelude(cix, q, kq, k, flags, ids, scores, st);
+  if (rs != SLASH_OK) return rs;
+  if (q.n_rows == 0) return SLASH_OK;
+  slash_index* ix = const_cast<slash_index*>(cix);
+  slash_schedule sc = default_schedule(ix);
+  if (sched) {
+    sc = *sched;
+  } else {
+    for (int c = 0; c < 4; ++c)
+      if (ix->has_tuned[c]) {
+        sc = ix->tuned[c];
+        break;
+      }
+  }
+  QueryArgs a{q, kq, k, 1, ids, scores};
+  return run_batched(ix, a, sc, st);
+}
+
+extern "C" slash_status slash_autotune(slash_index* ix, slash_csr sample, uint32_t k, slash_schedule* best_out,
+                                       void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  slash_status rs = query_prelude(ix, sample, nullptr, k, 0, (uint32_t*)1, (uint32_t*)1, st);
+  if (rs != SLASH_OK) return rs;
+  if (sample.n_rows == 0) return fail(SLASH_E_INVAL, "empty tuning sample");
+  const uint64_t n = sample.n_rows;
+  const uint32_t km = ix->p.k_max;
+  DBuf ref_i, ref_s, got_i, got_s;
+  if (!ref_i.get(n * km * 4) || !ref_s.get(n * km * 4) || !got_i.get(n * km * 4) || !got_s.get(n * km * 4))
+    return fail(SLASH_E_NOMEM, "autotune buffers");
+  QueryArgs ra{sample, nullptr, k, 1, ref_i.as<uint32_t>(), ref_s.as<uint32_t>()};
+  HIP_TRY(launch_query(ix->shape, ix->cv, tables(ix), ra, st));
+  std::vector<uint32_t> h_ref(n * km * 2), h_got(n * km * 2);
+  HIP_TRY(hipMemcpyAsync(h_ref.data(), ref_i.p, n * km * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h_ref.data() + n * km, ref_s.p, n * km * 4, hipMemcpyDeviceToHost, st));
+  int64_t ends[2];
+  HIP_TRY(hipMemcpyAsync(&ends[0], sample.indptr, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&ends[1], sample.indptr + n, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  uint32_t cls = size_class((double)(ends[1] - ends[0]) / (double)n);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  slash_schedule best = default_schedule(ix);
+  const uint32_t wv[] = {1, 2, 4, 8, 16};
+  const uint32_t tk[] = {1, 2, 8};
+  const uint32_t gpc[] = {0, 2};
+  for (uint32_t w : wv) {
+    if (!query_supported(ix->shape, w)) continue;
+    for (uint32_t t : tk)
+      for (uint32_t g : gpc) {
+        slash_schedule sc{w, t, g, 0};
+        QueryArgs ga{sample, nullptr, k, 1, got_i.as<uint32_t>(), got_s.as<uint32_t>()};
+        rs = run_batched(ix, ga, sc, st);  // warm-up + correctness
+        if (rs != SLASH_OK) continue;
+        HIP_TRY(hipMemcpyAsync(h_got.data(), got_i.p, n * km * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h_got.data() + n * km, got_s.p, n * km * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h_got != h_ref) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return fail(SLASH_E_DEVICE, "schedule (%u waves, %u per ticket, %u per CU) disagrees with the plain path", w, t, g);
+        }
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int rep = 0; rep < 3; ++rep) {
+          rs = run_batched(ix, ga, sc, st);
+          if (rs != SLASH_OK) return rs;
+        }
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = sc;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ix->tuned[cls] = best;
+  ix->has_tuned[cls] = true;
+  if (best_out) *best_out = best;
+  return SLASH_OK;
+}
+
+// ----------------------------------------------------------- small calls
+
+extern "C" slash_status slash_hash(const slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* buckets,
+                                   void* stream) {
+  if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (rows.n_rows == 0) return SLASH_OK;
+  if (!buckets) return fail(SLASH_E_INVAL, "output is NULL");
+  slash_status rs;
+  if (!(flags & SLASH_FLAG_TRUSTED) && (rs = validate_rows(const_cast<slash_index*>(ix), rows, nullptr, st)) != SLASH_OK)
+    return rs;
+  HIP_TRY(launch_hash_rowmajor(ix->shape, ix->cv, rows, buckets, st));
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_export_tables(const slash_index* ix, uint32_t* ids, uint32_t* seen, void* stream) {
+  if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const Shape& s = ix->shape;
+  if (ids) HIP_TRY(hipMemcpyAsync(ids, ix->ids, (size_t)s.L * s.nb * s.R * 4, hipMemcpyDeviceToDevice, st));
+  if (seen) HIP_TRY(hipMemcpyAsync(seen, ix->seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st));
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_index_info_get(const slash_index* ix, slash_index_info* info) {
+  if (!ix || !info) return fail(SLASH_E_INVAL, "NULL argument");
+  memset(info, 0, sizeof *info);
+  info->params = ix->p;
+  info->n_items = ix->n_items;
+  info->n_buckets = ix->shape.nb;
+  info->table_bytes = (uint64_t)ix->shape.L * ix->shape.nb * (ix->shape.R + 1) * 4;
+  return SLASH_OK;
+}

@@ -1,0 +1,144 @@
+// Wave-level densified one-permutation hashing (Section 2.2) and table
+// addresses (Section 2.3), used by the build, insert, hash and query kernels.
+#pragma once
+
+#include "slash_internal.h"
+
+namespace slash {
+
+// Words of the per-row non-empty mask (built 64 bins at a time).
+__host__ __device__ constexpr uint32_t mask_words(uint32_t M) { return ((M + 63) / 64) * 2; }
+
+// LDS words one wave needs for doph_wave: minima[M] + densified[M] + mask.
+__host__ __device__ constexpr uint32_t doph_lds_words(uint32_t M) { return 2 * M + mask_words(M); }
+
+// Nearest set bit of `mask` walking right (increasing, circular) from pos
+// inside the domain [lo, lo + n).  Requires a set bit in the domain other
+// than pos.
+__device__ __forceinline__ uint32_t find_right(const uint32_t* mask, uint32_t lo, uint32_t n, uint32_t pos) {
+  const uint32_t end = lo + n;
+  uint32_t q = pos + 1 == end ? lo : pos + 1;
+  for (;;) {
+    uint32_t o = q & 31u;
+    uint32_t bits = mask[q >> 5] >> o;
+    uint32_t span = min(32u - o, end - q);
+    if (span < 32u) bits &= (1u << span) - 1u;
+    if (bits) return q + (uint32_t)__builtin_ctz(bits);
+    q += span;
+    if (q >= end) q = lo;
+  }
+}
+
+// Same, walking left (decreasing, circular).
+__device__ __forceinline__ uint32_t find_left(const uint32_t* mask, uint32_t lo, uint32_t n, uint32_t pos) {
+  uint32_t q = pos == lo ? lo + n - 1 : pos - 1;
+  for (;;) {
+    uint32_t o = q & 31u;
+    uint32_t bits = mask[q >> 5] << (31u - o);
+    uint32_t span = min(o + 1u, q - lo + 1u);
+    if (span < 32u) bits &= ~((1u << (32u - span)) - 1u);
+    if (bits) return q - (uint32_t)__builtin_clz(bits);
+    if (span == q - lo + 1u)
+      q = lo + n - 1;
+    else
+      q -= span;
+  }
+}
+
+__device__ __forceinline__ bool domain_any(const uint32_t* mask, uint32_t lo, uint32_t n) {
+  for (uint32_t q = lo; q < lo + n;) {
+    uint32_t o = q & 31u;
+    uint32_t span = min(32u - o, lo + n - q);
+    uint32_t bits = mask[q >> 5] >> o;
+    if (span < 32u) bits &= (1u << span) - 1u;
+    if (bits) return true;
+    q += span;
+  }
+  return false;
+}
+
+// One wave hashes one row: per-bin minima of the nonzero hashes, then
+// densification (an empty bin copies the nearest non-empty bin in its fixed
+// direction, circularly, reading the pre-densification minima; all-empty
+// domains stay EMPTY).
+// `idx` points at the row's nnz indices.  All 64 lanes must call.  Returns
+// the densified values (lds + M, M entries).
+__device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const ConstView& c,
+                                                     const int32_t* __restrict__ idx, uint32_t nnz,
+                                                     uint32_t* lds_m) {
+  const uint32_t lane = lane_id();
+  const uint32_t M = s.M;
+  uint32_t* lds_h = lds_m + M;
+  uint32_t* mask = lds_m + 2 * M;
+  for (uint32_t b = lane; b < M; b += SL_WAVE) lds_m[b] = SL_EMPTY;
+  wave_sync();
+  if (s.mode == 0) {
+    const uint64_t a = c.a_h[0], bb = c.b_h[0];
+    for (uint32_t e = lane; e < nnz; e += SL_WAVE) {
+      uint32_t u = nz_hash(a, bb, (uint32_t)idx[e]);
+      uint32_t bin;
+      if (s.mshift == 0xFFu)
+        bin = range_bin(u, M);
+      else
+        bin = s.mshift ? u >> (32 - s.mshift) : 0u;
+      atomicMin(&lds_m[bin], u);
+    }
+  } else {
+    const uint32_t L = s.L, K = s.K;
+    for (uint32_t w = lane; w < nnz * L; w += SL_WAVE) {
+      uint32_t e = w / L, t = w - e * L;
+      uint32_t u = nz_hash(c.a_h[t], c.b_h[t], (uint32_t)idx[e]);
+      atomicMin(&lds_m[t * K + range_bin(u, K)], u);
+    }
+  }
+  wave_sync();
+  // non-empty mask, 64 bins per ballot
+  for (uint32_t base = 0; base < M; base += SL_WAVE) {
+    uint32_t b = base + lane;
+    bool ne = b < M && lds_m[b] != SL_EMPTY;
+    uint64_t bal = ballot64(ne);
+    if (lane == 0) {
+      mask[base / 32] = (uint32_t)bal;
+      mask[base / 32 + 1] = (uint32_t)(bal >> 32);
+    }
+  }
+  wave_sync();
+  // one-pass mode: is any bin of the row non-empty?
+  bool any_all = false;
+  if (s.mode == 0) {
+    const uint32_t nw = mask_words(M);
+    bool mine = false;
+    for (uint32_t w = lane; w < nw; w += SL_WAVE) mine |= mask[w] != 0u;
+    any_all = ballot64(mine) != 0ull;
+  }
+  // densify into lds_h, reading only the minima
+#pragma unroll 1
+  for (uint32_t b = lane; b < M; b += SL_WAVE) {
+    uint32_t v = lds_m[b];
+    if (v == SL_EMPTY) {
+      uint32_t lo = s.mode == 0 ? 0u : (b / s.K) * s.K;
+      uint32_t n = s.mode == 0 ? M : s.K;
+      if (s.mode == 0 ? any_all : domain_any(mask, lo, n)) {
+        bool right = (c.dirw[b >> 5] >> (b & 31)) & 1u;
+        uint32_t src = right ? find_right(mask, lo, n, b) : find_left(mask, lo, n, b);
+        v = lds_m[src];
+      }
+    }
+    lds_h[b] = v;
+  }
+  wave_sync();
+  return lds_h;
+}
+
+// Bucket id of table t from densified values h (Section 2.3):
+// (b_t + sum_j a_tj * h[tK + j]) >> (64 - B), arithmetic mod 2^64.
+__device__ __forceinline__ uint32_t table_bucket(const Shape& s, const ConstView& c, const uint32_t* h,
+                                                 uint32_t t) {
+  uint64_t acc = c.b_t[t];
+  const uint64_t* a = c.a_tj + (uint64_t)t * s.K;
+  const uint32_t* ht = h + t * s.K;
+  for (uint32_t j = 0; j < s.K; ++j) acc += a[j] * (uint64_t)ht[j];
+  return (uint32_t)(acc >> (64 - s.B));
+}
+
+}  // namespace slash

@@ -1,0 +1,210 @@
+// Hash kernels (Section 2.2 DOPH, Section 2.3 table addresses), input
+// validation and small utility kernels.
+#include "doph.h"
+
+namespace slash {
+
+namespace {
+
+constexpr int kMaxHashWaves = 4;
+
+// Each block takes chunks of `rpc` consecutive rows; each wave hashes one row
+// at a time and stages its L bucket ids in LDS; the block then writes every
+// table's rpc ids as one contiguous run (keys are table-major).
+__global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
+    k_hash_rows(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ keys, uint64_t key_stride,
+                int combine, uint32_t rpc) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t nw = blockDim.x / SL_WAVE;
+  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
+  const uint32_t per_wave = doph_lds_words(s.M);
+  uint32_t* my = lds + wave * per_wave;
+  uint32_t* stage = lds + nw * per_wave;  // [L][rpc]
+  const uint64_t n = rows.n_rows;
+  const uint64_t n_chunks = (n + rpc - 1) / rpc;
+  for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+    const uint64_t r0 = ch * rpc;
+    for (uint32_t rl = wave; rl < rpc; rl += nw) {
+      const uint64_t r = r0 + rl;
+      if (r >= n) break;
+      const int64_t beg = rows.indptr[r], end = rows.indptr[r + 1];
+      const uint32_t* h = doph_wave(s, c, rows.indices + beg, (uint32_t)(end - beg), my);
+      for (uint32_t t = lane; t < s.L; t += SL_WAVE) {
+        uint32_t b = table_bucket(s, c, h, t);
+        stage[t * rpc + rl] = combine ? t * s.nb + b : b;
+      }
+      wave_sync();
+    }
+    __syncthreads();
+    const uint32_t tot = s.L * rpc;
+    for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
+      uint32_t t = e / rpc, rl = e - t * rpc;
+      if (r0 + rl < n) keys[t * key_stride + r0 + rl] = stage[e];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
+    k_hash_rowmajor(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ out) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t nw = blockDim.x / SL_WAVE;
+  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
+  uint32_t* my = lds + wave * doph_lds_words(s.M);
+  const uint64_t n = rows.n_rows;
+  for (uint64_t r = (uint64_t)blockIdx.x * nw + wave; r < n; r += (uint64_t)gridDim.x * nw) {
+    const int64_t beg = rows.indptr[r], end = rows.indptr[r + 1];
+    const uint32_t* h = doph_wave(s, c, rows.indices + beg, (uint32_t)(end - beg), my);
+    for (uint32_t t = lane; t < s.L; t += SL_WAVE) out[r * s.L + t] = table_bucket(s, c, h, t);
+    wave_sync();
+  }
+}
+
+constexpr size_t kLdsCap = 160 * 1024;
+
+// Rows staged per chunk: at most 64, and the stage stays within 32 KB.
+uint32_t hash_rpc(const Shape& s) {
+  uint32_t r = 8192u / s.L;
+  if (r < 1) r = 1;
+  if (r > 64) r = 64;
+  return r;
+}
+
+// Waves per block such that the block's LDS fits.
+uint32_t hash_waves(const Shape& s, size_t fixed) {
+  for (uint32_t w = kMaxHashWaves; w > 1; w >>= 1)
+    if ((size_t)w * doph_lds_words(s.M) * 4 + fixed <= kLdsCap) return w;
+  return 1;
+}
+
+hipError_t allow_lds(const void* f, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// flag bits: 1 = empty row or decreasing indptr, 2 = index outside [0, dim),
+// 4 = per-query k above k_max.
+__global__ void k_validate_rows(slash_csr rows, const uint32_t* kq, uint32_t k_max, uint32_t* flag) {
+  uint32_t f = 0;
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < rows.n_rows;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    if (rows.indptr[r + 1] <= rows.indptr[r]) f |= 1u;
+    if (kq && kq[r] > k_max) f |= 4u;
+  }
+  if (f) atomicOr(flag, f);
+}
+
+__global__ void k_validate_idx(const int32_t* idx, uint64_t n, uint32_t dim, uint32_t* flag) {
+  uint32_t f = 0;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n; e += (uint64_t)gridDim.x * blockDim.x) {
+    int32_t v = idx[e];
+    if (v < 0 || (uint32_t)v >= dim) f |= 2u;
+  }
+  if (__ballot(f != 0) && f) atomicOr(flag, f);
+}
+
+__global__ void k_fill(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_iota(uint32_t* p, uint32_t first, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = first + (uint32_t)i;
+}
+
+__global__ void k_segment_bounds(const uint32_t* __restrict__ sk, uint64_t n, uint32_t* start, uint32_t* end) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t k = sk[i];
+    if (i == 0 || sk[i - 1] != k) start[k] = (uint32_t)i;
+    if (i + 1 == n || sk[i + 1] != k) end[k] = (uint32_t)(i + 1);
+  }
+}
+
+// Sort values of an insert batch: item i = t * n_rows + r belongs to row r.
+__global__ void k_item_ids(uint32_t* v, uint32_t first, uint64_t n_rows, uint64_t items) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < items; i += (uint64_t)gridDim.x * blockDim.x)
+    v[i] = first + (uint32_t)(i % n_rows);
+}
+
+uint32_t grid_for(uint64_t work, uint32_t block, uint32_t cap = 65536) {
+  uint64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+}  // namespace
+
+hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, uint32_t* keys, uint64_t key_stride,
+                            int combine, hipStream_t st) {
+  if (rows.n_rows == 0) return hipSuccess;
+  const uint32_t rpc = hash_rpc(s);
+  const size_t stage = (size_t)s.L * rpc * 4;
+  const uint32_t nw = hash_waves(s, stage);
+  const size_t lds = (size_t)nw * doph_lds_words(s.M) * 4 + stage;
+  hipError_t e = allow_lds((const void*)k_hash_rows, lds);
+  if (e != hipSuccess) return e;
+  uint64_t chunks = (rows.n_rows + rpc - 1) / rpc;
+  uint32_t grid = (uint32_t)(chunks < 8192 ? chunks : 8192);
+  hipLaunchKernelGGL(k_hash_rows, dim3(grid), dim3(nw * SL_WAVE), lds, st, s, c, rows, keys, key_stride, combine,
+                     rpc);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr rows, uint32_t* out, hipStream_t st) {
+  if (rows.n_rows == 0) return hipSuccess;
+  const uint32_t nw = hash_waves(s, 0);
+  const size_t lds = (size_t)nw * doph_lds_words(s.M) * 4;
+  hipError_t e = allow_lds((const void*)k_hash_rowmajor, lds);
+  if (e != hipSuccess) return e;
+  uint32_t grid = grid_for(rows.n_rows, nw, 8192);
+  hipLaunchKernelGGL(k_hash_rowmajor, dim3(grid), dim3(nw * SL_WAVE), lds, st, s, c, rows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(slash_csr rows, uint32_t dim, const uint32_t* kq, uint32_t k_max, uint32_t* flag,
+                           hipStream_t st) {
+  if (rows.n_rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate_rows, dim3(grid_for(rows.n_rows, 256, 4096)), dim3(256), 0, st, rows, kq, k_max,
+                     flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // indices of all rows are the contiguous range [indptr[0], indptr[n]);
+  // the range is read on the host by the caller and passed via rows.indices
+  return hipSuccess;
+}
+
+hipError_t launch_validate_indices(const int32_t* idx, uint64_t n, uint32_t dim, uint32_t* flag, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate_idx, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, idx, n, dim, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota_u32(uint32_t* p, uint32_t first, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, first, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_item_ids(uint32_t* vals, uint32_t first_id, uint64_t n_rows, uint64_t items, hipStream_t st) {
+  if (items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_ids, dim3(grid_for(items, 256, 8192)), dim3(256), 0, st, vals, first_id, n_rows, items);
+  return hipGetLastError();
+}
+
+void* fill_kernel_ptr() { return (void*)k_fill; }
+
+hipError_t launch_segment_bounds(const uint32_t* skeys, uint64_t n, uint32_t* start, uint32_t* end, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segment_bounds, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, skeys, n, start, end);
+  return hipGetLastError();
+}
+
+}  // namespace slash

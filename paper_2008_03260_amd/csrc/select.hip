@@ -1,0 +1,307 @@
+// Bottom-R reservoir selection (Section 3 "Avoid Skewed buckets": heavy
+// buckets are sub-sampled to a fixed size; here the kept set is the R ids of
+// smallest priority, which does not depend on insertion order).
+//
+// One wave streams the ids of one bucket (or one chunk of a heavy bucket)
+// through a sorted list of at most R (priority, id) keys held in LDS.  An id
+// can only enter when its key is below the current R-th key; entrants gather
+// in a 64-slot buffer that is sorted across the wave (bitonic, shuffles) and
+// merged into the list (each element's new position = its own index + the
+// number of smaller elements in the other sorted list, found by binary
+// search).  Work is bounded per wave, so skewed buckets split into chunks
+// whose partial bottom-R lists are reduced again.
+#include "slash_internal.h"
+
+namespace slash {
+
+namespace {
+
+constexpr int kSelWaves = 4;
+constexpr uint64_t kNoKey = ~0ull;
+
+struct WaveList {
+  uint64_t* a;    // current list [R]
+  uint64_t* b;    // merge target [R]
+  uint64_t* buf;  // pending entrants [64]
+  uint32_t cnt;   // live entries of a (uniform)
+  uint32_t nbuf;  // live entries of buf (uniform)
+  uint32_t R;
+};
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+  uint32_t lo = __shfl_xor((uint32_t)x, m, SL_WAVE);
+  uint32_t hi = __shfl_xor((uint32_t)(x >> 32), m, SL_WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of one key per lane across the wave.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= SL_WAVE; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      uint64_t y = shfl_xor64(x, j);
+      bool up = (lane & k) == 0;
+      bool lower = (lane & j) == 0;
+      bool keep_min = lower == up;
+      x = keep_min ? (x < y ? x : y) : (x < y ? y : x);
+    }
+  }
+  return x;
+}
+
+// Number of entries of sorted arr[0..n) below x.
+__device__ __forceinline__ uint32_t lower_bound64(const uint64_t* arr, uint32_t n, uint64_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (arr[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void wl_flush(WaveList& w) {
+  if (w.nbuf == 0) return;
+  const uint32_t lane = lane_id();
+  uint64_t x = lane < w.nbuf ? w.buf[lane] : kNoKey;
+  wave_sync();
+  x = wave_sort64(x);
+  w.buf[lane] = x;
+  wave_sync();
+  // new position of each pending key
+  if (lane < w.nbuf) {
+    uint32_t pos = lane + lower_bound64(w.a, w.cnt, x);
+    if (pos < w.R) w.b[pos] = x;
+  }
+  // new position of each listed key
+  for (uint32_t i = lane; i < w.cnt; i += SL_WAVE) {
+    uint64_t y = w.a[i];
+    uint32_t pos = i + lower_bound64(w.buf, w.nbuf, y);
+    if (pos < w.R) w.b[pos] = y;
+  }
+  wave_sync();
+  uint64_t* t = w.a;
+  w.a = w.b;
+  w.b = t;
+  w.cnt = min(w.R, w.cnt + w.nbuf);
+  w.nbuf = 0;
+}
+
+// Offer one key per lane (valid lanes only).
+__device__ __forceinline__ void wl_offer(WaveList& w, bool valid, uint64_t key) {
+  const uint32_t lane = lane_id();
+  uint64_t thr = w.cnt < w.R ? kNoKey : w.a[w.R - 1];
+  bool pass = valid && (w.cnt < w.R || key < thr);
+  uint64_t m = ballot64(pass);
+  uint32_t np = (uint32_t)__builtin_popcountll(m);
+  if (np == 0) return;
+  if (w.nbuf + np > SL_WAVE) wl_flush(w);
+  if (pass) w.buf[w.nbuf + (uint32_t)__builtin_popcountll(m & lanemask_lt())] = key;
+  wave_sync();
+  w.nbuf += np;
+}
+
+__device__ __forceinline__ uint64_t prio_key(uint32_t id, uint32_t key, uint32_t m1, uint32_t m2) {
+  return ((uint64_t)priority(id, key, m1, m2) << 32) | id;
+}
+
+// Stream ids src[off .. off+len) (EMPTY entries skipped) through the list.
+__device__ __forceinline__ void wl_stream(WaveList& w, const uint32_t* __restrict__ src, uint64_t off, uint64_t len,
+                                          uint32_t key, uint32_t m1, uint32_t m2) {
+  const uint32_t lane = lane_id();
+  for (uint64_t i = 0; i < len; i += SL_WAVE) {
+    uint64_t j = i + lane;
+    uint32_t id = j < len ? src[off + j] : SL_EMPTY;
+    bool v = id != SL_EMPTY;
+    wl_offer(w, v, v ? prio_key(id, key, m1, m2) : kNoKey);
+  }
+  wl_flush(w);
+}
+
+__device__ __forceinline__ void wl_write(const WaveList& w, uint32_t* __restrict__ out, uint32_t R) {
+  for (uint32_t i = lane_id(); i < R; i += SL_WAVE) out[i] = i < w.cnt ? (uint32_t)w.a[i] : SL_EMPTY;
+}
+
+__device__ __forceinline__ WaveList wl_init(uint64_t* lds, uint32_t R) {
+  WaveList w;
+  w.a = lds;
+  w.b = lds + R;
+  w.buf = lds + 2 * R;
+  w.cnt = 0;
+  w.nbuf = 0;
+  w.R = R;
+  return w;
+}
+
+__host__ __device__ constexpr uint32_t wl_words(uint32_t R) { return 2 * R + SL_WAVE; }
+
+__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
+    k_select_light(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ svals,
+                   const uint32_t* __restrict__ start, const uint32_t* __restrict__ end, TablesView tab,
+                   uint32_t heavy_t, uint32_t* heavy_list, uint32_t* heavy_n) {
+  extern __shared__ uint64_t lds64[];
+  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
+  uint64_t* my = lds64 + wave * wl_words(s.R);
+  const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  const uint32_t nwaves = gridDim.x * kSelWaves;
+  for (uint32_t b = blockIdx.x * kSelWaves + wave; b < s.nb; b += nwaves) {
+    const uint32_t s0 = start[b], e0 = end[b];
+    const uint32_t n = e0 - s0;
+    uint32_t* out = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
+    if (n > heavy_t) {
+      if (lane == 0) {
+        uint32_t slot = atomicAdd(heavy_n, 1u);
+        heavy_list[3 * slot] = b;
+        heavy_list[3 * slot + 1] = s0;
+        heavy_list[3 * slot + 2] = n;
+      }
+      continue;
+    }
+    WaveList w = wl_init(my, s.R);
+    wl_stream(w, svals, s0, n, key, m1, m2);
+    wl_write(w, out, s.R);
+    if (lane == 0) tab.seen[(uint64_t)t * s.nb + b] = n;
+    wave_sync();
+  }
+}
+
+__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
+    k_select_chunks(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ src,
+                    const ChunkWork* __restrict__ work, uint32_t n_work, uint32_t* __restrict__ dst) {
+  extern __shared__ uint64_t lds64[];
+  const uint32_t wave = threadIdx.x / SL_WAVE;
+  uint64_t* my = lds64 + wave * wl_words(s.R);
+  const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  for (uint32_t wi = blockIdx.x * kSelWaves + wave; wi < n_work; wi += gridDim.x * kSelWaves) {
+    ChunkWork cw = work[wi];
+    WaveList w = wl_init(my, s.R);
+    wl_stream(w, src, cw.off, cw.len, key, m1, m2);
+    wl_write(w, dst + (uint64_t)cw.dst * s.R, s.R);
+    wave_sync();
+  }
+}
+
+__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
+    k_select_final(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ src,
+                   const FinalWork* __restrict__ work, uint32_t n_work, TablesView tab) {
+  extern __shared__ uint64_t lds64[];
+  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
+  uint64_t* my = lds64 + wave * wl_words(s.R);
+  const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  for (uint32_t wi = blockIdx.x * kSelWaves + wave; wi < n_work; wi += gridDim.x * kSelWaves) {
+    FinalWork fw = work[wi];
+    WaveList w = wl_init(my, s.R);
+    wl_stream(w, src, fw.off, fw.len, key, m1, m2);
+    wl_write(w, tab.ids + ((uint64_t)t * s.nb + fw.bucket) * s.R, s.R);
+    if (lane == 0) tab.seen[(uint64_t)t * s.nb + fw.bucket] = fw.seen;
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------- insert
+
+__global__ void k_head_flags(const uint32_t* __restrict__ sk, uint64_t n, uint32_t* __restrict__ flag) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    flag[i] = (i == 0 || sk[i - 1] != sk[i]) ? 1u : 0u;
+}
+
+// After the exclusive scan, flag[i] is the segment number of a head i.
+__global__ void k_head_scatter(const uint32_t* __restrict__ sk, uint64_t n, const uint32_t* __restrict__ segno,
+                               uint32_t* __restrict__ seg_start, uint32_t* __restrict__ nseg) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    bool head = i == 0 || sk[i - 1] != sk[i];
+    if (head) seg_start[segno[i]] = (uint32_t)i;
+    if (i + 1 == n) *nseg = segno[i] + (head ? 1u : 0u);
+  }
+}
+
+// One wave per touched (table, bucket): seed the list with the current
+// reservoir (already in ascending priority), stream the new ids, write back.
+__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
+    k_insert_merge(Shape s, ConstView c, const uint32_t* __restrict__ sk, const uint32_t* __restrict__ sv,
+                   uint64_t n, const uint32_t* __restrict__ seg_start, const uint32_t* __restrict__ nseg,
+                   TablesView tab) {
+  extern __shared__ uint64_t lds64[];
+  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
+  uint64_t* my = lds64 + wave * wl_words(s.R);
+  const uint32_t ns = *nseg;
+  for (uint32_t g = blockIdx.x * kSelWaves + wave; g < ns; g += gridDim.x * kSelWaves) {
+    const uint32_t s0 = seg_start[g];
+    const uint32_t e0 = g + 1 < ns ? seg_start[g + 1] : (uint32_t)n;
+    const uint32_t ck = sk[s0];
+    const uint32_t t = ck >> s.B, b = ck & (s.nb - 1);
+    const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+    uint32_t* res = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
+    uint32_t* seen = tab.seen + (uint64_t)t * s.nb + b;
+    WaveList w = wl_init(my, s.R);
+    const uint32_t old = *seen;
+    const uint32_t fill = min(old, s.R);
+    for (uint32_t i = lane; i < fill; i += SL_WAVE) w.a[i] = prio_key(res[i], key, m1, m2);
+    w.cnt = fill;
+    wave_sync();
+    wl_stream(w, sv, s0, e0 - s0, key, m1, m2);
+    wl_write(w, res, s.R);
+    if (lane == 0) *seen = old + (e0 - s0);
+    wave_sync();
+  }
+}
+
+uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap) {
+  uint64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+}  // namespace
+
+hipError_t launch_select_light(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* svals,
+                               const uint32_t* start, const uint32_t* end, TablesView tab, uint32_t heavy_t,
+                               uint32_t* heavy_list, uint32_t* heavy_n, hipStream_t st) {
+  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  hipLaunchKernelGGL(k_select_light, dim3(grid_for(s.nb, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st,
+                     s, c, t, svals, start, end, tab, heavy_t, heavy_list, heavy_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_chunks(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
+                                const ChunkWork* work, uint32_t n_work, uint32_t* dst, hipStream_t st) {
+  if (n_work == 0) return hipSuccess;
+  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  hipLaunchKernelGGL(k_select_chunks, dim3(grid_for(n_work, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st,
+                     s, c, t, src, work, n_work, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_final(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
+                               const FinalWork* work, uint32_t n_work, TablesView tab, hipStream_t st) {
+  if (n_work == 0) return hipSuccess;
+  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  hipLaunchKernelGGL(k_select_final, dim3(grid_for(n_work, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st,
+                     s, c, t, src, work, n_work, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys, const uint32_t* svals,
+                               uint64_t n, uint32_t* seg_scratch, uint32_t* part, TablesView tab, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  // seg_scratch: [0, n) flags -> segment numbers, [n, 2n) starts, [2n] count
+  uint32_t* segno = seg_scratch;
+  uint32_t* seg_start = seg_scratch + n;
+  uint32_t* nseg = seg_scratch + 2 * n;
+  hipLaunchKernelGGL(k_head_flags, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, skeys, n, segno);
+  hipError_t e = exclusive_scan(segno, n, part, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_head_scatter, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, skeys, n, segno, seg_start,
+                     nseg);
+  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st, s, c,
+                     skeys, svals, n, seg_start, nseg, tab);
+  return hipGetLastError();
+}
+
+}  // namespace slash

@@ -1,0 +1,532 @@
+// Continuous-batching server over a resident index.
+//
+// The paper's query process is online (Section 2.3); this loop keeps one
+// shard's tables resident in HBM and serves a stream of queries and inserts:
+//   - submit calls copy the request and append it to a FIFO (E_BUSY when the
+//     FIFO is full);
+//   - a scheduler thread owns `max_inflight` slots, each with its own stream
+//     and its own device staging memory carved from the HBM budget.  As soon
+//     as a slot is free it takes the longest run of queries at the head of the
+//     FIFO that fits the slot (continuous batching: no waiting for a full
+//     batch while the device has room), copies them in, runs slash_query on
+//     the slot's stream and copies the results back;
+//   - an insert at the head of the FIFO closes the current epoch: it is
+//     ordered after every in-flight batch (stream waits on their events) and
+//     every later batch waits on it, so a query of epoch e sees exactly the
+//     inserts submitted before it, without blocking the host;
+//   - finished work is detected with events and turned into completions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "slash_internal.h"
+
+using namespace slash;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  uint32_t kind = 0;  // 0 query, 1 insert
+  uint32_t k = 0;
+  uint32_t n_rows = 0;
+  std::vector<int32_t> idx;
+  std::vector<int64_t> indptr;  // inserts
+  double t_submit = 0;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  uint32_t kind = 0;
+  uint64_t epoch = 0;
+  std::vector<Request> reqs;
+  // device staging
+  int64_t* d_indptr = nullptr;
+  int32_t* d_idx = nullptr;
+  uint32_t* d_k = nullptr;
+  uint32_t* d_out = nullptr;  // ids then scores, [cap_q][k_max] each
+  // pinned host staging
+  int64_t* h_indptr = nullptr;
+  int32_t* h_idx = nullptr;
+  uint32_t* h_k = nullptr;
+  uint32_t* h_out = nullptr;
+  uint32_t cap_q = 0;
+  uint64_t cap_nnz = 0;
+  uint32_t first_id = 0;
+};
+
+}  // namespace
+
+struct slash_server {
+  slash_index* ix = nullptr;
+  slash_serve_config cfg{};
+  slash_index_info info{};
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request> pending;
+  std::deque<slash_completion> done;
+  std::vector<Slot> slots;
+  Slot ins;  // insert staging + its stream
+  hipEvent_t last_insert = nullptr;
+  bool have_insert = false;
+  uint64_t epoch = 0;
+  uint64_t next_ticket = 0;
+  bool stopping = false;
+  bool closed = false;
+  std::thread th;
+  slash_serve_stats stats{};
+  uint64_t hbm_used = 0;
+  int device = 0;
+  hipError_t dev_err = hipSuccess;
+};
+
+namespace {
+
+void free_slot(Slot& s) {
+  if (s.stream) (void)hipStreamSynchronize(s.stream);
+  if (s.done) (void)hipEventDestroy(s.done);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  (void)hipFree(s.d_indptr);
+  (void)hipFree(s.d_idx);
+  (void)hipFree(s.d_k);
+  (void)hipFree(s.d_out);
+  (void)hipHostFree(s.h_indptr);
+  (void)hipHostFree(s.h_idx);
+  (void)hipHostFree(s.h_k);
+  (void)hipHostFree(s.h_out);
+  s = Slot();
+}
+
+// Device + pinned staging for up to cap_q queries / rows and cap_nnz indices.
+bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool with_out) {
+  s.cap_q = cap_q;
+  s.cap_nnz = cap_nnz;
+  if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
+  if (hipMalloc(&s.d_indptr, (cap_q + 1) * 8) != hipSuccess) return false;
+  if (hipMalloc(&s.d_idx, cap_nnz * 4) != hipSuccess) return false;
+  if (hipHostMalloc(&s.h_indptr, (cap_q + 1) * 8) != hipSuccess) return false;
+  if (hipHostMalloc(&s.h_idx, cap_nnz * 4) != hipSuccess) return false;
+  if (with_out) {
+    if (hipMalloc(&s.d_k, cap_q * 4) != hipSuccess) return false;
+    if (hipMalloc(&s.d_out, (size_t)cap_q * k_max * 8) != hipSuccess) return false;
+    if (hipHostMalloc(&s.h_k, cap_q * 4) != hipSuccess) return false;
+    if (hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8) != hipSuccess) return false;
+  }
+  return true;
+}
+
+uint64_t slot_bytes(uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max) {
+  return (uint64_t)(cap_q + 1) * 8 + cap_nnz * 4 + (uint64_t)cap_q * 4 + (uint64_t)cap_q * k_max * 8;
+}
+
+// Turn a finished slot into completions (called with the lock held).
+void finish_slot(slash_server* srv, Slot& s) {
+  const uint32_t km = srv->info.params.k_max;
+  double t = now_s();
+  if (s.kind == 0) {
+    for (size_t q = 0; q < s.reqs.size(); ++q) {
+      const Request& r = s.reqs[q];
+      slash_completion c;
+      memset(&c, 0, sizeof c);
+      c.ticket = r.ticket;
+      c.epoch = s.epoch;
+      c.status = SLASH_OK;
+      c.kind = 0;
+      c.k = r.k;
+      const uint32_t* oi = s.h_out + q * km;
+      const uint32_t* os = s.h_out + (size_t)s.cap_q * km + q * km;
+      memcpy(c.ids, oi, r.k * 4);
+      memcpy(c.scores, os, r.k * 4);
+      c.t_submit_s = r.t_submit;
+      c.t_done_s = t;
+      srv->done.push_back(c);
+    }
+    srv->stats.queries_done += s.reqs.size();
+  } else {
+    const Request& r = s.reqs[0];
+    slash_completion c;
+    memset(&c, 0, sizeof c);
+    c.ticket = r.ticket;
+    c.epoch = s.epoch;
+    c.status = SLASH_OK;
+    c.kind = 1;
+    c.n_ids = r.n_rows;
+    c.first_id = s.first_id;
+    c.t_submit_s = r.t_submit;
+    c.t_done_s = t;
+    srv->done.push_back(c);
+    srv->stats.inserts_done += 1;
+    srv->stats.rows_inserted += r.n_rows;
+  }
+  s.reqs.clear();
+  s.busy = false;
+}
+
+// Launch a query batch on slot s (lock not held; reqs already moved in).
+hipError_t launch_queries(slash_server* srv, Slot& s) {
+  const uint32_t n = (uint32_t)s.reqs.size();
+  const uint32_t km = srv->info.params.k_max;
+  uint64_t off = 0;
+  s.h_indptr[0] = 0;
+  for (uint32_t q = 0; q < n; ++q) {
+    const Request& r = s.reqs[q];
+    memcpy(s.h_idx + off, r.idx.data(), r.idx.size() * 4);
+    off += r.idx.size();
+    s.h_indptr[q + 1] = (int64_t)off;
+    s.h_k[q] = r.k;
+  }
+  hipError_t e;
+  if (srv->have_insert && (e = hipStreamWaitEvent(s.stream, srv->last_insert, 0)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(s.d_indptr, s.h_indptr, (n + 1) * 8, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(s.d_idx, s.h_idx, off * 4, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(s.d_k, s.h_k, n * 4, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  slash_csr q{s.d_indptr, s.d_idx, n};
+  slash_status st = slash_query(srv->ix, q, s.d_k, 0, SLASH_FLAG_TRUSTED, s.d_out, s.d_out + (size_t)s.cap_q * km,
+                                s.stream);
+  if (st != SLASH_OK) return hipErrorLaunchFailure;
+  if ((e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * km * 4, hipMemcpyDeviceToHost, s.stream)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(s.h_out + (size_t)s.cap_q * km, s.d_out + (size_t)s.cap_q * km, (size_t)n * km * 4,
+                          hipMemcpyDeviceToHost, s.stream)) != hipSuccess)
+    return e;
+  return hipEventRecord(s.done, s.stream);
+}
+
+// Apply an insert after every in-flight batch; later batches wait on it.
+hipError_t launch_insert(slash_server* srv, Slot& s) {
+  const Request& r = s.reqs[0];
+  hipError_t e;
+  for (Slot& o : srv->slots)
+    if (o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
+  memcpy(s.h_indptr, r.indptr.data(), (r.n_rows + 1) * 8);
+  memcpy(s.h_idx, r.idx.data(), r.idx.size() * 4);
+  if ((e = hipMemcpyAsync(s.d_indptr, s.h_indptr, (r.n_rows + 1) * 8, hipMemcpyHostToDevice, s.stream)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(s.d_idx, s.h_idx, r.idx.size() * 4, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  slash_index_info info;
+  slash_index_info_get(srv->ix, &info);
+  s.first_id = (uint32_t)info.n_items;
+  slash_csr rows{s.d_indptr, s.d_idx, r.n_rows};
+  if (slash_insert(srv->ix, rows, SLASH_FLAG_TRUSTED, nullptr, s.stream) != SLASH_OK) return hipErrorLaunchFailure;
+  if ((e = hipEventRecord(s.done, s.stream)) != hipSuccess) return e;
+  srv->last_insert = s.done;
+  srv->have_insert = true;
+  return hipSuccess;
+}
+
+void scheduler(slash_server* srv) {
+  (void)hipSetDevice(srv->device);
+  const uint32_t max_batch = srv->cfg.max_batch;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  for (;;) {
+    // 1. retire finished work
+    bool progressed = false;
+    for (Slot& s : srv->slots)
+      if (s.busy && hipEventQuery(s.done) == hipSuccess) {
+        finish_slot(srv, s);
+        progressed = true;
+      }
+    if (srv->ins.busy && hipEventQuery(srv->ins.done) == hipSuccess) {
+      finish_slot(srv, srv->ins);
+      progressed = true;
+    }
+    if (progressed) srv->cv.notify_all();
+    // 2. admit the head of the FIFO
+    while (!srv->pending.empty()) {
+      Request& head = srv->pending.front();
+      if (head.kind == 1) {
+        if (srv->ins.busy) break;  // one insert at a time, in order
+        uint64_t need_nnz = head.idx.size();
+        if (need_nnz > srv->ins.cap_nnz || head.n_rows > srv->ins.cap_q) break;  // checked at submit
+        Slot& s = srv->ins;
+        s.reqs.clear();
+        s.reqs.push_back(std::move(head));
+        srv->pending.pop_front();
+        s.kind = 1;
+        s.busy = true;
+        s.epoch = ++srv->epoch;
+        srv->stats.batches++;
+        // slots, events and streams belong to this thread: launch unlocked
+        lk.unlock();
+        hipError_t e = launch_insert(srv, s);
+        lk.lock();
+        if (e != hipSuccess) srv->dev_err = e;
+        continue;
+      }
+      Slot* free_s = nullptr;
+      for (Slot& s : srv->slots)
+        if (!s.busy) {
+          free_s = &s;
+          break;
+        }
+      if (!free_s) break;
+      Slot& s = *free_s;
+      s.reqs.clear();
+      uint64_t nnz = 0;
+      while (!srv->pending.empty() && s.reqs.size() < std::min(max_batch, s.cap_q)) {
+        Request& r = srv->pending.front();
+        if (r.kind != 0 || nnz + r.idx.size() > s.cap_nnz) break;
+        nnz += r.idx.size();
+        s.reqs.push_back(std::move(r));
+        srv->pending.pop_front();
+      }
+      s.kind = 0;
+      s.busy = true;
+      s.epoch = srv->epoch;
+      srv->stats.batches++;
+      lk.unlock();
+      hipError_t e = launch_queries(srv, s);
+      lk.lock();
+      if (e != hipSuccess) srv->dev_err = e;
+      uint64_t inflight = 0;
+      for (Slot& o : srv->slots) inflight += o.busy;
+      srv->stats.peak_inflight = std::max(srv->stats.peak_inflight, inflight);
+    }
+    bool busy = srv->ins.busy;
+    for (Slot& s : srv->slots) busy |= s.busy;
+    if (srv->stopping && srv->pending.empty() && !busy) break;
+    if (busy) {
+      // device work in flight: poll its events without sleeping long
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      lk.lock();
+    } else {
+      srv->cv.wait_for(lk, std::chrono::milliseconds(1), [&] { return srv->stopping || !srv->pending.empty(); });
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_config* cfg, slash_server** out) {
+  if (!ix || !cfg || !out) return fail(SLASH_E_INVAL, "NULL argument");
+  if (cfg->max_batch == 0 || cfg->max_inflight == 0 || cfg->queue_capacity == 0 || cfg->max_query_nnz == 0)
+    return fail(SLASH_E_INVAL, "max_batch, max_inflight, queue_capacity and max_query_nnz must be >= 1");
+  slash_server* srv = new slash_server();
+  srv->ix = ix;
+  srv->cfg = *cfg;
+  slash_index_info_get(ix, &srv->info);
+  (void)hipGetDevice(&srv->device);
+  const uint32_t km = srv->info.params.k_max;
+  // a batch holds max_batch queries of 64 indices on average, and at least
+  // one query of max_query_nnz
+  const uint32_t cap_q = cfg->max_batch;
+  const uint64_t cap_nnz = std::max<uint64_t>((uint64_t)cap_q * 64, cfg->max_query_nnz);
+  const uint64_t per_slot = slot_bytes(cap_q, cap_nnz, km);
+  // insert staging: 4096 rows of up to 8 * max_query_nnz indices in total
+  const uint32_t ins_rows = 4096;
+  const uint64_t ins_nnz = std::max<uint64_t>((uint64_t)ins_rows * 64, 8ull * cfg->max_query_nnz);
+  const uint64_t ins_bytes = (uint64_t)(ins_rows + 1) * 8 + ins_nnz * 4;
+  if (ins_bytes + per_slot > cfg->hbm_budget_bytes) {
+    delete srv;
+    return fail(SLASH_E_NOMEM, "HBM budget %llu below one batch slot (%llu bytes)",
+                (unsigned long long)cfg->hbm_budget_bytes, (unsigned long long)(ins_bytes + per_slot));
+  }
+  if (!alloc_slot(srv->ins, ins_rows, ins_nnz, km, false)) {
+    free_slot(srv->ins);
+    delete srv;
+    return fail(SLASH_E_NOMEM, "insert staging allocation failed");
+  }
+  srv->hbm_used = ins_bytes;
+  for (uint32_t i = 0; i < cfg->max_inflight && srv->hbm_used + per_slot <= cfg->hbm_budget_bytes; ++i) {
+    srv->slots.emplace_back();
+    if (!alloc_slot(srv->slots.back(), cap_q, cap_nnz, km, true)) {
+      free_slot(srv->slots.back());
+      srv->slots.pop_back();
+      break;
+    }
+    srv->hbm_used += per_slot;
+  }
+  if (srv->slots.empty()) {
+    free_slot(srv->ins);
+    delete srv;
+    return fail(SLASH_E_NOMEM, "no batch slot fits the HBM budget");
+  }
+  srv->stats.peak_hbm_bytes = srv->hbm_used;
+  srv->th = std::thread(scheduler, srv);
+  *out = srv;
+  return SLASH_OK;
+}
+
+static slash_status enqueue(slash_server* srv, Request&& r, uint64_t* ticket) {
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->closed) return fail(SLASH_E_CLOSED, "server stopped");
+  if (srv->pending.size() >= srv->cfg.queue_capacity) {
+    srv->stats.rejected_busy++;
+    return fail(SLASH_E_BUSY, "queue full");
+  }
+  r.ticket = srv->next_ticket++;
+  r.t_submit = now_s();
+  if (ticket) *ticket = r.ticket;
+  srv->pending.push_back(std::move(r));
+  srv->cv.notify_all();
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_serve_submit_query(slash_server* srv, const int32_t* idx, uint32_t nnz, uint32_t k,
+                                                 uint64_t* ticket) {
+  if (!srv || (!idx && nnz)) return fail(SLASH_E_INVAL, "NULL argument");
+  if (nnz == 0 || nnz > srv->cfg.max_query_nnz) return fail(SLASH_E_INVAL, "query nnz %u outside [1, %u]", nnz, srv->cfg.max_query_nnz);
+  if (k > srv->info.params.k_max || k > SLASH_SERVE_MAX_K) return fail(SLASH_E_INVAL, "k %u too large", k);
+  const uint32_t dim = srv->info.params.dim;
+  for (uint32_t i = 0; i < nnz; ++i)
+    if (idx[i] < 0 || (uint32_t)idx[i] >= dim) return fail(SLASH_E_INVAL, "index outside [0, dim)");
+  Request r;
+  r.kind = 0;
+  r.k = k;
+  r.n_rows = 1;
+  r.idx.assign(idx, idx + nnz);
+  return enqueue(srv, std::move(r), ticket);
+}
+
+extern "C" slash_status slash_serve_submit_insert(slash_server* srv, const int64_t* indptr, const int32_t* idx,
+                                                  uint32_t n_rows, uint64_t* ticket) {
+  if (!srv || !indptr || (!idx && n_rows)) return fail(SLASH_E_INVAL, "NULL argument");
+  if (n_rows == 0 || n_rows > srv->ins.cap_q) return fail(SLASH_E_INVAL, "insert of %u rows outside [1, %u]", n_rows, srv->ins.cap_q);
+  if (indptr[0] != 0) return fail(SLASH_E_INVAL, "indptr[0] must be 0");
+  const uint32_t dim = srv->info.params.dim;
+  for (uint32_t r = 0; r < n_rows; ++r)
+    if (indptr[r + 1] <= indptr[r]) return fail(SLASH_E_INVAL, "empty row in insert");
+  const uint64_t nnz = (uint64_t)indptr[n_rows];
+  if (nnz > srv->ins.cap_nnz) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stats.rejected_nomem++;
+    return fail(SLASH_E_NOMEM, "insert of %llu indices exceeds the staging budget", (unsigned long long)nnz);
+  }
+  for (uint64_t i = 0; i < nnz; ++i)
+    if (idx[i] < 0 || (uint32_t)idx[i] >= dim) return fail(SLASH_E_INVAL, "index outside [0, dim)");
+  Request r;
+  r.kind = 1;
+  r.n_rows = n_rows;
+  r.indptr.assign(indptr, indptr + n_rows + 1);
+  r.idx.assign(idx, idx + nnz);
+  return enqueue(srv, std::move(r), ticket);
+}
+
+extern "C" slash_status slash_serve_poll(slash_server* srv, slash_completion* out, uint32_t max, uint32_t* n) {
+  if (!srv || !n || (!out && max)) return fail(SLASH_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  uint32_t c = 0;
+  while (c < max && !srv->done.empty()) {
+    out[c++] = srv->done.front();
+    srv->done.pop_front();
+  }
+  *n = c;
+  if (srv->dev_err != hipSuccess) return fail(SLASH_E_DEVICE, "serve: %s", hipGetErrorString(srv->dev_err));
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_serve_stop(slash_server* srv, slash_serve_stats* stats) {
+  if (!srv) return fail(SLASH_E_INVAL, "NULL server");
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+    srv->closed = true;
+    srv->cv.notify_all();
+  }
+  if (srv->th.joinable()) srv->th.join();
+  hipError_t err = srv->dev_err;
+  if (stats) *stats = srv->stats;
+  for (Slot& s : srv->slots) free_slot(s);
+  free_slot(srv->ins);
+  delete srv;
+  if (err != hipSuccess) return fail(SLASH_E_DEVICE, "serve: %s", hipGetErrorString(err));
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_serve_replay(slash_server* srv, uint64_t n, const double* t_arr, const uint8_t* is_ins,
+                                           const uint32_t* ins_rows, const int64_t* q_indptr, const int32_t* q_idx,
+                                           const uint32_t* q_k, const int64_t* ins_indptr, const int32_t* ins_idx,
+                                           double* lat, uint32_t* out_ids, uint32_t out_stride) {
+  if (!srv || !t_arr || !is_ins || !lat) return fail(SLASH_E_INVAL, "NULL argument");
+  std::vector<uint64_t> tickets(n, ~0ull);
+  std::vector<int64_t> by_ticket;
+  std::atomic<uint64_t> submitted{0};
+  std::atomic<int> client_err{0};
+  const double t0 = now_s() + 0.002;
+  std::thread client([&] {
+    uint64_t qi = 0, ii = 0;  // next query row, next insert row
+    for (uint64_t i = 0; i < n; ++i) {
+      const double due = t0 + t_arr[i];
+      while (now_s() < due) {
+      }
+      slash_status st;
+      for (;;) {
+        if (is_ins[i]) {
+          uint32_t m = ins_rows[i];
+          std::vector<int64_t> ip(m + 1);
+          for (uint32_t r = 0; r <= m; ++r) ip[r] = ins_indptr[ii + r] - ins_indptr[ii];
+          st = slash_serve_submit_insert(srv, ip.data(), ins_idx + ins_indptr[ii], m, &tickets[i]);
+        } else {
+          st = slash_serve_submit_query(srv, q_idx + q_indptr[qi], (uint32_t)(q_indptr[qi + 1] - q_indptr[qi]),
+                                        q_k ? q_k[qi] : 10, &tickets[i]);
+        }
+        if (st != SLASH_E_BUSY) break;
+        std::this_thread::yield();
+      }
+      if (st != SLASH_OK) {
+        client_err = st;
+        tickets[i] = ~0ull;
+      }
+      if (is_ins[i])
+        ii += ins_rows[i];
+      else
+        ++qi;
+      submitted.store(i + 1, std::memory_order_release);
+    }
+  });
+  // map ticket -> request once tickets are known; poll completions
+  std::vector<slash_completion> buf(256);
+  uint64_t got = 0;
+  std::vector<std::pair<uint64_t, uint64_t>> pending_done;  // (ticket, completion index in store)
+  std::vector<slash_completion> store;
+  slash_status rs = SLASH_OK;
+  uint64_t expected = n;
+  while (got < expected) {
+    uint32_t m = 0;
+    rs = slash_serve_poll(srv, buf.data(), (uint32_t)buf.size(), &m);
+    if (rs != SLASH_OK) break;
+    for (uint32_t j = 0; j < m; ++j) store.push_back(buf[j]);
+    got += m;
+    if (client_err.load() && submitted.load() == n) {
+      uint64_t ok = 0;
+      for (uint64_t i = 0; i < n; ++i) ok += tickets[i] != ~0ull;
+      expected = ok;
+    }
+    if (m == 0) std::this_thread::sleep_for(std::chrono::microseconds(2));
+  }
+  client.join();
+  if (rs != SLASH_OK) return rs;
+  uint64_t base = ~0ull;
+  for (uint64_t i = 0; i < n; ++i) base = std::min(base, tickets[i]);
+  std::vector<int64_t> req_of(n + 1, -1);
+  for (uint64_t i = 0; i < n; ++i)
+    if (tickets[i] != ~0ull && tickets[i] - base < n) req_of[tickets[i] - base] = (int64_t)i;
+  for (const slash_completion& c : store) {
+    if (c.ticket - base >= n) continue;
+    int64_t i = req_of[c.ticket - base];
+    if (i < 0) continue;
+    lat[i] = c.t_done_s - (t0 + t_arr[i]);
+    if (out_ids && c.kind == 0)
+      for (uint32_t j = 0; j < std::min<uint32_t>(c.k, out_stride); ++j) out_ids[(uint64_t)i * out_stride + j] = c.ids[j];
+  }
+  for (uint64_t i = 0; i < n; ++i)
+    if (tickets[i] == ~0ull) lat[i] = -1.0;
+  if (client_err.load()) return fail((slash_status)client_err.load(), "some requests were rejected");
+  return SLASH_OK;
+}

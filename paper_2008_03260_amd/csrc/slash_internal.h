@@ -1,0 +1,206 @@
+// Internal declarations of libslash: constant layout, device helpers and the
+// kernel launchers shared by the host orchestration files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "slash.h"
+
+#define SL_EMPTY 0xFFFFFFFFu
+#define SL_WAVE 64
+
+namespace slash {
+
+// ------------------------------------------------------------ constants
+// Device-resident constant table of one index.  Everything derives from the
+// seed (Section 3 "Design": one shared seed gives every worker the same hash
+// functions).  Offsets are in elements of the named type.
+struct ConstView {
+  const uint64_t* a_h;   // [n_h]  nonzero-hash multipliers (odd)
+  const uint64_t* b_h;   // [n_h]
+  const uint32_t* dirw;  // [ceil(M/32)] densification direction bits (1 = right)
+  const uint64_t* a_tj;  // [L*K] bucket multipliers (odd)
+  const uint64_t* b_t;   // [L]
+  const uint32_t* key_t; // [L] priority keys
+  const uint32_t* m1_t;  // [L] odd
+  const uint32_t* m2_t;  // [L] odd
+  const uint64_t* a_r;   // [d] count-min multipliers (odd)
+  const uint64_t* b_r;   // [d]
+};
+
+struct HostConsts {
+  std::vector<uint64_t> a_h, b_h, a_tj, b_t, a_r, b_r;
+  std::vector<uint32_t> dirw, key_t, m1_t, m2_t;
+};
+
+// Shape of an index as the kernels see it.
+struct Shape {
+  uint32_t dim, K, L, M, B, R, d, lw, k_max, mode;
+  uint32_t nb;     // 2^B
+  uint32_t mshift; // M = 2^mshift when pow2, else 0xFF
+};
+
+struct TablesView {
+  uint32_t* ids;   // [L][nb][R]
+  uint32_t* seen;  // [L][nb]
+};
+
+// ------------------------------------------------------- device helpers
+
+__device__ __forceinline__ uint32_t hi32(uint64_t z) { return (uint32_t)(z >> 32); }
+
+// Nonzero hash u(i) = hi32(a * i + b) (mod 2^64), a 2-universal stand-in for
+// the random permutation of MinHash (Section 2.2).
+__device__ __forceinline__ uint32_t nz_hash(uint64_t a, uint64_t b, uint32_t i) {
+  return hi32(a * (uint64_t)i + b);
+}
+
+// Range bin of u among n equal bins: hi32(u * n).
+__device__ __forceinline__ uint32_t range_bin(uint32_t u, uint32_t n) {
+  return (uint32_t)(((uint64_t)u * n) >> 32);
+}
+
+// Reservoir priority: xor-multiply-xorshift bijection of uint32.
+__device__ __forceinline__ uint32_t priority(uint32_t id, uint32_t key, uint32_t m1, uint32_t m2) {
+  uint32_t x = (id ^ key) * m1;
+  x ^= x >> 16;
+  x *= m2;
+  x ^= x >> 15;
+  return x;
+}
+
+// Count-min row hash (a * c + b) >> (64 - lw); lw = 0 means one counter.
+__device__ __forceinline__ uint32_t cm_hash(uint64_t a, uint64_t b, uint32_t c, uint32_t lw) {
+  return lw ? (uint32_t)((a * (uint64_t)c + b) >> (64 - lw)) : 0u;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  uint32_t l = lane_id();
+  return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// Lanes of the wave whose `nbits`-bit digit equals this lane's digit,
+// restricted to `active`.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int nbits, uint64_t active) {
+  uint64_t m = active;
+  for (int b = 0; b < nbits; ++b) {
+    bool bit = (d >> b) & 1u;
+    uint64_t v = ballot64(bit);
+    m &= bit ? v : ~v;
+  }
+  return m;
+}
+
+// Record the thread-local error text and return s.
+slash_status fail(slash_status s, const char* fmt, ...);
+
+// ------------------------------------------------------------ launchers
+// Every launcher enqueues on `st` and returns hipSuccess or the launch error.
+
+hipError_t launch_validate(slash_csr rows, uint32_t dim, const uint32_t* kq, uint32_t k_max,
+                           uint32_t* flag, hipStream_t st);
+// Hash rows into keys: keys[t * key_stride + r] = bucket id (combined with t
+// when `combine`: t * nb + bucket).
+hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, uint32_t* keys,
+                            uint64_t key_stride, int combine, hipStream_t st);
+// Bucket ids in row-major [n][L].
+hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr rows, uint32_t* out,
+                                hipStream_t st);
+
+// Key-value radix sort of n uint32 keys on bits [0, nbits).  vals_in may be
+// NULL: values are then the positions 0..n-1.  Results land in
+// (keys_out, vals_out); the tmp buffers hold n entries each.
+struct SortBuffers {
+  uint32_t *k0, *v0, *k1, *v1;  // ping-pong, n each
+  uint32_t* hist;               // >= hist_entries(n)
+  uint32_t* part;               // scan partials
+};
+size_t sort_hist_entries(uint64_t n);
+size_t sort_part_entries(uint64_t n);
+hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t n, int nbits,
+                      SortBuffers& b, uint32_t** keys_out, uint32_t** vals_out, hipStream_t st);
+
+// Exclusive scan of n uint32 (in place), scratch `part` of sort_part_entries(n).
+hipError_t exclusive_scan(uint32_t* data, uint64_t n, uint32_t* part, hipStream_t st);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
+// Kernel entry of the fill kernel (for HIP graph nodes): (uint32_t* p, uint32_t v, uint64_t n).
+void* fill_kernel_ptr();
+// Kernel entry of the persistent query kernel for `waves` waves per query.
+void* persistent_query_kernel(uint32_t waves);
+hipError_t launch_validate_indices(const int32_t* idx, uint64_t n, uint32_t dim, uint32_t* flag, hipStream_t st);
+hipError_t launch_item_ids(uint32_t* vals, uint32_t first_id, uint64_t n_rows, uint64_t items, hipStream_t st);
+hipError_t launch_iota_u32(uint32_t* p, uint32_t first, uint64_t n, hipStream_t st);
+
+// Per-bucket [start, end) of a sorted key array (start/end pre-zeroed, nb entries).
+hipError_t launch_segment_bounds(const uint32_t* skeys, uint64_t n, uint32_t* start, uint32_t* end,
+                                 hipStream_t st);
+
+// Bottom-R selection for table t: buckets with <= heavy_t items are finished
+// in place; heavier ones are appended to heavy_list (count in *heavy_n).
+hipError_t launch_select_light(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* svals,
+                               const uint32_t* start, const uint32_t* end, TablesView tab,
+                               uint32_t heavy_t, uint32_t* heavy_list, uint32_t* heavy_n, hipStream_t st);
+// Chunk work: items [off, off+len) of `src` -> bottom-R candidates written to
+// dst[w * R ..] (padded with EMPTY), for table t.
+struct ChunkWork {
+  uint64_t off;
+  uint32_t len;
+  uint32_t dst;  // output slot (in units of R)
+};
+hipError_t launch_select_chunks(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
+                                const ChunkWork* work, uint32_t n_work, uint32_t* dst, hipStream_t st);
+// Final: items [off, off+len) of src -> reservoir of bucket b, seen = seen_v.
+struct FinalWork {
+  uint64_t off;
+  uint32_t len;
+  uint32_t bucket;
+  uint32_t seen;
+  uint32_t pad;
+};
+hipError_t launch_select_final(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
+                               const FinalWork* work, uint32_t n_work, TablesView tab, hipStream_t st);
+
+// Insert merge: sorted combined keys (t*nb+b) with new ids -> merged reservoirs.
+hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys,
+                               const uint32_t* svals, uint64_t n, uint32_t* seg_scratch,
+                               uint32_t* part, TablesView tab, hipStream_t st);
+
+// Query kernels.
+struct QueryArgs {
+  slash_csr q;
+  const uint32_t* kq;
+  uint32_t k;
+  uint32_t clamp;  // 1: clamp k to k_max
+  uint32_t* out_ids;
+  uint32_t* out_scores;
+};
+int query_block_threads(const Shape& s, uint32_t waves);
+size_t query_lds_bytes(const Shape& s, uint32_t waves);
+bool query_supported(const Shape& s);
+bool query_supported(const Shape& s, uint32_t waves);
+uint32_t query_default_waves(const Shape& s);
+hipError_t query_occupancy(const Shape& s, uint32_t waves, int* per_cu);
+hipError_t launch_query_waves(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
+                              uint32_t waves, hipStream_t st);
+hipError_t launch_query(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
+                        hipStream_t st);
+hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const TablesView& tab,
+                                   const QueryArgs& a, uint32_t waves, uint32_t per_ticket, uint32_t grid,
+                                   uint32_t* ticket, hipStream_t st);
+
+}  // namespace slash

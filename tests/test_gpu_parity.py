@@ -1,0 +1,273 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element (bucket ids, every reservoir slot and seen count, every top-k id
+and score).  All integer, so the bar is bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EMPTY = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_03260_amd import api as a
+    a.lib()
+    return a
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def params_pair(api, k_max=10, **kw):
+    base = dict(dim=1 << 20, K=4, L=8, log2_buckets=10, R=16, cm_rows=4, log2_cm_width=10, hash_mode=0, seed=99)
+    base.update(kw)
+    return api.Params.of(k_max=k_max, **base), oracle.Params(**base)
+
+
+def rows_of(n, seed=1, dim=1 << 20, **law):
+    lw = synth.RowLaw(synth.derive(seed, synth.STREAM_DATA), dim, **law)
+    return lw, lw.rows(0, n)
+
+
+def csr_from_lists(rows):
+    ip = np.zeros(len(rows) + 1, dtype=np.int64)
+    for i, r in enumerate(rows):
+        ip[i + 1] = ip[i] + len(r)
+    return ip, np.array([v for r in rows for v in r], dtype=np.int32)
+
+
+# ------------------------------------------------------------------ hash
+
+
+HASH_SHAPES = [
+    dict(K=4, L=16, hash_mode=0),           # M = 64 (tiny configuration)
+    dict(K=4, L=32, hash_mode=0),           # M = 128 (200M-point shard)
+    dict(K=3, L=7, hash_mode=0),            # M = 21, not a power of two
+    dict(K=8, L=128, log2_buckets=18),      # M = 1024 (wide configuration)
+    dict(K=1, L=1, hash_mode=0),            # M = 1, textbook MinHash
+    dict(K=4, L=16, hash_mode=1),           # per-table DOPH
+    dict(K=5, L=3, hash_mode=1),
+    dict(K=64, L=64, log2_buckets=12),      # M = 4096, the largest
+]
+
+
+@pytest.mark.parametrize("shape", HASH_SHAPES, ids=lambda s: "-".join(f"{k}{v}" for k, v in s.items()))
+def test_hash_parity(api, shape):
+    gp, op = params_pair(api, **shape)
+    _, (ip, ix) = rows_of(3000, seed=3)
+    # edge rows: single nonzero, repeats, long rows, extreme indices
+    extra = [[0], [(1 << 20) - 1], [5, 5, 5], list(range(0, 3000, 3)), [7, 1 << 19, 7, 3]]
+    eip, eix = csr_from_lists(extra)
+    ip = np.concatenate([ip, ip[-1] + eip[1:]])
+    ix = np.concatenate([ix, eix])
+    idx = api.Index(gp, dev(ip[:2]), dev(ix[: ip[1]]))
+    got = u32(idx.hash(dev(ip), dev(ix)))
+    cs = oracle.constants(op)
+    want = oracle.hash_rows(op, cs, ip, ix)
+    assert (got == want).all(), np.argwhere(got != want)[:5]
+
+
+# ----------------------------------------------------------------- build
+
+
+def check_tables(api, idx, op, cs, ip, ix):
+    gi, gsn = idx.tables()
+    wi, wsn = oracle.build(op, cs, ip, ix)
+    gi, gsn = u32(gi), u32(gsn)
+    assert (gsn == wsn).all(), np.argwhere(gsn != wsn)[:5]
+    bad = np.argwhere(gi != wi)
+    assert len(bad) == 0, bad[:5]
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(L=16, log2_buckets=12, R=32), dict(K=2, L=5, log2_buckets=3, R=7),
+                                   dict(hash_mode=1, L=6), dict(R=1), dict(R=130, log2_buckets=6)],
+                         ids=["base", "wide", "tiny-buckets", "mode1", "R1", "R130"])
+def test_build_parity(api, shape):
+    gp, op = params_pair(api, **shape)
+    _, (ip, ix) = rows_of(20000, seed=5)
+    idx = api.Index(gp, dev(ip), dev(ix))
+    check_tables(api, idx, op, oracle.constants(op), ip, ix)
+    assert idx.info()["n_items"] == 20000
+
+
+def test_build_heavy_buckets(api):
+    # identical rows pile into one bucket per table: 40000 > one wave's share,
+    # so the chunked bottom-R reduction runs (two rounds)
+    gp, op = params_pair(api, L=4, R=24)
+    _, (ip0, ix0) = rows_of(3000, seed=6)
+    dup = [[11, 22, 33, 44]] * 40000
+    dip, dix = csr_from_lists(dup)
+    ip = np.concatenate([ip0, ip0[-1] + dip[1:]])
+    ix = np.concatenate([ix0, dix])
+    idx = api.Index(gp, dev(ip), dev(ix))
+    check_tables(api, idx, op, oracle.constants(op), ip, ix)
+
+
+def test_build_ragged_and_tiny(api):
+    for n in (1, 2, 63, 64, 65, 4097):
+        gp, op = params_pair(api, L=3, log2_buckets=4, R=5)
+        _, (ip, ix) = rows_of(n, seed=10 + n)
+        idx = api.Index(gp, dev(ip), dev(ix))
+        check_tables(api, idx, op, oracle.constants(op), ip, ix)
+
+
+def test_build_empty_index(api):
+    gp, op = params_pair(api, L=2, log2_buckets=3, R=2)
+    idx = api.Index(gp, dev(np.zeros(1, dtype=np.int64)), dev(np.zeros(1, dtype=np.int32)))
+    gi, gsn = idx.tables()
+    assert (u32(gi) == EMPTY).all() and (u32(gsn) == 0).all()
+
+
+def test_insert_equals_bulk_build(api):
+    gp, op = params_pair(api, L=6, log2_buckets=8, R=8)
+    _, (ip, ix) = rows_of(9000, seed=8)
+    n0 = 3000
+    idx = api.Index(gp, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    rng = np.random.default_rng(0)
+    cur = n0
+    while cur < 9000:
+        m = int(min(9000 - cur, rng.integers(1, 1500)))
+        sip = ip[cur: cur + m + 1] - ip[cur]
+        six = ix[ip[cur]: ip[cur + m]]
+        nid = torch.empty(m, dtype=torch.int32, device="cuda")
+        idx.insert(dev(sip), dev(six), new_ids=nid)
+        assert (u32(nid) == np.arange(cur, cur + m)).all()
+        cur += m
+    torch.cuda.synchronize()
+    check_tables(api, idx, op, oracle.constants(op), ip, ix)
+    assert idx.info()["n_items"] == 9000
+
+
+def test_invalid_rows_rejected(api):
+    gp, op = params_pair(api, dim=1000, L=2, log2_buckets=4, R=3)
+    for rows in ([[1, 2], []], [[1, 2], [1000]], [[-3]]):
+        ip, ix = csr_from_lists(rows)
+        with pytest.raises(api.SlashError) as e:
+            api.Index(gp, dev(ip), dev(ix))
+        assert e.value.code == api.E_INVAL
+    ip, ix = csr_from_lists([[1, 2], [3]])
+    idx = api.Index(gp, dev(ip), dev(ix))
+    before = [u32(t).copy() for t in idx.tables()]
+    bip, bix = csr_from_lists([[4], [5000]])
+    with pytest.raises(api.SlashError):
+        idx.insert(dev(bip), dev(bix))
+    after = [u32(t) for t in idx.tables()]
+    assert all((a == b).all() for a, b in zip(before, after))
+    assert idx.info()["n_items"] == 2
+
+
+def test_invalid_params_rejected(api):
+    ip, ix = csr_from_lists([[1]])
+    for bad in (dict(K=0), dict(L=0), dict(R=0), dict(log2_buckets=0), dict(log2_buckets=31), dict(k_max=0),
+                dict(hash_mode=2), dict(cm_rows=0), dict(log2_cm_width=17)):
+        gp, _ = params_pair(api, **bad)
+        with pytest.raises(api.SlashError) as e:
+            api.Index(gp, dev(ip), dev(ix))
+        assert e.value.code in (api.E_INVAL, api.E_UNSUPPORTED)
+
+
+# ----------------------------------------------------------------- query
+
+
+@pytest.fixture(scope="module")
+def qsetup(api):
+    gp, op = params_pair(api, k_max=24, L=16, log2_buckets=12, R=16, cm_rows=3, log2_cm_width=8)
+    law, (ip, ix) = rows_of(30000, seed=21)
+    qi, qx, src, _ = law.queries(synth.derive(21, synth.STREAM_QUERY), 30000, 0, 300, nnz_mode="lognormal",
+                                 median=40, sigma=1.0, lo=1, hi=2000, f=(0.1, 0.4))
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    return idx, op, cs, oids, oseen, qi, qx
+
+
+@pytest.mark.parametrize("k", [1, 10, 24])
+def test_query_parity(api, qsetup, k):
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    gi, gs = idx.query(dev(qi), dev(qx), k)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, k, k_max=24)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+
+
+def test_query_per_query_k(api, qsetup):
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    kq = np.random.default_rng(1).choice([0, 1, 10, 24], size=len(qi) - 1).astype(np.uint32)
+    gi, gs = idx.query(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=24, kq=kq)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+
+
+def test_query_k_above_kmax_rejected(api, qsetup):
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    with pytest.raises(api.SlashError):
+        idx.query(dev(qi), dev(qx), 25)
+    kq = np.full(len(qi) - 1, 30, dtype=np.uint32)
+    with pytest.raises(api.SlashError):
+        idx.query(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
+
+
+def test_query_exact_special_cases(api):
+    # one counter (w = 1): every estimate is |C|, so ranking is by id
+    gp, op = params_pair(api, k_max=7, L=8, log2_buckets=6, R=6, cm_rows=1, log2_cm_width=0)
+    law, (ip, ix) = rows_of(3000, seed=31)
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    gi, gs = idx.query(dev(ip[:101]), dev(ix[: ip[100]]), 7)
+    wi, ws = oracle.query(op, cs, oids, oseen, ip[:101], ix[: ip[100]], 7)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+
+
+@pytest.mark.parametrize("sched", [dict(waves_per_query=1, queries_per_ticket=1),
+                                   dict(waves_per_query=2, queries_per_ticket=3),
+                                   dict(waves_per_query=4, queries_per_ticket=8, groups_per_cu=1),
+                                   dict(waves_per_query=8, queries_per_ticket=1),
+                                   dict(waves_per_query=16, queries_per_ticket=2)])
+def test_batched_equals_plain(api, qsetup, sched):
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    a = idx.query(dev(qi), dev(qx), 10)
+    for _ in range(2):  # second call replays the recorded graph
+        b = idx.query_batched(dev(qi), dev(qx), 10, schedule=sched)
+        torch.cuda.synchronize()
+        assert (u32(a[0]) == u32(b[0])).all() and (u32(a[1]) == u32(b[1])).all()
+
+
+def test_autotune_and_batched_default(api, qsetup):
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    best = idx.autotune(dev(qi), dev(qx), 10)
+    assert best["waves_per_query"] in (1, 2, 4, 8, 16)
+    a = idx.query(dev(qi), dev(qx), 10)
+    b = idx.query_batched(dev(qi), dev(qx), 10)
+    assert (u32(a[0]) == u32(b[0])).all() and (u32(a[1]) == u32(b[1])).all()
+
+
+def test_tiny_config_end_to_end(api):
+    # tiny configuration: N = 1e5, K=4, L=16, 2^16 buckets, R=32, count-min
+    # 4 x 1024, k = 10, 1000 planted-perturbation queries
+    master = 2020
+    gp, op = params_pair(api, k_max=10, L=16, log2_buckets=16, R=32, cm_rows=4, log2_cm_width=10,
+                         seed=synth.derive(master, synth.STREAM_INDEX))
+    law = synth.RowLaw(synth.derive(master, synth.STREAM_DATA), 1 << 20)
+    ip, ix = law.rows(0, 100000)
+    qi, qx, src, _ = law.queries(synth.derive(master, synth.STREAM_QUERY), 100000, 0, 1000)
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    check_tables(api, idx, op, cs, ip, ix)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    gi, gs = idx.query(dev(qi), dev(qx), 10)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 10)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+    recall = np.mean([s in r for s, r in zip(src.tolist(), u32(gi).tolist())])
+    assert recall >= 0.9
