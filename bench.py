@@ -1,0 +1,215 @@
+"""Benchmark of the SLASH hot path on one MI355X.
+
+Workload (default): one node's shard at the paper's per-node Criteo scale,
+synthetic: N = 200M binary rows, D = 2^20, nnz ~ Poisson(40), Zipf(1.1)
+feature indices (int32 CSR, ~32 GB, generated in HBM); K=4, L=32, 2^20
+buckets per table, R=64; 100,000 planted-perturbation queries (20% of each
+source row replaced), count-min 4 x 4096, top-10.
+
+One step = the whole hot path over the resident inputs: build the index over
+all rows (hash, sort, bottom-R reservoirs), insert one batch of 4096 new rows,
+answer the 100k queries in one batched (persistent, graph-replayed) launch.
+value = queries/s of the query phase over the timed steps; inserts/s of the
+build and of the insert batch are reported beside it, and the one-at-a-time
+query latency (p50/p99) is measured after the timed steps.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c1|c0]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # tiny: N = 1e5, K=4, L=16, 2^16 buckets, R=32, count-min 4 x 1024, k = 10
+    "c0": dict(n=100_000, dim=1 << 20, K=4, L=16, B=16, R=32, d=4, lw=10, k=10, nq=1000, master=2020,
+               desc="tiny: N=1e5, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=16 B=16 R=32; CM 4x1024; k=10; 1000 queries f=0.2"),
+    # one node's 200M-point shard
+    "c1": dict(n=200_000_000, dim=1 << 20, K=4, L=32, B=20, R=64, d=4, lw=12, k=10, nq=100_000, master=2021,
+               desc="200M-point shard: N=2e8, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=32 B=20 R=64; CM 4x4096; "
+                    "k=10; 100k queries f=0.2"),
+}
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, law, seeds, budget_s=20.0):
+    """The plain CPU oracle, single-threaded, on a bounded sample of the same
+    workload: a prefix of the rows and a slice of the queries."""
+    import oracle
+    import synth
+
+    n_rows = min(w["n"], 1_000_000 if w["n"] > 1_000_000 else w["n"])
+    op = oracle.Params(dim=w["dim"], K=w["K"], L=w["L"], log2_buckets=w["B"], R=w["R"], cm_rows=w["d"],
+                       log2_cm_width=w["lw"], seed=seeds["index"])
+    cs = oracle.constants(op)
+    ip, ix = law.rows(0, n_rows)
+    t0 = time.perf_counter()
+    ids, seen = oracle.build(op, cs, ip, ix)
+    t_build = time.perf_counter() - t0
+    nq = 200
+    qi, qx, _, _ = law.queries(seeds["query"], n_rows, 0, nq)
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < max(1.0, budget_s - t_build) and done < 20 * nq:
+        oracle.query(op, cs, ids, seen, qi, qx, w["k"])
+        done += nq
+    t_q = time.perf_counter() - t0
+    return {
+        "value": done / t_q, "unit": "queries/s", "cores": 1, "kind": "oracle",
+        "sample": f"oracle (single-threaded C, -O2) on the first {n_rows:,} rows of the same workload "
+                  f"(same K, L, B, R, count-min); {done} queries answered; build {n_rows / t_build:,.0f} rows/s",
+        "build_rows_per_s": n_rows / t_build,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-queries", type=int, default=20000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2008_03260_amd import api
+
+    w = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    seeds = {k: synth.derive(w["master"], t) for k, t in
+             (("data", synth.STREAM_DATA), ("query", synth.STREAM_QUERY), ("index", synth.STREAM_INDEX))}
+    law = synth.RowLaw(seeds["data"], w["dim"])
+    log(f"workload {args.workload}: {w['desc']}")
+    t0 = time.perf_counter()
+    ip, ix = law.gpu_rows(0, w["n"])
+    ins_ip, ins_ix = law.gpu_rows(w["n"], 4096)
+    torch.cuda.synchronize()
+    nnz = int(ip[-1].item())
+    log(f"generated {w['n']:,} rows, {nnz:,} nonzeros in HBM in {time.perf_counter() - t0:.1f}s")
+    qi_h, qx_h, src, _ = law.queries(seeds["query"], w["n"], 0, w["nq"])
+    qi, qx = torch.from_numpy(qi_h).to(dev), torch.from_numpy(qx_h).to(dev)
+    params = api.Params.of(dim=w["dim"], K=w["K"], L=w["L"], log2_buckets=w["B"], R=w["R"], cm_rows=w["d"],
+                           log2_cm_width=w["lw"], k_max=w["k"], hash_mode=0, seed=seeds["index"])
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    sched = None
+
+    def step(record):
+        e = [ev() for _ in range(6)]
+        e[0].record(stream)
+        h = api.slash_build(params, ip, ix, stream)
+        e[1].record(stream)
+        api.slash_insert(h, ins_ip, ins_ix, api.FLAG_TRUSTED, None, stream)
+        e[2].record(stream)
+        e[3].record(stream)
+        oi, osc = api.slash_query_batched(h, qi, qx, w["k"], flags=api.FLAG_TRUSTED, schedule=sched, stream=stream)
+        e[4].record(stream)
+        torch.cuda.synchronize()
+        if record is not None:
+            record.append((e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[3].elapsed_time(e[4])))
+        return h, oi
+
+    # tune the batched schedule once on the first index
+    h, _ = step(None)
+    sched = api.slash_autotune(h, qi[: 20001] if w["nq"] > 20000 else qi,
+                               qx[: int(qi_h[min(20000, w['nq'])])] if w["nq"] > 20000 else qx, w["k"], stream)
+    log(f"autotuned schedule {sched}")
+    api.slash_free(h)
+    for _ in range(args.warmup):
+        h, _ = step(None)
+        api.slash_free(h)
+    rec = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        h, oi = step(rec)
+        if i + 1 < args.steps:
+            api.slash_free(h)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b_ms = np.array([r[0] for r in rec])
+    i_ms = np.array([r[1] for r in rec])
+    q_ms = np.array([r[2] for r in rec])
+    qps = w["nq"] * len(rec) / (q_ms.sum() / 1e3)
+    got = api.as_u32(oi)
+    recall = float(np.mean([s in row for s, row in zip(src.tolist(), got.tolist())]))
+    log(f"build {b_ms.mean():.1f} ms, insert(4096) {i_ms.mean():.2f} ms, batched query {q_ms.mean():.2f} ms, "
+        f"recall@10 {recall:.4f}")
+
+    # one-at-a-time plain path: per-query latency, host-synchronised
+    npl = min(args.plain_queries, w["nq"])
+    lat = np.empty(npl)
+    single_ip = [qi[i:i + 2] - qi[i] for i in range(npl)]
+    for i in range(min(200, npl)):  # warm
+        api.slash_query(h, single_ip[i], qx[int(qi_h[i]):int(qi_h[i + 1])], w["k"], flags=api.FLAG_TRUSTED)
+    torch.cuda.synchronize()
+    out_i = torch.empty((1, w["k"]), dtype=torch.int32, device=dev)
+    out_s = torch.empty((1, w["k"]), dtype=torch.int32, device=dev)
+    t_pl = time.perf_counter()
+    for i in range(npl):
+        t = time.perf_counter()
+        api.slash_query(h, single_ip[i], qx[int(qi_h[i]):int(qi_h[i + 1])], w["k"], flags=api.FLAG_TRUSTED,
+                        out_ids=out_i, out_scores=out_s)
+        torch.cuda.synchronize()
+        lat[i] = time.perf_counter() - t
+    t_pl = time.perf_counter() - t_pl
+    log(f"plain one-at-a-time: {npl / t_pl:,.0f} q/s, p50 {np.percentile(lat, 50) * 1e6:.1f} us, "
+        f"p99 {np.percentile(lat, 99) * 1e6:.1f} us")
+
+    # roofline of the query kernel (algorithmic bytes per query: the query row
+    # 4*nnz + 8, per table the reservoir row read 4*R (fill read as the
+    # EMPTY-padded row), the output 8*k)
+    alg_bytes = 4 * (int(qi_h[-1])) + 8 * w["nq"] + w["nq"] * w["L"] * 4 * w["R"] + w["nq"] * 8 * w["k"]
+    q_s = q_ms.mean() / 1e3
+    achieved = alg_bytes / q_s / 1e9
+    build_alg = 4 * nnz + 8 * w["n"] + w["L"] * (1 << w["B"]) * (4 * w["R"] + 4)
+    api.slash_free(h)
+
+    res = {
+        "metric": "queries/s & p99 latency at recall@10>=0.9, 200M-pt shard; inserts/s",
+        "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": w["desc"], "queries_per_step": w["nq"], "rows": w["n"], "nnz": nnz,
+                   "schedule": sched},
+        "recall_at_10": recall,
+        "p50_latency_us": float(np.percentile(lat, 50) * 1e6),
+        "p99_latency_us": float(np.percentile(lat, 99) * 1e6),
+        "plain_queries_per_s": npl / t_pl,
+        "build_inserts_per_s": w["n"] / (b_ms.mean() / 1e3),
+        "build_ms": float(b_ms.mean()),
+        "insert_batch_rows_per_s": 4096 / (i_ms.mean() / 1e3),
+        "batched_query_ms": float(q_ms.mean()),
+        "build_algorithmic_hbm_frac": build_alg / (b_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_query_persistent"},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        res["cpu_baseline"] = cpu_baseline(w, law, seeds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,12 +138,13 @@ def slash_insert(index, indptr, indices, flags: int = 0, new_ids: torch.Tensor |
 
 
 def _outputs(index, n, out_ids, out_scores):
-    km = slash_index_info_get(index)["k_max"]
-    dev = torch.device("cuda", torch.cuda.current_device())
-    if out_ids is None:
-        out_ids = torch.empty((n, km), dtype=torch.int32, device=dev)
-    if out_scores is None:
-        out_scores = torch.empty((n, km), dtype=torch.int32, device=dev)
+    if out_ids is None or out_scores is None:
+        km = slash_index_info_get(index)["k_max"]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if out_ids is None:
+            out_ids = torch.empty((n, km), dtype=torch.int32, device=dev)
+        if out_scores is None:
+            out_scores = torch.empty((n, km), dtype=torch.int32, device=dev)
     return out_ids, out_scores
 
 

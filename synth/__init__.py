@@ -18,12 +18,23 @@ _SO = os.path.join(_HERE, "libsynth.so")
 _lib = None
 
 
+_SO_GPU = os.path.join(_HERE, "libsynth_gpu.so")
+_lib_gpu = None
+
+
 def build_lib() -> str:
-    """Compile the generator library in-tree (always recompiles)."""
+    """Compile the generator libraries in-tree (always recompiles): the host
+    library (gcc) and its device build (hipcc, gfx950)."""
     src = os.path.join(_HERE, "synth.c")
     tmp = _SO + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-pthread", "-o", tmp, src, "-lm"])
     os.replace(tmp, _SO)
+    tmp = _SO_GPU + ".tmp"
+    subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "-o", tmp, os.path.join(_HERE, "synth_gpu.hip")],
+                          stderr=subprocess.DEVNULL)
+    os.replace(tmp, _SO_GPU)
     return _SO
 
 
@@ -64,8 +75,22 @@ def lib():
         L.synth_arrivals.argtypes = [C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_uint32,
                                      C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.synth_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.synth_ctx_tables.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(RowsSpec)]
         _lib = L
     return _lib
+
+
+def lib_gpu():
+    global _lib_gpu
+    if _lib_gpu is None:
+        if not os.path.exists(_SO_GPU):
+            raise RuntimeError("synth/libsynth_gpu.so is not built; run __graft_entry__.build()")
+        L = C.CDLL(_SO_GPU)
+        u64, u32, vp = C.c_uint64, C.c_uint32, C.c_void_p
+        L.synth_gpu_rows_nnz.argtypes = [u64, u64, u64, vp, u32, u32, u32, vp, vp]
+        L.synth_gpu_rows_fill.argtypes = [u64, u64, u64, u32, C.c_int, vp, vp, vp, vp]
+        _lib_gpu = L
+    return _lib_gpu
 
 
 def _ptr(a: np.ndarray):
@@ -124,6 +149,42 @@ class RowLaw:
         indices = np.empty(int(indptr[-1]), dtype=np.int32)
         lib().synth_rows_fill(self._ctx, row0, n, _ptr(indptr), _ptr(indices), th)
         return indptr, indices
+
+    def gpu_rows(self, row0: int, n: int, stream=None):
+        """Rows [row0, row0+n) generated on the current HIP device, bit-identical
+        to rows(); returns (indptr int64, indices int32) device tensors."""
+        import torch
+        g = lib_gpu()
+        tab_p, pcdf_p, pn, spec = C.c_void_p(), C.c_void_p(), C.c_uint32(), RowsSpec()
+        lib().synth_ctx_tables(self._ctx, C.byref(tab_p), C.byref(pcdf_p), C.byref(pn), C.byref(spec))
+        if spec.nnz_kind != 0:
+            raise NotImplementedError("device generation supports Poisson row sizes only")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if getattr(self, "_dev_tabs", None) is None:
+            pcdf = np.ctypeslib.as_array(C.cast(pcdf_p, C.POINTER(C.c_double)), shape=(pn.value,)).copy()
+            tab = None
+            if spec.index_kind == 0:
+                tab = np.ctypeslib.as_array(C.cast(tab_p, C.POINTER(C.c_uint64)), shape=(spec.dim,)).copy()
+                tab = torch.from_numpy(tab.view(np.int64)).to(dev)
+            self._dev_tabs = (torch.from_numpy(pcdf).to(dev), tab)
+        pcdf_t, tab_t = self._dev_tabs
+        st = C.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+        nnz = torch.empty(n, dtype=torch.int32, device=dev)
+        rc = g.synth_gpu_rows_nnz(spec.key, row0, n, C.c_void_p(pcdf_t.data_ptr()), pn.value, spec.nnz_lo,
+                                  spec.nnz_hi, C.c_void_p(nnz.data_ptr()), st)
+        if rc:
+            raise RuntimeError("synth_gpu_rows_nnz failed")
+        indptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+        torch.cumsum(nnz, 0, out=indptr[1:])
+        del nnz
+        total = int(indptr[-1].item())
+        indices = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+        rc = g.synth_gpu_rows_fill(spec.key, row0, n, spec.dim, 1 if spec.index_kind == 0 else 0,
+                                   C.c_void_p(tab_t.data_ptr()) if tab_t is not None else None,
+                                   C.c_void_p(indptr.data_ptr()), C.c_void_p(indices.data_ptr()), st)
+        if rc:
+            raise RuntimeError("synth_gpu_rows_fill failed")
+        return indptr, indices[:total]
 
     def queries(self, key: int, n_data: int, q0: int, n: int, nnz_mode: str = "same",
                 median: float = 40.0, sigma: float = 1.0, lo: int = 5, hi: int = 2000,

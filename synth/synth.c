@@ -553,3 +553,13 @@ EXPORT int synth_arrivals(uint64_t key, uint64_t n, double rate, double insert_f
   }
   return 0;
 }
+
+/* Tables of a row law, for the device build of the generator: alias table
+ * (D entries, Zipf only) and Poisson inverse CDF (pcdf_n doubles). */
+EXPORT void synth_ctx_tables(const synth_ctx* c, const uint64_t** tab, const double** pcdf, uint32_t* pcdf_n,
+                             synth_rows_spec* spec) {
+  *tab = c->tab;
+  *pcdf = c->pcdf;
+  *pcdf_n = c->pcdf_n;
+  *spec = c->s;
+}
