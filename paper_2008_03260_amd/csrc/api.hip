@@ -563,7 +563,7 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a, const slash
   uint32_t* tk = ticket;
   void* fill_args[] = {&tk, &zero, &one};
   hipKernelNodeParams rp{};
-  rp.func = persistent_query_kernel(waves);
+  rp.func = persistent_query_kernel(s, waves);
   rp.gridDim = dim3(grid);
   rp.blockDim = dim3(waves * SL_WAVE);
   rp.sharedMemBytes = (unsigned)query_lds_bytes(s, waves);

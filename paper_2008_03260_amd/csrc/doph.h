@@ -6,16 +6,73 @@
 
 namespace slash {
 
+// Loads of hash constants.  With CL = true the pointer is a staged copy in
+// LDS and is read with LDS instructions; otherwise from global memory.
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+
+template <bool CL>
+__device__ __forceinline__ uint64_t cld64(const uint64_t* p, uint32_t i) {
+  if constexpr (CL)
+    return ((lds_u64*)p)[i];
+  else
+    return p[i];
+}
+
+template <bool CL>
+__device__ __forceinline__ uint32_t cld32(const uint32_t* p, uint32_t i) {
+  if constexpr (CL)
+    return ((lds_u32*)p)[i];
+  else
+    return p[i];
+}
+
 // Words of the per-row non-empty mask (built 64 bins at a time).
 __host__ __device__ constexpr uint32_t mask_words(uint32_t M) { return ((M + 63) / 64) * 2; }
 
 // LDS words one wave needs for doph_wave: minima[M] + densified[M] + mask.
 __host__ __device__ constexpr uint32_t doph_lds_words(uint32_t M) { return 2 * M + mask_words(M); }
 
+// 32-bit LDS words of the staged hash constants: u64 a_h, b_h, a_tj, b_t,
+// a_r, b_r, then the u32 direction words.
+__host__ __device__ inline uint32_t const_words(const Shape& s) {
+  uint32_t n_h = s.mode ? s.L : 1;
+  return 2 * (2 * n_h + s.M + s.L + 2 * s.d) + (s.M + 31) / 32 + 1;
+}
+
+// Largest constant table staged in LDS (larger ones are read from global).
+constexpr uint32_t kConstCapWords = 4096;
+
+// Copy the hash constants into LDS at `dst` (8-byte aligned) with all
+// `nthreads` threads of the block; returns a view of the staged copy.  The
+// caller synchronises the block before use.
+__device__ inline ConstView stage_consts(const Shape& s, const ConstView& c, uint32_t* dst, uint32_t nthreads) {
+  const uint32_t n_h = s.mode ? s.L : 1;
+  ConstView v = c;
+  uint64_t* p = (uint64_t*)dst;
+  auto put64 = [&](const uint64_t* src, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += nthreads) p[i] = src[i];
+    const uint64_t* r = p;
+    p += n;
+    return r;
+  };
+  v.a_h = put64(c.a_h, n_h);
+  v.b_h = put64(c.b_h, n_h);
+  v.a_tj = put64(c.a_tj, s.M);
+  v.b_t = put64(c.b_t, s.L);
+  v.a_r = put64(c.a_r, s.d);
+  v.b_r = put64(c.b_r, s.d);
+  uint32_t* q = (uint32_t*)p;
+  const uint32_t nd = (s.M + 31) / 32 + 1;
+  for (uint32_t i = threadIdx.x; i < nd; i += nthreads) q[i] = c.dirw[i];
+  v.dirw = q;
+  return v;
+}
+
 // Nearest set bit of `mask` walking right (increasing, circular) from pos
 // inside the domain [lo, lo + n).  Requires a set bit in the domain other
 // than pos.
-__device__ __forceinline__ uint32_t find_right(const uint32_t* mask, uint32_t lo, uint32_t n, uint32_t pos) {
+__device__ __forceinline__ uint32_t find_right(const lds_u32* mask, uint32_t lo, uint32_t n, uint32_t pos) {
   const uint32_t end = lo + n;
   uint32_t q = pos + 1 == end ? lo : pos + 1;
   for (;;) {
@@ -30,7 +87,7 @@ __device__ __forceinline__ uint32_t find_right(const uint32_t* mask, uint32_t lo
 }
 
 // Same, walking left (decreasing, circular).
-__device__ __forceinline__ uint32_t find_left(const uint32_t* mask, uint32_t lo, uint32_t n, uint32_t pos) {
+__device__ __forceinline__ uint32_t find_left(const lds_u32* mask, uint32_t lo, uint32_t n, uint32_t pos) {
   uint32_t q = pos == lo ? lo + n - 1 : pos - 1;
   for (;;) {
     uint32_t o = q & 31u;
@@ -45,7 +102,7 @@ __device__ __forceinline__ uint32_t find_left(const uint32_t* mask, uint32_t lo,
   }
 }
 
-__device__ __forceinline__ bool domain_any(const uint32_t* mask, uint32_t lo, uint32_t n) {
+__device__ __forceinline__ bool domain_any(const lds_u32* mask, uint32_t lo, uint32_t n) {
   for (uint32_t q = lo; q < lo + n;) {
     uint32_t o = q & 31u;
     uint32_t span = min(32u - o, lo + n - q);
@@ -63,6 +120,7 @@ __device__ __forceinline__ bool domain_any(const uint32_t* mask, uint32_t lo, ui
 // domains stay EMPTY).
 // `idx` points at the row's nnz indices.  All 64 lanes must call.  Returns
 // the densified values (lds + M, M entries).
+template <bool CL>
 __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const ConstView& c,
                                                      const int32_t* __restrict__ idx, uint32_t nnz,
                                                      uint32_t* lds_m) {
@@ -70,10 +128,14 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
   const uint32_t M = s.M;
   uint32_t* lds_h = lds_m + M;
   uint32_t* mask = lds_m + 2 * M;
+  typedef __attribute__((address_space(3))) uint32_t lw32;
+  lw32* m3 = (lw32*)lds_m;
+  lw32* h3 = (lw32*)lds_h;
+  const lds_u32* k3 = (const lds_u32*)mask;
   for (uint32_t b = lane; b < M; b += SL_WAVE) lds_m[b] = SL_EMPTY;
   wave_sync();
   if (s.mode == 0) {
-    const uint64_t a = c.a_h[0], bb = c.b_h[0];
+    const uint64_t a = cld64<CL>(c.a_h, 0), bb = cld64<CL>(c.b_h, 0);
     for (uint32_t e = lane; e < nnz; e += SL_WAVE) {
       uint32_t u = nz_hash(a, bb, (uint32_t)idx[e]);
       uint32_t bin;
@@ -87,7 +149,7 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
     const uint32_t L = s.L, K = s.K;
     for (uint32_t w = lane; w < nnz * L; w += SL_WAVE) {
       uint32_t e = w / L, t = w - e * L;
-      uint32_t u = nz_hash(c.a_h[t], c.b_h[t], (uint32_t)idx[e]);
+      uint32_t u = nz_hash(cld64<CL>(c.a_h, t), cld64<CL>(c.b_h, t), (uint32_t)idx[e]);
       atomicMin(&lds_m[t * K + range_bin(u, K)], u);
     }
   }
@@ -95,7 +157,7 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
   // non-empty mask, 64 bins per ballot
   for (uint32_t base = 0; base < M; base += SL_WAVE) {
     uint32_t b = base + lane;
-    bool ne = b < M && lds_m[b] != SL_EMPTY;
+    bool ne = b < M && m3[b] != SL_EMPTY;
     uint64_t bal = ballot64(ne);
     if (lane == 0) {
       mask[base / 32] = (uint32_t)bal;
@@ -108,23 +170,23 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
   if (s.mode == 0) {
     const uint32_t nw = mask_words(M);
     bool mine = false;
-    for (uint32_t w = lane; w < nw; w += SL_WAVE) mine |= mask[w] != 0u;
+    for (uint32_t w = lane; w < nw; w += SL_WAVE) mine |= k3[w] != 0u;
     any_all = ballot64(mine) != 0ull;
   }
   // densify into lds_h, reading only the minima
 #pragma unroll 1
   for (uint32_t b = lane; b < M; b += SL_WAVE) {
-    uint32_t v = lds_m[b];
+    uint32_t v = m3[b];
     if (v == SL_EMPTY) {
       uint32_t lo = s.mode == 0 ? 0u : (b / s.K) * s.K;
       uint32_t n = s.mode == 0 ? M : s.K;
-      if (s.mode == 0 ? any_all : domain_any(mask, lo, n)) {
-        bool right = (c.dirw[b >> 5] >> (b & 31)) & 1u;
-        uint32_t src = right ? find_right(mask, lo, n, b) : find_left(mask, lo, n, b);
-        v = lds_m[src];
+      if (s.mode == 0 ? any_all : domain_any(k3, lo, n)) {
+        bool right = (cld32<CL>(c.dirw, b >> 5) >> (b & 31)) & 1u;
+        uint32_t src = right ? find_right(k3, lo, n, b) : find_left(k3, lo, n, b);
+        v = m3[src];
       }
     }
-    lds_h[b] = v;
+    h3[b] = v;
   }
   wave_sync();
   return lds_h;
@@ -132,12 +194,13 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
 
 // Bucket id of table t from densified values h (Section 2.3):
 // (b_t + sum_j a_tj * h[tK + j]) >> (64 - B), arithmetic mod 2^64.
+template <bool CL>
 __device__ __forceinline__ uint32_t table_bucket(const Shape& s, const ConstView& c, const uint32_t* h,
                                                  uint32_t t) {
-  uint64_t acc = c.b_t[t];
-  const uint64_t* a = c.a_tj + (uint64_t)t * s.K;
-  const uint32_t* ht = h + t * s.K;
-  for (uint32_t j = 0; j < s.K; ++j) acc += a[j] * (uint64_t)ht[j];
+  uint64_t acc = cld64<CL>(c.b_t, t);
+  const uint32_t base = t * s.K;
+  const lds_u32* ht = (const lds_u32*)h;
+  for (uint32_t j = 0; j < s.K; ++j) acc += cld64<CL>(c.a_tj, base + j) * (uint64_t)ht[base + j];
   return (uint32_t)(acc >> (64 - s.B));
 }
 

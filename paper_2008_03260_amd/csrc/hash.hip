@@ -8,9 +8,12 @@ namespace {
 
 constexpr int kMaxHashWaves = 4;
 
+__host__ __device__ inline bool const_staged(const Shape& s) { return const_words(s) <= kConstCapWords; }
+
 // Each block takes chunks of `rpc` consecutive rows; each wave hashes one row
 // at a time and stages its L bucket ids in LDS; the block then writes every
 // table's rpc ids as one contiguous run (keys are table-major).
+template <bool CL>
 __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
     k_hash_rows(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ keys, uint64_t key_stride,
                 int combine, uint32_t rpc) {
@@ -18,8 +21,11 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
   const uint32_t nw = blockDim.x / SL_WAVE;
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
   const uint32_t per_wave = doph_lds_words(s.M);
-  uint32_t* my = lds + wave * per_wave;
-  uint32_t* stage = lds + nw * per_wave;  // [L][rpc]
+  const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
+  const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
+  uint32_t* my = lds + cw + wave * per_wave;
+  uint32_t* stage = lds + cw + nw * per_wave;  // [L][rpc]
+  __syncthreads();
   const uint64_t n = rows.n_rows;
   const uint64_t n_chunks = (n + rpc - 1) / rpc;
   for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
@@ -28,9 +34,9 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
       const uint64_t r = r0 + rl;
       if (r >= n) break;
       const int64_t beg = rows.indptr[r], end = rows.indptr[r + 1];
-      const uint32_t* h = doph_wave(s, c, rows.indices + beg, (uint32_t)(end - beg), my);
+      const uint32_t* h = doph_wave<CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
       for (uint32_t t = lane; t < s.L; t += SL_WAVE) {
-        uint32_t b = table_bucket(s, c, h, t);
+        uint32_t b = table_bucket<CL>(s, cl, h, t);
         stage[t * rpc + rl] = combine ? t * s.nb + b : b;
       }
       wave_sync();
@@ -45,22 +51,29 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
   }
 }
 
+template <bool CL>
 __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
     k_hash_rowmajor(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ out) {
   extern __shared__ uint32_t lds[];
   const uint32_t nw = blockDim.x / SL_WAVE;
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
-  uint32_t* my = lds + wave * doph_lds_words(s.M);
+  const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
+  const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
+  uint32_t* my = lds + cw + wave * doph_lds_words(s.M);
   const uint64_t n = rows.n_rows;
+  __syncthreads();
   for (uint64_t r = (uint64_t)blockIdx.x * nw + wave; r < n; r += (uint64_t)gridDim.x * nw) {
     const int64_t beg = rows.indptr[r], end = rows.indptr[r + 1];
-    const uint32_t* h = doph_wave(s, c, rows.indices + beg, (uint32_t)(end - beg), my);
-    for (uint32_t t = lane; t < s.L; t += SL_WAVE) out[r * s.L + t] = table_bucket(s, c, h, t);
+    const uint32_t* h = doph_wave<CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
+    for (uint32_t t = lane; t < s.L; t += SL_WAVE) out[r * s.L + t] = table_bucket<CL>(s, cl, h, t);
     wave_sync();
   }
 }
 
 constexpr size_t kLdsCap = 160 * 1024;
+
+// LDS words ahead of the per-wave DOPH scratch.
+uint32_t const_lds_words(const Shape& s) { return const_staged(s) ? (const_words(s) + 1) & ~1u : 0u; }
 
 // Rows staged per chunk: at most 64, and the stage stays within 32 KB.
 uint32_t hash_rpc(const Shape& s) {
@@ -140,26 +153,36 @@ hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, 
                             int combine, hipStream_t st) {
   if (rows.n_rows == 0) return hipSuccess;
   const uint32_t rpc = hash_rpc(s);
-  const size_t stage = (size_t)s.L * rpc * 4;
+  const size_t stage = (size_t)s.L * rpc * 4 + (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, stage);
   const size_t lds = (size_t)nw * doph_lds_words(s.M) * 4 + stage;
-  hipError_t e = allow_lds((const void*)k_hash_rows, lds);
+  const void* fn = const_staged(s) ? (const void*)k_hash_rows<true> : (const void*)k_hash_rows<false>;
+  hipError_t e = allow_lds(fn, lds);
   if (e != hipSuccess) return e;
   uint64_t chunks = (rows.n_rows + rpc - 1) / rpc;
   uint32_t grid = (uint32_t)(chunks < 8192 ? chunks : 8192);
-  hipLaunchKernelGGL(k_hash_rows, dim3(grid), dim3(nw * SL_WAVE), lds, st, s, c, rows, keys, key_stride, combine,
-                     rpc);
+  Shape sh = s;
+  ConstView cv = c;
+  void* args[] = {&sh, &cv, &rows, &keys, &key_stride, &combine, const_cast<uint32_t*>(&rpc)};
+  e = hipLaunchKernel(fn, dim3(grid), dim3(nw * SL_WAVE), args, lds, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
 hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr rows, uint32_t* out, hipStream_t st) {
   if (rows.n_rows == 0) return hipSuccess;
-  const uint32_t nw = hash_waves(s, 0);
-  const size_t lds = (size_t)nw * doph_lds_words(s.M) * 4;
-  hipError_t e = allow_lds((const void*)k_hash_rowmajor, lds);
+  const size_t fixed = (size_t)const_lds_words(s) * 4;
+  const uint32_t nw = hash_waves(s, fixed);
+  const size_t lds = (size_t)nw * doph_lds_words(s.M) * 4 + fixed;
+  const void* fn = const_staged(s) ? (const void*)k_hash_rowmajor<true> : (const void*)k_hash_rowmajor<false>;
+  hipError_t e = allow_lds(fn, lds);
   if (e != hipSuccess) return e;
   uint32_t grid = grid_for(rows.n_rows, nw, 8192);
-  hipLaunchKernelGGL(k_hash_rowmajor, dim3(grid), dim3(nw * SL_WAVE), lds, st, s, c, rows, out);
+  Shape sh = s;
+  ConstView cv = c;
+  void* args[] = {&sh, &cv, &rows, &out};
+  e = hipLaunchKernel(fn, dim3(grid), dim3(nw * SL_WAVE), args, lds, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

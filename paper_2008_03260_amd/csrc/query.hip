@@ -20,11 +20,12 @@ namespace slash {
 
 namespace {
 
-constexpr uint32_t kMaxSpt = 16;  // reservoir slots per thread
+constexpr uint32_t kMaxSpt = 16;     // reservoir slots per thread
 
 struct QLayout {
-  uint32_t doph, buckets, cm, hs, hist, sel, misc, total;  // offsets in 32-bit words
-  uint32_t cm_words, hs_size;
+  uint32_t cst, doph, buckets, cm, hist, sel, misc, total;  // offsets in 32-bit words
+  uint32_t cm_words, hs_size, cst_words;
+  bool cst_fit;
 };
 
 __host__ __device__ inline uint32_t next_pow2(uint32_t x) {
@@ -36,86 +37,110 @@ __host__ __device__ inline uint32_t next_pow2(uint32_t x) {
 __host__ __device__ inline QLayout q_layout(const Shape& s) {
   QLayout o;
   uint32_t w = 1u << s.lw;
-  o.doph = 0;
+  o.cst_words = const_words(s);
+  o.cst_fit = o.cst_words <= kConstCapWords;
+  o.cst = 0;
+  o.doph = o.cst + (o.cst_fit ? ((o.cst_words + 1) & ~1u) : 0u);
   o.buckets = o.doph + 2 * s.M + ((s.M + 63) / 64) * 2;
   o.cm = o.buckets + s.L;
   o.cm_words = (s.d * w + 1) / 2;
   o.hs_size = next_pow2(2 * s.L * s.R);
   if (o.hs_size < 64) o.hs_size = 64;
-  o.hs = o.cm + o.cm_words;
-  o.hist = o.hs + o.hs_size;
-  o.sel = o.hist + 256;
+  // the id set reuses the count-min region once the estimates are read
+  uint32_t region = o.cm_words > o.hs_size ? o.cm_words : o.hs_size;
+  o.hist = o.cm + region;
+  o.sel = o.hist + 512;
   if (o.sel & 1) o.sel++;
   o.misc = o.sel + 2 * s.k_max;
   o.total = o.misc + 16;
   return o;
 }
 
-__device__ __forceinline__ uint32_t hs_slot(uint32_t id, uint32_t mask) { return (id * 0x9E3779B1u) & mask; }
+// Slot of an id in the id set: high bits of a multiplicative hash.
+__device__ __forceinline__ uint32_t hs_slot(uint32_t id, uint32_t log2_size) {
+  return (id * 0x9E3779B1u) >> (32 - log2_size);
+}
 
-template <int WAVES>
+// Add one to hist[d] for every participating lane, one LDS atomic per
+// distinct digit of the wave.
+__device__ __forceinline__ void hist_add(uint32_t* hist, bool part, uint32_t d) {
+  uint64_t act = ballot64(part);
+  if (act == 0) return;
+  uint64_t peers = match_digit(d, 8, act);
+  if (part && lane_id() == (uint32_t)__builtin_ctzll(peers)) atomicAdd(&hist[d], (uint32_t)__builtin_popcountll(peers));
+}
+
+template <int WAVES, int SPT, bool CL>
 __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a, uint32_t q,
                           uint32_t* lds, const QLayout& lay) {
   constexpr uint32_t NT = WAVES * SL_WAVE;
   const uint32_t tid = threadIdx.x, wave = tid / SL_WAVE, lane = lane_id();
   uint32_t* bk = lds + lay.buckets;
   uint32_t* cmw = lds + lay.cm;
-  uint32_t* hs = lds + lay.hs;
-  uint32_t* hist = lds + lay.hist;
+  uint32_t* hs = lds + lay.cm;  // reused after the estimates
+  uint32_t* hist = lds + lay.hist;  // two 256-bin histograms
   uint64_t* sel = (uint64_t*)(lds + lay.sel);
   uint32_t* misc = lds + lay.misc;
   const uint32_t hs_mask = lay.hs_size - 1;
+  const uint32_t hs_log2 = 31 - __builtin_clz(lay.hs_size);
   const uint32_t slots = s.L * s.R;
-  const uint32_t spt = (slots + NT - 1) / NT;
 
-  // clear sketch, id set and counters
+  // 0. clear the sketch, histograms and counters; hash the query (wave 0)
   for (uint32_t e = tid; e < lay.cm_words; e += NT) cmw[e] = 0;
-  for (uint32_t e = tid; e < lay.hs_size; e += NT) hs[e] = SL_EMPTY;
+  for (uint32_t e = tid; e < 512; e += NT) hist[e] = 0;
   if (tid < 16) misc[tid] = 0;
-  // 1. hash
   if (wave == 0) {
     const int64_t beg = a.q.indptr[q], end = a.q.indptr[q + 1];
-    const uint32_t* h = doph_wave(s, c, a.q.indices + beg, (uint32_t)(end - beg), lds + lay.doph);
-    for (uint32_t t = lane; t < s.L; t += SL_WAVE) bk[t] = table_bucket(s, c, h, t);
+    const uint32_t* h = doph_wave<CL>(s, c, a.q.indices + beg, (uint32_t)(end - beg), lds + lay.doph);
+    for (uint32_t t = lane; t < s.L; t += SL_WAVE) bk[t] = table_bucket<CL>(s, c, h, t);
   }
   __syncthreads();
-  // 2. gather + 3. count
-  uint32_t id[kMaxSpt];
+  // 1. gather the probed reservoirs and count every occurrence
+  uint32_t id[SPT];
 #pragma unroll
-  for (uint32_t i = 0; i < kMaxSpt; ++i) {
+  for (int i = 0; i < SPT; ++i) {
+    uint32_t sl = tid + i * NT;
     id[i] = SL_EMPTY;
-    if (i < spt) {
-      uint32_t sl = tid + i * NT;
-      if (sl < slots) {
-        uint32_t t = sl / s.R, j = sl - t * s.R;
-        id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
-      }
+    if (sl < slots) {
+      uint32_t t = sl / s.R, j = sl - t * s.R;
+      id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
     }
   }
+  for (uint32_t r = 0; r < s.d; ++r) {
+    const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
 #pragma unroll
-  for (uint32_t i = 0; i < kMaxSpt; ++i) {
-    if (i < spt && id[i] != SL_EMPTY) {
-      for (uint32_t r = 0; r < s.d; ++r) {
-        uint32_t g = (r << s.lw) + cm_hash(c.a_r[r], c.b_r[r], id[i], s.lw);
+    for (int i = 0; i < SPT; ++i) {
+      if (id[i] != SL_EMPTY) {
+        uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
         atomicAdd(&cmw[g >> 1], 1u << ((g & 1u) * 16));
       }
     }
   }
   __syncthreads();
-  // 4. estimates and distinct representatives
-  uint64_t key[kMaxSpt];
-  uint32_t nrep = 0;
+  // 2. estimates (min over rows), kept in the high half of the sort key
+  uint32_t est[SPT];
 #pragma unroll
-  for (uint32_t i = 0; i < kMaxSpt; ++i) {
-    key[i] = 0;
-    if (i < spt && id[i] != SL_EMPTY) {
-      uint32_t est = 0xFFFFFFFFu;
-      for (uint32_t r = 0; r < s.d; ++r) {
-        uint32_t g = (r << s.lw) + cm_hash(c.a_r[r], c.b_r[r], id[i], s.lw);
-        uint32_t v = (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu;
-        est = min(est, v);
-      }
-      uint32_t h = hs_slot(id[i], hs_mask);
+  for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
+  for (uint32_t r = 0; r < s.d; ++r) {
+    const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+      est[i] = min(est[i], (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu);
+    }
+  }
+  uint64_t key[SPT];
+#pragma unroll
+  for (int i = 0; i < SPT; ++i) key[i] = id[i] != SL_EMPTY ? ((uint64_t)est[i] << 32) | (uint32_t)~id[i] : 0ull;
+  __syncthreads();
+  // 3. distinct ids: the first insertion into the LDS id set represents the id
+  for (uint32_t e = tid; e < lay.hs_size; e += NT) hs[e] = SL_EMPTY;
+  __syncthreads();
+  uint32_t nrep = 0, emax = 0;
+#pragma unroll
+  for (int i = 0; i < SPT; ++i) {
+    if (id[i] != SL_EMPTY) {
+      uint32_t h = hs_slot(id[i], hs_log2);
       bool rep = false;
       for (;;) {
         uint32_t prev = atomicCAS(&hs[h], SL_EMPTY, id[i]);
@@ -127,16 +152,23 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
         h = (h + 1) & hs_mask;
       }
       if (rep) {
-        key[i] = ((uint64_t)est << 32) | (uint32_t)~id[i];
         ++nrep;
+        emax = max(emax, (uint32_t)(key[i] >> 32));
+      } else {
+        key[i] = 0;
       }
     }
   }
-  // block total of representatives
   {
-    uint32_t v = nrep;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, SL_WAVE);
-    if (lane == 0) atomicAdd(&misc[0], v);
+    uint32_t v = nrep, m = emax;
+    for (int o = 32; o > 0; o >>= 1) {
+      v += __shfl_xor(v, o, SL_WAVE);
+      m = max(m, (uint32_t)__shfl_xor(m, o, SL_WAVE));
+    }
+    if (lane == 0) {
+      atomicAdd(&misc[0], v);
+      atomicMax(&misc[5], m);
+    }
   }
   __syncthreads();
   const uint32_t total = misc[0];
@@ -145,34 +177,39 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   const uint32_t kk = min(kq, total);
   uint32_t* oid = a.out_ids + (uint64_t)q * s.k_max;
   uint32_t* osc = a.out_scores + (uint64_t)q * s.k_max;
-  // 5. threshold key: keys >= thr are exactly the kk largest
+  // 4. threshold key: keys >= thr are exactly the kk largest.  MSD radix
+  //    select over 8-bit digits of (estimate << 32 | ~id), starting at the
+  //    estimate's low byte when every estimate is below 256.
   uint64_t thr = 1;  // every representative (their keys are >= 2^32)
   if (kk > 0 && kk < total) {
     uint64_t prefix = 0;
     uint32_t remaining = kk;
-    for (int shift = 40; shift >= 0; shift -= 8) {
-      for (uint32_t e = tid; e < 256; e += NT) hist[e] = 0;
-      __syncthreads();
-      const uint64_t hi_mask = shift + 8 >= 64 ? 0ull : (~0ull << (shift + 8));
+    uint32_t cur = 0;
+    const int top = misc[5] < 256u ? 32 : 40;
+    for (int shift = top; shift >= 0; shift -= 8, cur ^= 1u) {
+      uint32_t* H = hist + 256 * cur;
+      const uint64_t hi_mask = ~0ull << (shift + 8);
 #pragma unroll
-      for (uint32_t i = 0; i < kMaxSpt; ++i) {
-        if (key[i] != 0 && (key[i] & hi_mask) == (prefix & hi_mask))
-          atomicAdd(&hist[(uint32_t)(key[i] >> shift) & 255u], 1u);
+      for (int i = 0; i < SPT; ++i) {
+        bool part = key[i] != 0 && (key[i] & hi_mask) == (prefix & hi_mask);
+        hist_add(H, part, (uint32_t)(key[i] >> shift) & 255u);
       }
       __syncthreads();
       if (wave == 0) {
-        // lane owns digits 4*lane .. 4*lane+3; suffix sums from the top
-        uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+        // lane owns digits 4*lane .. 4*lane+3; sums over the digits above
+        uint32_t h0 = H[4 * lane], h1 = H[4 * lane + 1], h2 = H[4 * lane + 2], h3 = H[4 * lane + 3];
+        H[4 * lane] = 0;
+        H[4 * lane + 1] = 0;
+        H[4 * lane + 2] = 0;
+        H[4 * lane + 3] = 0;
         uint32_t mine = h0 + h1 + h2 + h3;
-        uint32_t above = 0;  // sum over lanes > lane
         uint32_t v = mine;
         for (int o = 1; o < SL_WAVE; o <<= 1) {
           uint32_t y = __shfl_down(v, o, SL_WAVE);
           if (lane + o < SL_WAVE) v += y;
         }
-        above = v - mine;
         uint32_t hh[4] = {h0, h1, h2, h3};
-        uint32_t cum = above;
+        uint32_t cum = v - mine;
         for (int j = 3; j >= 0; --j) {
           if (cum < remaining && remaining <= cum + hh[j]) {
             misc[1] = 4 * lane + j;
@@ -186,15 +223,14 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       uint32_t D = misc[1], cum = misc[2], cnt = misc[3];
       remaining -= cum;
       prefix |= (uint64_t)D << shift;
-      __syncthreads();
       if (remaining == cnt) break;  // the whole digit bin is selected
     }
     thr = prefix;
   }
-  // 6. collect winners
+  // 5. collect winners, rank them by counting (keys are distinct), write
   if (kk > 0) {
 #pragma unroll
-    for (uint32_t i = 0; i < kMaxSpt; ++i) {
+    for (int i = 0; i < SPT; ++i) {
       if (key[i] != 0 && key[i] >= thr) {
         uint32_t p = atomicAdd(&misc[4], 1u);
         sel[p] = key[i];
@@ -202,7 +238,6 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     }
   }
   __syncthreads();
-  // 7. rank winners by counting (keys are distinct) and write the row
   for (uint32_t e = tid; e < kk; e += NT) {
     uint64_t x = sel[e];
     uint32_t r = 0;
@@ -217,19 +252,23 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   __syncthreads();
 }
 
-template <int WAVES>
+template <int WAVES, int SPT, bool CL>
 __global__ void __launch_bounds__(WAVES * SL_WAVE) k_query(Shape s, ConstView c, TablesView tab, QueryArgs a) {
   extern __shared__ uint32_t lds[];
   const QLayout lay = q_layout(s);
-  for (uint64_t q = blockIdx.x; q < a.q.n_rows; q += gridDim.x) query_one<WAVES>(s, c, tab, a, (uint32_t)q, lds, lay);
+  const ConstView cl = CL ? stage_consts(s, c, lds + lay.cst, WAVES * SL_WAVE) : c;
+  __syncthreads();
+  for (uint64_t q = blockIdx.x; q < a.q.n_rows; q += gridDim.x)
+    query_one<WAVES, SPT, CL>(s, cl, tab, a, (uint32_t)q, lds, lay);
 }
 
-template <int WAVES>
+template <int WAVES, int SPT, bool CL>
 __global__ void __launch_bounds__(WAVES * SL_WAVE)
     k_query_persistent(Shape s, ConstView c, TablesView tab, QueryArgs a, uint32_t per_ticket, uint32_t* ticket) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t base_sh;
   const QLayout lay = q_layout(s);
+  const ConstView cl = CL ? stage_consts(s, c, lds + lay.cst, WAVES * SL_WAVE) : c;
   const uint64_t n = a.q.n_rows;
   for (;;) {
     if (threadIdx.x == 0) base_sh = atomicAdd(ticket, per_ticket);
@@ -238,32 +277,72 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE)
     __syncthreads();
     if (base >= n) break;
     const uint64_t stop = base + per_ticket < n ? base + per_ticket : n;
-    for (uint64_t q = base; q < stop; ++q) query_one<WAVES>(s, c, tab, a, (uint32_t)q, lds, lay);
+    for (uint64_t q = base; q < stop; ++q) query_one<WAVES, SPT, CL>(s, cl, tab, a, (uint32_t)q, lds, lay);
   }
 }
 
-template <int WAVES>
-hipError_t set_lds_attr(size_t lds) {
-  static bool done = false;
-  if (!done && lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_query<WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_query_persistent<WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-    if (e != hipSuccess) return e;
-    done = true;
-  }
-  return hipSuccess;
+struct KPair {
+  const void* plain;
+  const void* persistent;
+};
+
+template <int W, int S, bool CL>
+constexpr KPair kp1() {
+  return KPair{(const void*)k_query<W, S, CL>, (const void*)k_query_persistent<W, S, CL>};
+}
+template <int W, int S>
+constexpr KPair kp() { return kp1<W, S, true>(); }
+template <int W, int S>
+constexpr KPair kg() { return kp1<W, S, false>(); }
+
+// kernels reading global constants (tables too large for LDS)
+const KPair kKernelsG[5][5] = {
+    {kg<1, 1>(), kg<1, 2>(), kg<1, 4>(), kg<1, 8>(), kg<1, 16>()},
+    {kg<2, 1>(), kg<2, 2>(), kg<2, 4>(), kg<2, 8>(), kg<2, 16>()},
+    {kg<4, 1>(), kg<4, 2>(), kg<4, 4>(), kg<4, 8>(), kg<4, 16>()},
+    {kg<8, 1>(), kg<8, 2>(), kg<8, 4>(), kg<8, 8>(), kg<8, 16>()},
+    {kg<16, 1>(), kg<16, 2>(), kg<16, 4>(), kg<16, 8>(), kg<16, 16>()},
+};
+
+// kernels by [log2 waves][log2 slots per thread]
+const KPair kKernels[5][5] = {
+    {kp<1, 1>(), kp<1, 2>(), kp<1, 4>(), kp<1, 8>(), kp<1, 16>()},
+    {kp<2, 1>(), kp<2, 2>(), kp<2, 4>(), kp<2, 8>(), kp<2, 16>()},
+    {kp<4, 1>(), kp<4, 2>(), kp<4, 4>(), kp<4, 8>(), kp<4, 16>()},
+    {kp<8, 1>(), kp<8, 2>(), kp<8, 4>(), kp<8, 8>(), kp<8, 16>()},
+    {kp<16, 1>(), kp<16, 2>(), kp<16, 4>(), kp<16, 8>(), kp<16, 16>()},
+};
+
+int ilog2(uint32_t x) {
+  int b = 0;
+  while ((1u << b) < x) ++b;
+  return b;
+}
+
+// Kernel pair for `waves` waves per query, or nullptr.
+const KPair* pick(const Shape& s, uint32_t waves) {
+  if (waves == 0 || waves > 16 || (waves & (waves - 1))) return nullptr;
+  uint32_t slots = s.L * s.R;
+  uint32_t spt = (slots + waves * SL_WAVE - 1) / (waves * SL_WAVE);
+  if (spt > kMaxSpt) return nullptr;
+  const int wi = ilog2(waves), si = ilog2(spt < 1 ? 1 : spt);
+  return q_layout(s).cst_fit ? &kKernels[wi][si] : &kKernelsG[wi][si];
+}
+
+hipError_t allow_lds(const KPair* k, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(k->plain, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(k->persistent, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 }  // namespace
 
 uint32_t query_default_waves(const Shape& s) {
+  // enough waves that a thread holds at most 8 reservoir slots
   uint32_t slots = s.L * s.R;
-  uint32_t w = (slots + kMaxSpt * SL_WAVE - 1) / (kMaxSpt * SL_WAVE);
   uint32_t waves = 1;
-  while (waves < w) waves <<= 1;
-  if (waves < 4 && slots >= 4 * SL_WAVE * 2) waves = 4;
+  while (waves < 16 && slots > waves * SL_WAVE * 8) waves <<= 1;
   return waves;
 }
 
@@ -275,39 +354,28 @@ size_t query_lds_bytes(const Shape& s, uint32_t waves) {
 }
 
 bool query_supported(const Shape& s, uint32_t waves) {
-  if (waves == 0 || waves > 16) return false;
-  if (s.L * s.R > kMaxSpt * SL_WAVE * waves) return false;
+  if (!pick(s, waves)) return false;
   if (s.L * s.R > 65535u) return false;
   return query_lds_bytes(s, waves) <= 160 * 1024;
 }
 
 bool query_supported(const Shape& s) { return query_supported(s, query_default_waves(s)); }
 
-#define SLASH_Q_DISPATCH(W, ...)        \
-  switch (W) {                          \
-    case 1: __VA_ARGS__(1); break;      \
-    case 2: __VA_ARGS__(2); break;      \
-    case 4: __VA_ARGS__(4); break;      \
-    case 8: __VA_ARGS__(8); break;      \
-    case 16: __VA_ARGS__(16); break;    \
-    default: return hipErrorInvalidValue; \
-  }
-
 hipError_t launch_query_waves(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
                               uint32_t waves, hipStream_t st) {
   if (a.q.n_rows == 0) return hipSuccess;
   if (!query_supported(s, waves)) return hipErrorInvalidValue;
+  const KPair* k = pick(s, waves);
   size_t lds = query_lds_bytes(s, waves);
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
   uint32_t grid = (uint32_t)(a.q.n_rows < (1u << 30) ? a.q.n_rows : (1u << 30));
-  hipError_t e = hipSuccess;
-#define L1(W)                                                                                 \
-  do {                                                                                        \
-    e = set_lds_attr<W>(lds);                                                                 \
-    if (e == hipSuccess)                                                                      \
-      hipLaunchKernelGGL(k_query<W>, dim3(grid), dim3(W * SL_WAVE), lds, st, s, c, tab, a);   \
-  } while (0)
-  SLASH_Q_DISPATCH(waves, L1)
-#undef L1
+  Shape sh = s;
+  ConstView cv = c;
+  TablesView tv = tab;
+  QueryArgs qa = a;
+  void* args[] = {&sh, &cv, &tv, &qa};
+  e = hipLaunchKernel(k->plain, dim3(grid), dim3(waves * SL_WAVE), args, lds, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -322,46 +390,33 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
                                    hipStream_t st) {
   if (!query_supported(s, waves)) return hipErrorInvalidValue;
   if (per_ticket == 0) per_ticket = 1;
+  const KPair* k = pick(s, waves);
   size_t lds = query_lds_bytes(s, waves);
-  hipError_t e = hipSuccess;
-#define L2(W)                                                                                        \
-  do {                                                                                               \
-    e = set_lds_attr<W>(lds);                                                                        \
-    if (e == hipSuccess)                                                                             \
-      hipLaunchKernelGGL(k_query_persistent<W>, dim3(grid), dim3(W * SL_WAVE), lds, st, s, c, tab, a, \
-                         per_ticket, ticket);                                                        \
-  } while (0)
-  SLASH_Q_DISPATCH(waves, L2)
-#undef L2
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  Shape sh = s;
+  ConstView cv = c;
+  TablesView tv = tab;
+  QueryArgs qa = a;
+  void* args[] = {&sh, &cv, &tv, &qa, &per_ticket, &ticket};
+  e = hipLaunchKernel(k->persistent, dim3(grid), dim3(waves * SL_WAVE), args, lds, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
-void* persistent_query_kernel(uint32_t waves) {
-  switch (waves) {
-    case 1: return (void*)k_query_persistent<1>;
-    case 2: return (void*)k_query_persistent<2>;
-    case 4: return (void*)k_query_persistent<4>;
-    case 8: return (void*)k_query_persistent<8>;
-    case 16: return (void*)k_query_persistent<16>;
-    default: return nullptr;
-  }
+void* persistent_query_kernel(const Shape& s, uint32_t waves) {
+  const KPair* k = pick(s, waves);
+  return k ? const_cast<void*>(k->persistent) : nullptr;
 }
 
 // Occupancy of the persistent kernel: resident work-groups per CU.
 hipError_t query_occupancy(const Shape& s, uint32_t waves, int* per_cu) {
+  const KPair* k = pick(s, waves);
+  if (!k) return hipErrorInvalidValue;
   size_t lds = query_lds_bytes(s, waves);
-  hipError_t e = hipSuccess;
-#define L3(W)                                                                                                \
-  do {                                                                                                       \
-    e = set_lds_attr<W>(lds);                                                                                \
-    if (e == hipSuccess)                                                                                     \
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)k_query_persistent<W>, W * SL_WAVE, \
-                                                       lds);                                                 \
-  } while (0)
-  SLASH_Q_DISPATCH(waves, L3)
-#undef L3
-  return e;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k->persistent, waves * SL_WAVE, lds);
 }
 
 }  // namespace slash

@@ -141,7 +141,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
 // Kernel entry of the fill kernel (for HIP graph nodes): (uint32_t* p, uint32_t v, uint64_t n).
 void* fill_kernel_ptr();
 // Kernel entry of the persistent query kernel for `waves` waves per query.
-void* persistent_query_kernel(uint32_t waves);
+void* persistent_query_kernel(const Shape& s, uint32_t waves);
 hipError_t launch_validate_indices(const int32_t* idx, uint64_t n, uint32_t dim, uint32_t* flag, hipStream_t st);
 hipError_t launch_item_ids(uint32_t* vals, uint32_t first_id, uint64_t n_rows, uint64_t items, hipStream_t st);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t first, uint64_t n, hipStream_t st);
