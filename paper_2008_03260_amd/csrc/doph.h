@@ -70,12 +70,13 @@ __device__ inline ConstView stage_consts(const Shape& s, const ConstView& c, uin
 }
 
 // Nearest set bit of `mask` walking right (increasing, circular) from pos
-// inside the domain [lo, lo + n).  Requires a set bit in the domain other
-// than pos.
+// inside the domain [lo, lo + n).  Callers guarantee a set bit in the domain
+// other than pos; the walk is still bounded (one lap over the domain's words)
+// and returns pos when nothing is found.
 __device__ __forceinline__ uint32_t find_right(const lds_u32* mask, uint32_t lo, uint32_t n, uint32_t pos) {
   const uint32_t end = lo + n;
   uint32_t q = pos + 1 == end ? lo : pos + 1;
-  for (;;) {
+  for (uint32_t step = 0; step <= n / 32 + 2; ++step) {
     uint32_t o = q & 31u;
     uint32_t bits = mask[q >> 5] >> o;
     uint32_t span = min(32u - o, end - q);
@@ -84,12 +85,13 @@ __device__ __forceinline__ uint32_t find_right(const lds_u32* mask, uint32_t lo,
     q += span;
     if (q >= end) q = lo;
   }
+  return pos;
 }
 
 // Same, walking left (decreasing, circular).
 __device__ __forceinline__ uint32_t find_left(const lds_u32* mask, uint32_t lo, uint32_t n, uint32_t pos) {
   uint32_t q = pos == lo ? lo + n - 1 : pos - 1;
-  for (;;) {
+  for (uint32_t step = 0; step <= n / 32 + 2; ++step) {
     uint32_t o = q & 31u;
     uint32_t bits = mask[q >> 5] << (31u - o);
     uint32_t span = min(o + 1u, q - lo + 1u);
@@ -100,6 +102,7 @@ __device__ __forceinline__ uint32_t find_left(const lds_u32* mask, uint32_t lo, 
     else
       q -= span;
   }
+  return pos;
 }
 
 __device__ __forceinline__ bool domain_any(const lds_u32* mask, uint32_t lo, uint32_t n) {
@@ -114,17 +117,22 @@ __device__ __forceinline__ bool domain_any(const lds_u32* mask, uint32_t lo, uin
   return false;
 }
 
-// One wave hashes one row: per-bin minima of the nonzero hashes, then
-// densification (an empty bin copies the nearest non-empty bin in its fixed
-// direction, circularly, reading the pre-densification minima; all-empty
-// domains stay EMPTY).
-// `idx` points at the row's nnz indices.  All 64 lanes must call.  Returns
-// the densified values (lds + M, M entries).
-template <bool CL>
-__device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const ConstView& c,
-                                                     const int32_t* __restrict__ idx, uint32_t nnz,
-                                                     uint32_t* lds_m) {
+// A group of G consecutive lanes (G = 16, 32 or 64) hashes one row: per-bin
+// minima of the nonzero hashes, then densification (an empty bin copies the
+// nearest non-empty bin in its fixed direction, circularly, reading the
+// pre-densification minima; all-empty domains stay EMPTY).  A wave holds
+// 64 / G groups, each with its own row and its own LDS scratch lds_m (see
+// doph_lds_words).  Every lane of the wave must call (the synchronisation is
+// wave-wide); `idx` points at the group's row of nnz indices.  Returns the
+// densified values (lds_m + M, M entries).
+template <int G, bool CL>
+__device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const ConstView& c,
+                                                      const int32_t* __restrict__ idx, uint32_t nnz,
+                                                      uint32_t* lds_m) {
+  static_assert(G == 16 || G == 32 || G == 64, "group size");
   const uint32_t lane = lane_id();
+  const uint32_t gl = lane & (G - 1);
+  const uint32_t gshift = lane & ~(uint32_t)(G - 1);
   const uint32_t M = s.M;
   uint32_t* lds_h = lds_m + M;
   uint32_t* mask = lds_m + 2 * M;
@@ -132,11 +140,13 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
   lw32* m3 = (lw32*)lds_m;
   lw32* h3 = (lw32*)lds_h;
   const lds_u32* k3 = (const lds_u32*)mask;
-  for (uint32_t b = lane; b < M; b += SL_WAVE) lds_m[b] = SL_EMPTY;
+  for (uint32_t b = gl; b < M; b += G) m3[b] = SL_EMPTY;
+  // every mask word, including bits past M that no ballot covers
+  for (uint32_t w = gl; w < mask_words(M); w += G) mask[w] = 0u;
   wave_sync();
   if (s.mode == 0) {
     const uint64_t a = cld64<CL>(c.a_h, 0), bb = cld64<CL>(c.b_h, 0);
-    for (uint32_t e = lane; e < nnz; e += SL_WAVE) {
+    for (uint32_t e = gl; e < nnz; e += G) {
       uint32_t u = nz_hash(a, bb, (uint32_t)idx[e]);
       uint32_t bin;
       if (s.mshift == 0xFFu)
@@ -147,35 +157,36 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
     }
   } else {
     const uint32_t L = s.L, K = s.K;
-    for (uint32_t w = lane; w < nnz * L; w += SL_WAVE) {
+    for (uint32_t w = gl; w < nnz * L; w += G) {
       uint32_t e = w / L, t = w - e * L;
       uint32_t u = nz_hash(cld64<CL>(c.a_h, t), cld64<CL>(c.b_h, t), (uint32_t)idx[e]);
       atomicMin(&lds_m[t * K + range_bin(u, K)], u);
     }
   }
   wave_sync();
-  // non-empty mask, 64 bins per ballot
-  for (uint32_t base = 0; base < M; base += SL_WAVE) {
-    uint32_t b = base + lane;
+  // non-empty mask, G bins per ballot; any_all: is any bin of the row non-empty
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+  bool any_all = false;
+  for (uint32_t base = 0; base < M; base += G) {
+    uint32_t b = base + gl;
     bool ne = b < M && m3[b] != SL_EMPTY;
-    uint64_t bal = ballot64(ne);
-    if (lane == 0) {
-      mask[base / 32] = (uint32_t)bal;
-      mask[base / 32 + 1] = (uint32_t)(bal >> 32);
+    uint64_t bal = (ballot64(ne) >> gshift) & gmask;
+    any_all |= bal != 0ull;
+    if (gl == 0) {
+      if (G == 64) {
+        mask[base / 32] = (uint32_t)bal;
+        mask[base / 32 + 1] = (uint32_t)(bal >> 32);
+      } else if (G == 32) {
+        mask[base / 32] = (uint32_t)bal;
+      } else {
+        ((uint16_t*)mask)[base / 16] = (uint16_t)bal;
+      }
     }
   }
   wave_sync();
-  // one-pass mode: is any bin of the row non-empty?
-  bool any_all = false;
-  if (s.mode == 0) {
-    const uint32_t nw = mask_words(M);
-    bool mine = false;
-    for (uint32_t w = lane; w < nw; w += SL_WAVE) mine |= k3[w] != 0u;
-    any_all = ballot64(mine) != 0ull;
-  }
   // densify into lds_h, reading only the minima
 #pragma unroll 1
-  for (uint32_t b = lane; b < M; b += SL_WAVE) {
+  for (uint32_t b = gl; b < M; b += G) {
     uint32_t v = m3[b];
     if (v == SL_EMPTY) {
       uint32_t lo = s.mode == 0 ? 0u : (b / s.K) * s.K;
@@ -191,6 +202,16 @@ __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const Const
   wave_sync();
   return lds_h;
 }
+
+template <bool CL>
+__device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const ConstView& c,
+                                                     const int32_t* __restrict__ idx, uint32_t nnz,
+                                                     uint32_t* lds_m) {
+  return doph_group<64, CL>(s, c, idx, nnz, lds_m);
+}
+
+// Lanes per row for the row-parallel hash kernels.
+__host__ __device__ inline uint32_t hash_group(uint32_t M) { return M <= 128 ? 16u : (M <= 512 ? 32u : 64u); }
 
 // Bucket id of table t from densified values h (Section 2.3):
 // (b_t + sum_j a_tj * h[tK + j]) >> (64 - B), arithmetic mod 2^64.

@@ -13,32 +13,48 @@ __host__ __device__ inline bool const_staged(const Shape& s) { return const_word
 // Each block takes chunks of `rpc` consecutive rows; each wave hashes one row
 // at a time and stages its L bucket ids in LDS; the block then writes every
 // table's rpc ids as one contiguous run (keys are table-major).
-template <bool CL>
+// Each block takes chunks of `rpc` consecutive rows; a group of G lanes
+// hashes one row at a time (64 / G rows per wave at once) and stages its L
+// bucket ids in LDS; the block then writes every table's rpc ids as one
+// contiguous run (keys are table-major).
+// Each block takes chunks of `rpc` consecutive rows; a group of G lanes
+// hashes one row at a time (64 / G rows per wave at once) and stages its L
+// bucket ids in LDS; the block then writes every table's rpc ids as one
+// contiguous run (keys are table-major).
+template <int G, bool CL>
 __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
     k_hash_rows(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ keys, uint64_t key_stride,
                 int combine, uint32_t rpc) {
   extern __shared__ uint32_t lds[];
-  const uint32_t nw = blockDim.x / SL_WAVE;
-  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
-  const uint32_t per_wave = doph_lds_words(s.M);
+  constexpr uint32_t GPW = SL_WAVE / G;  // groups per wave
+  const uint32_t ng = (blockDim.x / SL_WAVE) * GPW;
+  const uint32_t grp = threadIdx.x / G, gl = threadIdx.x & (G - 1);
+  const uint32_t per_grp = doph_lds_words(s.M);
   const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
   const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
-  uint32_t* my = lds + cw + wave * per_wave;
-  uint32_t* stage = lds + cw + nw * per_wave;  // [L][rpc]
+  uint32_t* my = lds + cw + grp * per_grp;
+  uint32_t* stage = lds + cw + ng * per_grp;  // [L][rpc]
   __syncthreads();
   const uint64_t n = rows.n_rows;
   const uint64_t n_chunks = (n + rpc - 1) / rpc;
   for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
     const uint64_t r0 = ch * rpc;
-    for (uint32_t rl = wave; rl < rpc; rl += nw) {
+    // every group runs the same number of rounds (wave-wide syncs inside)
+    for (uint32_t rb = 0; rb < rpc; rb += ng) {
+      const uint32_t rl = rb + grp;
       const uint64_t r = r0 + rl;
-      if (r >= n) break;
-      const int64_t beg = rows.indptr[r], end = rows.indptr[r + 1];
-      const uint32_t* h = doph_wave<CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
-      for (uint32_t t = lane; t < s.L; t += SL_WAVE) {
-        uint32_t b = table_bucket<CL>(s, cl, h, t);
-        stage[t * rpc + rl] = combine ? t * s.nb + b : b;
+      const bool live = rl < rpc && r < n;
+      int64_t beg = 0, end = 0;
+      if (live) {
+        beg = rows.indptr[r];
+        end = rows.indptr[r + 1];
       }
+      const uint32_t* h = doph_group<G, CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
+      if (live)
+        for (uint32_t t = gl; t < s.L; t += G) {
+          uint32_t b = table_bucket<CL>(s, cl, h, t);
+          stage[t * rpc + rl] = combine ? t * s.nb + b : b;
+        }
       wave_sync();
     }
     __syncthreads();
@@ -51,21 +67,31 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
   }
 }
 
-template <bool CL>
+template <int G, bool CL>
 __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
     k_hash_rowmajor(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ out) {
   extern __shared__ uint32_t lds[];
-  const uint32_t nw = blockDim.x / SL_WAVE;
-  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
+  constexpr uint32_t GPW = SL_WAVE / G;
+  const uint32_t ng = (blockDim.x / SL_WAVE) * GPW;
+  const uint32_t grp = threadIdx.x / G, gl = threadIdx.x & (G - 1);
   const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
   const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
-  uint32_t* my = lds + cw + wave * doph_lds_words(s.M);
-  const uint64_t n = rows.n_rows;
+  uint32_t* my = lds + cw + grp * doph_lds_words(s.M);
   __syncthreads();
-  for (uint64_t r = (uint64_t)blockIdx.x * nw + wave; r < n; r += (uint64_t)gridDim.x * nw) {
-    const int64_t beg = rows.indptr[r], end = rows.indptr[r + 1];
-    const uint32_t* h = doph_wave<CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
-    for (uint32_t t = lane; t < s.L; t += SL_WAVE) out[r * s.L + t] = table_bucket<CL>(s, cl, h, t);
+  const uint64_t n = rows.n_rows;
+  const uint64_t stride = (uint64_t)gridDim.x * ng;
+  const uint64_t rounds = (n + stride - 1) / stride;
+  for (uint64_t k = 0; k < rounds; ++k) {
+    const uint64_t r = k * stride + (uint64_t)blockIdx.x * ng + grp;
+    const bool live = r < n;
+    int64_t beg = 0, end = 0;
+    if (live) {
+      beg = rows.indptr[r];
+      end = rows.indptr[r + 1];
+    }
+    const uint32_t* h = doph_group<G, CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
+    if (live)
+      for (uint32_t t = gl; t < s.L; t += G) out[r * s.L + t] = table_bucket<CL>(s, cl, h, t);
     wave_sync();
   }
 }
@@ -83,11 +109,30 @@ uint32_t hash_rpc(const Shape& s) {
   return r;
 }
 
-// Waves per block such that the block's LDS fits.
+// Waves per block such that the block's LDS fits (64 / G rows per wave).
 uint32_t hash_waves(const Shape& s, size_t fixed) {
+  const size_t per_wave = (size_t)(SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4;
   for (uint32_t w = kMaxHashWaves; w > 1; w >>= 1)
-    if ((size_t)w * doph_lds_words(s.M) * 4 + fixed <= kLdsCap) return w;
+    if (w * per_wave + fixed <= kLdsCap) return w;
   return 1;
+}
+
+const void* hash_rows_fn(const Shape& s) {
+  const bool cl = const_staged(s);
+  switch (hash_group(s.M)) {
+    case 16: return cl ? (const void*)k_hash_rows<16, true> : (const void*)k_hash_rows<16, false>;
+    case 32: return cl ? (const void*)k_hash_rows<32, true> : (const void*)k_hash_rows<32, false>;
+    default: return cl ? (const void*)k_hash_rows<64, true> : (const void*)k_hash_rows<64, false>;
+  }
+}
+
+const void* hash_rowmajor_fn(const Shape& s) {
+  const bool cl = const_staged(s);
+  switch (hash_group(s.M)) {
+    case 16: return cl ? (const void*)k_hash_rowmajor<16, true> : (const void*)k_hash_rowmajor<16, false>;
+    case 32: return cl ? (const void*)k_hash_rowmajor<32, true> : (const void*)k_hash_rowmajor<32, false>;
+    default: return cl ? (const void*)k_hash_rowmajor<64, true> : (const void*)k_hash_rowmajor<64, false>;
+  }
 }
 
 hipError_t allow_lds(const void* f, size_t lds) {
@@ -155,8 +200,8 @@ hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, 
   const uint32_t rpc = hash_rpc(s);
   const size_t stage = (size_t)s.L * rpc * 4 + (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, stage);
-  const size_t lds = (size_t)nw * doph_lds_words(s.M) * 4 + stage;
-  const void* fn = const_staged(s) ? (const void*)k_hash_rows<true> : (const void*)k_hash_rows<false>;
+  const size_t lds = (size_t)nw * (SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4 + stage;
+  const void* fn = hash_rows_fn(s);
   hipError_t e = allow_lds(fn, lds);
   if (e != hipSuccess) return e;
   uint64_t chunks = (rows.n_rows + rpc - 1) / rpc;
@@ -173,11 +218,11 @@ hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr ro
   if (rows.n_rows == 0) return hipSuccess;
   const size_t fixed = (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, fixed);
-  const size_t lds = (size_t)nw * doph_lds_words(s.M) * 4 + fixed;
-  const void* fn = const_staged(s) ? (const void*)k_hash_rowmajor<true> : (const void*)k_hash_rowmajor<false>;
+  const size_t lds = (size_t)nw * (SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4 + fixed;
+  const void* fn = hash_rowmajor_fn(s);
   hipError_t e = allow_lds(fn, lds);
   if (e != hipSuccess) return e;
-  uint32_t grid = grid_for(rows.n_rows, nw, 8192);
+  uint32_t grid = grid_for(rows.n_rows, nw * (SL_WAVE / hash_group(s.M)), 8192);
   Shape sh = s;
   ConstView cv = c;
   void* args[] = {&sh, &cv, &rows, &out};
