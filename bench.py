@@ -177,14 +177,30 @@ def main():
     log(f"plain one-at-a-time: {npl / t_pl:,.0f} q/s, p50 {np.percentile(lat, 50) * 1e6:.1f} us, "
         f"p99 {np.percentile(lat, 99) * 1e6:.1f} us")
 
-    # roofline of the query kernel (algorithmic bytes per query: the query row
-    # 4*nnz + 8, per table the reservoir row read 4*R (fill read as the
-    # EMPTY-padded row), the output 8*k)
-    alg_bytes = 4 * (int(qi_h[-1])) + 8 * w["nq"] + w["nq"] * w["L"] * 4 * w["R"] + w["nq"] * 8 * w["k"]
-    q_s = q_ms.mean() / 1e3
-    achieved = alg_bytes / q_s / 1e9
+    # query kernel: algorithmic bytes per query = the query row 4*nnz + 8,
+    # per table the reservoir row 4*R (read whole, EMPTY-padded), output 8*k
+    alg_q = 4 * (int(qi_h[-1])) + 8 * w["nq"] + w["nq"] * w["L"] * 4 * w["R"] + w["nq"] * 8 * w["k"]
+    q_gbs = alg_q / (q_ms.mean() / 1e3) / 1e9
     build_alg = 4 * nnz + 8 * w["n"] + w["L"] * (1 << w["B"]) * (4 * w["R"] + 4)
+    # build phases, timed by the library with HIP events on the build stream
+    prof = api.slash_build_profile(h)
     api.slash_free(h)
+    dom = max((k for k in prof if prof[k]["launches"]), key=lambda k: prof[k]["total_ms"])
+    d = prof[dom]
+    dom_gbs = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9 if d["total_ms"] > 0 else 0.0
+    log("build phases: " + ", ".join(f"{k} {v['total_ms']:.1f} ms/{v['launches']}" for k, v in prof.items()))
+    # achievable HBM bandwidth: a plain device copy of 4 GiB (read + write)
+    src_t = torch.empty(1 << 30, dtype=torch.int32, device=dev)
+    dst_t = torch.empty_like(src_t)
+    dst_t.copy_(src_t)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(5):
+        dst_t.copy_(src_t)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src_t.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src_t, dst_t
 
     res = {
         "metric": "queries/s & p99 latency at recall@10>=0.9, 200M-pt shard; inserts/s",
@@ -202,8 +218,15 @@ def main():
         "insert_batch_rows_per_s": 4096 / (i_ms.mean() / 1e3),
         "batched_query_ms": float(q_ms.mean()),
         "build_algorithmic_hbm_frac": build_alg / (b_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_query_persistent"},
+        "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": dom, "launches": d["launches"], "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
+                     "alg_bytes_per_launch": d["alg_bytes"] / d["launches"]},
+        "query_roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": q_gbs / HBM_PEAK_GBS, "kernel": "k_query_persistent",
+                           "alg_bytes_per_query": alg_q / w["nq"]},
+        "build_phases": prof,
+        "stream_copy_gbs": copy_gbs,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")

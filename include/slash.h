@@ -177,6 +177,21 @@ SLASH_API slash_status slash_export_tables(const slash_index* index, uint32_t* i
 
 SLASH_API slash_status slash_index_info_get(const slash_index* index, slash_index_info* info);
 
+/* Per-phase timing of the build that made `index`, measured with HIP events
+ * recorded on the build's stream around every launch of the phase.  Phases:
+ * validate, hash, sort_upsweep, sort_scan, sort_downsweep, segment_bounds,
+ * select, heavy.  alg_bytes is the phase's algorithmic HBM traffic (bytes the
+ * phase must read and write, counted once).  Writes up to max entries to out
+ * (host memory), *n receives the number written. */
+typedef struct {
+  char name[32];
+  uint32_t launches;
+  uint32_t reserved;
+  double total_ms;
+  double alg_bytes;
+} slash_phase_stat;
+SLASH_API slash_status slash_build_profile(const slash_index* index, slash_phase_stat* out, uint32_t max, uint32_t* n);
+
 /* Free the index (waits for the device to finish with it). */
 SLASH_API void slash_free(slash_index* index);
 

@@ -51,6 +51,11 @@ class IndexInfo(C.Structure):
                 ("n_buckets", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class PhaseStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint32), ("reserved", C.c_uint32),
+                ("total_ms", C.c_double), ("alg_bytes", C.c_double)]
+
+
 class Schedule(C.Structure):
     _fields_ = [("waves_per_query", C.c_uint32), ("queries_per_ticket", C.c_uint32),
                 ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
@@ -74,6 +79,7 @@ def lib() -> C.CDLL:
             "slash_hash": ([vp, CSR, u32, vp, vp], st),
             "slash_export_tables": ([vp, vp, vp, vp], st),
             "slash_index_info_get": ([vp, P(IndexInfo)], st),
+            "slash_build_profile": ([vp, vp, u32, P(u32)], st),
             "slash_free": ([vp], None),
             "slash_last_error": ([], C.c_char_p),
             "slash_set_allocator": ([vp, vp, vp], st),
@@ -200,6 +206,16 @@ def slash_index_info_get(index) -> dict:
     d = {f: int(getattr(info.params, f)) for f, _ in Params._fields_}
     d.update(n_items=int(info.n_items), table_bytes=int(info.table_bytes), n_buckets=int(info.n_buckets))
     return d
+
+
+def slash_build_profile(index) -> dict:
+    """Per-phase build timing (HIP events on the build stream):
+    {phase: {launches, total_ms, alg_bytes}}."""
+    arr = (PhaseStat * 16)()
+    n = C.c_uint32()
+    _check(lib().slash_build_profile(index, arr, 16, C.byref(n)), "slash_build_profile")
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
+                                   "alg_bytes": float(arr[i].alg_bytes)} for i in range(n.value)}
 
 
 def slash_free(index):

@@ -159,8 +159,53 @@ struct GraphSlot {
   uint32_t waves = 0, per_ticket = 0, grid = 0;
 };
 
+// Event pairs around every launch of a phase; read after the stream syncs.
+struct EventTimer : PhaseTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[PH_COUNT];
+  hipEvent_t open[PH_COUNT] = {};
+  void begin(int ph, hipStream_t st) override {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    open[ph] = e;
+  }
+  void end(int ph, hipStream_t st) override {
+    if (!open[ph]) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    ev[ph].emplace_back(open[ph], e);
+    open[ph] = nullptr;
+  }
+  // total ms and launches per phase (events must have completed)
+  void collect(double* ms, uint32_t* n) {
+    for (int p = 0; p < PH_COUNT; ++p) {
+      ms[p] = 0;
+      n[p] = (uint32_t)ev[p].size();
+      for (auto& pr : ev[p]) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) ms[p] += t;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+      ev[p].clear();
+    }
+  }
+  ~EventTimer() override {
+    double ms[PH_COUNT];
+    uint32_t n[PH_COUNT];
+    collect(ms, n);
+  }
+};
+
+static const char* kPhaseNames[PH_COUNT] = {"validate", "hash", "sort_upsweep", "sort_scan", "sort_downsweep",
+                                            "segment_bounds", "select", "heavy"};
+
 struct slash_index {
   slash_params p{};
+  double phase_ms[PH_COUNT] = {};
+  uint32_t phase_n[PH_COUNT] = {};
+  double phase_bytes[PH_COUNT] = {};
   Shape shape{};
   HostConsts hc;
   int device = 0;
@@ -271,7 +316,8 @@ static void destroy_index(slash_index* ix) {
 extern "C" void slash_free(slash_index* ix) { destroy_index(ix); }
 
 // Device-side validation of rows (and per-query k); reads back one flag.
-static slash_status validate_rows(slash_index* ix, slash_csr rows, const uint32_t* kq, hipStream_t st) {
+static slash_status validate_rows(slash_index* ix, slash_csr rows, const uint32_t* kq, hipStream_t st,
+                                  PhaseTimer* timer = nullptr, int64_t* nnz_out = nullptr) {
   if (rows.n_rows == 0) return SLASH_OK;
   if (!rows.indptr || !rows.indices) return fail(SLASH_E_INVAL, "CSR pointers are NULL");
   int64_t ends[2];
@@ -279,9 +325,12 @@ static slash_status validate_rows(slash_index* ix, slash_csr rows, const uint32_
   HIP_TRY(hipMemcpyAsync(&ends[1], rows.indptr + rows.n_rows, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (ends[1] < ends[0]) return fail(SLASH_E_INVAL, "indptr is decreasing");
+  if (nnz_out) *nnz_out = ends[1] - ends[0];
   HIP_TRY(launch_fill_u32(ix->flag, 0u, 1, st));
+  if (timer) timer->begin(PH_VALIDATE, st);
   HIP_TRY(launch_validate(rows, ix->p.dim, kq, ix->p.k_max, ix->flag, st));
   HIP_TRY(launch_validate_indices(rows.indices + ends[0], (uint64_t)(ends[1] - ends[0]), ix->p.dim, ix->flag, st));
+  if (timer) timer->end(PH_VALIDATE, st);
   uint32_t f = 0;
   HIP_TRY(hipMemcpyAsync(&f, ix->flag, 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -408,7 +457,9 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
   };
   if ((rs = upload_consts(ix, st)) != SLASH_OK) return bail(rs);
   if ((rs = alloc_tables(ix)) != SLASH_OK) return bail(rs);
-  if ((rs = validate_rows(ix, data, nullptr, st)) != SLASH_OK) return bail(rs);
+  EventTimer timer;
+  int64_t nnz = 0;
+  if ((rs = validate_rows(ix, data, nullptr, st, &timer, &nnz)) != SLASH_OK) return bail(rs);
   const Shape& s = ix->shape;
   const uint64_t n = data.n_rows;
   {
@@ -424,21 +475,27 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
         !hist.get(hist_n * 4) || !part.get(part_n * 4) || !start.get((size_t)s.nb * 4) ||
         !end.get((size_t)s.nb * 4) || !heavy.get((size_t)s.nb * 12) || !heavy_n.get(4))
       return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
+    timer.begin(PH_HASH, st);
     hipError_t e = launch_hash_rows(s, ix->cv, data, keys.as<uint32_t>(), n, 0, st);
+    timer.end(PH_HASH, st);
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "hash: %s", hipGetErrorString(e)));
     SortBuffers sb{k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), hist.as<uint32_t>(),
                    part.as<uint32_t>()};
     std::vector<std::vector<uint8_t>> keep;
     for (uint32_t t = 0; t < s.L; ++t) {
       uint32_t *sk = nullptr, *sv = nullptr;
-      e = radix_sort(keys.as<uint32_t>() + (uint64_t)t * n, nullptr, n, (int)s.B, sb, &sk, &sv, st);
+      e = radix_sort(keys.as<uint32_t>() + (uint64_t)t * n, nullptr, n, (int)s.B, sb, &sk, &sv, st, &timer);
       if (e == hipSuccess) e = launch_fill_u32(start.as<uint32_t>(), 0u, s.nb, st);
       if (e == hipSuccess) e = launch_fill_u32(end.as<uint32_t>(), 0u, s.nb, st);
       if (e == hipSuccess) e = launch_fill_u32(heavy_n.as<uint32_t>(), 0u, 1, st);
+      timer.begin(PH_BOUNDS, st);
       if (e == hipSuccess) e = launch_segment_bounds(sk, n, start.as<uint32_t>(), end.as<uint32_t>(), st);
+      timer.end(PH_BOUNDS, st);
+      timer.begin(PH_SELECT, st);
       if (e == hipSuccess)
         e = launch_select_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
                                 heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
+      timer.end(PH_SELECT, st);
       if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build table %u: %s", t, hipGetErrorString(e)));
       uint32_t nh = 0;
       e = hipMemcpyAsync(&nh, heavy_n.p, 4, hipMemcpyDeviceToHost, st);
@@ -451,12 +508,27 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
         std::vector<HeavyBucket> hv;
         for (uint32_t i = 0; i < nh; ++i) hv.push_back(HeavyBucket{hl[3 * i], hl[3 * i + 2], hl[3 * i + 1], hl[3 * i + 2]});
         std::sort(hv.begin(), hv.end(), [](const HeavyBucket& a, const HeavyBucket& b) { return a.bucket < b.bucket; });
+        timer.begin(PH_HEAVY, st);
         rs = finish_heavy(ix, t, sv, hv, candA, candB, workbuf, keep, st);
+        timer.end(PH_HEAVY, st);
         if (rs != SLASH_OK) return bail(rs);
       }
     }
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build: %s", hipGetErrorString(e)));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  timer.collect(ix->phase_ms, ix->phase_n);
+  {
+    // algorithmic bytes: what each phase must read and write once
+    const double N = (double)n, L = s.L, NB = s.nb, R = s.R;
+    const double passes = (s.B + 7) / 8;
+    ix->phase_bytes[PH_VALIDATE] = 4.0 * nnz + 8.0 * (N + 1);
+    ix->phase_bytes[PH_HASH] = 4.0 * nnz + 8.0 * (N + 1) + 4.0 * L * N;
+    ix->phase_bytes[PH_UPSWEEP] = 4.0 * N * L * passes;
+    ix->phase_bytes[PH_DOWNSWEEP] = L * (12.0 * N + (passes - 1) * 16.0 * N);
+    ix->phase_bytes[PH_BOUNDS] = 4.0 * N * L + 8.0 * NB * L;
+    ix->phase_bytes[PH_SELECT] = L * (4.0 * N + 8.0 * NB + NB * (4.0 * R + 4.0));
   }
   ix->n_items = n;
   *out = ix;
@@ -698,6 +770,21 @@ extern "C" slash_status slash_export_tables(const slash_index* ix, uint32_t* ids
   const Shape& s = ix->shape;
   if (ids) HIP_TRY(hipMemcpyAsync(ids, ix->ids, (size_t)s.L * s.nb * s.R * 4, hipMemcpyDeviceToDevice, st));
   if (seen) HIP_TRY(hipMemcpyAsync(seen, ix->seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st));
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_build_profile(const slash_index* ix, slash_phase_stat* out, uint32_t max, uint32_t* n) {
+  if (!ix || !n || (!out && max)) return fail(SLASH_E_INVAL, "NULL argument");
+  uint32_t c = 0;
+  for (int p = 0; p < PH_COUNT && c < max; ++p) {
+    memset(&out[c], 0, sizeof out[c]);
+    snprintf(out[c].name, sizeof out[c].name, "%s", kPhaseNames[p]);
+    out[c].launches = ix->phase_n[p];
+    out[c].total_ms = ix->phase_ms[p];
+    out[c].alg_bytes = ix->phase_bytes[p];
+    ++c;
+  }
+  *n = c;
   return SLASH_OK;
 }
 

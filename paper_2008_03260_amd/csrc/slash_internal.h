@@ -124,6 +124,14 @@ hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr ro
 // Key-value radix sort of n uint32 keys on bits [0, nbits).  vals_in may be
 // NULL: values are then the positions 0..n-1.  Results land in
 // (keys_out, vals_out); the tmp buffers hold n entries each.
+// Optional event marks around kernel launches (build profiling).
+struct PhaseTimer {
+  virtual void begin(int phase, hipStream_t st) = 0;
+  virtual void end(int phase, hipStream_t st) = 0;
+  virtual ~PhaseTimer() {}
+};
+enum { PH_VALIDATE, PH_HASH, PH_UPSWEEP, PH_SCAN, PH_DOWNSWEEP, PH_BOUNDS, PH_SELECT, PH_HEAVY, PH_COUNT };
+
 struct SortBuffers {
   uint32_t *k0, *v0, *k1, *v1;  // ping-pong, n each
   uint32_t* hist;               // >= hist_entries(n)
@@ -132,7 +140,8 @@ struct SortBuffers {
 size_t sort_hist_entries(uint64_t n);
 size_t sort_part_entries(uint64_t n);
 hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t n, int nbits,
-                      SortBuffers& b, uint32_t** keys_out, uint32_t** vals_out, hipStream_t st);
+                      SortBuffers& b, uint32_t** keys_out, uint32_t** vals_out, hipStream_t st,
+                      PhaseTimer* timer = nullptr);
 
 // Exclusive scan of n uint32 (in place), scratch `part` of sort_part_entries(n).
 hipError_t exclusive_scan(uint32_t* data, uint64_t n, uint32_t* part, hipStream_t st);

@@ -202,7 +202,7 @@ hipError_t exclusive_scan(uint32_t* data, uint64_t n, uint32_t* part, hipStream_
 }
 
 hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t n, int nbits, SortBuffers& b,
-                      uint32_t** keys_out, uint32_t** vals_out, hipStream_t st) {
+                      uint32_t** keys_out, uint32_t** vals_out, hipStream_t st, PhaseTimer* timer) {
   const uint32_t* sk = keys_in;
   const uint32_t* sv = vals_in;
   if (nbits < 1) nbits = 1;
@@ -215,11 +215,17 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
     dk = (p & 1) ? b.k1 : b.k0;
     dv = (p & 1) ? b.v1 : b.v0;
     if (n > 0) {
+      if (timer) timer->begin(PH_UPSWEEP, st);
       hipLaunchKernelGGL(k_upsweep, dim3(n_tiles), dim3(kThreads), 0, st, sk, n, shift, bits, b.hist, n_tiles);
+      if (timer) timer->end(PH_UPSWEEP, st);
+      if (timer) timer->begin(PH_SCAN, st);
       hipError_t e = exclusive_scan(b.hist, (uint64_t)n_tiles << bits, b.part, st);
+      if (timer) timer->end(PH_SCAN, st);
       if (e != hipSuccess) return e;
+      if (timer) timer->begin(PH_DOWNSWEEP, st);
       hipLaunchKernelGGL(k_downsweep, dim3(n_tiles), dim3(kThreads), 0, st, sk, sv, n, shift, bits, b.hist, n_tiles,
                          dk, dv);
+      if (timer) timer->end(PH_DOWNSWEEP, st);
     }
     sk = dk;
     sv = dv;
