@@ -41,6 +41,34 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 
 
+# Which kernel each build phase is, its source file, and its row in the
+# committed counter summary (traffic is reported only while the kernel's
+# source is the one the counters were taken on).
+PHASE_KERNEL = {"sort_downsweep": ("k_downsweep", "sort.hip"), "sort_upsweep": ("k_upsweep", "sort.hip"),
+                "hash": ("k_hash_rows", "hash.hip"), "select": ("k_select_light", "select.hip"),
+                "segment_bounds": ("k_segment_bounds", "hash.hip")}
+
+
+def counted_traffic(phase):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the phase's kernel,
+    from profiles/c1_hbm_counters.md, or None if absent or stale."""
+    import hashlib
+    import re
+    if phase not in PHASE_KERNEL:
+        return None
+    kern, src = PHASE_KERNEL[phase]
+    path = os.path.join(ROOT, "profiles", "c1_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"csrc/%s sha256 ([0-9a-f]{64})" % re.escape(src), txt)
+    cur = hashlib.sha256(open(os.path.join(ROOT, "paper_2008_03260_amd", "csrc", src), "rb").read()).hexdigest()
+    if not m or m.group(1) != cur:
+        return None
+    row = re.search(r"^\| %s \| (\d+) \| ([\d.]+) \| ([\d.]+) \| ([\d.]+) \|" % re.escape(kern), txt, flags=re.M)
+    return float(row.group(4)) * 1e9 if row else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -219,7 +247,7 @@ def main():
         "batched_query_ms": float(q_ms.mean()),
         "build_algorithmic_hbm_frac": build_alg / (b_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": counted_traffic(dom),
                      "kernel": dom, "launches": d["launches"], "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
                      "alg_bytes_per_launch": d["alg_bytes"] / d["launches"]},
         "query_roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

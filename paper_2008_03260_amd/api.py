@@ -56,6 +56,28 @@ class PhaseStat(C.Structure):
                 ("total_ms", C.c_double), ("alg_bytes", C.c_double)]
 
 
+SERVE_MAX_K = 128
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_batch", C.c_uint32), ("max_inflight", C.c_uint32),
+                ("queue_capacity", C.c_uint32), ("max_wait_us", C.c_uint32), ("max_query_nnz", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("epoch", C.c_uint64), ("status", C.c_int32), ("kind", C.c_uint32),
+                ("k", C.c_uint32), ("n_ids", C.c_uint32), ("first_id", C.c_uint32), ("reserved", C.c_uint32),
+                ("ids", C.c_uint32 * SERVE_MAX_K), ("scores", C.c_uint32 * SERVE_MAX_K),
+                ("t_submit_s", C.c_double), ("t_done_s", C.c_double)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("queries_done", "inserts_done", "rows_inserted", "batches",
+                                          "rejected_busy", "rejected_nomem", "peak_inflight", "peak_hbm_bytes")] + \
+               [("busy_s", C.c_double)]
+
+
 class Schedule(C.Structure):
     _fields_ = [("waves_per_query", C.c_uint32), ("queries_per_ticket", C.c_uint32),
                 ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
@@ -83,6 +105,12 @@ def lib() -> C.CDLL:
             "slash_free": ([vp], None),
             "slash_last_error": ([], C.c_char_p),
             "slash_set_allocator": ([vp, vp, vp], st),
+            "slash_serve_start": ([vp, P(ServeConfig), P(vp)], st),
+            "slash_serve_submit_query": ([vp, vp, u32, u32, P(u64)], st),
+            "slash_serve_submit_insert": ([vp, vp, vp, u32, P(u64)], st),
+            "slash_serve_poll": ([vp, P(Completion), u32, P(u32)], st),
+            "slash_serve_stop": ([vp, P(ServeStats)], st),
+            "slash_serve_replay": ([vp, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u32], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -221,6 +249,77 @@ def slash_build_profile(index) -> dict:
 def slash_free(index):
     if index:
         lib().slash_free(index)
+
+
+# ------------------------------------------------------------- serving
+
+
+def _np(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def slash_serve_start(index, hbm_budget_bytes=1 << 30, max_batch=1024, max_inflight=4, queue_capacity=1 << 20,
+                      max_wait_us=0, max_query_nnz=4096) -> C.c_void_p:
+    cfg = ServeConfig(hbm_budget_bytes, max_batch, max_inflight, queue_capacity, max_wait_us, max_query_nnz, 0)
+    out = C.c_void_p()
+    _check(lib().slash_serve_start(index, C.byref(cfg), C.byref(out)), "slash_serve_start")
+    return out
+
+
+def slash_serve_submit_query(srv, indices, k: int) -> int:
+    a, p = _np(indices, np.int32)
+    t = C.c_uint64()
+    _check(lib().slash_serve_submit_query(srv, p, len(a), k, C.byref(t)), "slash_serve_submit_query")
+    return int(t.value)
+
+
+def slash_serve_submit_insert(srv, indptr, indices) -> int:
+    ip, pp = _np(indptr, np.int64)
+    ix, px = _np(indices, np.int32)
+    t = C.c_uint64()
+    _check(lib().slash_serve_submit_insert(srv, pp, px, len(ip) - 1, C.byref(t)), "slash_serve_submit_insert")
+    return int(t.value)
+
+
+def slash_serve_poll(srv, max_n: int = 1024) -> list:
+    buf = (Completion * max_n)()
+    n = C.c_uint32()
+    _check(lib().slash_serve_poll(srv, buf, max_n, C.byref(n)), "slash_serve_poll")
+    out = []
+    for i in range(n.value):
+        c = buf[i]
+        out.append({"ticket": int(c.ticket), "epoch": int(c.epoch), "status": int(c.status), "kind": int(c.kind),
+                    "k": int(c.k), "n_ids": int(c.n_ids), "first_id": int(c.first_id),
+                    "ids": np.array(c.ids[:c.k], dtype=np.uint32), "scores": np.array(c.scores[:c.k], dtype=np.uint32),
+                    "t_submit_s": float(c.t_submit_s), "t_done_s": float(c.t_done_s)})
+    return out
+
+
+def slash_serve_stop(srv) -> dict:
+    st = ServeStats()
+    _check(lib().slash_serve_stop(srv, C.byref(st)), "slash_serve_stop")
+    return {f: (float(getattr(st, f)) if f == "busy_s" else int(getattr(st, f))) for f, _ in ServeStats._fields_}
+
+
+def slash_serve_replay(srv, t_arrival, is_insert, ins_rows, q_indptr, q_indices, q_k, ins_indptr, ins_indices,
+                       out_stride: int = 0):
+    """Open-loop replay; returns (latency_s float64[n], ids uint32[n, out_stride] or None)."""
+    n = len(t_arrival)
+    ta, pta = _np(t_arrival, np.float64)
+    ii, pii = _np(np.asarray(is_insert).astype(np.uint8), np.uint8)
+    ir, pir = _np(ins_rows, np.uint32)
+    qp, pqp = _np(q_indptr, np.int64)
+    qx, pqx = _np(q_indices, np.int32)
+    qk, pqk = _np(q_k, np.uint32)
+    ip_, pip = _np(ins_indptr, np.int64)
+    ix, pix = _np(ins_indices, np.int32)
+    lat = np.zeros(n, dtype=np.float64)
+    ids = np.full((n, max(out_stride, 1)), EMPTY, dtype=np.uint32) if out_stride else None
+    _check(lib().slash_serve_replay(srv, n, pta, pii, pir, pqp, pqx, pqk, pip, pix, lat.ctypes.data_as(C.c_void_p),
+                                    ids.ctypes.data_as(C.c_void_p) if ids is not None else None, out_stride),
+           "slash_serve_replay")
+    return lat, ids
 
 
 def as_u32(t: torch.Tensor) -> np.ndarray:

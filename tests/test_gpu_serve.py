@@ -1,0 +1,153 @@
+"""Serving loop (continuous batching with epoch-ordered inserts): every
+served result equals the standalone result on the index state of its epoch."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EMPTY = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_03260_amd import api as a
+    a.lib()
+    return a
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+@pytest.fixture(scope="module")
+def setup(api):
+    law = synth.RowLaw(synth.derive(31, synth.STREAM_DATA), 1 << 20)
+    n0, n1 = 20000, 1500
+    ip, ix = law.rows(0, n0 + n1)
+    qi, qx, _, kq = law.queries(synth.derive(31, synth.STREAM_QUERY), n0, 0, 1200, nnz_mode="lognormal",
+                                median=40, sigma=1.0, lo=5, hi=2000, f=(0.1, 0.4), kmix=(1, 10, 100))
+    params = api.Params.of(dim=1 << 20, K=4, L=16, log2_buckets=12, R=16, cm_rows=4, log2_cm_width=10, k_max=100,
+                           seed=synth.derive(31, synth.STREAM_INDEX))
+    return law, params, ip, ix, n0, n1, qi, qx, kq
+
+
+def standalone(api, params, ip, ix, n_rows, qi, qx, kq):
+    idx = api.Index(params, dev(ip[: n_rows + 1]), dev(ix[: ip[n_rows]]))
+    gi, gs = idx.query(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
+    torch.cuda.synchronize()
+    out = u32(gi), u32(gs)
+    idx.close()
+    return out
+
+
+def test_served_results_equal_standalone(api, setup):
+    law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    ref_i, ref_s = standalone(api, params, ip, ix, n0, qi, qx, kq)
+    idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=64 << 20, max_batch=128, max_inflight=3)
+    tickets = {}
+    for q in range(len(qi) - 1):
+        t = api.slash_serve_submit_query(srv, qx[qi[q]:qi[q + 1]], int(kq[q]))
+        tickets[t] = q
+    got = []
+    while len(got) < len(tickets):
+        got += api.slash_serve_poll(srv)
+    stats = api.slash_serve_stop(srv)
+    assert stats["queries_done"] == len(tickets) and stats["batches"] >= 1
+    for c in got:
+        q = tickets[c["ticket"]]
+        k = int(kq[q])
+        assert c["status"] == 0 and c["epoch"] == 0 and c["k"] == k
+        assert (c["ids"] == ref_i[q, :k]).all() and (c["scores"] == ref_s[q, :k]).all()
+    idx.close()
+
+
+def test_inserts_close_epochs(api, setup):
+    # queries submitted before an insert see the index without it; those
+    # after see it (the inserted index equals a bulk build on the union)
+    law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    before = standalone(api, params, ip, ix, n0, qi, qx, kq)
+    after = standalone(api, params, ip, ix, n0 + n1, qi, qx, kq)
+    idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=64 << 20, max_batch=64, max_inflight=4)
+    nq = len(qi) - 1
+    tickets = {}
+    for q in range(nq // 2):
+        tickets[api.slash_serve_submit_query(srv, qx[qi[q]:qi[q + 1]], int(kq[q]))] = ("q", q, 0)
+    sip = ip[n0: n0 + n1 + 1] - ip[n0]
+    six = ix[ip[n0]: ip[n0 + n1]]
+    tickets[api.slash_serve_submit_insert(srv, sip, six)] = ("i", None, 1)
+    for q in range(nq // 2, nq):
+        tickets[api.slash_serve_submit_query(srv, qx[qi[q]:qi[q + 1]], int(kq[q]))] = ("q", q, 1)
+    got = []
+    while len(got) < len(tickets):
+        got += api.slash_serve_poll(srv)
+    api.slash_serve_stop(srv)
+    for c in got:
+        kind, q, epoch = tickets[c["ticket"]]
+        assert c["status"] == 0 and c["epoch"] == epoch
+        if kind == "i":
+            assert c["first_id"] == n0 and c["n_ids"] == n1
+            continue
+        ref_i, ref_s = before if epoch == 0 else after
+        k = int(kq[q])
+        assert (c["ids"] == ref_i[q, :k]).all() and (c["scores"] == ref_s[q, :k]).all()
+    assert idx.info()["n_items"] == n0 + n1
+    idx.close()
+
+
+def test_stop_drains_and_rejects(api, setup):
+    law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    with pytest.raises(api.SlashError) as e:
+        api.slash_serve_start(idx.handle, hbm_budget_bytes=1 << 10)
+    assert e.value.code == api.E_NOMEM
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=64 << 20, max_batch=32, max_inflight=2,
+                                max_query_nnz=2000)
+    with pytest.raises(api.SlashError) as e:
+        api.slash_serve_submit_query(srv, np.arange(2001), 10)
+    assert e.value.code == api.E_INVAL
+    with pytest.raises(api.SlashError) as e:
+        api.slash_serve_submit_query(srv, np.array([1, 2, 1 << 21]), 10)
+    assert e.value.code == api.E_INVAL
+    with pytest.raises(api.SlashError) as e:
+        api.slash_serve_submit_query(srv, np.array([1, 2]), 129)
+    assert e.value.code == api.E_INVAL
+    n = 0
+    for q in range(len(qi) - 1):
+        api.slash_serve_submit_query(srv, qx[qi[q]:qi[q + 1]], int(kq[q]))
+        n += 1
+    stats = api.slash_serve_stop(srv)  # returns only after every accepted request ran
+    assert stats["queries_done"] == n
+    idx.close()
+
+
+def test_replay_open_loop(api, setup):
+    law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=128 << 20, max_batch=256, max_inflight=4)
+    n = 1000
+    t, ins, sz = synth.arrivals(synth.derive(31, synth.STREAM_ARRIVAL), n, 20000.0, 0.1, 1, 64)
+    nq = int((~ins).sum())
+    q_ptr = np.zeros(nq + 1, dtype=np.int64)
+    reps = [(q % (len(qi) - 1)) for q in range(nq)]
+    lens = np.array([qi[r + 1] - qi[r] for r in reps])
+    q_ptr[1:] = np.cumsum(lens)
+    q_idx = np.concatenate([qx[qi[r]:qi[r + 1]] for r in reps])
+    q_k = np.array([kq[r] for r in reps], dtype=np.uint32)
+    rows = int(sz[ins].sum())
+    iip, iix = law.rows(n0, rows)
+    lat, ids = api.slash_serve_replay(srv, t, ins, sz, q_ptr, q_idx, q_k, iip, iix, out_stride=100)
+    stats = api.slash_serve_stop(srv)
+    assert (lat >= 0).all() and stats["queries_done"] == nq and stats["inserts_done"] == int(ins.sum())
+    assert stats["rows_inserted"] == rows
+    idx.close()
