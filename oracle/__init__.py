@@ -77,6 +77,7 @@ def lib():
         L.oracle_insert.argtypes = [P, vp, vp, vp, C.c_uint32, vp, vp, C.c_uint64]
         L.oracle_query.argtypes = [P, vp, vp, vp, vp, vp, C.c_uint64, vp, C.c_uint32, C.c_uint32,
                                    vp, vp, C.c_int]
+        L.oracle_aggregate.argtypes = [P, vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, C.c_int]
         _lib = L
     return _lib
 
@@ -188,4 +189,15 @@ def query(p: Params, cs, ids, seen, qindptr, qindices, k: int, k_max: int | None
     _check(lib().oracle_query(C.byref(p.c()), _p(cs), _p(ids), _p(seen), _p(qindptr),
                               _p(qindices), nq, _p(kqa) if kqa is not None else None, k, k_max,
                               _p(oi), _p(osc), 1 if exact else 0), "oracle_query")
+    return oi, osc
+
+
+def aggregate(p: Params, cs, cand, k: int, k_max: int | None = None, exact: bool = False):
+    """Top-k (ids, scores) of one candidate multiset (row of stride k_max)."""
+    k_max = k if k_max is None else k_max
+    c = np.ascontiguousarray(cand, dtype=np.uint32)
+    oi = np.zeros(k_max, dtype=np.uint32)
+    osc = np.zeros(k_max, dtype=np.uint32)
+    _check(lib().oracle_aggregate(C.byref(p.c()), _p(cs), _p(c) if len(c) else None, len(c), k, k_max, _p(oi),
+                                  _p(osc), 1 if exact else 0), "oracle_aggregate")
     return oi, osc

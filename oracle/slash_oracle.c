@@ -392,12 +392,67 @@ static int cmp_scored(const void* a, const void* b) {
   return (x->id > y->id) - (x->id < y->id);
 }
 
+/* Frequency aggregation of one query's candidate multiset cand[0..nc)
+ * (Section 2.3 "Cheap Frequency based Filtering"; Section 2.4, Appendix 2):
+ * estimate each distinct candidate's frequency with the count-min sketch
+ * (min over d rows of w counters) or, when exact != 0, count it exactly, and
+ * write the kk best (estimate desc, id asc) into out_ids / out_scores[0..k_max),
+ * padded with (EMPTY, 0). */
+EXPORT int oracle_aggregate(const oracle_params* p, const uint64_t* cs, const uint32_t* cand, uint64_t nc,
+                            uint32_t kk, uint32_t k_max, uint32_t* out_ids, uint32_t* out_scores, int exact) {
+  if (!params_ok(p) || !cs || !out_ids || !out_scores || kk > k_max) return O_EINVAL;
+  uint64_t w = 1ull << p->log2_cm_width;
+  uint32_t* sorted = (uint32_t*)malloc(sizeof(uint32_t) * (nc + 1));
+  scored_t* sc = (scored_t*)malloc(sizeof(scored_t) * (nc + 1));
+  uint64_t* cm = exact ? NULL : (uint64_t*)malloc(sizeof(uint64_t) * p->cm_rows * w);
+  if (!sorted || !sc || (!exact && !cm)) {
+    free(sorted);
+    free(sc);
+    free(cm);
+    return O_ENOMEM;
+  }
+  if (!exact) {
+    memset(cm, 0, sizeof(uint64_t) * p->cm_rows * w);
+    for (uint64_t i = 0; i < nc; ++i)
+      for (uint32_t r = 0; r < p->cm_rows; ++r) cm[r * w + cm_hash(p, cs, r, cand[i])] += 1;
+  }
+  memcpy(sorted, cand, sizeof(uint32_t) * nc);
+  qsort(sorted, nc, sizeof(uint32_t), cmp_u32);
+  uint64_t nd = 0;
+  for (uint64_t i = 0; i < nc;) {
+    uint64_t j = i;
+    while (j < nc && sorted[j] == sorted[i]) ++j;
+    uint32_t c = sorted[i];
+    uint64_t s;
+    if (exact) {
+      s = j - i;
+    } else {
+      s = UINT64_MAX;
+      for (uint32_t r = 0; r < p->cm_rows; ++r) {
+        uint64_t v = cm[r * w + cm_hash(p, cs, r, c)];
+        if (v < s) s = v;
+      }
+    }
+    sc[nd].score = (uint32_t)s;
+    sc[nd].id = c;
+    ++nd;
+    i = j;
+  }
+  qsort(sc, nd, sizeof(scored_t), cmp_scored);
+  for (uint32_t i = 0; i < k_max; ++i) {
+    int live = i < kk && i < nd;
+    out_ids[i] = live ? sc[i].id : EMPTY;
+    out_scores[i] = live ? sc[i].score : 0;
+  }
+  free(sorted);
+  free(sc);
+  free(cm);
+  return O_OK;
+}
+
 /* Query (Section 2.3 query phase; Algorithm 2's per-node part): hash the
  * query into its L buckets, take the union (with multiplicity) of the ids they
- * hold, estimate each candidate's frequency and report the k most frequent
- * identities (Section 2.4, Appendix 2).  The frequency estimate is the
- * count-min estimate (min over d rows of w counters), or the exact
- * multiplicity when exact != 0.  Output rows have stride k_max. */
+ * hold, and aggregate (oracle_aggregate).  Output rows have stride k_max. */
 EXPORT int oracle_query(const oracle_params* p, const uint64_t* cs, const uint32_t* ids,
                         const uint32_t* seen, const int64_t* qindptr, const int32_t* qindices,
                         uint64_t nq, const uint32_t* kq, uint32_t k, uint32_t k_max,
@@ -405,14 +460,10 @@ EXPORT int oracle_query(const oracle_params* p, const uint64_t* cs, const uint32
   if (!params_ok(p) || !cs || !ids || !seen || !out_ids || !out_scores) return O_EINVAL;
   if (k_max == 0) return O_EINVAL;
   uint64_t nb = 1ull << p->log2_buckets;
-  uint64_t w = 1ull << p->log2_cm_width;
   uint32_t* bk = (uint32_t*)malloc(sizeof(uint32_t) * p->L);
   uint32_t* cand = (uint32_t*)malloc(sizeof(uint32_t) * ((uint64_t)p->L * p->R + 1));
-  uint32_t* sorted = (uint32_t*)malloc(sizeof(uint32_t) * ((uint64_t)p->L * p->R + 1));
-  scored_t* sc = (scored_t*)malloc(sizeof(scored_t) * ((uint64_t)p->L * p->R + 1));
-  uint64_t* cm = exact ? NULL : (uint64_t*)malloc(sizeof(uint64_t) * p->cm_rows * w);
   int rc = O_OK;
-  if (!bk || !cand || !sorted || !sc || (!exact && !cm)) rc = O_ENOMEM;
+  if (!bk || !cand) rc = O_ENOMEM;
   for (uint64_t q = 0; q < nq && rc == O_OK; ++q) {
     uint32_t kk = kq ? kq[q] : k;
     if (kk > k_max) { rc = O_EINVAL; break; }
@@ -424,45 +475,10 @@ EXPORT int oracle_query(const oracle_params* p, const uint64_t* cs, const uint32
       uint32_t fill = seen[slot] < p->R ? seen[slot] : p->R;
       for (uint32_t i = 0; i < fill; ++i) cand[nc++] = ids[slot * p->R + i];
     }
-    if (!exact) {
-      memset(cm, 0, sizeof(uint64_t) * p->cm_rows * w);
-      for (uint64_t i = 0; i < nc; ++i)
-        for (uint32_t r = 0; r < p->cm_rows; ++r) cm[r * w + cm_hash(p, cs, r, cand[i])] += 1;
-    }
-    memcpy(sorted, cand, sizeof(uint32_t) * nc);
-    qsort(sorted, nc, sizeof(uint32_t), cmp_u32);
-    uint64_t nd = 0;
-    for (uint64_t i = 0; i < nc;) {
-      uint64_t j = i;
-      while (j < nc && sorted[j] == sorted[i]) ++j;
-      uint32_t c = sorted[i];
-      uint64_t s;
-      if (exact) {
-        s = j - i;
-      } else {
-        s = UINT64_MAX;
-        for (uint32_t r = 0; r < p->cm_rows; ++r) {
-          uint64_t v = cm[r * w + cm_hash(p, cs, r, c)];
-          if (v < s) s = v;
-        }
-      }
-      sc[nd].score = (uint32_t)s;
-      sc[nd].id = c;
-      ++nd;
-      i = j;
-    }
-    qsort(sc, nd, sizeof(scored_t), cmp_scored);
-    for (uint32_t i = 0; i < k_max; ++i) {
-      int live = i < kk && i < nd;
-      out_ids[q * k_max + i] = live ? sc[i].id : EMPTY;
-      out_scores[q * k_max + i] = live ? sc[i].score : 0;
-    }
+    rc = oracle_aggregate(p, cs, cand, nc, kk, k_max, out_ids + q * k_max, out_scores + q * k_max, exact);
   }
   free(bk);
   free(cand);
-  free(sorted);
-  free(sc);
-  free(cm);
   return rc;
 }
 

@@ -475,3 +475,18 @@ def test_recall_at_10_on_tiny_config():
     oi, _ = oracle.query(p, cs, ids, seen, qi, qx, k=10)
     recall = np.mean([s in row for s, row in zip(src.tolist(), oi.tolist())])
     assert recall >= 0.9, recall
+
+
+@pytest.mark.parametrize("variant", ["one_row", "two_rows", "exact"])
+def test_aggregate_hand_worked(variant):
+    # the aggregation step alone, on the hand fixture's candidate multiset
+    g = load_golden("query_hand.json")
+    d = load_golden("doph_hand.json")
+    p = params_from(d["params"])
+    v = g[variant] if variant != "exact" else g["one_row"]
+    p.cm_rows = len(v["a_r"])
+    cs = constants_with(p, a_r=v["a_r"], b_r=v["b_r"])
+    oi, osc = oracle.aggregate(p, cs, [10, 11, 12, 11, 14], k=g["k"], k_max=g["k_max"],
+                               exact=(variant == "exact"))
+    want = g[variant]
+    assert oi.tolist() == want["ids"] and osc.tolist() == want["scores"]
