@@ -103,6 +103,51 @@ def cpu_baseline(w, law, seeds, budget_s=20.0):
     }
 
 
+def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4, 1e5, 3e5, 1e6, 2e6)):
+    """Open-loop Poisson arrivals against the continuous-batching server on
+    the resident index: 90% queries (the batched mix), 10% inserts of 1-4096
+    new rows.  Latency = completion - scheduled arrival."""
+    import synth
+    out = []
+    next_row = w["n"] + 4096 * 64
+    for rate in rates:
+        n = int(min(rate * seconds, 400_000))
+        t, ins, sz = synth.arrivals(seeds["query"] ^ int(rate), n, rate, 0.1, 1, 4096)
+        nq = int((~ins).sum())
+        pick = np.arange(nq) % (len(mi_h) - 1)
+        lens = mi_h[pick + 1] - mi_h[pick]
+        q_ptr = np.zeros(nq + 1, dtype=np.int64)
+        q_ptr[1:] = np.cumsum(lens)
+        starts = mi_h[pick]
+        q_idx = np.concatenate([mx_h[a:a + b] for a, b in zip(starts.tolist(), lens.tolist())]) if nq else np.zeros(0, np.int32)
+        q_k = mk[pick].astype(np.uint32)
+        rows = int(sz[ins].sum())
+        if rows:
+            gip, gix = law.gpu_rows(next_row, rows)
+            iip, iix = gip.cpu().numpy(), gix.cpu().numpy()
+            next_row += rows
+        else:
+            iip, iix = np.zeros(1, np.int64), np.zeros(0, np.int32)
+        srv = api.slash_serve_start(h, hbm_budget_bytes=2 << 30, max_batch=2048, max_inflight=6,
+                                    queue_capacity=1 << 22, max_query_nnz=2000)
+        t0 = time.perf_counter()
+        lat, _ = api.slash_serve_replay(srv, t, ins, sz, q_ptr, q_idx, q_k, iip, iix)
+        wall = time.perf_counter() - t0
+        st = api.slash_serve_stop(srv)
+        ql, il = lat[~ins], lat[ins]
+        pt = {"offered_req_per_s": rate, "requests": n, "wall_s": wall,
+              "queries_per_s": nq / wall, "inserted_rows_per_s": rows / wall,
+              "query_p50_us": float(np.percentile(ql, 50) * 1e6) if nq else None,
+              "query_p99_us": float(np.percentile(ql, 99) * 1e6) if nq else None,
+              "insert_p50_us": float(np.percentile(il, 50) * 1e6) if len(il) else None,
+              "insert_p99_us": float(np.percentile(il, 99) * 1e6) if len(il) else None,
+              "batches": st["batches"], "peak_inflight": st["peak_inflight"]}
+        log(f"serve {rate:,.0f} req/s: {pt['queries_per_s']:,.0f} q/s, {pt['inserted_rows_per_s']:,.0f} rows/s inserted, "
+            f"query p50 {pt['query_p50_us']:.0f} us p99 {pt['query_p99_us']:.0f} us")
+        out.append(pt)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +156,9 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--plain-queries", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-seconds", type=float, default=0.5, help="arrival window per serving rate")
+    ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -136,8 +184,10 @@ def main():
     log(f"generated {w['n']:,} rows, {nnz:,} nonzeros in HBM in {time.perf_counter() - t0:.1f}s")
     qi_h, qx_h, src, _ = law.queries(seeds["query"], w["n"], 0, w["nq"])
     qi, qx = torch.from_numpy(qi_h).to(dev), torch.from_numpy(qx_h).to(dev)
+    # k_max = 100 so the same index also answers the batched/serving mix
+    # (k drawn from {1, 10, 100}); the planted-query workload asks k = 10
     params = api.Params.of(dim=w["dim"], K=w["K"], L=w["L"], log2_buckets=w["B"], R=w["R"], cm_rows=w["d"],
-                           log2_cm_width=w["lw"], k_max=w["k"], hash_mode=0, seed=seeds["index"])
+                           log2_cm_width=w["lw"], k_max=100, hash_mode=0, seed=seeds["index"])
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
@@ -180,7 +230,7 @@ def main():
     i_ms = np.array([r[1] for r in rec])
     q_ms = np.array([r[2] for r in rec])
     qps = w["nq"] * len(rec) / (q_ms.sum() / 1e3)
-    got = api.as_u32(oi)
+    got = api.as_u32(oi)[:, : w["k"]]
     recall = float(np.mean([s in row for s, row in zip(src.tolist(), got.tolist())]))
     log(f"build {b_ms.mean():.1f} ms, insert(4096) {i_ms.mean():.2f} ms, batched query {q_ms.mean():.2f} ms, "
         f"recall@10 {recall:.4f}")
@@ -192,8 +242,8 @@ def main():
     for i in range(min(200, npl)):  # warm
         api.slash_query(h, single_ip[i], qx[int(qi_h[i]):int(qi_h[i + 1])], w["k"], flags=api.FLAG_TRUSTED)
     torch.cuda.synchronize()
-    out_i = torch.empty((1, w["k"]), dtype=torch.int32, device=dev)
-    out_s = torch.empty((1, w["k"]), dtype=torch.int32, device=dev)
+    out_i = torch.empty((1, 100), dtype=torch.int32, device=dev)
+    out_s = torch.empty((1, 100), dtype=torch.int32, device=dev)
     t_pl = time.perf_counter()
     for i in range(npl):
         t = time.perf_counter()
@@ -204,6 +254,47 @@ def main():
     t_pl = time.perf_counter() - t_pl
     log(f"plain one-at-a-time: {npl / t_pl:,.0f} q/s, p50 {np.percentile(lat, 50) * 1e6:.1f} us, "
         f"p99 {np.percentile(lat, 99) * 1e6:.1f} us")
+
+    # batched mix: lognormal query sizes, 10-40% replaced, k in {1, 10, 100};
+    # one persistent graph-replayed launch vs the plain one-group-per-query grid
+    nm = min(args.mix_queries, w["n"])
+    mi_h, mx_h, msrc, mk = law.queries(seeds["query"] ^ 0x5EED, w["n"], 0, nm, nnz_mode="lognormal", median=40,
+                                       sigma=1.0, lo=5, hi=2000, f=(0.1, 0.4), kmix=(1, 10, 100))
+    mi, mx = torch.from_numpy(mi_h).to(dev), torch.from_numpy(mx_h).to(dev)
+    mkd = torch.from_numpy(mk.view(np.int32)).to(dev)
+    mix_sched = api.slash_autotune(h, mi[: 20001], mx[: int(mi_h[20000])], 100, stream)
+    res_b = api.slash_query_batched(h, mi, mx, 0, k_per_query=mkd, flags=api.FLAG_TRUSTED, schedule=mix_sched)
+    res_p = api.slash_query(h, mi, mx, 0, k_per_query=mkd, flags=api.FLAG_TRUSTED)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(res_b[0], res_p[0]) and torch.equal(res_b[1], res_p[1]))
+    tb, tp = [], []
+    for _ in range(3):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        api.slash_query_batched(h, mi, mx, 0, k_per_query=mkd, flags=api.FLAG_TRUSTED, schedule=mix_sched,
+                                out_ids=res_b[0], out_scores=res_b[1])
+        e1.record(stream)
+        api.slash_query(h, mi, mx, 0, k_per_query=mkd, flags=api.FLAG_TRUSTED, out_ids=res_p[0], out_scores=res_p[1])
+        e2.record(stream)
+        torch.cuda.synchronize()
+        tb.append(e0.elapsed_time(e1))
+        tp.append(e1.elapsed_time(e2))
+    mix_ids = api.as_u32(res_b[0])
+    qn = np.diff(mi_h)
+    mix_recall = {}
+    for lo_, hi_ in ((5, 20), (20, 80), (80, 320), (320, 2001)):
+        sel = np.nonzero((qn >= lo_) & (qn < hi_) & (mk >= 10))[0]
+        if len(sel):
+            mix_recall[f"nnz[{lo_},{hi_})"] = float(np.mean([msrc[i] in mix_ids[i, :10] for i in sel]))
+    mix = {"queries": nm, "batched_queries_per_s": nm / (min(tb) / 1e3), "plain_grid_queries_per_s": nm / (min(tp) / 1e3),
+           "batched_equals_plain": same, "schedule": mix_sched, "recall_at_10_by_nnz": mix_recall}
+    log(f"mix: batched {mix['batched_queries_per_s']:,.0f} q/s, plain grid {mix['plain_grid_queries_per_s']:,.0f} q/s, "
+        f"identical {same}, recall@10 by nnz {mix_recall}")
+    del res_b, res_p
+
+    serve = None
+    if not args.no_serve:
+        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, args.serve_seconds, seeds)
 
     # query kernel: algorithmic bytes per query = the query row 4*nnz + 8,
     # per table the reservoir row 4*R (read whole, EMPTY-padded), output 8*k
@@ -254,6 +345,8 @@ def main():
                            "frac": q_gbs / HBM_PEAK_GBS, "kernel": "k_query_persistent",
                            "alg_bytes_per_query": alg_q / w["nq"]},
         "build_phases": prof,
+        "batched_mix": mix,
+        "serve": serve,
         "stream_copy_gbs": copy_gbs,
     }
     if not args.no_cpu_baseline:

@@ -149,11 +149,14 @@ SLASH_API slash_status slash_insert(slash_index* index, slash_csr rows, uint32_t
 SLASH_API slash_status slash_query(const slash_index* index, slash_csr queries, const uint32_t* k_per_query_dev,
                          uint32_t k, uint32_t flags, uint32_t* ids_dev, uint32_t* scores_dev, void* stream);
 
-/* Same results as slash_query (bit-exact) through the batched path: one
- * persistent launch whose resident work-groups take queries from a device
- * work counter, with the schedule `sched` (NULL = the tuned schedule for
- * this index, see slash_autotune).  The launch is recorded once into a HIP
- * graph and replayed. */
+/* Same results as slash_query (bit-exact) through the batched path: every
+ * query is first hashed by the row-parallel hash kernel into an index-owned
+ * bucket-id buffer (grown on demand), then one persistent launch whose
+ * resident work-groups take queries from a device work counter answers
+ * them, with the schedule `sched` (NULL = the tuned schedule for this index,
+ * see slash_autotune).  Both launches are recorded once into a HIP graph and
+ * replayed.  Batched calls on one index share that buffer: issue them on one
+ * stream (or otherwise order them). */
 SLASH_API slash_status slash_query_batched(const slash_index* index, slash_csr queries, const uint32_t* k_per_query_dev,
                                  uint32_t k, uint32_t flags, uint32_t* ids_dev, uint32_t* scores_dev,
                                  const slash_schedule* sched, void* stream);

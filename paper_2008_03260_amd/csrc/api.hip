@@ -155,7 +155,7 @@ static slash_status check_params(const slash_params* p) {
 struct GraphSlot {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t fill = nullptr, run = nullptr;
+  hipGraphNode_t fill = nullptr, hash = nullptr, run = nullptr;
   uint32_t waves = 0, per_ticket = 0, grid = 0;
 };
 
@@ -219,6 +219,7 @@ struct slash_index {
   uint32_t* tickets = nullptr;  // ring of work counters for the batched path
   uint32_t ticket_next = 0;
   DBuf ins_keys, ins_vals, ins_k0, ins_v0, ins_k1, ins_v1, ins_hist, ins_part, ins_seg;
+  DBuf qbk;  // bucket ids of the batched path's queries [n][L]
   std::mutex mu;
   std::map<uint64_t, GraphSlot> graphs;
   // tuned schedule per query-size class (0: nnz < 64, 1: < 256, 2: < 1024, 3: larger)
@@ -548,6 +549,18 @@ extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t f
   slash_status rs;
   if (!(flags & SLASH_FLAG_TRUSTED) && (rs = validate_rows(ix, rows, nullptr, st)) != SLASH_OK) return rs;
   const Shape& s = ix->shape;
+  const uint32_t first = (uint32_t)ix->n_items;
+  if (small_insert_ok(s, n)) {
+    // three launches: hash the rows, sort per table in LDS, merge every run
+    if (!ix->ins_keys.get((size_t)n * s.L * 4) || !ix->ins_seg.get(small_insert_scratch(s, n)))
+      return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
+    HIP_TRY(launch_hash_rows(s, ix->cv, rows, ix->ins_keys.as<uint32_t>(), n, 0, st));
+    HIP_TRY(launch_insert_small(s, ix->cv, ix->ins_keys.as<uint32_t>(), (uint32_t)n, first, ix->ins_seg.p, tables(ix),
+                                st));
+    if (new_ids_dev) HIP_TRY(launch_iota_u32(new_ids_dev, first, n, st));
+    ix->n_items += n;
+    return SLASH_OK;
+  }
   const uint64_t items = n * s.L;
   if (items >= 0xFFFFFFFFull) return fail(SLASH_E_UNSUPPORTED, "insert batch too large");
   size_t hist_n = sort_hist_entries(items);
@@ -556,7 +569,6 @@ extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t f
       !ix->ins_v0.get(items * 4) || !ix->ins_k1.get(items * 4) || !ix->ins_v1.get(items * 4) ||
       !ix->ins_hist.get(hist_n * 4) || !ix->ins_part.get(part_n * 4) || !ix->ins_seg.get((2 * items + 4) * 4))
     return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
-  const uint32_t first = (uint32_t)ix->n_items;
   HIP_TRY(launch_hash_rows(s, ix->cv, rows, ix->ins_keys.as<uint32_t>(), n, 1, st));
   HIP_TRY(launch_item_ids(ix->ins_vals.as<uint32_t>(), first, n, items, st));
   SortBuffers sb{ix->ins_k0.as<uint32_t>(), ix->ins_v0.as<uint32_t>(), ix->ins_k1.as<uint32_t>(),
@@ -590,7 +602,7 @@ extern "C" slash_status slash_query(const slash_index* ix, slash_csr q, const ui
   slash_status rs = query_prelude(ix, q, kq, k, flags, ids, scores, st);
   if (rs != SLASH_OK) return rs;
   if (q.n_rows == 0) return SLASH_OK;
-  QueryArgs a{q, kq, k, 1, ids, scores};
+  QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
   HIP_TRY(launch_query(ix->shape, ix->cv, tables(ix), a, st));
   return SLASH_OK;
 }
@@ -607,9 +619,10 @@ static slash_schedule default_schedule(const slash_index* ix) {
   return sc;
 }
 
-// Graph = [reset work counter, persistent query kernel]; the kernel node's
-// arguments are updated per call.
-static slash_status run_batched(slash_index* ix, const QueryArgs& a, const slash_schedule& sc, hipStream_t st) {
+// Graph = [reset work counter, hash all queries (row-parallel), persistent
+// query kernel reading the bucket ids]; node arguments are updated per call.
+static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slash_schedule& sc, hipStream_t st) {
+  QueryArgs a = a0;
   const Shape& s = ix->shape;
   uint32_t waves = sc.waves_per_query;
   if (!query_supported(s, waves)) return fail(SLASH_E_UNSUPPORTED, "schedule with %u waves/query not supported", waves);
@@ -622,7 +635,16 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a, const slash
   if (grid > max_grid) grid = (uint32_t)std::max<uint64_t>(1, max_grid);
   uint32_t per_ticket = std::max(1u, sc.queries_per_ticket);
   std::lock_guard<std::mutex> lk(ix->mu);
+  const size_t need = (size_t)a.q.n_rows * s.L * 4;
+  if (need > ix->qbk.bytes) HIP_TRY(hipDeviceSynchronize());  // earlier launches may still read it
+  if (!ix->qbk.get(need)) return fail(SLASH_E_NOMEM, "batched bucket-id buffer");
+  a.qbk = ix->qbk.as<uint32_t>();
   uint32_t* ticket = ix->tickets + (ix->ticket_next++ % kTicketRing);
+  uint32_t hash_threads = 0;
+  size_t hash_lds = 0;
+  void* hash_fn = hash_rowmajor_kernel(s, &hash_threads, &hash_lds);
+  if (!hash_fn) return fail(SLASH_E_DEVICE, "hash kernel attributes");
+  const uint32_t hash_grid = hash_rowmajor_grid(s, a.q.n_rows);
   uint64_t gkey = ((uint64_t)waves << 48) | ((uint64_t)per_ticket << 32) | grid;
   GraphSlot& g = ix->graphs[gkey];
   Shape sh = s;
@@ -634,6 +656,15 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a, const slash
   void* run_args[] = {&sh, &cv, &tv, &qa, &per_ticket, &ticket};
   uint32_t* tk = ticket;
   void* fill_args[] = {&tk, &zero, &one};
+  slash_csr hq = a.q;
+  uint32_t* hout = const_cast<uint32_t*>(a.qbk);
+  void* hash_args[] = {&sh, &cv, &hq, &hout};
+  hipKernelNodeParams hp{};
+  hp.func = hash_fn;
+  hp.gridDim = dim3(hash_grid);
+  hp.blockDim = dim3(hash_threads);
+  hp.sharedMemBytes = (unsigned)hash_lds;
+  hp.kernelParams = hash_args;
   hipKernelNodeParams rp{};
   rp.func = persistent_query_kernel(s, waves);
   rp.gridDim = dim3(grid);
@@ -649,10 +680,12 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a, const slash
   if (!g.exec) {
     HIP_TRY(hipGraphCreate(&g.graph, 0));
     HIP_TRY(hipGraphAddKernelNode(&g.fill, g.graph, nullptr, 0, &fp));
-    HIP_TRY(hipGraphAddKernelNode(&g.run, g.graph, &g.fill, 1, &rp));
+    HIP_TRY(hipGraphAddKernelNode(&g.hash, g.graph, &g.fill, 1, &hp));
+    HIP_TRY(hipGraphAddKernelNode(&g.run, g.graph, &g.hash, 1, &rp));
     HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
   } else {
     HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.fill, &fp));
+    HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.hash, &hp));
     HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.run, &rp));
   }
   HIP_TRY(hipGraphLaunch(g.exec, st));
@@ -677,7 +710,7 @@ extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q,
         break;
       }
   }
-  QueryArgs a{q, kq, k, 1, ids, scores};
+  QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
   return run_batched(ix, a, sc, st);
 }
 
@@ -692,7 +725,7 @@ extern "C" slash_status slash_autotune(slash_index* ix, slash_csr sample, uint32
   DBuf ref_i, ref_s, got_i, got_s;
   if (!ref_i.get(n * km * 4) || !ref_s.get(n * km * 4) || !got_i.get(n * km * 4) || !got_s.get(n * km * 4))
     return fail(SLASH_E_NOMEM, "autotune buffers");
-  QueryArgs ra{sample, nullptr, k, 1, ref_i.as<uint32_t>(), ref_s.as<uint32_t>()};
+  QueryArgs ra{sample, nullptr, k, 1, ref_i.as<uint32_t>(), ref_s.as<uint32_t>(), nullptr};
   HIP_TRY(launch_query(ix->shape, ix->cv, tables(ix), ra, st));
   std::vector<uint32_t> h_ref(n * km * 2), h_got(n * km * 2);
   HIP_TRY(hipMemcpyAsync(h_ref.data(), ref_i.p, n * km * 4, hipMemcpyDeviceToHost, st));
@@ -715,7 +748,7 @@ extern "C" slash_status slash_autotune(slash_index* ix, slash_csr sample, uint32
     for (uint32_t t : tk)
       for (uint32_t g : gpc) {
         slash_schedule sc{w, t, g, 0};
-        QueryArgs ga{sample, nullptr, k, 1, got_i.as<uint32_t>(), got_s.as<uint32_t>()};
+        QueryArgs ga{sample, nullptr, k, 1, got_i.as<uint32_t>(), got_s.as<uint32_t>(), nullptr};
         rs = run_batched(ix, ga, sc, st);  // warm-up + correctness
         if (rs != SLASH_OK) continue;
         HIP_TRY(hipMemcpyAsync(h_got.data(), got_i.p, n * km * 4, hipMemcpyDeviceToHost, st));

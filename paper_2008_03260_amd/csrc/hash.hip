@@ -231,6 +231,21 @@ hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr ro
   return hipGetLastError();
 }
 
+void* hash_rowmajor_kernel(const Shape& s, uint32_t* threads, size_t* lds) {
+  const size_t fixed = (size_t)const_lds_words(s) * 4;
+  const uint32_t nw = hash_waves(s, fixed);
+  *threads = nw * SL_WAVE;
+  *lds = (size_t)nw * (SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4 + fixed;
+  const void* fn = hash_rowmajor_fn(s);
+  if (allow_lds(fn, *lds) != hipSuccess) return nullptr;
+  return const_cast<void*>(fn);
+}
+
+uint32_t hash_rowmajor_grid(const Shape& s, uint64_t n_rows) {
+  const uint32_t nw = hash_waves(s, (size_t)const_lds_words(s) * 4);
+  return grid_for(n_rows, nw * (SL_WAVE / hash_group(s.M)), 8192);
+}
+
 hipError_t launch_validate(slash_csr rows, uint32_t dim, const uint32_t* kq, uint32_t k_max, uint32_t* flag,
                            hipStream_t st) {
   if (rows.n_rows == 0) return hipSuccess;

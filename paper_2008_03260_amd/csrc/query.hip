@@ -89,7 +89,9 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   for (uint32_t e = tid; e < lay.cm_words; e += NT) cmw[e] = 0;
   for (uint32_t e = tid; e < 512; e += NT) hist[e] = 0;
   if (tid < 16) misc[tid] = 0;
-  if (wave == 0) {
+  if (a.qbk) {
+    for (uint32_t t = tid; t < s.L; t += NT) bk[t] = a.qbk[(uint64_t)q * s.L + t];
+  } else if (wave == 0) {
     const int64_t beg = a.q.indptr[q], end = a.q.indptr[q + 1];
     const uint32_t* h = doph_wave<CL>(s, c, a.q.indices + beg, (uint32_t)(end - beg), lds + lay.doph);
     for (uint32_t t = lane; t < s.L; t += SL_WAVE) bk[t] = table_bucket<CL>(s, c, h, t);

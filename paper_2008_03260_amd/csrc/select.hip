@@ -250,6 +250,106 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
   }
 }
 
+// Small insert batches (n <= kSmallInsert rows), two kernels after hashing:
+// k_insert_sort - one block per table sorts the table's (bucket, id) pairs in
+//   LDS (bitonic), finds the bucket runs with a block scan and writes the
+//   sorted pairs, the run starts and the run count to scratch;
+// k_insert_runs - one wave per run, over the whole GPU, merges the run into
+//   its reservoir.
+constexpr uint32_t kSmallInsert = 4096;
+
+__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
+    k_insert_sort(const uint32_t* __restrict__ keys, uint32_t n, uint32_t first_id, uint64_t* __restrict__ sorted,
+                  uint32_t* __restrict__ starts, uint32_t* __restrict__ runs) {
+  extern __shared__ uint64_t lds64[];
+  constexpr uint32_t NT = kSelWaves * SL_WAVE;
+  const uint32_t t = blockIdx.x;
+  uint32_t P = 1;
+  while (P < n) P <<= 1;
+  uint64_t* comp = lds64;                    // [P] (bucket << 32 | id)
+  uint32_t* scan = (uint32_t*)(lds64 + P);   // [NT + 1]
+  for (uint32_t i = threadIdx.x; i < P; i += NT)
+    comp[i] = i < n ? ((uint64_t)keys[(uint64_t)t * n + i] << 32) | (first_id + i) : ~0ull;
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += NT) {
+        uint32_t l = i ^ j;
+        if (l > i) {
+          uint64_t a = comp[i], b = comp[l];
+          bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            comp[i] = b;
+            comp[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  uint64_t* out = sorted + (uint64_t)t * n;
+  for (uint32_t i = threadIdx.x; i < n; i += NT) out[i] = comp[i];
+  // run heads -> compacted starts (each thread owns a contiguous slice)
+  const uint32_t per = (n + NT - 1) / NT;
+  const uint32_t i0 = min(n, threadIdx.x * per), i1 = min(n, i0 + per);
+  uint32_t cnt = 0;
+  for (uint32_t i = i0; i < i1; ++i) cnt += (i == 0 || (comp[i] >> 32) != (comp[i - 1] >> 32)) ? 1u : 0u;
+  scan[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t x = 0; x < NT; ++x) {
+      uint32_t v = scan[x];
+      scan[x] = acc;
+      acc += v;
+    }
+    scan[NT] = acc;
+  }
+  __syncthreads();
+  uint32_t* st = starts + (uint64_t)t * (n + 1);
+  uint32_t o = scan[threadIdx.x];
+  for (uint32_t i = i0; i < i1; ++i)
+    if (i == 0 || (comp[i] >> 32) != (comp[i - 1] >> 32)) st[o++] = i;
+  if (threadIdx.x == 0) {
+    st[scan[NT]] = n;
+    runs[t] = scan[NT];
+  }
+}
+
+// Block (t, c) merges runs [c * kSelWaves, (c + 1) * kSelWaves) of table t.
+__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
+    k_insert_runs(Shape s, ConstView c, const uint64_t* __restrict__ sorted, const uint32_t* __restrict__ starts,
+                  const uint32_t* __restrict__ runs, uint32_t n, uint32_t chunks, TablesView tab) {
+  extern __shared__ uint64_t lds64[];
+  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
+  const uint32_t t = blockIdx.x / chunks, ch = blockIdx.x - t * chunks;
+  const uint32_t g = ch * kSelWaves + wave;
+  if (g >= runs[t]) return;  // whole wave leaves together (g is wave-uniform)
+  uint64_t* my = lds64 + wave * wl_words(s.R);
+  const uint32_t* st = starts + (uint64_t)t * (n + 1);
+  const uint64_t* comp = sorted + (uint64_t)t * n;
+  const uint32_t s0 = st[g], e0 = st[g + 1];
+  const uint32_t b = (uint32_t)(comp[s0] >> 32);
+  const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  uint32_t* res = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
+  uint32_t* seen = tab.seen + (uint64_t)t * s.nb + b;
+  WaveList w = wl_init(my, s.R);
+  const uint32_t old = *seen;
+  const uint32_t fill = min(old, s.R);
+  for (uint32_t i = lane; i < fill; i += SL_WAVE) w.a[i] = prio_key(res[i], key, m1, m2);
+  w.cnt = fill;
+  wave_sync();
+  for (uint32_t i = s0; i < e0; i += SL_WAVE) {
+    uint32_t j = i + lane;
+    bool v = j < e0;
+    uint32_t id = v ? (uint32_t)comp[j] : 0u;
+    wl_offer(w, v, v ? prio_key(id, key, m1, m2) : kNoKey);
+  }
+  wl_flush(w);
+  wl_write(w, res, s.R);
+  if (lane == 0) *seen = old + (e0 - s0);
+}
+
 uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap) {
   uint64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -283,6 +383,36 @@ hipError_t launch_select_final(const Shape& s, const ConstView& c, uint32_t t, c
   size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
   hipLaunchKernelGGL(k_select_final, dim3(grid_for(n_work, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st,
                      s, c, t, src, work, n_work, tab);
+  return hipGetLastError();
+}
+
+size_t small_insert_lds(uint32_t n) {
+  uint32_t P = 1;
+  while (P < n) P <<= 1;
+  constexpr uint32_t NT = kSelWaves * SL_WAVE;
+  return (size_t)P * 8 + (NT + 1) * 4;
+}
+
+bool small_insert_ok(const Shape& s, uint64_t n) { return n >= 1 && n <= kSmallInsert; }
+
+size_t small_insert_scratch(const Shape& s, uint64_t n) {
+  return (size_t)s.L * n * 8 + (size_t)s.L * (n + 1) * 4 + (size_t)s.L * 4 + 64;
+}
+
+hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
+                               void* scratch, TablesView tab, hipStream_t st) {
+  uint64_t* sorted = (uint64_t*)scratch;
+  uint32_t* starts = (uint32_t*)(sorted + (size_t)s.L * n);
+  uint32_t* runs = starts + (size_t)s.L * (n + 1);
+  size_t lds = small_insert_lds(n);
+  hipLaunchKernelGGL(k_insert_sort, dim3(s.L), dim3(kSelWaves * SL_WAVE), lds, st, keys, n, first_id, sorted, starts,
+                     runs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t chunks = (n + kSelWaves - 1) / kSelWaves;
+  size_t l2 = (size_t)kSelWaves * wl_words(s.R) * 8;
+  hipLaunchKernelGGL(k_insert_runs, dim3(s.L * chunks), dim3(kSelWaves * SL_WAVE), l2, st, s, c, sorted, starts, runs,
+                     n, chunks, tab);
   return hipGetLastError();
 }
 

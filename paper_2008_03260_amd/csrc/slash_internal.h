@@ -184,6 +184,12 @@ struct FinalWork {
 hipError_t launch_select_final(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
                                const FinalWork* work, uint32_t n_work, TablesView tab, hipStream_t st);
 
+// Small insert (n rows, keys [L][n] as written by launch_hash_rows without
+// combining): one block per table sorts, groups and merges in LDS.
+bool small_insert_ok(const Shape& s, uint64_t n);
+size_t small_insert_scratch(const Shape& s, uint64_t n);
+hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
+                               void* scratch, TablesView tab, hipStream_t st);
 // Insert merge: sorted combined keys (t*nb+b) with new ids -> merged reservoirs.
 hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys,
                                const uint32_t* svals, uint64_t n, uint32_t* seg_scratch,
@@ -197,7 +203,12 @@ struct QueryArgs {
   uint32_t clamp;  // 1: clamp k to k_max
   uint32_t* out_ids;
   uint32_t* out_scores;
+  const uint32_t* qbk;  // bucket ids [n][L] hashed beforehand, or NULL (hash in the query kernel)
 };
+// Kernel entry of the row-major hash kernel for this shape and its launch
+// geometry (for HIP graph nodes): (Shape, ConstView, slash_csr, uint32_t* out).
+void* hash_rowmajor_kernel(const Shape& s, uint32_t* threads, size_t* lds);
+uint32_t hash_rowmajor_grid(const Shape& s, uint64_t n_rows);
 int query_block_threads(const Shape& s, uint32_t waves);
 size_t query_lds_bytes(const Shape& s, uint32_t waves);
 bool query_supported(const Shape& s);

@@ -271,3 +271,15 @@ def test_tiny_config_end_to_end(api):
     assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
     recall = np.mean([s in r for s, r in zip(src.tolist(), u32(gi).tolist())])
     assert recall >= 0.9
+
+
+def test_insert_large_batch_path(api):
+    # batches above 4096 rows take the sort-based insert path
+    gp, op = params_pair(api, L=5, log2_buckets=7, R=9)
+    _, (ip, ix) = rows_of(15000, seed=12)
+    n0 = 2000
+    idx = api.Index(gp, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    for a, b in ((n0, 8000), (8000, 8001), (8001, 15000)):
+        idx.insert(dev(ip[a: b + 1] - ip[a]), dev(ix[ip[a]: ip[b]]))
+    torch.cuda.synchronize()
+    check_tables(api, idx, op, oracle.constants(op), ip, ix)
