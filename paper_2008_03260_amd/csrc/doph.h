@@ -203,6 +203,103 @@ __device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const Cons
   return lds_h;
 }
 
+// Register form of doph_group for mode 0, for M = G * P with P in {4, 8, 16}
+// and K dividing P: lane gl of a group owns the P consecutive bins
+// [gl * P, gl * P + P) and with them P / K whole tables.  The minima are taken
+// with LDS atomics as in doph_group; densification then runs in registers.
+// For each bin the nearest non-empty bin on its right / left is either in
+// the lane's own chunk or is the first / last non-empty bin of the nearest
+// lane (circularly) whose chunk has one; that lane is found with one ballot
+// and its value fetched with one shuffle.  This is the same result as the
+// bin-by-bin circular walk over the pre-densification minima (a lane that
+// holds the only non-empty bins wraps onto itself).  Returns h, the P
+// densified values of the lane's bins.  Every lane of the wave must call.
+template <int G, int P, bool CL>
+__device__ __forceinline__ void doph_regs(const Shape& s, const ConstView& c, const int32_t* __restrict__ idx,
+                                          uint32_t nnz, uint32_t* lds_m, uint32_t (&h)[P]) {
+  static_assert(P == 4 || P == 8 || P == 16, "bins per lane");
+  const uint32_t lane = lane_id();
+  const uint32_t gl = lane & (G - 1);
+  const uint32_t gshift = lane & ~(uint32_t)(G - 1);
+  const uint32_t b0 = gl * P;
+  typedef __attribute__((address_space(3))) uint32_t lw32;
+  lw32* m3 = (lw32*)lds_m;
+#pragma unroll
+  for (int j = 0; j < P; ++j) m3[b0 + j] = SL_EMPTY;
+  wave_sync();
+  {
+    const uint64_t a = cld64<CL>(c.a_h, 0), bb = cld64<CL>(c.b_h, 0);
+    for (uint32_t e = gl; e < nnz; e += G) {
+      uint32_t u = nz_hash(a, bb, (uint32_t)idx[e]);
+      uint32_t bin = s.mshift == 0xFFu ? range_bin(u, s.M) : (s.mshift ? u >> (32 - s.mshift) : 0u);
+      atomicMin(&lds_m[bin], u);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < P; ++j) h[j] = m3[b0 + j];
+  uint32_t first = SL_EMPTY, last = SL_EMPTY;
+#pragma unroll
+  for (int j = P - 1; j >= 0; --j)
+    if (h[j] != SL_EMPTY) first = h[j];
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    if (h[j] != SL_EMPTY) last = h[j];
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+  const uint64_t bal = (ballot64(first != SL_EMPTY) >> gshift) & gmask;
+  // rotate so that bit i stands for lane (gl + i) mod G
+  const uint64_t rot = gl ? (((bal >> gl) | (bal << (G - gl))) & gmask) : bal;
+  const uint64_t after = rot & ~1ull;
+  const uint32_t up = after ? (gl + (uint32_t)__builtin_ctzll(after)) & (G - 1) : gl;
+  const uint32_t down = rot ? (gl + 63u - (uint32_t)__builtin_clzll(rot)) & (G - 1) : gl;
+  const uint32_t next_v = (uint32_t)__shfl(first, (int)(gshift + up), SL_WAVE);
+  const uint32_t prev_v = (uint32_t)__shfl(last, (int)(gshift + down), SL_WAVE);
+  uint32_t r[P];
+  uint32_t carry = next_v;
+#pragma unroll
+  for (int j = P - 1; j >= 0; --j) {
+    r[j] = carry;
+    if (h[j] != SL_EMPTY) carry = h[j];
+  }
+  const uint32_t dirs = cld32<CL>(c.dirw, b0 >> 5) >> (b0 & 31);
+  carry = prev_v;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const uint32_t v = h[j];
+    if (v != SL_EMPTY)
+      carry = v;
+    else
+      h[j] = ((dirs >> j) & 1u) ? r[j] : carry;
+  }
+}
+
+// Whether doph_regs applies to the shape with G lanes per row.
+__host__ __device__ inline uint32_t doph_regs_p(const Shape& s, uint32_t G) {
+  if (s.mode != 0 || s.M % G) return 0;
+  const uint32_t P = s.M / G;
+  if (P != 4 && P != 8 && P != 16) return 0;
+  return (s.K <= P && P % s.K == 0) ? P : 0;
+}
+
+// Bucket ids of the P / K tables owned by lane gl (doph_regs layout):
+// emit(t, bucket) for each, in table order.
+template <int P, bool CL, class Emit>
+__device__ __forceinline__ void table_buckets_regs(const Shape& s, const ConstView& c, const uint32_t (&h)[P],
+                                                   uint32_t gl, Emit emit) {
+  const uint32_t b0 = gl * P;
+  const uint32_t kmask = s.K - 1, kshift = (uint32_t)__builtin_ctz(s.K);  // K is a power of two here
+  uint64_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    acc += cld64<CL>(c.a_tj, b0 + j) * (uint64_t)h[j];
+    if (((j + 1) & kmask) == 0) {
+      const uint32_t t = (b0 + j) >> kshift;
+      emit(t, (uint32_t)((acc + cld64<CL>(c.b_t, t)) >> (64 - s.B)));
+      acc = 0;
+    }
+  }
+}
+
 template <bool CL>
 __device__ __forceinline__ const uint32_t* doph_wave(const Shape& s, const ConstView& c,
                                                      const int32_t* __restrict__ idx, uint32_t nnz,

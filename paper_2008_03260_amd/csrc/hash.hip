@@ -10,26 +10,44 @@ constexpr int kMaxHashWaves = 4;
 
 __host__ __device__ inline bool const_staged(const Shape& s) { return const_words(s) <= kConstCapWords; }
 
-// Each block takes chunks of `rpc` consecutive rows; each wave hashes one row
-// at a time and stages its L bucket ids in LDS; the block then writes every
-// table's rpc ids as one contiguous run (keys are table-major).
+// LDS words of one group's DOPH scratch: the register form needs only the
+// minima.
+__host__ __device__ inline uint32_t group_lds_words(const Shape& s, int P) {
+  return P ? s.M : doph_lds_words(s.M);
+}
+
+// Hash one row with a group of G lanes and call emit(t, bucket) for its L
+// tables (P > 0: register densification with P bins per lane, else the
+// generic LDS walk).  Every lane of the wave calls.
+template <int G, int P, bool CL, class Emit>
+__device__ __forceinline__ void hash_row(const Shape& s, const ConstView& c, const int32_t* idx, uint32_t nnz,
+                                         bool live, uint32_t* my, Emit emit) {
+  const uint32_t gl = threadIdx.x & (G - 1);
+  if constexpr (P > 0) {
+    uint32_t h[P];
+    doph_regs<G, P, CL>(s, c, idx, nnz, my, h);
+    if (live) table_buckets_regs<P, CL>(s, c, h, gl, emit);
+  } else {
+    const uint32_t* h = doph_group<G, CL>(s, c, idx, nnz, my);
+    if (live)
+      for (uint32_t t = gl; t < s.L; t += G) emit(t, table_bucket<CL>(s, c, h, t));
+  }
+  wave_sync();
+}
+
 // Each block takes chunks of `rpc` consecutive rows; a group of G lanes
 // hashes one row at a time (64 / G rows per wave at once) and stages its L
 // bucket ids in LDS; the block then writes every table's rpc ids as one
 // contiguous run (keys are table-major).
-// Each block takes chunks of `rpc` consecutive rows; a group of G lanes
-// hashes one row at a time (64 / G rows per wave at once) and stages its L
-// bucket ids in LDS; the block then writes every table's rpc ids as one
-// contiguous run (keys are table-major).
-template <int G, bool CL>
+template <int G, int P, bool CL>
 __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
     k_hash_rows(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ keys, uint64_t key_stride,
                 int combine, uint32_t rpc) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t GPW = SL_WAVE / G;  // groups per wave
   const uint32_t ng = (blockDim.x / SL_WAVE) * GPW;
-  const uint32_t grp = threadIdx.x / G, gl = threadIdx.x & (G - 1);
-  const uint32_t per_grp = doph_lds_words(s.M);
+  const uint32_t grp = threadIdx.x / G;
+  const uint32_t per_grp = group_lds_words(s, P);
   const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
   const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
   uint32_t* my = lds + cw + grp * per_grp;
@@ -49,13 +67,9 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
         beg = rows.indptr[r];
         end = rows.indptr[r + 1];
       }
-      const uint32_t* h = doph_group<G, CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
-      if (live)
-        for (uint32_t t = gl; t < s.L; t += G) {
-          uint32_t b = table_bucket<CL>(s, cl, h, t);
-          stage[t * rpc + rl] = combine ? t * s.nb + b : b;
-        }
-      wave_sync();
+      hash_row<G, P, CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), live, my, [&](uint32_t t, uint32_t b) {
+        stage[t * rpc + rl] = combine ? t * s.nb + b : b;
+      });
     }
     __syncthreads();
     const uint32_t tot = s.L * rpc;
@@ -67,16 +81,16 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
   }
 }
 
-template <int G, bool CL>
+template <int G, int P, bool CL>
 __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
     k_hash_rowmajor(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ out) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t GPW = SL_WAVE / G;
   const uint32_t ng = (blockDim.x / SL_WAVE) * GPW;
-  const uint32_t grp = threadIdx.x / G, gl = threadIdx.x & (G - 1);
+  const uint32_t grp = threadIdx.x / G;
   const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
   const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
-  uint32_t* my = lds + cw + grp * doph_lds_words(s.M);
+  uint32_t* my = lds + cw + grp * group_lds_words(s, P);
   __syncthreads();
   const uint64_t n = rows.n_rows;
   const uint64_t stride = (uint64_t)gridDim.x * ng;
@@ -89,10 +103,8 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
       beg = rows.indptr[r];
       end = rows.indptr[r + 1];
     }
-    const uint32_t* h = doph_group<G, CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), my);
-    if (live)
-      for (uint32_t t = gl; t < s.L; t += G) out[r * s.L + t] = table_bucket<CL>(s, cl, h, t);
-    wave_sync();
+    hash_row<G, P, CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), live, my,
+                       [&](uint32_t t, uint32_t b) { out[r * s.L + t] = b; });
   }
 }
 
@@ -109,29 +121,60 @@ uint32_t hash_rpc(const Shape& s) {
   return r;
 }
 
+// Bins per lane of the register DOPH form for this shape, or 0 (generic).
+int hash_p(const Shape& s) { return (int)doph_regs_p(s, hash_group(s.M)); }
+
 // Waves per block such that the block's LDS fits (64 / G rows per wave).
 uint32_t hash_waves(const Shape& s, size_t fixed) {
-  const size_t per_wave = (size_t)(SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4;
+  const size_t per_wave = (size_t)(SL_WAVE / hash_group(s.M)) * group_lds_words(s, hash_p(s)) * 4;
   for (uint32_t w = kMaxHashWaves; w > 1; w >>= 1)
     if (w * per_wave + fixed <= kLdsCap) return w;
   return 1;
 }
 
+// LDS bytes of a hash block with nw waves and `fixed` bytes ahead of the
+// per-group scratch.
+size_t hash_lds(const Shape& s, uint32_t nw, size_t fixed) {
+  return (size_t)nw * (SL_WAVE / hash_group(s.M)) * group_lds_words(s, hash_p(s)) * 4 + fixed;
+}
+
+template <int G, bool CL>
+const void* rows_fn_p(int P) {
+  switch (P) {
+    case 4: return (const void*)k_hash_rows<G, 4, CL>;
+    case 8: return (const void*)k_hash_rows<G, 8, CL>;
+    case 16: return (const void*)k_hash_rows<G, 16, CL>;
+    default: return (const void*)k_hash_rows<G, 0, CL>;
+  }
+}
+
+template <int G, bool CL>
+const void* rowmajor_fn_p(int P) {
+  switch (P) {
+    case 4: return (const void*)k_hash_rowmajor<G, 4, CL>;
+    case 8: return (const void*)k_hash_rowmajor<G, 8, CL>;
+    case 16: return (const void*)k_hash_rowmajor<G, 16, CL>;
+    default: return (const void*)k_hash_rowmajor<G, 0, CL>;
+  }
+}
+
 const void* hash_rows_fn(const Shape& s) {
   const bool cl = const_staged(s);
+  const int P = hash_p(s);
   switch (hash_group(s.M)) {
-    case 16: return cl ? (const void*)k_hash_rows<16, true> : (const void*)k_hash_rows<16, false>;
-    case 32: return cl ? (const void*)k_hash_rows<32, true> : (const void*)k_hash_rows<32, false>;
-    default: return cl ? (const void*)k_hash_rows<64, true> : (const void*)k_hash_rows<64, false>;
+    case 16: return cl ? rows_fn_p<16, true>(P) : rows_fn_p<16, false>(P);
+    case 32: return cl ? rows_fn_p<32, true>(P) : rows_fn_p<32, false>(P);
+    default: return cl ? rows_fn_p<64, true>(P) : rows_fn_p<64, false>(P);
   }
 }
 
 const void* hash_rowmajor_fn(const Shape& s) {
   const bool cl = const_staged(s);
+  const int P = hash_p(s);
   switch (hash_group(s.M)) {
-    case 16: return cl ? (const void*)k_hash_rowmajor<16, true> : (const void*)k_hash_rowmajor<16, false>;
-    case 32: return cl ? (const void*)k_hash_rowmajor<32, true> : (const void*)k_hash_rowmajor<32, false>;
-    default: return cl ? (const void*)k_hash_rowmajor<64, true> : (const void*)k_hash_rowmajor<64, false>;
+    case 16: return cl ? rowmajor_fn_p<16, true>(P) : rowmajor_fn_p<16, false>(P);
+    case 32: return cl ? rowmajor_fn_p<32, true>(P) : rowmajor_fn_p<32, false>(P);
+    default: return cl ? rowmajor_fn_p<64, true>(P) : rowmajor_fn_p<64, false>(P);
   }
 }
 
@@ -200,7 +243,7 @@ hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, 
   const uint32_t rpc = hash_rpc(s);
   const size_t stage = (size_t)s.L * rpc * 4 + (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, stage);
-  const size_t lds = (size_t)nw * (SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4 + stage;
+  const size_t lds = hash_lds(s, nw, stage);
   const void* fn = hash_rows_fn(s);
   hipError_t e = allow_lds(fn, lds);
   if (e != hipSuccess) return e;
@@ -218,7 +261,7 @@ hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr ro
   if (rows.n_rows == 0) return hipSuccess;
   const size_t fixed = (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, fixed);
-  const size_t lds = (size_t)nw * (SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4 + fixed;
+  const size_t lds = hash_lds(s, nw, fixed);
   const void* fn = hash_rowmajor_fn(s);
   hipError_t e = allow_lds(fn, lds);
   if (e != hipSuccess) return e;
@@ -235,7 +278,7 @@ void* hash_rowmajor_kernel(const Shape& s, uint32_t* threads, size_t* lds) {
   const size_t fixed = (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, fixed);
   *threads = nw * SL_WAVE;
-  *lds = (size_t)nw * (SL_WAVE / hash_group(s.M)) * doph_lds_words(s.M) * 4 + fixed;
+  *lds = hash_lds(s, nw, fixed);
   const void* fn = hash_rowmajor_fn(s);
   if (allow_lds(fn, *lds) != hipSuccess) return nullptr;
   return const_cast<void*>(fn);

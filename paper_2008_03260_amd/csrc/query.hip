@@ -7,7 +7,8 @@
 //   2. every thread gathers reservoir slots (table t, slot j) of the probed
 //      buckets straight from HBM (coalesced R-slot rows; EMPTY slots skipped);
 //   3. count-min: d rows of w 16-bit counters in LDS, incremented with LDS
-//      atomics (a counter never exceeds L * R <= 65535);
+//      atomics (a counter never exceeds L * R <= 65535); when the d rows do
+//      not fit in LDS together they are counted one row per pass;
 //   4. estimate = min over rows; duplicates of an id are folded by an LDS
 //      open-addressing set so each distinct id is ranked once;
 //   5. the k-th largest key (estimate << 32 | ~id) is found by an MSD radix
@@ -24,7 +25,7 @@ constexpr uint32_t kMaxSpt = 16;     // reservoir slots per thread
 
 struct QLayout {
   uint32_t cst, doph, buckets, cm, hist, sel, misc, total;  // offsets in 32-bit words
-  uint32_t cm_words, hs_size, cst_words;
+  uint32_t cm_words, hs_size, cst_words, rows_pass;
   bool cst_fit;
 };
 
@@ -33,6 +34,8 @@ __host__ __device__ inline uint32_t next_pow2(uint32_t x) {
   while (p < x) p <<= 1;
   return p;
 }
+
+constexpr uint32_t kLdsWords = 160 * 1024 / 4;  // LDS of one CU
 
 __host__ __device__ inline QLayout q_layout(const Shape& s) {
   QLayout o;
@@ -43,9 +46,23 @@ __host__ __device__ inline QLayout q_layout(const Shape& s) {
   o.doph = o.cst + (o.cst_fit ? ((o.cst_words + 1) & ~1u) : 0u);
   o.buckets = o.doph + 2 * s.M + ((s.M + 63) / 64) * 2;
   o.cm = o.buckets + s.L;
-  o.cm_words = (s.d * w + 1) / 2;
-  o.hs_size = next_pow2(2 * s.L * s.R);
+  const uint32_t tail = 512 + 2 + 2 * s.k_max + 16;  // hist, alignment, sel, misc
+  const uint32_t room = kLdsWords > o.cm + tail ? kLdsWords - (o.cm + tail) : 0u;
+  // The id set holds at most L * R distinct ids: twice that (load <= 1/2)
+  // when it fits, else the next power of two (a full set still terminates).
+  const uint32_t slots = s.L * s.R;
+  o.hs_size = next_pow2(2 * slots);
+  if (o.hs_size > room && next_pow2(slots) <= room) o.hs_size = next_pow2(slots);
   if (o.hs_size < 64) o.hs_size = 64;
+  // All d sketch rows stay resident when they fit; otherwise the rows are
+  // counted one at a time (each pass clears, counts and folds one row into
+  // the running minimum).
+  o.rows_pass = s.d;
+  o.cm_words = (s.d * w + 1) / 2;
+  if (o.cm_words > room) {
+    o.rows_pass = 1;
+    o.cm_words = (w + 1) / 2;
+  }
   // the id set reuses the count-min region once the estimates are read
   uint32_t region = o.cm_words > o.hs_size ? o.cm_words : o.hs_size;
   o.hist = o.cm + region;
@@ -108,33 +125,41 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
     }
   }
-  for (uint32_t r = 0; r < s.d; ++r) {
-    const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
-#pragma unroll
-    for (int i = 0; i < SPT; ++i) {
-      if (id[i] != SL_EMPTY) {
-        uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
-        atomicAdd(&cmw[g >> 1], 1u << ((g & 1u) * 16));
-      }
-    }
-  }
-  __syncthreads();
-  // 2. estimates (min over rows), kept in the high half of the sort key
+  // 2. estimates (min over rows), kept in the high half of the sort key;
+  //    the rows are counted in passes of lay.rows_pass rows
   uint32_t est[SPT];
 #pragma unroll
   for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
-  for (uint32_t r = 0; r < s.d; ++r) {
-    const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
-#pragma unroll
-    for (int i = 0; i < SPT; ++i) {
-      uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
-      est[i] = min(est[i], (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu);
+  for (uint32_t r0 = 0; r0 < s.d; r0 += lay.rows_pass) {
+    const uint32_t r1 = min(s.d, r0 + lay.rows_pass);
+    if (r0 > 0) {  // the first pass was cleared with the other state
+      for (uint32_t e = tid; e < lay.cm_words; e += NT) cmw[e] = 0;
+      __syncthreads();
     }
+    for (uint32_t r = r0; r < r1; ++r) {
+      const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) {
+        if (id[i] != SL_EMPTY) {
+          uint32_t g = ((r - r0) << s.lw) + cm_hash(ar, br, id[i], s.lw);
+          atomicAdd(&cmw[g >> 1], 1u << ((g & 1u) * 16));
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t r = r0; r < r1; ++r) {
+      const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) {
+        uint32_t g = ((r - r0) << s.lw) + cm_hash(ar, br, id[i], s.lw);
+        est[i] = min(est[i], (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu);
+      }
+    }
+    __syncthreads();
   }
   uint64_t key[SPT];
 #pragma unroll
   for (int i = 0; i < SPT; ++i) key[i] = id[i] != SL_EMPTY ? ((uint64_t)est[i] << 32) | (uint32_t)~id[i] : 0ull;
-  __syncthreads();
   // 3. distinct ids: the first insertion into the LDS id set represents the id
   for (uint32_t e = tid; e < lay.hs_size; e += NT) hs[e] = SL_EMPTY;
   __syncthreads();
@@ -358,7 +383,7 @@ size_t query_lds_bytes(const Shape& s, uint32_t waves) {
 bool query_supported(const Shape& s, uint32_t waves) {
   if (!pick(s, waves)) return false;
   if (s.L * s.R > 65535u) return false;
-  return query_lds_bytes(s, waves) <= 160 * 1024;
+  return query_lds_bytes(s, waves) <= (size_t)kLdsWords * 4;
 }
 
 bool query_supported(const Shape& s) { return query_supported(s, query_default_waves(s)); }

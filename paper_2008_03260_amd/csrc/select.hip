@@ -93,7 +93,6 @@ __device__ __forceinline__ void wl_flush(WaveList& w) {
 
 // Offer one key per lane (valid lanes only).
 __device__ __forceinline__ void wl_offer(WaveList& w, bool valid, uint64_t key) {
-  const uint32_t lane = lane_id();
   uint64_t thr = w.cnt < w.R ? kNoKey : w.a[w.R - 1];
   bool pass = valid && (w.cnt < w.R || key < thr);
   uint64_t m = ballot64(pass);

@@ -105,6 +105,16 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int nbits, uint64_t 
   return m;
 }
 
+// Work-groups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Map block b to a tile so that every XCD works through one contiguous range
+// of tiles; a bijection on [0, n) for any n.  Neighbouring tiles then share
+// an L2, so their partial-line writes to the same output run merge there.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t x = b % kXcds, i = b / kXcds, q = n / kXcds, r = n % kXcds;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Record the thread-local error text and return s.
 slash_status fail(slash_status s, const char* fmt, ...);
 

@@ -6,7 +6,8 @@
 // wave ranks 64 keys at once by matching digits with ballots; waves own
 // consecutive sub-tiles), stages them in LDS in digit order and writes each
 // digit's run contiguously.  No global atomics, so the output is
-// deterministic.
+// deterministic.  The scatter visits tiles in XCD-contiguous order so that
+// the short runs that neighbouring tiles write for one digit meet in one L2.
 #include "slash_internal.h"
 
 namespace slash {
@@ -75,6 +76,7 @@ __global__ void __launch_bounds__(kThreads)
                 uint32_t* __restrict__ vout) {
   __shared__ uint32_t wcnt[kWaves][256];
   __shared__ uint32_t tile_off[256];
+  __shared__ uint32_t goff[256];  // output offset of the digit's run, minus its tile offset
   __shared__ uint32_t scan_sh[kWaves];
   __shared__ uint32_t sk[kTile];
   __shared__ uint32_t sv[kTile];
@@ -82,7 +84,8 @@ __global__ void __launch_bounds__(kThreads)
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
   for (uint32_t e = threadIdx.x; e < kWaves * 256; e += kThreads) (&wcnt[0][0])[e] = 0;
   __syncthreads();
-  const uint64_t tbase = (uint64_t)blockIdx.x * kTile;
+  const uint32_t tile = xcd_tile(blockIdx.x, n_tiles);
+  const uint64_t tbase = (uint64_t)tile * kTile;
   const uint64_t sbase = tbase + (uint64_t)wave * kSubTile;
   uint32_t key[kRounds], val[kRounds], loc[kRounds];
 #pragma unroll
@@ -116,7 +119,10 @@ __global__ void __launch_bounds__(kThreads)
   }
   uint32_t total;
   uint32_t off = block_excl_scan(tot_d, scan_sh, &total);
-  if (threadIdx.x < 256) tile_off[threadIdx.x] = off;
+  if (threadIdx.x < nd) {
+    tile_off[threadIdx.x] = off;
+    goff[threadIdx.x] = offs[(uint64_t)threadIdx.x * n_tiles + tile] - off;
+  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -133,7 +139,7 @@ __global__ void __launch_bounds__(kThreads)
   for (uint32_t p = threadIdx.x; p < tn; p += kThreads) {
     uint32_t k = sk[p];
     uint32_t d = (k >> shift) & dmask;
-    uint64_t g = (uint64_t)offs[(uint64_t)d * n_tiles + blockIdx.x] + (p - tile_off[d]);
+    uint32_t g = goff[d] + p;
     kout[g] = k;
     vout[g] = sv[p];
   }

@@ -283,3 +283,35 @@ def test_insert_large_batch_path(api):
         idx.insert(dev(ip[a: b + 1] - ip[a]), dev(ix[ip[a]: ip[b]]))
     torch.cuda.synchronize()
     check_tables(api, idx, op, oracle.constants(op), ip, ix)
+
+
+@pytest.mark.parametrize("log2_buckets", [12, 6], ids=["B12", "B6-full-reservoirs"])
+def test_wide_config_end_to_end(api, log2_buckets):
+    # wide configuration at 20000 rows: D = 2^24, nnz ~ lognormal(median 500,
+    # sigma 0.8) clipped to [50, 20000], uniform indices; K=8, L=128, R=128,
+    # count-min 8 x 16384 (counted one row per pass), k in {1, 10, 100}.  The
+    # tables are kept at 2^12 buckets so the host copy stays small (2^18 is
+    # covered by the hash test); with 2^6 buckets every reservoir is full and
+    # a query aggregates 16384 slots.
+    master = 2024
+    gp, op = params_pair(api, k_max=100, dim=1 << 24, K=8, L=128, log2_buckets=log2_buckets, R=128, cm_rows=8,
+                         log2_cm_width=14, seed=synth.derive(master, synth.STREAM_INDEX))
+    law = synth.RowLaw(synth.derive(master, synth.STREAM_DATA), 1 << 24, index="uniform", nnz="lognormal",
+                       nnz_a=500.0, nnz_b=0.8, nnz_lo=50, nnz_hi=20000)
+    n = 20000
+    ip, ix = law.rows(0, n)
+    qi, qx, src, kq = law.queries(synth.derive(master, synth.STREAM_QUERY), n, 0, 48, nnz_mode="lognormal",
+                                  median=500, sigma=0.8, lo=50, hi=20000, f=(0.1, 0.4), kmix=(1, 10, 100))
+    idx = api.Index(gp, dev(ip[: 15001]), dev(ix[: ip[15000]]))
+    idx.insert(dev(ip[15000:] - ip[15000]), dev(ix[ip[15000]:]))
+    cs = oracle.constants(op)
+    check_tables(api, idx, op, cs, ip, ix)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=100, kq=kq)
+    gi, gs = idx.query(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+    bi, bs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
+    torch.cuda.synchronize()
+    assert (u32(bi) == wi).all() and (u32(bs) == ws).all()
+    if log2_buckets == 6:
+        assert int(oseen.min()) > 128  # every reservoir full
