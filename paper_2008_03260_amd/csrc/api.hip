@@ -603,7 +603,11 @@ extern "C" slash_status slash_query(const slash_index* ix, slash_csr q, const ui
   if (rs != SLASH_OK) return rs;
   if (q.n_rows == 0) return SLASH_OK;
   QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
-  HIP_TRY(launch_query(ix->shape, ix->cv, tables(ix), a, st));
+  // A batch too small to occupy the GPU runs each query with 16 waves
+  // (shorter per-query latency); larger batches use the default width.
+  uint32_t waves = query_default_waves(ix->shape);
+  if (q.n_rows * 2 <= (uint64_t)ix->n_cu && query_supported(ix->shape, 16)) waves = 16;
+  HIP_TRY(launch_query_waves(ix->shape, ix->cv, tables(ix), a, waves, st));
   return SLASH_OK;
 }
 

@@ -6,9 +6,9 @@
 //   1. wave 0 hashes the query (DOPH) into its L bucket ids;
 //   2. every thread gathers reservoir slots (table t, slot j) of the probed
 //      buckets straight from HBM (coalesced R-slot rows; EMPTY slots skipped);
-//   3. count-min: d rows of w 16-bit counters in LDS, incremented with LDS
-//      atomics (a counter never exceeds L * R <= 65535); when the d rows do
-//      not fit in LDS together they are counted one row per pass;
+//   3. count-min: d rows of w counters in LDS, incremented with LDS atomics;
+//      8-bit counters, and a 16-bit recount one row at a time for a query
+//      whose counts overflow a byte (a counter never exceeds L * R <= 65535);
 //   4. estimate = min over rows; duplicates of an id are folded by an LDS
 //      open-addressing set so each distinct id is ranked once;
 //   5. the k-th largest key (estimate << 32 | ~id) is found by an MSD radix
@@ -25,7 +25,7 @@ constexpr uint32_t kMaxSpt = 16;     // reservoir slots per thread
 
 struct QLayout {
   uint32_t cst, doph, buckets, cm, hist, sel, misc, total;  // offsets in 32-bit words
-  uint32_t cm_words, hs_size, cst_words, rows_pass;
+  uint32_t cm_words, cm16_words, hs_size, cst_words, tie_cap;
   bool cst_fit;
 };
 
@@ -46,6 +46,7 @@ __host__ __device__ inline QLayout q_layout(const Shape& s) {
   o.doph = o.cst + (o.cst_fit ? ((o.cst_words + 1) & ~1u) : 0u);
   o.buckets = o.doph + 2 * s.M + ((s.M + 63) / 64) * 2;
   o.cm = o.buckets + s.L;
+  if (o.cm & 1) o.cm++;  // 8-byte aligned: ranked keys are collected here
   const uint32_t tail = 512 + 2 + 2 * s.k_max + 16;  // hist, alignment, sel, misc
   const uint32_t room = kLdsWords > o.cm + tail ? kLdsWords - (o.cm + tail) : 0u;
   // The id set holds at most L * R distinct ids: twice that (load <= 1/2)
@@ -54,17 +55,17 @@ __host__ __device__ inline QLayout q_layout(const Shape& s) {
   o.hs_size = next_pow2(2 * slots);
   if (o.hs_size > room && next_pow2(slots) <= room) o.hs_size = next_pow2(slots);
   if (o.hs_size < 64) o.hs_size = 64;
-  // All d sketch rows stay resident when they fit; otherwise the rows are
-  // counted one at a time (each pass clears, counts and folds one row into
-  // the running minimum).
-  o.rows_pass = s.d;
-  o.cm_words = (s.d * w + 1) / 2;
-  if (o.cm_words > room) {
-    o.rows_pass = 1;
-    o.cm_words = (w + 1) / 2;
-  }
+  // The sketch is counted with 8-bit counters, all d rows resident; a query
+  // whose counts overflow a byte is recounted with 16-bit counters, one row
+  // at a time, in the same region.
+  o.cm_words = (s.d * w + 3) / 4;
+  o.cm16_words = (w + 1) / 2;
   // the id set reuses the count-min region once the estimates are read
-  uint32_t region = o.cm_words > o.hs_size ? o.cm_words : o.hs_size;
+  uint32_t region = o.cm_words > o.cm16_words ? o.cm_words : o.cm16_words;
+  if (o.hs_size > region) region = o.hs_size;
+  // keys with the kk-th estimate or above, ranked directly when at most this
+  // many (collected into the count-min region, free by then)
+  o.tie_cap = region / 2 < 128 ? region / 2 : 128;
   o.hist = o.cm + region;
   o.sel = o.hist + 512;
   if (o.sel & 1) o.sel++;
@@ -125,37 +126,70 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
     }
   }
-  // 2. estimates (min over rows), kept in the high half of the sort key;
-  //    the rows are counted in passes of lay.rows_pass rows
+  // 2. count-min with 8-bit counters.  Every live slot adds one to each of
+  //    the d rows, so without overflow the counters sum to d * live; an
+  //    increment that wraps a byte loses 255 or 256 from that sum.  A query
+  //    whose sum falls short is recounted with 16-bit counters (one row per
+  //    pass; a counter never exceeds L * R <= 65535).  The estimate (min over
+  //    rows) goes into the high half of the sort key.
   uint32_t est[SPT];
 #pragma unroll
   for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
-  for (uint32_t r0 = 0; r0 < s.d; r0 += lay.rows_pass) {
-    const uint32_t r1 = min(s.d, r0 + lay.rows_pass);
-    if (r0 > 0) {  // the first pass was cleared with the other state
-      for (uint32_t e = tid; e < lay.cm_words; e += NT) cmw[e] = 0;
-      __syncthreads();
-    }
-    for (uint32_t r = r0; r < r1; ++r) {
+  {
+    uint32_t live = 0;
+    for (uint32_t r = 0; r < s.d; ++r) {
       const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
         if (id[i] != SL_EMPTY) {
-          uint32_t g = ((r - r0) << s.lw) + cm_hash(ar, br, id[i], s.lw);
-          atomicAdd(&cmw[g >> 1], 1u << ((g & 1u) * 16));
+          const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+          atomicAdd(&cmw[g >> 2], 1u << ((g & 3u) * 8));
         }
       }
     }
-    __syncthreads();
-    for (uint32_t r = r0; r < r1; ++r) {
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) live += id[i] != SL_EMPTY ? 1u : 0u;
+    for (int o = 32; o > 0; o >>= 1) live += __shfl_xor(live, o, SL_WAVE);
+    if (lane == 0) atomicAdd(&misc[7], live);
+  }
+  __syncthreads();
+  {
+    uint32_t sum = 0;
+    for (uint32_t e = tid; e < lay.cm_words; e += NT) sum = __builtin_amdgcn_sad_u8(cmw[e], 0u, sum);
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, SL_WAVE);
+    if (lane == 0) atomicAdd(&misc[6], sum);
+  }
+  __syncthreads();
+  if (misc[6] == s.d * misc[7]) {
+    for (uint32_t r = 0; r < s.d; ++r) {
       const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
-        uint32_t g = ((r - r0) << s.lw) + cm_hash(ar, br, id[i], s.lw);
-        est[i] = min(est[i], (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu);
+        const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+        est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
       }
     }
     __syncthreads();
+  } else {
+    for (uint32_t r = 0; r < s.d; ++r) {
+      const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+      for (uint32_t e = tid; e < lay.cm16_words; e += NT) cmw[e] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) {
+        if (id[i] != SL_EMPTY) {
+          const uint32_t g = cm_hash(ar, br, id[i], s.lw);
+          atomicAdd(&cmw[g >> 1], 1u << ((g & 1u) * 16));
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) {
+        const uint32_t g = cm_hash(ar, br, id[i], s.lw);
+        est[i] = min(est[i], (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu);
+      }
+      __syncthreads();
+    }
   }
   uint64_t key[SPT];
 #pragma unroll
@@ -204,10 +238,16 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   const uint32_t kk = min(kq, total);
   uint32_t* oid = a.out_ids + (uint64_t)q * s.k_max;
   uint32_t* osc = a.out_scores + (uint64_t)q * s.k_max;
-  // 4. threshold key: keys >= thr are exactly the kk largest.  MSD radix
-  //    select over 8-bit digits of (estimate << 32 | ~id), starting at the
-  //    estimate's low byte when every estimate is below 256.
+  // 4. threshold key.  MSD radix select over 8-bit digits of
+  //    (estimate << 32 | ~id), starting at the estimate's low byte when every
+  //    estimate is below 256.  Once the estimate E of the kk-th key is known,
+  //    if the keys with estimate >= E are few they are all collected and
+  //    ranked directly (ties on E are then ordered by id without more radix
+  //    rounds); otherwise the select goes on through the id bytes until the
+  //    keys >= thr are exactly the kk largest.
   uint64_t thr = 1;  // every representative (their keys are >= 2^32)
+  uint32_t n_c = kk;  // keys collected for ranking
+  uint64_t* cb = sel;  // where they are collected
   if (kk > 0 && kk < total) {
     uint64_t prefix = 0;
     uint32_t remaining = kk;
@@ -251,26 +291,34 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       remaining -= cum;
       prefix |= (uint64_t)D << shift;
       if (remaining == cnt) break;  // the whole digit bin is selected
+      if (shift == 32 && kk - remaining + cnt <= lay.tie_cap) {
+        n_c = kk - remaining + cnt;  // every key with estimate >= E
+        cb = (uint64_t*)(lds + lay.cm);
+        break;
+      }
     }
     thr = prefix;
   }
-  // 5. collect winners, rank them by counting (keys are distinct), write
+  // 5. collect the n_c keys >= thr, rank each among them by counting (keys
+  //    are distinct), write the kk best in order
   if (kk > 0) {
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
       if (key[i] != 0 && key[i] >= thr) {
         uint32_t p = atomicAdd(&misc[4], 1u);
-        sel[p] = key[i];
+        cb[p] = key[i];
       }
     }
   }
   __syncthreads();
-  for (uint32_t e = tid; e < kk; e += NT) {
-    uint64_t x = sel[e];
+  for (uint32_t e = tid; e < n_c; e += NT) {
+    uint64_t x = cb[e];
     uint32_t r = 0;
-    for (uint32_t j = 0; j < kk; ++j) r += sel[j] > x ? 1u : 0u;
-    oid[r] = ~(uint32_t)x;
-    osc[r] = (uint32_t)(x >> 32);
+    for (uint32_t j = 0; j < n_c; ++j) r += cb[j] > x ? 1u : 0u;
+    if (r < kk) {
+      oid[r] = ~(uint32_t)x;
+      osc[r] = (uint32_t)(x >> 32);
+    }
   }
   for (uint32_t e = kk + tid; e < s.k_max; e += NT) {
     oid[e] = SL_EMPTY;
@@ -297,12 +345,17 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE)
   const QLayout lay = q_layout(s);
   const ConstView cl = CL ? stage_consts(s, c, lds + lay.cst, WAVES * SL_WAVE) : c;
   const uint64_t n = a.q.n_rows;
+  // the next ticket is taken while the current one is answered, so the
+  // atomic's round trip is off the critical path
+  uint32_t next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(ticket, per_ticket);
   for (;;) {
-    if (threadIdx.x == 0) base_sh = atomicAdd(ticket, per_ticket);
+    if (threadIdx.x == 0) base_sh = next;
     __syncthreads();
     const uint64_t base = base_sh;
     __syncthreads();
     if (base >= n) break;
+    if (threadIdx.x == 0) next = atomicAdd(ticket, per_ticket);
     const uint64_t stop = base + per_ticket < n ? base + per_ticket : n;
     for (uint64_t q = base; q < stop; ++q) query_one<WAVES, SPT, CL>(s, cl, tab, a, (uint32_t)q, lds, lay);
   }

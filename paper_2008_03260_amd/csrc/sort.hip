@@ -14,7 +14,7 @@ namespace slash {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / SL_WAVE;
 constexpr int kItems = 16;                 // per thread
 constexpr int kTile = kThreads * kItems;   // 4096

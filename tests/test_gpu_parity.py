@@ -201,6 +201,15 @@ def test_query_parity(api, qsetup, k):
     assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
 
 
+def test_query_small_batches(api, qsetup):
+    # batches too small to fill the GPU run each query with 16 waves
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 10, k_max=24)
+    for a, b in ((0, 1), (1, 4), (4, 37)):
+        gi, gs = idx.query(dev(qi[a: b + 1] - qi[a]), dev(qx[qi[a]: qi[b]]), 10)
+        assert (u32(gi) == wi[a:b]).all() and (u32(gs) == ws[a:b]).all()
+
+
 def test_query_per_query_k(api, qsetup):
     idx, op, cs, oids, oseen, qi, qx = qsetup
     kq = np.random.default_rng(1).choice([0, 1, 10, 24], size=len(qi) - 1).astype(np.uint32)
@@ -227,6 +236,24 @@ def test_query_exact_special_cases(api):
     oids, oseen = oracle.build(op, cs, ip, ix)
     gi, gs = idx.query(dev(ip[:101]), dev(ix[: ip[100]]), 7)
     wi, ws = oracle.query(op, cs, oids, oseen, ip[:101], ix[: ip[100]], 7)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+
+
+@pytest.mark.parametrize("lw", [0, 1], ids=["w1", "w2"])
+def test_query_counter_overflow_recount(api, lw):
+    # 16 tables x 32 full slots = 512 occurrences over 1 or 2 counters per
+    # row: counts pass 255, so the 8-bit sketch overflows and the query is
+    # recounted with 16-bit counters
+    gp, op = params_pair(api, k_max=12, L=16, log2_buckets=3, R=32, cm_rows=2, log2_cm_width=lw)
+    law, (ip, ix) = rows_of(4000, seed=41)
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    assert int(oseen.min()) > op.R
+    qi, qx = ip[:41], ix[: ip[40]]
+    gi, gs = idx.query(dev(qi), dev(qx), 12)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 12)
+    assert int(ws.max()) > 255
     assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
 
 
