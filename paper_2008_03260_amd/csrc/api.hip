@@ -90,6 +90,15 @@ struct DBuf {
   T* as() const { return (T*)p; }
 };
 
+// Grow index-owned scratch.  Work queued earlier on another stream may still
+// read the old buffer, so the device is drained before it is replaced (sizes
+// only grow, so this happens a few times per index).
+static bool grow(DBuf& b, size_t bytes) {
+  if (b.p && bytes <= b.bytes) return true;
+  if (b.p && hipDeviceSynchronize() != hipSuccess) return false;
+  return b.get(bytes);
+}
+
 // ------------------------------------------------------------- constants
 
 // SplitMix64 (Steele, Lea, Flood 2014).
@@ -552,7 +561,7 @@ extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t f
   const uint32_t first = (uint32_t)ix->n_items;
   if (small_insert_ok(s, n)) {
     // three launches: hash the rows, sort per table in LDS, merge every run
-    if (!ix->ins_keys.get((size_t)n * s.L * 4) || !ix->ins_seg.get(small_insert_scratch(s, n)))
+    if (!grow(ix->ins_keys, (size_t)n * s.L * 4) || !grow(ix->ins_seg, small_insert_scratch(s, n)))
       return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
     HIP_TRY(launch_hash_rows(s, ix->cv, rows, ix->ins_keys.as<uint32_t>(), n, 0, st));
     HIP_TRY(launch_insert_small(s, ix->cv, ix->ins_keys.as<uint32_t>(), (uint32_t)n, first, ix->ins_seg.p, tables(ix),
@@ -565,9 +574,9 @@ extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t f
   if (items >= 0xFFFFFFFFull) return fail(SLASH_E_UNSUPPORTED, "insert batch too large");
   size_t hist_n = sort_hist_entries(items);
   size_t part_n = std::max(sort_part_entries(hist_n), sort_part_entries(items)) + 16;
-  if (!ix->ins_keys.get(items * 4) || !ix->ins_vals.get(items * 4) || !ix->ins_k0.get(items * 4) ||
-      !ix->ins_v0.get(items * 4) || !ix->ins_k1.get(items * 4) || !ix->ins_v1.get(items * 4) ||
-      !ix->ins_hist.get(hist_n * 4) || !ix->ins_part.get(part_n * 4) || !ix->ins_seg.get((2 * items + 4) * 4))
+  if (!grow(ix->ins_keys, items * 4) || !grow(ix->ins_vals, items * 4) || !grow(ix->ins_k0, items * 4) ||
+      !grow(ix->ins_v0, items * 4) || !grow(ix->ins_k1, items * 4) || !grow(ix->ins_v1, items * 4) ||
+      !grow(ix->ins_hist, hist_n * 4) || !grow(ix->ins_part, part_n * 4) || !grow(ix->ins_seg, (2 * items + 4) * 4))
     return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
   HIP_TRY(launch_hash_rows(s, ix->cv, rows, ix->ins_keys.as<uint32_t>(), n, 1, st));
   HIP_TRY(launch_item_ids(ix->ins_vals.as<uint32_t>(), first, n, items, st));
@@ -640,8 +649,7 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   uint32_t per_ticket = std::max(1u, sc.queries_per_ticket);
   std::lock_guard<std::mutex> lk(ix->mu);
   const size_t need = (size_t)a.q.n_rows * s.L * 4;
-  if (need > ix->qbk.bytes) HIP_TRY(hipDeviceSynchronize());  // earlier launches may still read it
-  if (!ix->qbk.get(need)) return fail(SLASH_E_NOMEM, "batched bucket-id buffer");
+  if (!grow(ix->qbk, need)) return fail(SLASH_E_NOMEM, "batched bucket-id buffer");
   a.qbk = ix->qbk.as<uint32_t>();
   uint32_t* ticket = ix->tickets + (ix->ticket_next++ % kTicketRing);
   uint32_t hash_threads = 0;

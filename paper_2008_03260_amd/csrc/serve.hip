@@ -11,9 +11,11 @@
 //     batch while the device has room), copies them in, runs slash_query on
 //     the slot's stream and copies the results back;
 //   - an insert at the head of the FIFO closes the current epoch: it is
-//     ordered after every in-flight batch (stream waits on their events) and
-//     every later batch waits on it, so a query of epoch e sees exactly the
-//     inserts submitted before it, without blocking the host;
+//     ordered after every in-flight batch and insert (stream waits on their
+//     events) and every later batch waits on it, so a query of epoch e sees
+//     exactly the inserts submitted before it, without blocking the host.
+//     Two insert staging slots let the next insert be queued behind a
+//     running one, so the device runs epochs back to back;
 //   - finished work is detected with events and turned into completions.
 #include <hip/hip_runtime.h>
 
@@ -80,7 +82,7 @@ struct slash_server {
   std::deque<Request> pending;
   std::deque<slash_completion> done;
   std::vector<Slot> slots;
-  Slot ins;  // insert staging + its stream
+  std::vector<Slot> ins;  // insert staging + streams (one or two)
   hipEvent_t last_insert = nullptr;
   bool have_insert = false;
   uint64_t epoch = 0;
@@ -207,12 +209,15 @@ hipError_t launch_queries(slash_server* srv, Slot& s) {
   return hipEventRecord(s.done, s.stream);
 }
 
-// Apply an insert after every in-flight batch; later batches wait on it.
+// Apply an insert after every in-flight batch and insert; later batches wait
+// on it.
 hipError_t launch_insert(slash_server* srv, Slot& s) {
   const Request& r = s.reqs[0];
   hipError_t e;
   for (Slot& o : srv->slots)
     if (o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
+  for (Slot& o : srv->ins)
+    if (&o != &s && o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
   memcpy(s.h_indptr, r.indptr.data(), (r.n_rows + 1) * 8);
   memcpy(s.h_idx, r.idx.data(), r.idx.size() * 4);
   if ((e = hipMemcpyAsync(s.d_indptr, s.h_indptr, (r.n_rows + 1) * 8, hipMemcpyHostToDevice, s.stream)) != hipSuccess)
@@ -241,19 +246,24 @@ void scheduler(slash_server* srv) {
         finish_slot(srv, s);
         progressed = true;
       }
-    if (srv->ins.busy && hipEventQuery(srv->ins.done) == hipSuccess) {
-      finish_slot(srv, srv->ins);
-      progressed = true;
-    }
+    for (Slot& s : srv->ins)
+      if (s.busy && hipEventQuery(s.done) == hipSuccess) {
+        finish_slot(srv, s);
+        progressed = true;
+      }
     if (progressed) srv->cv.notify_all();
     // 2. admit the head of the FIFO
     while (!srv->pending.empty()) {
       Request& head = srv->pending.front();
       if (head.kind == 1) {
-        if (srv->ins.busy) break;  // one insert at a time, in order
-        uint64_t need_nnz = head.idx.size();
-        if (need_nnz > srv->ins.cap_nnz || head.n_rows > srv->ins.cap_q) break;  // checked at submit
-        Slot& s = srv->ins;
+        Slot* free_i = nullptr;  // inserts launch in FIFO order, each behind the last
+        for (Slot& o : srv->ins)
+          if (!o.busy) {
+            free_i = &o;
+            break;
+          }
+        if (!free_i) break;
+        Slot& s = *free_i;
         s.reqs.clear();
         s.reqs.push_back(std::move(head));
         srv->pending.pop_front();
@@ -297,7 +307,8 @@ void scheduler(slash_server* srv) {
       for (Slot& o : srv->slots) inflight += o.busy;
       srv->stats.peak_inflight = std::max(srv->stats.peak_inflight, inflight);
     }
-    bool busy = srv->ins.busy;
+    bool busy = false;
+    for (Slot& s : srv->ins) busy |= s.busy;
     for (Slot& s : srv->slots) busy |= s.busy;
     if (srv->stopping && srv->pending.empty() && !busy) break;
     if (busy) {
@@ -337,12 +348,23 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     return fail(SLASH_E_NOMEM, "HBM budget %llu below one batch slot (%llu bytes)",
                 (unsigned long long)cfg->hbm_budget_bytes, (unsigned long long)(ins_bytes + per_slot));
   }
-  if (!alloc_slot(srv->ins, ins_rows, ins_nnz, km, false)) {
-    free_slot(srv->ins);
+  srv->ins.emplace_back();
+  if (!alloc_slot(srv->ins[0], ins_rows, ins_nnz, km, false)) {
+    free_slot(srv->ins[0]);
     delete srv;
     return fail(SLASH_E_NOMEM, "insert staging allocation failed");
   }
   srv->hbm_used = ins_bytes;
+  // a second insert slot when the budget still leaves room for a batch slot
+  if (srv->hbm_used + ins_bytes + per_slot <= cfg->hbm_budget_bytes) {
+    srv->ins.emplace_back();
+    if (alloc_slot(srv->ins[1], ins_rows, ins_nnz, km, false)) {
+      srv->hbm_used += ins_bytes;
+    } else {
+      free_slot(srv->ins[1]);
+      srv->ins.pop_back();
+    }
+  }
   for (uint32_t i = 0; i < cfg->max_inflight && srv->hbm_used + per_slot <= cfg->hbm_budget_bytes; ++i) {
     srv->slots.emplace_back();
     if (!alloc_slot(srv->slots.back(), cap_q, cap_nnz, km, true)) {
@@ -353,7 +375,7 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     srv->hbm_used += per_slot;
   }
   if (srv->slots.empty()) {
-    free_slot(srv->ins);
+    for (Slot& o : srv->ins) free_slot(o);
     delete srv;
     return fail(SLASH_E_NOMEM, "no batch slot fits the HBM budget");
   }
@@ -397,13 +419,13 @@ extern "C" slash_status slash_serve_submit_query(slash_server* srv, const int32_
 extern "C" slash_status slash_serve_submit_insert(slash_server* srv, const int64_t* indptr, const int32_t* idx,
                                                   uint32_t n_rows, uint64_t* ticket) {
   if (!srv || !indptr || (!idx && n_rows)) return fail(SLASH_E_INVAL, "NULL argument");
-  if (n_rows == 0 || n_rows > srv->ins.cap_q) return fail(SLASH_E_INVAL, "insert of %u rows outside [1, %u]", n_rows, srv->ins.cap_q);
+  if (n_rows == 0 || n_rows > srv->ins[0].cap_q) return fail(SLASH_E_INVAL, "insert of %u rows outside [1, %u]", n_rows, srv->ins[0].cap_q);
   if (indptr[0] != 0) return fail(SLASH_E_INVAL, "indptr[0] must be 0");
   const uint32_t dim = srv->info.params.dim;
   for (uint32_t r = 0; r < n_rows; ++r)
     if (indptr[r + 1] <= indptr[r]) return fail(SLASH_E_INVAL, "empty row in insert");
   const uint64_t nnz = (uint64_t)indptr[n_rows];
-  if (nnz > srv->ins.cap_nnz) {
+  if (nnz > srv->ins[0].cap_nnz) {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->stats.rejected_nomem++;
     return fail(SLASH_E_NOMEM, "insert of %llu indices exceeds the staging budget", (unsigned long long)nnz);
@@ -443,7 +465,7 @@ extern "C" slash_status slash_serve_stop(slash_server* srv, slash_serve_stats* s
   hipError_t err = srv->dev_err;
   if (stats) *stats = srv->stats;
   for (Slot& s : srv->slots) free_slot(s);
-  free_slot(srv->ins);
+  for (Slot& o : srv->ins) free_slot(o);
   delete srv;
   if (err != hipSuccess) return fail(SLASH_E_DEVICE, "serve: %s", hipGetErrorString(err));
   return SLASH_OK;
