@@ -214,11 +214,33 @@ __global__ void k_iota(uint32_t* p, uint32_t first, uint64_t n) {
     p[i] = first + (uint32_t)i;
 }
 
+// Start and end of every key's run in the sorted keys.  A thread takes 8
+// consecutive keys (all loads issued before any compare) plus the neighbours
+// on either side.
 __global__ void k_segment_bounds(const uint32_t* __restrict__ sk, uint64_t n, uint32_t* start, uint32_t* end) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t k = sk[i];
-    if (i == 0 || sk[i - 1] != k) start[k] = (uint32_t)i;
-    if (i + 1 == n || sk[i + 1] != k) end[k] = (uint32_t)(i + 1);
+  constexpr uint32_t kPer = 8;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kPer;
+  for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kPer; i0 < n; i0 += stride) {
+    uint32_t k[kPer];
+    if (i0 + kPer <= n) {
+#pragma unroll
+      for (uint32_t j = 0; j < kPer; ++j) k[j] = sk[i0 + j];
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < kPer; ++j) k[j] = i0 + j < n ? sk[i0 + j] : 0u;
+    }
+    const uint32_t prev = i0 > 0 ? sk[i0 - 1] : ~k[0];
+    const uint32_t next = i0 + kPer < n ? sk[i0 + kPer] : 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint64_t i = i0 + j;
+      if (i >= n) break;
+      const uint32_t before = j ? k[j - 1] : prev;
+      if (i == 0 || before != k[j]) start[k[j]] = (uint32_t)i;
+      const bool last = i + 1 == n;
+      const uint32_t after = j + 1 < kPer ? k[j + 1] : next;
+      if (last || after != k[j]) end[k[j]] = (uint32_t)(i + 1);
+    }
   }
 }
 
@@ -329,7 +351,8 @@ void* fill_kernel_ptr() { return (void*)k_fill; }
 
 hipError_t launch_segment_bounds(const uint32_t* skeys, uint64_t n, uint32_t* start, uint32_t* end, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segment_bounds, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, skeys, n, start, end);
+  hipLaunchKernelGGL(k_segment_bounds, dim3(grid_for((n + 7) / 8, 256, 16384)), dim3(256), 0, st, skeys, n, start,
+                     end);
   return hipGetLastError();
 }
 

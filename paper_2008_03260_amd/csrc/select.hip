@@ -109,14 +109,25 @@ __device__ __forceinline__ uint64_t prio_key(uint32_t id, uint32_t key, uint32_t
 }
 
 // Stream ids src[off .. off+len) (EMPTY entries skipped) through the list.
+// Four 64-id chunks are loaded before any is offered, so a bucket of up to
+// 256 ids costs one memory round trip.
 __device__ __forceinline__ void wl_stream(WaveList& w, const uint32_t* __restrict__ src, uint64_t off, uint64_t len,
                                           uint32_t key, uint32_t m1, uint32_t m2) {
+  constexpr int kChunks = 4;
   const uint32_t lane = lane_id();
-  for (uint64_t i = 0; i < len; i += SL_WAVE) {
-    uint64_t j = i + lane;
-    uint32_t id = j < len ? src[off + j] : SL_EMPTY;
-    bool v = id != SL_EMPTY;
-    wl_offer(w, v, v ? prio_key(id, key, m1, m2) : kNoKey);
+  for (uint64_t i = 0; i < len; i += kChunks * SL_WAVE) {
+    uint32_t id[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      const uint64_t j = i + (uint64_t)c * SL_WAVE + lane;
+      id[c] = j < len ? src[off + j] : SL_EMPTY;
+    }
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      if (i + (uint64_t)c * SL_WAVE >= len) break;  // wave-uniform
+      const bool v = id[c] != SL_EMPTY;
+      wl_offer(w, v, v ? prio_key(id[c], key, m1, m2) : kNoKey);
+    }
   }
   wl_flush(w);
 }
@@ -147,8 +158,19 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
   uint64_t* my = lds64 + wave * wl_words(s.R);
   const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
   const uint32_t nwaves = gridDim.x * kSelWaves;
-  for (uint32_t b = blockIdx.x * kSelWaves + wave; b < s.nb; b += nwaves) {
-    const uint32_t s0 = start[b], e0 = end[b];
+  // the bounds of the wave's next bucket are loaded while this one is reduced
+  uint32_t b = blockIdx.x * kSelWaves + wave;
+  uint32_t s_next = 0, e_next = 0;
+  if (b < s.nb) {
+    s_next = start[b];
+    e_next = end[b];
+  }
+  for (; b < s.nb; b += nwaves) {
+    const uint32_t s0 = s_next, e0 = e_next;
+    if (b + nwaves < s.nb) {
+      s_next = start[b + nwaves];
+      e_next = end[b + nwaves];
+    }
     const uint32_t n = e0 - s0;
     uint32_t* out = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
     if (n > heavy_t) {

@@ -48,31 +48,71 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return off + inc - v;
 }
 
+// Keys (and values) of one wave's sub-tile: every load is issued before any
+// is used, unpredicated when the tile is full.
+template <bool WITH_VALS>
+__device__ __forceinline__ void load_subtile(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                             uint64_t sbase, uint64_t n, bool full, uint32_t (&key)[kRounds],
+                                             uint32_t (&val)[kRounds]) {
+  const uint32_t lane = lane_id();
+  if (full) {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) key[r] = kin[sbase + (uint64_t)r * SL_WAVE + lane];
+    if (WITH_VALS) {
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) val[r] = vin[sbase + (uint64_t)r * SL_WAVE + lane];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint64_t i = sbase + (uint64_t)r * SL_WAVE + lane;
+      key[r] = i < n ? kin[i] : 0u;
+      if (WITH_VALS) val[r] = i < n ? vin[i] : 0u;
+    }
+  }
+  if (!WITH_VALS) {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) val[r] = (uint32_t)(sbase + (uint64_t)r * SL_WAVE + lane);
+  }
+}
+
+template <int BITS>
 __global__ void __launch_bounds__(kThreads)
-    k_upsweep(const uint32_t* __restrict__ keys, uint64_t n, int shift, int bits, uint32_t* __restrict__ hist,
+    k_upsweep(const uint32_t* __restrict__ keys, uint64_t n, int shift, uint32_t* __restrict__ hist,
               uint32_t n_tiles) {
   __shared__ uint32_t cnt[256];
-  const uint32_t nd = 1u << bits, dmask = nd - 1;
+  constexpr uint32_t nd = 1u << BITS, dmask = nd - 1;
   for (uint32_t d = threadIdx.x; d < nd; d += kThreads) cnt[d] = 0;
   __syncthreads();
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   const uint32_t lane = lane_id();
-#pragma unroll 4
+  const bool full = base + kTile <= n;
+  uint32_t k[kItems];
+  if (full) {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) k[j] = keys[base + (uint64_t)j * kThreads + threadIdx.x];
+  } else {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+      k[j] = i < n ? keys[i] : 0u;
+    }
+  }
+#pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
-    bool v = i < n;
-    uint32_t d = v ? (keys[i] >> shift) & dmask : 0u;
-    uint64_t act = ballot64(v);
-    uint64_t peers = match_digit(d, bits, act);
+    const bool v = full || base + (uint64_t)j * kThreads + threadIdx.x < n;
+    const uint32_t d = (k[j] >> shift) & dmask;
+    const uint64_t peers = match_digit(d, BITS, ballot64(v));
     if (v && lane == (uint32_t)__builtin_ctzll(peers)) atomicAdd(&cnt[d], (uint32_t)__builtin_popcountll(peers));
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < nd; d += kThreads) hist[(uint64_t)d * n_tiles + blockIdx.x] = cnt[d];
 }
 
+template <int BITS>
 __global__ void __launch_bounds__(kThreads)
     k_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t n, int shift,
-                int bits, const uint32_t* __restrict__ offs, uint32_t n_tiles, uint32_t* __restrict__ kout,
+                const uint32_t* __restrict__ offs, uint32_t n_tiles, uint32_t* __restrict__ kout,
                 uint32_t* __restrict__ vout) {
   __shared__ uint32_t wcnt[kWaves][256];
   __shared__ uint32_t tile_off[256];
@@ -80,23 +120,24 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ uint32_t scan_sh[kWaves];
   __shared__ uint32_t sk[kTile];
   __shared__ uint32_t sv[kTile];
-  const uint32_t nd = 1u << bits, dmask = nd - 1;
+  constexpr uint32_t nd = 1u << BITS, dmask = nd - 1;
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
-  for (uint32_t e = threadIdx.x; e < kWaves * 256; e += kThreads) (&wcnt[0][0])[e] = 0;
-  __syncthreads();
   const uint32_t tile = xcd_tile(blockIdx.x, n_tiles);
   const uint64_t tbase = (uint64_t)tile * kTile;
   const uint64_t sbase = tbase + (uint64_t)wave * kSubTile;
+  const bool full = tbase + kTile <= n;
   uint32_t key[kRounds], val[kRounds], loc[kRounds];
+  if (vin)
+    load_subtile<true>(kin, vin, sbase, n, full, key, val);
+  else
+    load_subtile<false>(kin, vin, sbase, n, full, key, val);
+  for (uint32_t e = threadIdx.x; e < kWaves * 256; e += kThreads) (&wcnt[0][0])[e] = 0;
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    uint64_t i = sbase + (uint64_t)r * SL_WAVE + lane;
-    bool v = i < n;
-    key[r] = v ? kin[i] : 0u;
-    val[r] = v ? (vin ? vin[i] : (uint32_t)i) : 0u;
+    const bool v = full || sbase + (uint64_t)r * SL_WAVE + lane < n;
     uint32_t d = (key[r] >> shift) & dmask;
-    uint64_t act = ballot64(v);
-    uint64_t peers = match_digit(d, bits, act);
+    uint64_t peers = match_digit(d, BITS, ballot64(v));
     uint32_t before = (uint32_t)__builtin_popcountll(peers & lanemask_lt());
     uint32_t b0 = v ? wcnt[wave][d] : 0u;
     wave_sync();
@@ -126,8 +167,7 @@ __global__ void __launch_bounds__(kThreads)
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    uint64_t i = sbase + (uint64_t)r * SL_WAVE + lane;
-    if (i < n) {
+    if (full || sbase + (uint64_t)r * SL_WAVE + lane < n) {
       uint32_t d = (key[r] >> shift) & dmask;
       uint32_t p = tile_off[d] + wcnt[wave][d] + loc[r];
       sk[p] = key[r];
@@ -193,6 +233,36 @@ __global__ void __launch_bounds__(kThreads) k_scan_down(uint32_t* __restrict__ d
   }
 }
 
+typedef void (*UpFn)(const uint32_t*, uint64_t, int, uint32_t*, uint32_t);
+typedef void (*DownFn)(const uint32_t*, const uint32_t*, uint64_t, int, const uint32_t*, uint32_t, uint32_t*,
+                       uint32_t*);
+
+UpFn upsweep_fn(int bits) {
+  switch (bits) {
+    case 1: return k_upsweep<1>;
+    case 2: return k_upsweep<2>;
+    case 3: return k_upsweep<3>;
+    case 4: return k_upsweep<4>;
+    case 5: return k_upsweep<5>;
+    case 6: return k_upsweep<6>;
+    case 7: return k_upsweep<7>;
+    default: return k_upsweep<8>;
+  }
+}
+
+DownFn downsweep_fn(int bits) {
+  switch (bits) {
+    case 1: return k_downsweep<1>;
+    case 2: return k_downsweep<2>;
+    case 3: return k_downsweep<3>;
+    case 4: return k_downsweep<4>;
+    case 5: return k_downsweep<5>;
+    case 6: return k_downsweep<6>;
+    case 7: return k_downsweep<7>;
+    default: return k_downsweep<8>;
+  }
+}
+
 }  // namespace
 
 size_t sort_hist_entries(uint64_t n) { return (size_t)256 * ((n + kTile - 1) / kTile) + 1; }
@@ -222,14 +292,14 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
     dv = (p & 1) ? b.v1 : b.v0;
     if (n > 0) {
       if (timer) timer->begin(PH_UPSWEEP, st);
-      hipLaunchKernelGGL(k_upsweep, dim3(n_tiles), dim3(kThreads), 0, st, sk, n, shift, bits, b.hist, n_tiles);
+      hipLaunchKernelGGL(upsweep_fn(bits), dim3(n_tiles), dim3(kThreads), 0, st, sk, n, shift, b.hist, n_tiles);
       if (timer) timer->end(PH_UPSWEEP, st);
       if (timer) timer->begin(PH_SCAN, st);
       hipError_t e = exclusive_scan(b.hist, (uint64_t)n_tiles << bits, b.part, st);
       if (timer) timer->end(PH_SCAN, st);
       if (e != hipSuccess) return e;
       if (timer) timer->begin(PH_DOWNSWEEP, st);
-      hipLaunchKernelGGL(k_downsweep, dim3(n_tiles), dim3(kThreads), 0, st, sk, sv, n, shift, bits, b.hist, n_tiles,
+      hipLaunchKernelGGL(downsweep_fn(bits), dim3(n_tiles), dim3(kThreads), 0, st, sk, sv, n, shift, b.hist, n_tiles,
                          dk, dv);
       if (timer) timer->end(PH_DOWNSWEEP, st);
     }
