@@ -262,6 +262,8 @@ static Shape make_shape(const slash_params& p) {
   return s;
 }
 
+// One contiguous table; kernels stage its leading part (the u64 arrays, then
+// the direction words) into LDS as a flat copy, so this order is fixed.
 static slash_status upload_consts(slash_index* ix, hipStream_t st) {
   const HostConsts& h = ix->hc;
   std::vector<uint64_t> u64;

@@ -45,27 +45,36 @@ constexpr uint32_t kConstCapWords = 4096;
 
 // Copy the hash constants into LDS at `dst` (8-byte aligned) with all
 // `nthreads` threads of the block; returns a view of the staged copy.  The
-// caller synchronises the block before use.
+// caller synchronises the block before use.  The device table is one
+// contiguous block in this order (a_h, b_h, a_tj, b_t, a_r, b_r as u64, then
+// the u32 direction words), so it is copied as const_words(s) flat words,
+// every load of a thread issued before its stores.
 __device__ inline ConstView stage_consts(const Shape& s, const ConstView& c, uint32_t* dst, uint32_t nthreads) {
   const uint32_t n_h = s.mode ? s.L : 1;
+  const uint32_t W = const_words(s);
+  const uint32_t* src = (const uint32_t*)c.a_h;
+  for (uint32_t base = 0; base < W; base += 4 * nthreads) {
+    uint32_t x[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t i = base + j * nthreads + threadIdx.x;
+      x[j] = i < W ? src[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t i = base + j * nthreads + threadIdx.x;
+      if (i < W) dst[i] = x[j];
+    }
+  }
   ConstView v = c;
-  uint64_t* p = (uint64_t*)dst;
-  auto put64 = [&](const uint64_t* src, uint32_t n) {
-    for (uint32_t i = threadIdx.x; i < n; i += nthreads) p[i] = src[i];
-    const uint64_t* r = p;
-    p += n;
-    return r;
-  };
-  v.a_h = put64(c.a_h, n_h);
-  v.b_h = put64(c.b_h, n_h);
-  v.a_tj = put64(c.a_tj, s.M);
-  v.b_t = put64(c.b_t, s.L);
-  v.a_r = put64(c.a_r, s.d);
-  v.b_r = put64(c.b_r, s.d);
-  uint32_t* q = (uint32_t*)p;
-  const uint32_t nd = (s.M + 31) / 32 + 1;
-  for (uint32_t i = threadIdx.x; i < nd; i += nthreads) q[i] = c.dirw[i];
-  v.dirw = q;
+  const uint64_t* p = (const uint64_t*)dst;
+  v.a_h = p;
+  v.b_h = p += n_h;
+  v.a_tj = p += n_h;
+  v.b_t = p += s.M;
+  v.a_r = p += s.L;
+  v.b_r = p += s.d;
+  v.dirw = (const uint32_t*)(p + s.d);
   return v;
 }
 
@@ -117,6 +126,32 @@ __device__ __forceinline__ bool domain_any(const lds_u32* mask, uint32_t lo, uin
   return false;
 }
 
+// Per-bin minima of one row's nonzero hashes (mode 0): a group of G lanes
+// takes 4·G nonzeros per round, loading all of them before hashing any, so a
+// row of up to 4·G nonzeros costs one memory round trip.
+template <int G>
+__device__ __forceinline__ void row_minima(const Shape& s, uint64_t a, uint64_t bb, const int32_t* __restrict__ idx,
+                                           uint32_t nnz, uint32_t gl, uint32_t* lds_m) {
+  constexpr uint32_t kC = 4;
+  const uint32_t msh = s.mshift;
+  for (uint32_t e0 = 0; e0 < nnz; e0 += kC * G) {
+    uint32_t x[kC];
+#pragma unroll
+    for (uint32_t c = 0; c < kC; ++c) {
+      const uint32_t e = e0 + c * G + gl;
+      x[c] = e < nnz ? (uint32_t)idx[e] : 0u;
+    }
+#pragma unroll
+    for (uint32_t c = 0; c < kC; ++c) {
+      if (e0 + c * G + gl < nnz) {
+        const uint32_t u = nz_hash(a, bb, x[c]);
+        const uint32_t bin = msh == 0xFFu ? range_bin(u, s.M) : (msh ? u >> (32 - msh) : 0u);
+        atomicMin(&lds_m[bin], u);
+      }
+    }
+  }
+}
+
 // A group of G consecutive lanes (G = 16, 32 or 64) hashes one row: per-bin
 // minima of the nonzero hashes, then densification (an empty bin copies the
 // nearest non-empty bin in its fixed direction, circularly, reading the
@@ -145,16 +180,7 @@ __device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const Cons
   for (uint32_t w = gl; w < mask_words(M); w += G) mask[w] = 0u;
   wave_sync();
   if (s.mode == 0) {
-    const uint64_t a = cld64<CL>(c.a_h, 0), bb = cld64<CL>(c.b_h, 0);
-    for (uint32_t e = gl; e < nnz; e += G) {
-      uint32_t u = nz_hash(a, bb, (uint32_t)idx[e]);
-      uint32_t bin;
-      if (s.mshift == 0xFFu)
-        bin = range_bin(u, M);
-      else
-        bin = s.mshift ? u >> (32 - s.mshift) : 0u;
-      atomicMin(&lds_m[bin], u);
-    }
+    row_minima<G>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m);
   } else {
     const uint32_t L = s.L, K = s.K;
     for (uint32_t w = gl; w < nnz * L; w += G) {
@@ -227,14 +253,7 @@ __device__ __forceinline__ void doph_regs(const Shape& s, const ConstView& c, co
 #pragma unroll
   for (int j = 0; j < P; ++j) m3[b0 + j] = SL_EMPTY;
   wave_sync();
-  {
-    const uint64_t a = cld64<CL>(c.a_h, 0), bb = cld64<CL>(c.b_h, 0);
-    for (uint32_t e = gl; e < nnz; e += G) {
-      uint32_t u = nz_hash(a, bb, (uint32_t)idx[e]);
-      uint32_t bin = s.mshift == 0xFFu ? range_bin(u, s.M) : (s.mshift ? u >> (32 - s.mshift) : 0u);
-      atomicMin(&lds_m[bin], u);
-    }
-  }
+  row_minima<G>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m);
   wave_sync();
 #pragma unroll
   for (int j = 0; j < P; ++j) h[j] = m3[b0 + j];

@@ -57,19 +57,25 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
   const uint64_t n_chunks = (n + rpc - 1) / rpc;
   for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
     const uint64_t r0 = ch * rpc;
-    // every group runs the same number of rounds (wave-wide syncs inside)
+    // every group runs the same number of rounds (wave-wide syncs inside);
+    // the row bounds of the group's next round are loaded before this round
+    // hashes, so their round trip overlaps the index loads
+    int64_t nbeg = 0, nend = 0;
+    if (grp < rpc && r0 + grp < n) {
+      nbeg = rows.indptr[r0 + grp];
+      nend = rows.indptr[r0 + grp + 1];
+    }
     for (uint32_t rb = 0; rb < rpc; rb += ng) {
       const uint32_t rl = rb + grp;
       const uint64_t r = r0 + rl;
       const bool live = rl < rpc && r < n;
-      int64_t beg = 0, end = 0;
-      if (live) {
-        beg = rows.indptr[r];
-        end = rows.indptr[r + 1];
+      const int64_t beg = nbeg, end = nend;
+      if (rl + ng < rpc && r + ng < n) {
+        nbeg = rows.indptr[r + ng];
+        nend = rows.indptr[r + ng + 1];
       }
-      hash_row<G, P, CL>(s, cl, rows.indices + beg, (uint32_t)(end - beg), live, my, [&](uint32_t t, uint32_t b) {
-        stage[t * rpc + rl] = combine ? t * s.nb + b : b;
-      });
+      hash_row<G, P, CL>(s, cl, rows.indices + beg, live ? (uint32_t)(end - beg) : 0u, live, my,
+                         [&](uint32_t t, uint32_t b) { stage[t * rpc + rl] = combine ? t * s.nb + b : b; });
     }
     __syncthreads();
     const uint32_t tot = s.L * rpc;

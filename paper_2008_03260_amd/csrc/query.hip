@@ -328,7 +328,8 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
 }
 
 template <int WAVES, int SPT, bool CL>
-__global__ void __launch_bounds__(WAVES * SL_WAVE) k_query(Shape s, ConstView c, TablesView tab, QueryArgs a) {
+__global__ void __launch_bounds__(WAVES * SL_WAVE)
+    k_query(Shape s, ConstView c, TablesView tab, QueryArgs a) {
   extern __shared__ uint32_t lds[];
   const QLayout lay = q_layout(s);
   const ConstView cl = CL ? stage_consts(s, c, lds + lay.cst, WAVES * SL_WAVE) : c;
