@@ -244,6 +244,7 @@ template <int G, int P, bool CL>
 __device__ __forceinline__ void doph_regs(const Shape& s, const ConstView& c, const int32_t* __restrict__ idx,
                                           uint32_t nnz, uint32_t* lds_m, uint32_t (&h)[P]) {
   static_assert(P == 4 || P == 8 || P == 16, "bins per lane");
+  static_assert(G == 16 || G == 32 || G == 64, "group size");
   const uint32_t lane = lane_id();
   const uint32_t gl = lane & (G - 1);
   const uint32_t gshift = lane & ~(uint32_t)(G - 1);

@@ -127,12 +127,25 @@ uint32_t hash_rpc(const Shape& s) {
   return r;
 }
 
+// Lanes per row.
+uint32_t row_group(const Shape& s) { return hash_group(s.M); }
+
 // Bins per lane of the register DOPH form for this shape, or 0 (generic).
-int hash_p(const Shape& s) { return (int)doph_regs_p(s, hash_group(s.M)); }
+int hash_p(const Shape& s) { return (int)doph_regs_p(s, row_group(s)); }
+
+// Host check that the chosen kernel fits the shape: the register form needs
+// M = G * P bins with K dividing P (its lanes own whole tables); the generic
+// form needs a group size it is instantiated for.
+bool hash_shape_ok(const Shape& s) {
+  const uint32_t G = row_group(s);
+  const int P = hash_p(s);
+  if (P) return s.mode == 0 && s.M == G * (uint32_t)P && (uint32_t)P % s.K == 0;
+  return G == 16 || G == 32 || G == 64;
+}
 
 // Waves per block such that the block's LDS fits (64 / G rows per wave).
 uint32_t hash_waves(const Shape& s, size_t fixed) {
-  const size_t per_wave = (size_t)(SL_WAVE / hash_group(s.M)) * group_lds_words(s, hash_p(s)) * 4;
+  const size_t per_wave = (size_t)(SL_WAVE / row_group(s)) * group_lds_words(s, hash_p(s)) * 4;
   for (uint32_t w = kMaxHashWaves; w > 1; w >>= 1)
     if (w * per_wave + fixed <= kLdsCap) return w;
   return 1;
@@ -141,7 +154,7 @@ uint32_t hash_waves(const Shape& s, size_t fixed) {
 // LDS bytes of a hash block with nw waves and `fixed` bytes ahead of the
 // per-group scratch.
 size_t hash_lds(const Shape& s, uint32_t nw, size_t fixed) {
-  return (size_t)nw * (SL_WAVE / hash_group(s.M)) * group_lds_words(s, hash_p(s)) * 4 + fixed;
+  return (size_t)nw * (SL_WAVE / row_group(s)) * group_lds_words(s, hash_p(s)) * 4 + fixed;
 }
 
 template <int G, bool CL>
@@ -167,7 +180,7 @@ const void* rowmajor_fn_p(int P) {
 const void* hash_rows_fn(const Shape& s) {
   const bool cl = const_staged(s);
   const int P = hash_p(s);
-  switch (hash_group(s.M)) {
+  switch (row_group(s)) {
     case 16: return cl ? rows_fn_p<16, true>(P) : rows_fn_p<16, false>(P);
     case 32: return cl ? rows_fn_p<32, true>(P) : rows_fn_p<32, false>(P);
     default: return cl ? rows_fn_p<64, true>(P) : rows_fn_p<64, false>(P);
@@ -177,7 +190,7 @@ const void* hash_rows_fn(const Shape& s) {
 const void* hash_rowmajor_fn(const Shape& s) {
   const bool cl = const_staged(s);
   const int P = hash_p(s);
-  switch (hash_group(s.M)) {
+  switch (row_group(s)) {
     case 16: return cl ? rowmajor_fn_p<16, true>(P) : rowmajor_fn_p<16, false>(P);
     case 32: return cl ? rowmajor_fn_p<32, true>(P) : rowmajor_fn_p<32, false>(P);
     default: return cl ? rowmajor_fn_p<64, true>(P) : rowmajor_fn_p<64, false>(P);
@@ -268,6 +281,7 @@ uint32_t grid_for(uint64_t work, uint32_t block, uint32_t cap = 65536) {
 hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, uint32_t* keys, uint64_t key_stride,
                             int combine, hipStream_t st) {
   if (rows.n_rows == 0) return hipSuccess;
+  if (!hash_shape_ok(s)) return hipErrorInvalidValue;
   const uint32_t rpc = hash_rpc(s);
   const size_t stage = (size_t)s.L * rpc * 4 + (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, stage);
@@ -287,13 +301,14 @@ hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, 
 
 hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr rows, uint32_t* out, hipStream_t st) {
   if (rows.n_rows == 0) return hipSuccess;
+  if (!hash_shape_ok(s)) return hipErrorInvalidValue;
   const size_t fixed = (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, fixed);
   const size_t lds = hash_lds(s, nw, fixed);
   const void* fn = hash_rowmajor_fn(s);
   hipError_t e = allow_lds(fn, lds);
   if (e != hipSuccess) return e;
-  uint32_t grid = grid_for(rows.n_rows, nw * (SL_WAVE / hash_group(s.M)), 8192);
+  uint32_t grid = grid_for(rows.n_rows, nw * (SL_WAVE / row_group(s)), 8192);
   Shape sh = s;
   ConstView cv = c;
   void* args[] = {&sh, &cv, &rows, &out};
@@ -303,6 +318,7 @@ hipError_t launch_hash_rowmajor(const Shape& s, const ConstView& c, slash_csr ro
 }
 
 void* hash_rowmajor_kernel(const Shape& s, uint32_t* threads, size_t* lds) {
+  if (!hash_shape_ok(s)) return nullptr;
   const size_t fixed = (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, fixed);
   *threads = nw * SL_WAVE;
@@ -314,7 +330,7 @@ void* hash_rowmajor_kernel(const Shape& s, uint32_t* threads, size_t* lds) {
 
 uint32_t hash_rowmajor_grid(const Shape& s, uint64_t n_rows) {
   const uint32_t nw = hash_waves(s, (size_t)const_lds_words(s) * 4);
-  return grid_for(n_rows, nw * (SL_WAVE / hash_group(s.M)), 8192);
+  return grid_for(n_rows, nw * (SL_WAVE / row_group(s)), 8192);
 }
 
 hipError_t launch_validate(slash_csr rows, uint32_t dim, const uint32_t* kq, uint32_t k_max, uint32_t* flag,
