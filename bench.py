@@ -13,7 +13,12 @@ value = queries/s of the query phase over the timed steps; inserts/s of the
 build and of the insert batch are reported beside it, and the one-at-a-time
 query latency (p50/p99) is measured after the timed steps.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c1|c0]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c1|c0|c4]
+
+The wide workload (c4: N = 2e7, D = 2^24, lognormal nnz with median 500,
+uniform indices; K=8, L=128, 2^18 buckets, R=128; count-min 8 x 16384; k=100)
+is generated on the host (its row-size law has no device generator), which
+takes a few minutes.
 """
 from __future__ import annotations
 
@@ -28,14 +33,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# row law, planted-query law and batched/serving mix law of each workload
+C1_LAW = dict(index="zipf", nnz="poisson", nnz_a=40.0)
+C1_Q = dict()  # the source row's own size, 20% replaced
+C1_MIX = dict(nnz_mode="lognormal", median=40, sigma=1.0, lo=5, hi=2000, f=(0.1, 0.4), kmix=(1, 10, 100))
+WIDE_LAW = dict(index="uniform", nnz="lognormal", nnz_a=500.0, nnz_b=0.8, nnz_lo=50, nnz_hi=20000)
+WIDE_MIX = dict(nnz_mode="lognormal", median=500, sigma=0.8, lo=50, hi=20000, f=(0.1, 0.4), kmix=(1, 10, 100))
+
 WORKLOADS = {
     # tiny: N = 1e5, K=4, L=16, 2^16 buckets, R=32, count-min 4 x 1024, k = 10
     "c0": dict(n=100_000, dim=1 << 20, K=4, L=16, B=16, R=32, d=4, lw=10, k=10, nq=1000, master=2020,
+               law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=100_000,
                desc="tiny: N=1e5, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=16 B=16 R=32; CM 4x1024; k=10; 1000 queries f=0.2"),
     # one node's 200M-point shard
     "c1": dict(n=200_000_000, dim=1 << 20, K=4, L=32, B=20, R=64, d=4, lw=12, k=10, nq=100_000, master=2021,
+               law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=1_000_000,
                desc="200M-point shard: N=2e8, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=32 B=20 R=64; CM 4x4096; "
                     "k=10; 100k queries f=0.2"),
+    # denser, wider shard under serving
+    "c4": dict(n=20_000_000, dim=1 << 24, K=8, L=128, B=18, R=128, d=8, lw=14, k=100, nq=10_000, master=2024,
+               law=WIDE_LAW, q=dict(nnz_mode="lognormal", median=500, sigma=0.8, lo=50, hi=20000, f=(0.1, 0.4)),
+               mix=WIDE_MIX, max_nnz=20000, max_insert_nnz=8_000_000, cpu_rows=100_000, mix_n=100_000,
+               serve_rates=(1e3, 3e3, 1e4, 3e4),
+               desc="wide shard: N=2e7, D=2^24, nnz~lognormal(median 500, sigma 0.8) in [50, 20000], uniform "
+                    "indices; K=8 L=128 B=18 R=128; CM 8x16384; k=100; 10k queries f~U[0.1,0.4]"),
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -79,7 +100,7 @@ def cpu_baseline(w, law, seeds, budget_s=20.0):
     import oracle
     import synth
 
-    n_rows = min(w["n"], 1_000_000 if w["n"] > 1_000_000 else w["n"])
+    n_rows = min(w["n"], w["cpu_rows"])
     op = oracle.Params(dim=w["dim"], K=w["K"], L=w["L"], log2_buckets=w["B"], R=w["R"], cm_rows=w["d"],
                        log2_cm_width=w["lw"], seed=seeds["index"])
     cs = oracle.constants(op)
@@ -88,7 +109,7 @@ def cpu_baseline(w, law, seeds, budget_s=20.0):
     ids, seen = oracle.build(op, cs, ip, ix)
     t_build = time.perf_counter() - t0
     nq = 200
-    qi, qx, _, _ = law.queries(seeds["query"], n_rows, 0, nq)
+    qi, qx, _, _ = law.queries(seeds["query"], n_rows, 0, nq, **w["q"])
     t0 = time.perf_counter()
     done = 0
     while time.perf_counter() - t0 < max(1.0, budget_s - t_build) and done < 20 * nq:
@@ -123,13 +144,14 @@ def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4,
         q_k = mk[pick].astype(np.uint32)
         rows = int(sz[ins].sum())
         if rows:
-            gip, gix = law.gpu_rows(next_row, rows)
+            gip, gix = law.device_rows(next_row, rows)
             iip, iix = gip.cpu().numpy(), gix.cpu().numpy()
             next_row += rows
         else:
             iip, iix = np.zeros(1, np.int64), np.zeros(0, np.int32)
         srv = api.slash_serve_start(h, hbm_budget_bytes=2 << 30, max_batch=2048, max_inflight=6,
-                                    queue_capacity=1 << 22, max_query_nnz=2000)
+                                    queue_capacity=1 << 22, max_query_nnz=w["max_nnz"],
+                                    max_insert_nnz=w.get("max_insert_nnz", 0))
         t0 = time.perf_counter()
         lat, _ = api.slash_serve_replay(srv, t, ins, sz, q_ptr, q_idx, q_k, iip, iix)
         wall = time.perf_counter() - t0
@@ -174,15 +196,15 @@ def main():
     dev = torch.device("cuda:0")
     seeds = {k: synth.derive(w["master"], t) for k, t in
              (("data", synth.STREAM_DATA), ("query", synth.STREAM_QUERY), ("index", synth.STREAM_INDEX))}
-    law = synth.RowLaw(seeds["data"], w["dim"])
+    law = synth.RowLaw(seeds["data"], w["dim"], **w["law"])
     log(f"workload {args.workload}: {w['desc']}")
     t0 = time.perf_counter()
-    ip, ix = law.gpu_rows(0, w["n"])
-    ins_ip, ins_ix = law.gpu_rows(w["n"], 4096)
+    ip, ix = law.device_rows(0, w["n"])
+    ins_ip, ins_ix = law.device_rows(w["n"], 4096)
     torch.cuda.synchronize()
     nnz = int(ip[-1].item())
     log(f"generated {w['n']:,} rows, {nnz:,} nonzeros in HBM in {time.perf_counter() - t0:.1f}s")
-    qi_h, qx_h, src, _ = law.queries(seeds["query"], w["n"], 0, w["nq"])
+    qi_h, qx_h, src, _ = law.queries(seeds["query"], w["n"], 0, w["nq"], **w["q"])
     qi, qx = torch.from_numpy(qi_h).to(dev), torch.from_numpy(qx_h).to(dev)
     # k_max = 100 so the same index also answers the batched/serving mix
     # (k drawn from {1, 10, 100}); the planted-query workload asks k = 10
@@ -257,12 +279,12 @@ def main():
 
     # batched mix: lognormal query sizes, 10-40% replaced, k in {1, 10, 100};
     # one persistent graph-replayed launch vs the plain one-group-per-query grid
-    nm = min(args.mix_queries, w["n"])
-    mi_h, mx_h, msrc, mk = law.queries(seeds["query"] ^ 0x5EED, w["n"], 0, nm, nnz_mode="lognormal", median=40,
-                                       sigma=1.0, lo=5, hi=2000, f=(0.1, 0.4), kmix=(1, 10, 100))
+    nm = min(args.mix_queries, w["n"], w.get("mix_n", args.mix_queries))
+    mi_h, mx_h, msrc, mk = law.queries(seeds["query"] ^ 0x5EED, w["n"], 0, nm, **w["mix"])
     mi, mx = torch.from_numpy(mi_h).to(dev), torch.from_numpy(mx_h).to(dev)
     mkd = torch.from_numpy(mk.view(np.int32)).to(dev)
-    mix_sched = api.slash_autotune(h, mi[: 20001], mx[: int(mi_h[20000])], 100, stream)
+    ns = min(20000, nm)
+    mix_sched = api.slash_autotune(h, mi[: ns + 1], mx[: int(mi_h[ns])], 100, stream)
     res_b = api.slash_query_batched(h, mi, mx, 0, k_per_query=mkd, flags=api.FLAG_TRUSTED, schedule=mix_sched)
     res_p = api.slash_query(h, mi, mx, 0, k_per_query=mkd, flags=api.FLAG_TRUSTED)
     torch.cuda.synchronize()
@@ -294,7 +316,8 @@ def main():
 
     serve = None
     if not args.no_serve:
-        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, args.serve_seconds, seeds)
+        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, args.serve_seconds, seeds,
+                            **({"rates": w["serve_rates"]} if "serve_rates" in w else {}))
 
     # query kernel: algorithmic bytes per query = the query row 4*nnz + 8,
     # per table the reservoir row 4*R (read whole, EMPTY-padded), output 8*k

@@ -226,7 +226,7 @@ typedef struct {
   uint32_t queue_capacity;    /* pending requests accepted before E_BUSY */
   uint32_t max_wait_us;       /* a partial batch is launched after this wait */
   uint32_t max_query_nnz;     /* largest query row accepted */
-  uint32_t reserved;
+  uint32_t max_insert_nnz;    /* indices one insert request may carry (0: max(4096 * 64, 8 * max_query_nnz)) */
 } slash_serve_config;
 
 typedef struct {

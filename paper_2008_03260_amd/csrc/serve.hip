@@ -339,9 +339,11 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   const uint32_t cap_q = cfg->max_batch;
   const uint64_t cap_nnz = std::max<uint64_t>((uint64_t)cap_q * 64, cfg->max_query_nnz);
   const uint64_t per_slot = slot_bytes(cap_q, cap_nnz, km);
-  // insert staging: 4096 rows of up to 8 * max_query_nnz indices in total
+  // insert staging: 4096 rows of max_insert_nnz indices in total (default
+  // the larger of 64 per row and 8 * max_query_nnz)
   const uint32_t ins_rows = 4096;
-  const uint64_t ins_nnz = std::max<uint64_t>((uint64_t)ins_rows * 64, 8ull * cfg->max_query_nnz);
+  const uint64_t ins_nnz = cfg->max_insert_nnz ? cfg->max_insert_nnz
+                                               : std::max<uint64_t>((uint64_t)ins_rows * 64, 8ull * cfg->max_query_nnz);
   const uint64_t ins_bytes = (uint64_t)(ins_rows + 1) * 8 + ins_nnz * 4;
   if (ins_bytes + per_slot > cfg->hbm_budget_bytes) {
     delete srv;

@@ -186,6 +186,29 @@ class RowLaw:
             raise RuntimeError("synth_gpu_rows_fill failed")
         return indptr, indices[:total]
 
+    def device_rows(self, row0: int, n: int, chunk: int = 1 << 20, threads: int | None = None):
+        """Rows [row0, row0+n) as one CSR on the current HIP device, the same
+        rows as rows(): generated on the device for Poisson row sizes, else on
+        the host chunk by chunk (bounded host memory) and copied over."""
+        if self.spec.nnz_kind == 0:
+            return self.gpu_rows(row0, n)
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        th = threads or default_threads()
+        nnz = np.empty(n, dtype=np.uint32)
+        lib().synth_rows_nnz(self._ctx, row0, n, _ptr(nnz), th)
+        indptr = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(nnz, out=indptr[1:])
+        total = int(indptr[-1])
+        indices = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            sub = np.ascontiguousarray(indptr[a:b + 1])
+            part = np.empty(int(sub[-1] - sub[0]), dtype=np.int32)
+            lib().synth_rows_fill(self._ctx, row0 + a, b - a, _ptr(sub), _ptr(part), th)
+            indices[int(sub[0]):int(sub[-1])].copy_(torch.from_numpy(part))
+        return torch.from_numpy(indptr).to(dev), indices[:total]
+
     def queries(self, key: int, n_data: int, q0: int, n: int, nnz_mode: str = "same",
                 median: float = 40.0, sigma: float = 1.0, lo: int = 5, hi: int = 2000,
                 f: tuple = (0.2, 0.2), kmix=(10,), threads: int | None = None):
