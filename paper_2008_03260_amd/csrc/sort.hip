@@ -98,12 +98,20 @@ __global__ void __launch_bounds__(kThreads)
       k[j] = i < n ? keys[i] : 0u;
     }
   }
+  // Counts need no ranks: each key adds one with an LDS atomic, except that a
+  // wave whose valid keys all share one digit (runs of one heavy bucket) adds
+  // them with a single atomic.
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const bool v = full || base + (uint64_t)j * kThreads + threadIdx.x < n;
     const uint32_t d = (k[j] >> shift) & dmask;
-    const uint64_t peers = match_digit(d, BITS, ballot64(v));
-    if (v && lane == (uint32_t)__builtin_ctzll(peers)) atomicAdd(&cnt[d], (uint32_t)__builtin_popcountll(peers));
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t valid = ballot64(v);
+    if (ballot64(v && d == d0) == valid) {
+      if (valid && lane == (uint32_t)__builtin_ctzll(valid)) atomicAdd(&cnt[d0], (uint32_t)__builtin_popcountll(valid));
+    } else if (v) {
+      atomicAdd(&cnt[d], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < nd; d += kThreads) hist[(uint64_t)d * n_tiles + blockIdx.x] = cnt[d];
