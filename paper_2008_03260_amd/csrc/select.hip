@@ -147,7 +147,98 @@ __device__ __forceinline__ WaveList wl_init(uint64_t* lds, uint32_t R) {
   return w;
 }
 
-__host__ __device__ constexpr uint32_t wl_words(uint32_t R) { return 2 * R + SL_WAVE; }
+// Per-wave LDS (u64 words): the list, its merge target and the entrant
+// buffer; at least 128 words, which the small-bucket select uses as a
+// 256-bin histogram.
+__host__ __device__ constexpr uint32_t wl_words(uint32_t R) { return 2 * R + SL_WAVE > 128 ? 2 * R + SL_WAVE : 128; }
+
+// Bottom-R of a bucket of at most 256 ids (R <= 64), all held in registers:
+// an MSD radix select over 8-bit digits of the priority finds the R-th
+// smallest priority (priorities of one table are distinct), the R keys at or
+// below it are compacted into LDS and sorted across the wave once.  Writes R
+// slots of out (EMPTY past the bucket's size).
+__device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __restrict__ src, uint64_t off,
+                                             uint32_t n, uint32_t R, uint32_t key, uint32_t m1, uint32_t m2,
+                                             uint32_t* __restrict__ out) {
+  constexpr int kC = 4;
+  const uint32_t lane = lane_id();
+  uint32_t id[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    const uint32_t j = c * SL_WAVE + lane;
+    id[c] = j < n ? src[off + j] : SL_EMPTY;
+  }
+  uint32_t pr[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) pr[c] = id[c] != SL_EMPTY ? priority(id[c], key, m1, m2) : 0u;
+  // upper bound (inclusive) of the kept priorities
+  uint32_t upper = 0xFFFFFFFFu;
+  if (n > R) {
+    uint32_t* hist = (uint32_t*)lds;
+    uint32_t need = R, prefix = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      const uint32_t hi_mask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) hist[4 * lane + c] = 0;
+      wave_sync();
+#pragma unroll
+      for (int c = 0; c < kC; ++c)
+        if (id[c] != SL_EMPTY && (pr[c] & hi_mask) == prefix) atomicAdd(&hist[(pr[c] >> shift) & 255u], 1u);
+      wave_sync();
+      // lane owns digits 4*lane .. 4*lane+3
+      uint32_t h[4], mine = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        h[c] = hist[4 * lane + c];
+        mine += h[c];
+      }
+      uint32_t inc = mine;
+#pragma unroll
+      for (int o = 1; o < SL_WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, SL_WAVE);
+        if (lane >= (uint32_t)o) inc += y;
+      }
+      uint32_t cum = inc - mine, digit = 0, below = 0, cnt = 0;
+      bool here = false;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (cum < need && need <= cum + h[c]) {
+          here = true;
+          digit = 4 * lane + c;
+          below = cum;
+          cnt = h[c];
+        }
+        cum += h[c];
+      }
+      const uint32_t src_lane = (uint32_t)__builtin_ctzll(ballot64(here));
+      digit = __shfl(digit, src_lane, SL_WAVE);
+      below = __shfl(below, src_lane, SL_WAVE);
+      cnt = __shfl(cnt, src_lane, SL_WAVE);
+      wave_sync();
+      need -= below;
+      prefix |= digit << shift;
+      if (need == cnt) {  // the whole digit bin is kept
+        upper = prefix | (shift ? (1u << shift) - 1u : 0u);
+        break;
+      }
+    }
+  }
+  // compact the kept keys (exactly min(n, R)) and sort them once
+  uint32_t base = 0;
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    const bool keep = id[c] != SL_EMPTY && pr[c] <= upper;
+    const uint64_t m = ballot64(keep);
+    const uint32_t pos = base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
+    if (keep && pos < SL_WAVE) lds[pos] = ((uint64_t)pr[c] << 32) | id[c];
+    base += (uint32_t)__builtin_popcountll(m);
+  }
+  wave_sync();
+  uint64_t x = lane < min(base, (uint32_t)SL_WAVE) ? lds[lane] : kNoKey;
+  x = wave_sort64(x);
+  if (lane < R) out[lane] = lane < base ? (uint32_t)x : SL_EMPTY;
+  wave_sync();
+}
 
 __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     k_select_light(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ svals,
@@ -173,6 +264,11 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     }
     const uint32_t n = e0 - s0;
     uint32_t* out = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
+    if (n <= 4 * SL_WAVE && s.R <= SL_WAVE) {
+      select_small(my, svals, s0, n, s.R, key, m1, m2, out);
+      if (lane == 0) tab.seen[(uint64_t)t * s.nb + b] = n;
+      continue;
+    }
     if (n > heavy_t) {
       if (lane == 0) {
         uint32_t slot = atomicAdd(heavy_n, 1u);
