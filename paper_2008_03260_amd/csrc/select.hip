@@ -152,15 +152,15 @@ __device__ __forceinline__ WaveList wl_init(uint64_t* lds, uint32_t R) {
 // 256-bin histogram.
 __host__ __device__ constexpr uint32_t wl_words(uint32_t R) { return 2 * R + SL_WAVE > 128 ? 2 * R + SL_WAVE : 128; }
 
-// Bottom-R of a bucket of at most 256 ids (R <= 64), all held in registers:
+// Bottom-R of a bucket of at most 64·kC ids (R <= 64), all held in registers:
 // an MSD radix select over 8-bit digits of the priority finds the R-th
 // smallest priority (priorities of one table are distinct), the R keys at or
 // below it are compacted into LDS and sorted across the wave once.  Writes R
 // slots of out (EMPTY past the bucket's size).
+template <int kC>
 __device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __restrict__ src, uint64_t off,
                                              uint32_t n, uint32_t R, uint32_t key, uint32_t m1, uint32_t m2,
                                              uint32_t* __restrict__ out) {
-  constexpr int kC = 4;
   const uint32_t lane = lane_id();
   uint32_t id[kC];
 #pragma unroll
@@ -264,8 +264,11 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     }
     const uint32_t n = e0 - s0;
     uint32_t* out = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
-    if (n <= 4 * SL_WAVE && s.R <= SL_WAVE) {
-      select_small(my, svals, s0, n, s.R, key, m1, m2, out);
+    if (n <= 8 * SL_WAVE && s.R <= SL_WAVE) {
+      if (n <= 4 * SL_WAVE)
+        select_small<4>(my, svals, s0, n, s.R, key, m1, m2, out);
+      else
+        select_small<8>(my, svals, s0, n, s.R, key, m1, m2, out);
       if (lane == 0) tab.seen[(uint64_t)t * s.nb + b] = n;
       continue;
     }
