@@ -61,6 +61,8 @@ typedef enum {
 
 /* Flags for calls that take a `flags` argument. */
 #define SLASH_FLAG_TRUSTED 1u /* skip device-side input validation (no host sync) */
+#define SLASH_FLAG_EXACT 2u   /* queries: rank candidates by their exact multiplicity among the probed
+                                 slots instead of the count-min estimate (scores are the multiplicities) */
 
 /* Index parameters (Section 4 "Initialization"; Section 6 "Values of K and
  * L").  Constraints checked by every call:
@@ -144,8 +146,11 @@ SLASH_API slash_status slash_insert(slash_index* index, slash_csr rows, uint32_t
  * min(k, #distinct candidates) hold (0xFFFFFFFF, 0).  k_per_query_dev
  * (nullable) gives each query its own k; else `k` applies to all.  k and each
  * k_per_query must be <= k_max (checked on the device unless TRUSTED; under
- * TRUSTED larger values are clamped to k_max).  One work-group per query, no
- * device allocation, asynchronous under TRUSTED. */
+ * TRUSTED larger values are clamped to k_max).  With SLASH_FLAG_EXACT the
+ * candidates are ranked by their exact multiplicity among the probed slots
+ * (at most L) instead of the estimate (the sketch-versus-exact comparison of
+ * Section 6.2); scores are then the multiplicities.  One work-group per query,
+ * no device allocation, asynchronous under TRUSTED. */
 SLASH_API slash_status slash_query(const slash_index* index, slash_csr queries, const uint32_t* k_per_query_dev,
                          uint32_t k, uint32_t flags, uint32_t* ids_dev, uint32_t* scores_dev, void* stream);
 

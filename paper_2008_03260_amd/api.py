@@ -19,6 +19,7 @@ _lib = None
 
 SLASH_OK, E_INVAL, E_NOMEM, E_DEVICE, E_CAPACITY, E_BUSY, E_CLOSED, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FLAG_TRUSTED = 1
+FLAG_EXACT = 2
 EMPTY = 0xFFFFFFFF
 _NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_CAPACITY", -5: "E_BUSY",
           -6: "E_CLOSED", -7: "E_UNSUPPORTED"}

@@ -601,7 +601,8 @@ static slash_status query_prelude(const slash_index* ix, slash_csr q, const uint
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
   if (q.n_rows && (!ids || !scores)) return fail(SLASH_E_INVAL, "output pointers are NULL");
   if (!kq && k > ix->p.k_max) return fail(SLASH_E_INVAL, "k (%u) exceeds k_max (%u)", k, ix->p.k_max);
-  if (!query_supported(ix->shape)) return fail(SLASH_E_UNSUPPORTED, "query shape not supported (count-min too large for LDS)");
+  if (!query_supported(ix->shape, query_default_waves(ix->shape), (flags & SLASH_FLAG_EXACT) != 0))
+    return fail(SLASH_E_UNSUPPORTED, "query shape not supported (count-min or id set too large for LDS)");
   if (!(flags & SLASH_FLAG_TRUSTED))
     return validate_rows(const_cast<slash_index*>(ix), q, kq, st);
   return SLASH_OK;
@@ -614,10 +615,11 @@ extern "C" slash_status slash_query(const slash_index* ix, slash_csr q, const ui
   if (rs != SLASH_OK) return rs;
   if (q.n_rows == 0) return SLASH_OK;
   QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
+  a.exact = (flags & SLASH_FLAG_EXACT) ? 1u : 0u;
   // A batch too small to occupy the GPU runs each query with 16 waves
   // (shorter per-query latency); larger batches use the default width.
   uint32_t waves = query_default_waves(ix->shape);
-  if (q.n_rows * 2 <= (uint64_t)ix->n_cu && query_supported(ix->shape, 16)) waves = 16;
+  if (q.n_rows * 2 <= (uint64_t)ix->n_cu && query_supported(ix->shape, 16u, a.exact != 0)) waves = 16;
   HIP_TRY(launch_query_waves(ix->shape, ix->cv, tables(ix), a, waves, st));
   return SLASH_OK;
 }
@@ -640,9 +642,10 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   QueryArgs a = a0;
   const Shape& s = ix->shape;
   uint32_t waves = sc.waves_per_query;
-  if (!query_supported(s, waves)) return fail(SLASH_E_UNSUPPORTED, "schedule with %u waves/query not supported", waves);
+  if (!query_supported(s, waves, a.exact != 0))
+    return fail(SLASH_E_UNSUPPORTED, "schedule with %u waves/query not supported", waves);
   int occ = 0;
-  HIP_TRY(query_occupancy(s, waves, &occ));
+  HIP_TRY(query_occupancy(s, waves, &occ, a.exact != 0));
   if (occ < 1) occ = 1;
   uint32_t per_cu = sc.groups_per_cu ? std::min<uint32_t>(sc.groups_per_cu, (uint32_t)occ) : (uint32_t)occ;
   uint32_t grid = per_cu * (uint32_t)ix->n_cu;
@@ -659,7 +662,7 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   void* hash_fn = hash_rowmajor_kernel(s, &hash_threads, &hash_lds);
   if (!hash_fn) return fail(SLASH_E_DEVICE, "hash kernel attributes");
   const uint32_t hash_grid = hash_rowmajor_grid(s, a.q.n_rows);
-  uint64_t gkey = ((uint64_t)waves << 48) | ((uint64_t)per_ticket << 32) | grid;
+  uint64_t gkey = ((uint64_t)a.exact << 63) | ((uint64_t)waves << 48) | ((uint64_t)per_ticket << 32) | grid;
   GraphSlot& g = ix->graphs[gkey];
   Shape sh = s;
   ConstView cv = ix->cv;
@@ -680,10 +683,10 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   hp.sharedMemBytes = (unsigned)hash_lds;
   hp.kernelParams = hash_args;
   hipKernelNodeParams rp{};
-  rp.func = persistent_query_kernel(s, waves);
+  rp.func = persistent_query_kernel(s, waves, a.exact != 0);
   rp.gridDim = dim3(grid);
   rp.blockDim = dim3(waves * SL_WAVE);
-  rp.sharedMemBytes = (unsigned)query_lds_bytes(s, waves);
+  rp.sharedMemBytes = (unsigned)query_lds_bytes(s, waves, a.exact != 0);
   rp.kernelParams = run_args;
   hipKernelNodeParams fp{};
   fp.func = fill_kernel_ptr();
@@ -725,6 +728,7 @@ extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q,
       }
   }
   QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
+  a.exact = (flags & SLASH_FLAG_EXACT) ? 1u : 0u;
   return run_batched(ix, a, sc, st);
 }
 

@@ -37,7 +37,7 @@ __host__ __device__ inline uint32_t next_pow2(uint32_t x) {
 
 constexpr uint32_t kLdsWords = 160 * 1024 / 4;  // LDS of one CU
 
-__host__ __device__ inline QLayout q_layout(const Shape& s) {
+__host__ __device__ inline QLayout q_layout(const Shape& s, bool exact = false) {
   QLayout o;
   uint32_t w = 1u << s.lw;
   o.cst_words = const_words(s);
@@ -51,9 +51,11 @@ __host__ __device__ inline QLayout q_layout(const Shape& s) {
   const uint32_t room = kLdsWords > o.cm + tail ? kLdsWords - (o.cm + tail) : 0u;
   // The id set holds at most L * R distinct ids: twice that (load <= 1/2)
   // when it fits, else the next power of two (a full set still terminates).
+  // The exact variant keeps a count beside every id (two words per entry).
   const uint32_t slots = s.L * s.R;
+  const uint32_t per = exact ? 2u : 1u;
   o.hs_size = next_pow2(2 * slots);
-  if (o.hs_size > room && next_pow2(slots) <= room) o.hs_size = next_pow2(slots);
+  if (o.hs_size * per > room && next_pow2(slots) * per <= room) o.hs_size = next_pow2(slots);
   if (o.hs_size < 64) o.hs_size = 64;
   // The sketch is counted with 8-bit counters, all d rows resident; a query
   // whose counts overflow a byte is recounted with 16-bit counters, one row
@@ -62,7 +64,7 @@ __host__ __device__ inline QLayout q_layout(const Shape& s) {
   o.cm16_words = (w + 1) / 2;
   // the id set reuses the count-min region once the estimates are read
   uint32_t region = o.cm_words > o.cm16_words ? o.cm_words : o.cm16_words;
-  if (o.hs_size > region) region = o.hs_size;
+  if (o.hs_size * per > region) region = o.hs_size * per;
   // keys with the kk-th estimate or above, ranked directly when at most this
   // many (collected into the count-min region, free by then)
   o.tie_cap = region / 2 < 128 ? region / 2 : 128;
@@ -88,7 +90,7 @@ __device__ __forceinline__ void hist_add(uint32_t* hist, bool part, uint32_t d) 
   if (part && lane_id() == (uint32_t)__builtin_ctzll(peers)) atomicAdd(&hist[d], (uint32_t)__builtin_popcountll(peers));
 }
 
-template <int WAVES, int SPT, bool CL>
+template <int WAVES, int SPT, bool CL, bool EX>
 __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a, uint32_t q,
                           uint32_t* lds, const QLayout& lay) {
   constexpr uint32_t NT = WAVES * SL_WAVE;
@@ -126,97 +128,138 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
     }
   }
-  // 2. count-min with 8-bit counters.  Every live slot adds one to each of
-  //    the d rows, so without overflow the counters sum to d * live; an
-  //    increment that wraps a byte loses 255 or 256 from that sum.  A query
-  //    whose sum falls short is recounted with 16-bit counters (one row per
-  //    pass; a counter never exceeds L * R <= 65535).  The estimate (min over
-  //    rows) goes into the high half of the sort key.
-  uint32_t est[SPT];
+  uint64_t key[SPT];
+  uint32_t nrep = 0, emax = 0;
+  if constexpr (!EX) {
+    // 2. count-min with 8-bit counters.  Every live slot adds one to each of
+    //    the d rows, so without overflow the counters sum to d * live; an
+    //    increment that wraps a byte loses 255 or 256 from that sum.  A query
+    //    whose sum falls short is recounted with 16-bit counters (one row per
+    //    pass; a counter never exceeds L * R <= 65535).  The estimate (min over
+    //    rows) goes into the high half of the sort key.
+    uint32_t est[SPT];
 #pragma unroll
-  for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
-  {
-    uint32_t live = 0;
-    for (uint32_t r = 0; r < s.d; ++r) {
-      const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+    for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
+    {
+      uint32_t live = 0;
+      for (uint32_t r = 0; r < s.d; ++r) {
+        const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
 #pragma unroll
-      for (int i = 0; i < SPT; ++i) {
-        if (id[i] != SL_EMPTY) {
-          const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
-          atomicAdd(&cmw[g >> 2], 1u << ((g & 3u) * 8));
+        for (int i = 0; i < SPT; ++i) {
+          if (id[i] != SL_EMPTY) {
+            const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+            atomicAdd(&cmw[g >> 2], 1u << ((g & 3u) * 8));
+          }
         }
+      }
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) live += id[i] != SL_EMPTY ? 1u : 0u;
+      for (int o = 32; o > 0; o >>= 1) live += __shfl_xor(live, o, SL_WAVE);
+      if (lane == 0) atomicAdd(&misc[7], live);
+    }
+    __syncthreads();
+    {
+      uint32_t sum = 0;
+      for (uint32_t e = tid; e < lay.cm_words; e += NT) sum = __builtin_amdgcn_sad_u8(cmw[e], 0u, sum);
+      for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, SL_WAVE);
+      if (lane == 0) atomicAdd(&misc[6], sum);
+    }
+    __syncthreads();
+    if (misc[6] == s.d * misc[7]) {
+      for (uint32_t r = 0; r < s.d; ++r) {
+        const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+          const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+          est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
+        }
+      }
+      __syncthreads();
+    } else {
+      for (uint32_t r = 0; r < s.d; ++r) {
+        const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+        for (uint32_t e = tid; e < lay.cm16_words; e += NT) cmw[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+          if (id[i] != SL_EMPTY) {
+            const uint32_t g = cm_hash(ar, br, id[i], s.lw);
+            atomicAdd(&cmw[g >> 1], 1u << ((g & 1u) * 16));
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+          const uint32_t g = cm_hash(ar, br, id[i], s.lw);
+          est[i] = min(est[i], (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu);
+        }
+        __syncthreads();
       }
     }
 #pragma unroll
-    for (int i = 0; i < SPT; ++i) live += id[i] != SL_EMPTY ? 1u : 0u;
-    for (int o = 32; o > 0; o >>= 1) live += __shfl_xor(live, o, SL_WAVE);
-    if (lane == 0) atomicAdd(&misc[7], live);
-  }
-  __syncthreads();
-  {
-    uint32_t sum = 0;
-    for (uint32_t e = tid; e < lay.cm_words; e += NT) sum = __builtin_amdgcn_sad_u8(cmw[e], 0u, sum);
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, SL_WAVE);
-    if (lane == 0) atomicAdd(&misc[6], sum);
-  }
-  __syncthreads();
-  if (misc[6] == s.d * misc[7]) {
-    for (uint32_t r = 0; r < s.d; ++r) {
-      const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+    for (int i = 0; i < SPT; ++i) key[i] = id[i] != SL_EMPTY ? ((uint64_t)est[i] << 32) | (uint32_t)~id[i] : 0ull;
+    // 3. distinct ids: the first insertion into the LDS id set represents the id
+    for (uint32_t e = tid; e < lay.hs_size; e += NT) hs[e] = SL_EMPTY;
+    __syncthreads();
 #pragma unroll
-      for (int i = 0; i < SPT; ++i) {
-        const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
-        est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
+    for (int i = 0; i < SPT; ++i) {
+      if (id[i] != SL_EMPTY) {
+        uint32_t h = hs_slot(id[i], hs_log2);
+        bool rep = false;
+        for (;;) {
+          uint32_t prev = atomicCAS(&hs[h], SL_EMPTY, id[i]);
+          if (prev == SL_EMPTY) {
+            rep = true;
+            break;
+          }
+          if (prev == id[i]) break;
+          h = (h + 1) & hs_mask;
+        }
+        if (rep) {
+          ++nrep;
+          emax = max(emax, (uint32_t)(key[i] >> 32));
+        } else {
+          key[i] = 0;
+        }
+      }
+    }
+  } else {
+    // 2'. exact variant: the id set also counts the occurrences of each id
+    //     (its multiplicity among the probed slots, at most L); the slot that
+    //     inserted the id represents it and takes the count as its score
+    uint32_t* hc = hs + lay.hs_size;  // counts beside the ids
+    for (uint32_t e = tid; e < lay.hs_size; e += NT) {
+      hs[e] = SL_EMPTY;
+      hc[e] = 0;
+    }
+    __syncthreads();
+    uint32_t at[SPT];
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      key[i] = 0;
+      at[i] = 0xFFFFFFFFu;
+      if (id[i] != SL_EMPTY) {
+        uint32_t h = hs_slot(id[i], hs_log2);
+        for (;;) {
+          uint32_t prev = atomicCAS(&hs[h], SL_EMPTY, id[i]);
+          if (prev == SL_EMPTY) {
+            at[i] = h;  // representative
+            break;
+          }
+          if (prev == id[i]) break;
+          h = (h + 1) & hs_mask;
+        }
+        atomicAdd(&hc[h], 1u);
       }
     }
     __syncthreads();
-  } else {
-    for (uint32_t r = 0; r < s.d; ++r) {
-      const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
-      for (uint32_t e = tid; e < lay.cm16_words; e += NT) cmw[e] = 0;
-      __syncthreads();
 #pragma unroll
-      for (int i = 0; i < SPT; ++i) {
-        if (id[i] != SL_EMPTY) {
-          const uint32_t g = cm_hash(ar, br, id[i], s.lw);
-          atomicAdd(&cmw[g >> 1], 1u << ((g & 1u) * 16));
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < SPT; ++i) {
-        const uint32_t g = cm_hash(ar, br, id[i], s.lw);
-        est[i] = min(est[i], (cmw[g >> 1] >> ((g & 1u) * 16)) & 0xFFFFu);
-      }
-      __syncthreads();
-    }
-  }
-  uint64_t key[SPT];
-#pragma unroll
-  for (int i = 0; i < SPT; ++i) key[i] = id[i] != SL_EMPTY ? ((uint64_t)est[i] << 32) | (uint32_t)~id[i] : 0ull;
-  // 3. distinct ids: the first insertion into the LDS id set represents the id
-  for (uint32_t e = tid; e < lay.hs_size; e += NT) hs[e] = SL_EMPTY;
-  __syncthreads();
-  uint32_t nrep = 0, emax = 0;
-#pragma unroll
-  for (int i = 0; i < SPT; ++i) {
-    if (id[i] != SL_EMPTY) {
-      uint32_t h = hs_slot(id[i], hs_log2);
-      bool rep = false;
-      for (;;) {
-        uint32_t prev = atomicCAS(&hs[h], SL_EMPTY, id[i]);
-        if (prev == SL_EMPTY) {
-          rep = true;
-          break;
-        }
-        if (prev == id[i]) break;
-        h = (h + 1) & hs_mask;
-      }
-      if (rep) {
+    for (int i = 0; i < SPT; ++i) {
+      if (at[i] != 0xFFFFFFFFu) {
+        const uint32_t cnt = hc[at[i]];
+        key[i] = ((uint64_t)cnt << 32) | (uint32_t)~id[i];
         ++nrep;
-        emax = max(emax, (uint32_t)(key[i] >> 32));
-      } else {
-        key[i] = 0;
+        emax = max(emax, cnt);
       }
     }
   }
@@ -327,23 +370,23 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   __syncthreads();
 }
 
-template <int WAVES, int SPT, bool CL>
+template <int WAVES, int SPT, bool CL, bool EX>
 __global__ void __launch_bounds__(WAVES * SL_WAVE)
     k_query(Shape s, ConstView c, TablesView tab, QueryArgs a) {
   extern __shared__ uint32_t lds[];
-  const QLayout lay = q_layout(s);
+  const QLayout lay = q_layout(s, EX);
   const ConstView cl = CL ? stage_consts(s, c, lds + lay.cst, WAVES * SL_WAVE) : c;
   __syncthreads();
   for (uint64_t q = blockIdx.x; q < a.q.n_rows; q += gridDim.x)
-    query_one<WAVES, SPT, CL>(s, cl, tab, a, (uint32_t)q, lds, lay);
+    query_one<WAVES, SPT, CL, EX>(s, cl, tab, a, (uint32_t)q, lds, lay);
 }
 
-template <int WAVES, int SPT, bool CL>
+template <int WAVES, int SPT, bool CL, bool EX>
 __global__ void __launch_bounds__(WAVES * SL_WAVE)
     k_query_persistent(Shape s, ConstView c, TablesView tab, QueryArgs a, uint32_t per_ticket, uint32_t* ticket) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t base_sh;
-  const QLayout lay = q_layout(s);
+  const QLayout lay = q_layout(s, EX);
   const ConstView cl = CL ? stage_consts(s, c, lds + lay.cst, WAVES * SL_WAVE) : c;
   const uint64_t n = a.q.n_rows;
   // the next ticket is taken while the current one is answered, so the
@@ -358,7 +401,7 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE)
     if (base >= n) break;
     if (threadIdx.x == 0) next = atomicAdd(ticket, per_ticket);
     const uint64_t stop = base + per_ticket < n ? base + per_ticket : n;
-    for (uint64_t q = base; q < stop; ++q) query_one<WAVES, SPT, CL>(s, cl, tab, a, (uint32_t)q, lds, lay);
+    for (uint64_t q = base; q < stop; ++q) query_one<WAVES, SPT, CL, EX>(s, cl, tab, a, (uint32_t)q, lds, lay);
   }
 }
 
@@ -367,14 +410,16 @@ struct KPair {
   const void* persistent;
 };
 
-template <int W, int S, bool CL>
+template <int W, int S, bool CL, bool EX>
 constexpr KPair kp1() {
-  return KPair{(const void*)k_query<W, S, CL>, (const void*)k_query_persistent<W, S, CL>};
+  return KPair{(const void*)k_query<W, S, CL, EX>, (const void*)k_query_persistent<W, S, CL, EX>};
 }
 template <int W, int S>
-constexpr KPair kp() { return kp1<W, S, true>(); }
+constexpr KPair kp() { return kp1<W, S, true, false>(); }
 template <int W, int S>
-constexpr KPair kg() { return kp1<W, S, false>(); }
+constexpr KPair kg() { return kp1<W, S, false, false>(); }
+template <int W, int S>
+constexpr KPair kx() { return kp1<W, S, true, true>(); }
 
 // kernels reading global constants (tables too large for LDS)
 const KPair kKernelsG[5][5] = {
@@ -394,19 +439,30 @@ const KPair kKernels[5][5] = {
     {kp<16, 1>(), kp<16, 2>(), kp<16, 4>(), kp<16, 8>(), kp<16, 16>()},
 };
 
+// exact-multiplicity kernels (constants staged in LDS)
+const KPair kKernelsX[5][5] = {
+    {kx<1, 1>(), kx<1, 2>(), kx<1, 4>(), kx<1, 8>(), kx<1, 16>()},
+    {kx<2, 1>(), kx<2, 2>(), kx<2, 4>(), kx<2, 8>(), kx<2, 16>()},
+    {kx<4, 1>(), kx<4, 2>(), kx<4, 4>(), kx<4, 8>(), kx<4, 16>()},
+    {kx<8, 1>(), kx<8, 2>(), kx<8, 4>(), kx<8, 8>(), kx<8, 16>()},
+    {kx<16, 1>(), kx<16, 2>(), kx<16, 4>(), kx<16, 8>(), kx<16, 16>()},
+};
+
 int ilog2(uint32_t x) {
   int b = 0;
   while ((1u << b) < x) ++b;
   return b;
 }
 
-// Kernel pair for `waves` waves per query, or nullptr.
-const KPair* pick(const Shape& s, uint32_t waves) {
+// Kernel pair for `waves` waves per query, or nullptr (the exact variant
+// needs the constants staged in LDS).
+const KPair* pick(const Shape& s, uint32_t waves, bool exact) {
   if (waves == 0 || waves > 16 || (waves & (waves - 1))) return nullptr;
   uint32_t slots = s.L * s.R;
   uint32_t spt = (slots + waves * SL_WAVE - 1) / (waves * SL_WAVE);
   if (spt > kMaxSpt) return nullptr;
   const int wi = ilog2(waves), si = ilog2(spt < 1 ? 1 : spt);
+  if (exact) return q_layout(s).cst_fit ? &kKernelsX[wi][si] : nullptr;
   return q_layout(s).cst_fit ? &kKernels[wi][si] : &kKernelsG[wi][si];
 }
 
@@ -429,25 +485,25 @@ uint32_t query_default_waves(const Shape& s) {
 
 int query_block_threads(const Shape& s, uint32_t waves) { return (int)(waves * SL_WAVE); }
 
-size_t query_lds_bytes(const Shape& s, uint32_t waves) {
+size_t query_lds_bytes(const Shape& s, uint32_t waves, bool exact) {
   (void)waves;
-  return (size_t)q_layout(s).total * 4;
+  return (size_t)q_layout(s, exact).total * 4;
 }
 
-bool query_supported(const Shape& s, uint32_t waves) {
-  if (!pick(s, waves)) return false;
+bool query_supported(const Shape& s, uint32_t waves, bool exact) {
+  if (!pick(s, waves, exact)) return false;
   if (s.L * s.R > 65535u) return false;
-  return query_lds_bytes(s, waves) <= (size_t)kLdsWords * 4;
+  return query_lds_bytes(s, waves, exact) <= (size_t)kLdsWords * 4;
 }
 
-bool query_supported(const Shape& s) { return query_supported(s, query_default_waves(s)); }
+bool query_supported(const Shape& s) { return query_supported(s, query_default_waves(s), false); }
 
 hipError_t launch_query_waves(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
                               uint32_t waves, hipStream_t st) {
   if (a.q.n_rows == 0) return hipSuccess;
-  if (!query_supported(s, waves)) return hipErrorInvalidValue;
-  const KPair* k = pick(s, waves);
-  size_t lds = query_lds_bytes(s, waves);
+  if (!query_supported(s, waves, a.exact != 0)) return hipErrorInvalidValue;
+  const KPair* k = pick(s, waves, a.exact != 0);
+  size_t lds = query_lds_bytes(s, waves, a.exact != 0);
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
   uint32_t grid = (uint32_t)(a.q.n_rows < (1u << 30) ? a.q.n_rows : (1u << 30));
@@ -469,10 +525,10 @@ hipError_t launch_query(const Shape& s, const ConstView& c, const TablesView& ta
 hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
                                    uint32_t waves, uint32_t per_ticket, uint32_t grid, uint32_t* ticket,
                                    hipStream_t st) {
-  if (!query_supported(s, waves)) return hipErrorInvalidValue;
+  if (!query_supported(s, waves, a.exact != 0)) return hipErrorInvalidValue;
   if (per_ticket == 0) per_ticket = 1;
-  const KPair* k = pick(s, waves);
-  size_t lds = query_lds_bytes(s, waves);
+  const KPair* k = pick(s, waves, a.exact != 0);
+  size_t lds = query_lds_bytes(s, waves, a.exact != 0);
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
   Shape sh = s;
@@ -485,16 +541,16 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
   return hipGetLastError();
 }
 
-void* persistent_query_kernel(const Shape& s, uint32_t waves) {
-  const KPair* k = pick(s, waves);
+void* persistent_query_kernel(const Shape& s, uint32_t waves, bool exact) {
+  const KPair* k = pick(s, waves, exact);
   return k ? const_cast<void*>(k->persistent) : nullptr;
 }
 
 // Occupancy of the persistent kernel: resident work-groups per CU.
-hipError_t query_occupancy(const Shape& s, uint32_t waves, int* per_cu) {
-  const KPair* k = pick(s, waves);
+hipError_t query_occupancy(const Shape& s, uint32_t waves, int* per_cu, bool exact) {
+  const KPair* k = pick(s, waves, exact);
   if (!k) return hipErrorInvalidValue;
-  size_t lds = query_lds_bytes(s, waves);
+  size_t lds = query_lds_bytes(s, waves, exact);
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k->persistent, waves * SL_WAVE, lds);

@@ -160,7 +160,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
 // Kernel entry of the fill kernel (for HIP graph nodes): (uint32_t* p, uint32_t v, uint64_t n).
 void* fill_kernel_ptr();
 // Kernel entry of the persistent query kernel for `waves` waves per query.
-void* persistent_query_kernel(const Shape& s, uint32_t waves);
+void* persistent_query_kernel(const Shape& s, uint32_t waves, bool exact = false);
 hipError_t launch_validate_indices(const int32_t* idx, uint64_t n, uint32_t dim, uint32_t* flag, hipStream_t st);
 hipError_t launch_item_ids(uint32_t* vals, uint32_t first_id, uint64_t n_rows, uint64_t items, hipStream_t st);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t first, uint64_t n, hipStream_t st);
@@ -214,17 +214,18 @@ struct QueryArgs {
   uint32_t* out_ids;
   uint32_t* out_scores;
   const uint32_t* qbk;  // bucket ids [n][L] hashed beforehand, or NULL (hash in the query kernel)
+  uint32_t exact = 0;   // 1: rank by exact multiplicity instead of the count-min estimate
 };
 // Kernel entry of the row-major hash kernel for this shape and its launch
 // geometry (for HIP graph nodes): (Shape, ConstView, slash_csr, uint32_t* out).
 void* hash_rowmajor_kernel(const Shape& s, uint32_t* threads, size_t* lds);
 uint32_t hash_rowmajor_grid(const Shape& s, uint64_t n_rows);
 int query_block_threads(const Shape& s, uint32_t waves);
-size_t query_lds_bytes(const Shape& s, uint32_t waves);
+size_t query_lds_bytes(const Shape& s, uint32_t waves, bool exact = false);
 bool query_supported(const Shape& s);
-bool query_supported(const Shape& s, uint32_t waves);
+bool query_supported(const Shape& s, uint32_t waves, bool exact = false);
 uint32_t query_default_waves(const Shape& s);
-hipError_t query_occupancy(const Shape& s, uint32_t waves, int* per_cu);
+hipError_t query_occupancy(const Shape& s, uint32_t waves, int* per_cu, bool exact = false);
 hipError_t launch_query_waves(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
                               uint32_t waves, hipStream_t st);
 hipError_t launch_query(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,

@@ -201,6 +201,20 @@ def test_query_parity(api, qsetup, k):
     assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
 
 
+@pytest.mark.parametrize("k", [1, 10, 24])
+def test_query_exact_variant(api, qsetup, k):
+    # ranking by exact multiplicity (the oracle's exact variant), plain and
+    # batched, and the count-min estimate never below the exact count
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    gi, gs = idx.query(dev(qi), dev(qx), k, flags=api.FLAG_EXACT)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, k, k_max=24, exact=True)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+    bi, bs = idx.query_batched(dev(qi), dev(qx), k, flags=api.FLAG_EXACT)
+    torch.cuda.synchronize()
+    assert (u32(bi) == wi).all() and (u32(bs) == ws).all()
+    assert int(ws.max()) <= op.L
+
+
 def test_query_small_batches(api, qsetup):
     # batches too small to fill the GPU run each query with 16 waves
     idx, op, cs, oids, oseen, qi, qx = qsetup
@@ -340,5 +354,8 @@ def test_wide_config_end_to_end(api, log2_buckets):
     bi, bs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
     torch.cuda.synchronize()
     assert (u32(bi) == wi).all() and (u32(bs) == ws).all()
+    ei, es = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=100, kq=kq, exact=True)
+    gi, gs = idx.query(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)), flags=api.FLAG_EXACT)
+    assert (u32(gi) == ei).all() and (u32(gs) == es).all()
     if log2_buckets == 6:
         assert int(oseen.min()) > 128  # every reservoir full
