@@ -128,27 +128,46 @@ __device__ __forceinline__ bool domain_any(const lds_u32* mask, uint32_t lo, uin
 
 // Per-bin minima of one row's nonzero hashes (mode 0): a group of G lanes
 // takes 4·G nonzeros per round, loading all of them before hashing any, so a
-// row of up to 4·G nonzeros costs one memory round trip.
+// row of up to 4·G nonzeros costs one memory round trip.  load_batch loads
+// one round; a caller may load the first round early (x0, PRE = true) so that
+// its latency overlaps other work.
 template <int G>
-__device__ __forceinline__ void row_minima(const Shape& s, uint64_t a, uint64_t bb, const int32_t* __restrict__ idx,
-                                           uint32_t nnz, uint32_t gl, uint32_t* lds_m) {
-  constexpr uint32_t kC = 4;
+__device__ __forceinline__ void load_batch(const int32_t* __restrict__ idx, uint32_t e0, uint32_t nnz, uint32_t gl,
+                                           uint32_t (&x)[4]) {
+#pragma unroll
+  for (uint32_t c = 0; c < 4; ++c) {
+    const uint32_t e = e0 + c * G + gl;
+    x[c] = e < nnz ? (uint32_t)idx[e] : 0u;
+  }
+}
+
+template <int G>
+__device__ __forceinline__ void minima_batch(const Shape& s, uint64_t a, uint64_t bb, const uint32_t (&x)[4],
+                                             uint32_t e0, uint32_t nnz, uint32_t gl, uint32_t* lds_m) {
   const uint32_t msh = s.mshift;
-  for (uint32_t e0 = 0; e0 < nnz; e0 += kC * G) {
-    uint32_t x[kC];
 #pragma unroll
-    for (uint32_t c = 0; c < kC; ++c) {
-      const uint32_t e = e0 + c * G + gl;
-      x[c] = e < nnz ? (uint32_t)idx[e] : 0u;
+  for (uint32_t c = 0; c < 4; ++c) {
+    if (e0 + c * G + gl < nnz) {
+      const uint32_t u = nz_hash(a, bb, x[c]);
+      const uint32_t bin = msh == 0xFFu ? range_bin(u, s.M) : (msh ? u >> (32 - msh) : 0u);
+      atomicMin(&lds_m[bin], u);
     }
-#pragma unroll
-    for (uint32_t c = 0; c < kC; ++c) {
-      if (e0 + c * G + gl < nnz) {
-        const uint32_t u = nz_hash(a, bb, x[c]);
-        const uint32_t bin = msh == 0xFFu ? range_bin(u, s.M) : (msh ? u >> (32 - msh) : 0u);
-        atomicMin(&lds_m[bin], u);
-      }
-    }
+  }
+}
+
+template <int G, bool PRE = false>
+__device__ __forceinline__ void row_minima(const Shape& s, uint64_t a, uint64_t bb, const int32_t* __restrict__ idx,
+                                           uint32_t nnz, uint32_t gl, uint32_t* lds_m, const uint32_t* x0 = nullptr) {
+  uint32_t e0 = 0;
+  if constexpr (PRE) {
+    const uint32_t x[4] = {x0[0], x0[1], x0[2], x0[3]};
+    minima_batch<G>(s, a, bb, x, 0, nnz, gl, lds_m);
+    e0 = 4 * G;
+  }
+  for (; e0 < nnz; e0 += 4 * G) {
+    uint32_t x[4];
+    load_batch<G>(idx, e0, nnz, gl, x);
+    minima_batch<G>(s, a, bb, x, e0, nnz, gl, lds_m);
   }
 }
 
@@ -239,25 +258,36 @@ __device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const Cons
 // and its value fetched with one shuffle.  This is the same result as the
 // bin-by-bin circular walk over the pre-densification minima (a lane that
 // holds the only non-empty bins wraps onto itself).  Returns h, the P
-// densified values of the lane's bins.  Every lane of the wave must call.
-template <int G, int P, bool CL>
+// densified values of the lane's bins.  Every lane of the wave must call;
+// lds_m must be 16-byte aligned.
+template <int G, int P, bool CL, bool PRE = false>
 __device__ __forceinline__ void doph_regs(const Shape& s, const ConstView& c, const int32_t* __restrict__ idx,
-                                          uint32_t nnz, uint32_t* lds_m, uint32_t (&h)[P]) {
+                                          uint32_t nnz, uint32_t* lds_m, uint32_t (&h)[P],
+                                          const uint32_t* x0 = nullptr) {
   static_assert(P == 4 || P == 8 || P == 16, "bins per lane");
   static_assert(G == 16 || G == 32 || G == 64, "group size");
   const uint32_t lane = lane_id();
   const uint32_t gl = lane & (G - 1);
   const uint32_t gshift = lane & ~(uint32_t)(G - 1);
   const uint32_t b0 = gl * P;
-  typedef __attribute__((address_space(3))) uint32_t lw32;
-  lw32* m3 = (lw32*)lds_m;
+  // the lane's P bins are cleared and read back as 16-byte vectors (lds_m is
+  // 16-byte aligned), one LDS instruction per 4 bins
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) v4u lv4u;
+  lv4u* m4 = (lv4u*)(lds_m + b0);
 #pragma unroll
-  for (int j = 0; j < P; ++j) m3[b0 + j] = SL_EMPTY;
+  for (int q = 0; q < P / 4; ++q) m4[q] = (v4u)(SL_EMPTY);
   wave_sync();
-  row_minima<G>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m);
+  row_minima<G, PRE>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m, x0);
   wave_sync();
 #pragma unroll
-  for (int j = 0; j < P; ++j) h[j] = m3[b0 + j];
+  for (int q = 0; q < P / 4; ++q) {
+    const v4u t = m4[q];
+    h[4 * q] = t.x;
+    h[4 * q + 1] = t.y;
+    h[4 * q + 2] = t.z;
+    h[4 * q + 3] = t.w;
+  }
   uint32_t first = SL_EMPTY, last = SL_EMPTY;
 #pragma unroll
   for (int j = P - 1; j >= 0; --j)
@@ -308,10 +338,26 @@ __device__ __forceinline__ void table_buckets_regs(const Shape& s, const ConstVi
                                                    uint32_t gl, Emit emit) {
   const uint32_t b0 = gl * P;
   const uint32_t kmask = s.K - 1, kshift = (uint32_t)__builtin_ctz(s.K);  // K is a power of two here
+  uint64_t a[P];
+  if constexpr (CL) {
+    // the lane's P multipliers as 16-byte LDS vectors (two per vector)
+    typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const v2u64 lv2u64;
+    const lv2u64* av = (const lv2u64*)(c.a_tj + b0);
+#pragma unroll
+    for (int q = 0; q < P / 2; ++q) {
+      const v2u64 t = av[q];
+      a[2 * q] = t.x;
+      a[2 * q + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < P; ++j) a[j] = c.a_tj[b0 + j];
+  }
   uint64_t acc = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    acc += cld64<CL>(c.a_tj, b0 + j) * (uint64_t)h[j];
+    acc += a[j] * (uint64_t)h[j];
     if (((j + 1) & kmask) == 0) {
       const uint32_t t = (b0 + j) >> kshift;
       emit(t, (uint32_t)((acc + cld64<CL>(c.b_t, t)) >> (64 - s.B)));

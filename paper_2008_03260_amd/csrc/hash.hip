@@ -18,14 +18,15 @@ __host__ __device__ inline uint32_t group_lds_words(const Shape& s, int P) {
 
 // Hash one row with a group of G lanes and call emit(t, bucket) for its L
 // tables (P > 0: register densification with P bins per lane, else the
-// generic LDS walk).  Every lane of the wave calls.
-template <int G, int P, bool CL, class Emit>
+// generic LDS walk).  With PRE the row's first 4·G indices are already in x0
+// (register form only).  Every lane of the wave calls.
+template <int G, int P, bool CL, bool PRE = false, class Emit>
 __device__ __forceinline__ void hash_row(const Shape& s, const ConstView& c, const int32_t* idx, uint32_t nnz,
-                                         bool live, uint32_t* my, Emit emit) {
+                                         bool live, uint32_t* my, Emit emit, const uint32_t* x0 = nullptr) {
   const uint32_t gl = threadIdx.x & (G - 1);
   if constexpr (P > 0) {
     uint32_t h[P];
-    doph_regs<G, P, CL>(s, c, idx, nnz, my, h);
+    doph_regs<G, P, CL, PRE>(s, c, idx, nnz, my, h, x0);
     if (live) table_buckets_regs<P, CL>(s, c, h, gl, emit);
   } else {
     const uint32_t* h = doph_group<G, CL>(s, c, idx, nnz, my);
@@ -48,40 +49,55 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
   const uint32_t ng = (blockDim.x / SL_WAVE) * GPW;
   const uint32_t grp = threadIdx.x / G;
   const uint32_t per_grp = group_lds_words(s, P);
-  const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
+  const uint32_t cw = CL ? (const_words(s) + 3) & ~3u : 0u;  // 16-byte aligned scratch after it
   const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
   uint32_t* my = lds + cw + grp * per_grp;
-  uint32_t* stage = lds + cw + ng * per_grp;  // [L][rpc]
+  uint32_t* stage = lds + cw + ng * per_grp;  // [L][rpc + 1]: the pad spreads one row's tables over banks
+  const uint32_t sst = rpc + 1;
   __syncthreads();
   const uint64_t n = rows.n_rows;
   const uint64_t n_chunks = (n + rpc - 1) / rpc;
   for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
     const uint64_t r0 = ch * rpc;
-    // every group runs the same number of rounds (wave-wide syncs inside);
-    // the row bounds of the group's next round are loaded before this round
-    // hashes, so their round trip overlaps the index loads
-    int64_t nbeg = 0, nend = 0;
-    if (grp < rpc && r0 + grp < n) {
-      nbeg = rows.indptr[r0 + grp];
-      nend = rows.indptr[r0 + grp + 1];
-    }
+    // Every group runs the same number of rounds (wave-wide syncs inside).
+    // Software pipeline over the group's rows of this chunk: while row j is
+    // hashed, the first indices of row j+1 and the bounds of row j+2 are in
+    // flight.
+    auto bounds = [&](uint32_t rl, int64_t& b, int64_t& e) {
+      if (rl < rpc && r0 + rl < n) {
+        b = rows.indptr[r0 + rl];
+        e = rows.indptr[r0 + rl + 1];
+      } else {
+        b = e = 0;
+      }
+    };
+    const uint32_t gl = threadIdx.x & (G - 1);
+    int64_t b0, e0, b1, e1;
+    bounds(grp, b0, e0);
+    bounds(grp + ng, b1, e1);
+    uint32_t x[4];
+    if constexpr (P > 0) load_batch<G>(rows.indices + b0, 0, (uint32_t)(e0 - b0), gl, x);
     for (uint32_t rb = 0; rb < rpc; rb += ng) {
       const uint32_t rl = rb + grp;
-      const uint64_t r = r0 + rl;
-      const bool live = rl < rpc && r < n;
-      const int64_t beg = nbeg, end = nend;
-      if (rl + ng < rpc && r + ng < n) {
-        nbeg = rows.indptr[r + ng];
-        nend = rows.indptr[r + ng + 1];
-      }
-      hash_row<G, P, CL>(s, cl, rows.indices + beg, live ? (uint32_t)(end - beg) : 0u, live, my,
-                         [&](uint32_t t, uint32_t b) { stage[t * rpc + rl] = combine ? t * s.nb + b : b; });
+      const bool live = rl < rpc && r0 + rl < n;
+      const int64_t beg = b0;
+      const uint32_t nnz = (uint32_t)(e0 - b0);
+      uint32_t xc[4] = {x[0], x[1], x[2], x[3]};
+      if constexpr (P > 0) load_batch<G>(rows.indices + b1, 0, (uint32_t)(e1 - b1), gl, x);
+      b0 = b1;
+      e0 = e1;
+      bounds(rl + 2 * ng, b1, e1);
+      auto emit = [&](uint32_t t, uint32_t b) { stage[t * sst + rl] = combine ? t * s.nb + b : b; };
+      if constexpr (P > 0)
+        hash_row<G, P, CL, true>(s, cl, rows.indices + beg, live ? nnz : 0u, live, my, emit, xc);
+      else
+        hash_row<G, P, CL>(s, cl, rows.indices + beg, live ? nnz : 0u, live, my, emit);
     }
     __syncthreads();
     const uint32_t tot = s.L * rpc;
     for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
       uint32_t t = e / rpc, rl = e - t * rpc;
-      if (r0 + rl < n) keys[t * key_stride + r0 + rl] = stage[e];
+      if (r0 + rl < n) keys[t * key_stride + r0 + rl] = stage[t * sst + rl];
     }
     __syncthreads();
   }
@@ -94,7 +110,7 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
   constexpr uint32_t GPW = SL_WAVE / G;
   const uint32_t ng = (blockDim.x / SL_WAVE) * GPW;
   const uint32_t grp = threadIdx.x / G;
-  const uint32_t cw = CL ? (const_words(s) + 1) & ~1u : 0u;
+  const uint32_t cw = CL ? (const_words(s) + 3) & ~3u : 0u;  // 16-byte aligned scratch after it
   const ConstView cl = CL ? stage_consts(s, c, lds, blockDim.x) : c;
   uint32_t* my = lds + cw + grp * group_lds_words(s, P);
   __syncthreads();
@@ -117,7 +133,7 @@ __global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
 constexpr size_t kLdsCap = 160 * 1024;
 
 // LDS words ahead of the per-wave DOPH scratch.
-uint32_t const_lds_words(const Shape& s) { return const_staged(s) ? (const_words(s) + 1) & ~1u : 0u; }
+uint32_t const_lds_words(const Shape& s) { return const_staged(s) ? (const_words(s) + 3) & ~3u : 0u; }
 
 // Rows staged per chunk: at most 64, and the stage stays within 32 KB.
 uint32_t hash_rpc(const Shape& s) {
@@ -283,7 +299,7 @@ hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, 
   if (rows.n_rows == 0) return hipSuccess;
   if (!hash_shape_ok(s)) return hipErrorInvalidValue;
   const uint32_t rpc = hash_rpc(s);
-  const size_t stage = (size_t)s.L * rpc * 4 + (size_t)const_lds_words(s) * 4;
+  const size_t stage = (size_t)s.L * (rpc + 1) * 4 + (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, stage);
   const size_t lds = hash_lds(s, nw, stage);
   const void* fn = hash_rows_fn(s);
