@@ -45,8 +45,7 @@ __host__ __device__ inline QLayout q_layout(const Shape& s, bool exact = false) 
   o.cst = 0;
   o.doph = o.cst + (o.cst_fit ? ((o.cst_words + 1) & ~1u) : 0u);
   o.buckets = o.doph + 2 * s.M + ((s.M + 63) / 64) * 2;
-  o.cm = o.buckets + s.L;
-  if (o.cm & 1) o.cm++;  // 8-byte aligned: ranked keys are collected here
+  o.cm = (o.buckets + s.L + 3) & ~3u;  // 16-byte aligned: cleared as vectors, ranked keys collected here
   const uint32_t tail = 512 + 2 + 2 * s.k_max + 16;  // hist, alignment, sel, misc
   const uint32_t room = kLdsWords > o.cm + tail ? kLdsWords - (o.cm + tail) : 0u;
   // The id set holds at most L * R distinct ids: twice that (load <= 1/2)
@@ -370,8 +369,13 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   __syncthreads();
 }
 
+// Register budget: at least 4 waves per SIMD (at most 128 VGPRs) for the
+// 4-wave groups, whose LDS lets 7 of them share a CU.
+template <int WAVES>
+constexpr int query_min_waves() { return WAVES <= 4 ? 4 : 1; }
+
 template <int WAVES, int SPT, bool CL, bool EX>
-__global__ void __launch_bounds__(WAVES * SL_WAVE)
+__global__ void __launch_bounds__(WAVES * SL_WAVE, query_min_waves<WAVES>())
     k_query(Shape s, ConstView c, TablesView tab, QueryArgs a) {
   extern __shared__ uint32_t lds[];
   const QLayout lay = q_layout(s, EX);
@@ -382,7 +386,7 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE)
 }
 
 template <int WAVES, int SPT, bool CL, bool EX>
-__global__ void __launch_bounds__(WAVES * SL_WAVE)
+__global__ void __launch_bounds__(WAVES * SL_WAVE, query_min_waves<WAVES>())
     k_query_persistent(Shape s, ConstView c, TablesView tab, QueryArgs a, uint32_t per_ticket, uint32_t* ticket) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t base_sh;

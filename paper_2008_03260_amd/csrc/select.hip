@@ -178,20 +178,18 @@ __device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __re
     uint32_t need = R, prefix = 0;
     for (int shift = 24; shift >= 0; shift -= 8) {
       const uint32_t hi_mask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
-#pragma unroll
-      for (int c = 0; c < 4; ++c) hist[4 * lane + c] = 0;
+      typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+      v4u* hv = (v4u*)hist;  // lane owns digits 4*lane .. 4*lane+3 as one vector
+      hv[lane] = (v4u)(0u);
       wave_sync();
 #pragma unroll
       for (int c = 0; c < kC; ++c)
         if (id[c] != SL_EMPTY && (pr[c] & hi_mask) == prefix) atomicAdd(&hist[(pr[c] >> shift) & 255u], 1u);
       wave_sync();
       // lane owns digits 4*lane .. 4*lane+3
-      uint32_t h[4], mine = 0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        h[c] = hist[4 * lane + c];
-        mine += h[c];
-      }
+      const v4u hl = hv[lane];
+      const uint32_t h[4] = {hl.x, hl.y, hl.z, hl.w};
+      const uint32_t mine = h[0] + h[1] + h[2] + h[3];
       uint32_t inc = mine;
 #pragma unroll
       for (int o = 1; o < SL_WAVE; o <<= 1) {
