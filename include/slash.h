@@ -121,8 +121,11 @@ typedef struct {
  * per bucket the R ids of smallest priority p_t(id) in ascending priority,
  * plus seen = the number of ids hashed there.  Row i gets id i.  Tables live
  * in device memory: ids [L][2^B][R] (uint32, 0xFFFFFFFF-padded), seen
- * [L][2^B] (uint32).  Synchronises `stream` before returning (validation
- * flag, work-list sizes).  Errors: E_INVAL (params, rows), E_NOMEM,
+ * [L][2^B] (uint32).  Rows are checked (non-empty, indptr increasing)
+ * before any work; indices are checked against [0, dim) by the hash kernel
+ * itself, and the build stops with E_INVAL after the hash pass when one is
+ * outside.  Synchronises `stream` before returning (validation flags,
+ * work-list sizes).  Errors: E_INVAL (params, rows, indices), E_NOMEM,
  * E_CAPACITY (n_rows > 0xFFFFFFFE), E_UNSUPPORTED, E_DEVICE.  *out is set
  * only on success. */
 SLASH_API slash_status slash_build(const slash_params* params, slash_csr data, void* stream, slash_index** out);

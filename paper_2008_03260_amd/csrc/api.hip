@@ -328,8 +328,12 @@ static void destroy_index(slash_index* ix) {
 extern "C" void slash_free(slash_index* ix) { destroy_index(ix); }
 
 // Device-side validation of rows (and per-query k); reads back one flag.
+// Checks rows (non-empty, indptr increasing), per-query k and, unless
+// check_indices is false (the build checks indices while hashing them), that
+// every index is in [0, dim).
 static slash_status validate_rows(slash_index* ix, slash_csr rows, const uint32_t* kq, hipStream_t st,
-                                  PhaseTimer* timer = nullptr, int64_t* nnz_out = nullptr) {
+                                  PhaseTimer* timer = nullptr, int64_t* nnz_out = nullptr,
+                                  bool check_indices = true) {
   if (rows.n_rows == 0) return SLASH_OK;
   if (!rows.indptr || !rows.indices) return fail(SLASH_E_INVAL, "CSR pointers are NULL");
   int64_t ends[2];
@@ -341,7 +345,8 @@ static slash_status validate_rows(slash_index* ix, slash_csr rows, const uint32_
   HIP_TRY(launch_fill_u32(ix->flag, 0u, 1, st));
   if (timer) timer->begin(PH_VALIDATE, st);
   HIP_TRY(launch_validate(rows, ix->p.dim, kq, ix->p.k_max, ix->flag, st));
-  HIP_TRY(launch_validate_indices(rows.indices + ends[0], (uint64_t)(ends[1] - ends[0]), ix->p.dim, ix->flag, st));
+  if (check_indices)
+    HIP_TRY(launch_validate_indices(rows.indices + ends[0], (uint64_t)(ends[1] - ends[0]), ix->p.dim, ix->flag, st));
   if (timer) timer->end(PH_VALIDATE, st);
   uint32_t f = 0;
   HIP_TRY(hipMemcpyAsync(&f, ix->flag, 4, hipMemcpyDeviceToHost, st));
@@ -471,7 +476,7 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
   if ((rs = alloc_tables(ix)) != SLASH_OK) return bail(rs);
   EventTimer timer;
   int64_t nnz = 0;
-  if ((rs = validate_rows(ix, data, nullptr, st, &timer, &nnz)) != SLASH_OK) return bail(rs);
+  if ((rs = validate_rows(ix, data, nullptr, st, &timer, &nnz, false)) != SLASH_OK) return bail(rs);
   const Shape& s = ix->shape;
   const uint64_t n = data.n_rows;
   {
@@ -487,10 +492,20 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
         !hist.get(hist_n * 4) || !part.get(part_n * 4) || !start.get((size_t)s.nb * 4) ||
         !end.get((size_t)s.nb * 4) || !heavy.get((size_t)s.nb * 12) || !heavy_n.get(4))
       return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
+    // the hash kernel also checks every index against [0, dim) (flag bit 2)
+    ConstView cvb = ix->cv;
+    cvb.bad = ix->flag;
     timer.begin(PH_HASH, st);
-    hipError_t e = launch_hash_rows(s, ix->cv, data, keys.as<uint32_t>(), n, 0, st);
+    hipError_t e = launch_hash_rows(s, cvb, data, keys.as<uint32_t>(), n, 0, st);
     timer.end(PH_HASH, st);
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "hash: %s", hipGetErrorString(e)));
+    {
+      uint32_t f = 0;
+      e = hipMemcpyAsync(&f, ix->flag, 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "hash: %s", hipGetErrorString(e)));
+      if (f & 2u) return bail(fail(SLASH_E_INVAL, "a feature index is outside [0, dim)"));
+    }
     SortBuffers sb{k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), hist.as<uint32_t>(),
                    part.as<uint32_t>()};
     std::vector<std::vector<uint8_t>> keep;

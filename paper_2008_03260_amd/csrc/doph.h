@@ -141,33 +141,40 @@ __device__ __forceinline__ void load_batch(const int32_t* __restrict__ idx, uint
   }
 }
 
+// With `bad` set, an index outside [0, dim) ORs 2 into *bad (the build checks
+// its input while hashing it).
 template <int G>
 __device__ __forceinline__ void minima_batch(const Shape& s, uint64_t a, uint64_t bb, const uint32_t (&x)[4],
-                                             uint32_t e0, uint32_t nnz, uint32_t gl, uint32_t* lds_m) {
+                                             uint32_t e0, uint32_t nnz, uint32_t gl, uint32_t* lds_m,
+                                             uint32_t* bad) {
   const uint32_t msh = s.mshift;
+  bool out = false;
 #pragma unroll
   for (uint32_t c = 0; c < 4; ++c) {
     if (e0 + c * G + gl < nnz) {
+      out |= (int32_t)x[c] < 0 || x[c] >= s.dim;
       const uint32_t u = nz_hash(a, bb, x[c]);
       const uint32_t bin = msh == 0xFFu ? range_bin(u, s.M) : (msh ? u >> (32 - msh) : 0u);
       atomicMin(&lds_m[bin], u);
     }
   }
+  if (bad && out) atomicOr(bad, 2u);
 }
 
 template <int G, bool PRE = false>
 __device__ __forceinline__ void row_minima(const Shape& s, uint64_t a, uint64_t bb, const int32_t* __restrict__ idx,
-                                           uint32_t nnz, uint32_t gl, uint32_t* lds_m, const uint32_t* x0 = nullptr) {
+                                           uint32_t nnz, uint32_t gl, uint32_t* lds_m, const uint32_t* x0 = nullptr,
+                                           uint32_t* bad = nullptr) {
   uint32_t e0 = 0;
   if constexpr (PRE) {
     const uint32_t x[4] = {x0[0], x0[1], x0[2], x0[3]};
-    minima_batch<G>(s, a, bb, x, 0, nnz, gl, lds_m);
+    minima_batch<G>(s, a, bb, x, 0, nnz, gl, lds_m, bad);
     e0 = 4 * G;
   }
   for (; e0 < nnz; e0 += 4 * G) {
     uint32_t x[4];
     load_batch<G>(idx, e0, nnz, gl, x);
-    minima_batch<G>(s, a, bb, x, e0, nnz, gl, lds_m);
+    minima_batch<G>(s, a, bb, x, e0, nnz, gl, lds_m, bad);
   }
 }
 
@@ -199,12 +206,14 @@ __device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const Cons
   for (uint32_t w = gl; w < mask_words(M); w += G) mask[w] = 0u;
   wave_sync();
   if (s.mode == 0) {
-    row_minima<G>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m);
+    row_minima<G>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m, nullptr, c.bad);
   } else {
     const uint32_t L = s.L, K = s.K;
     for (uint32_t w = gl; w < nnz * L; w += G) {
       uint32_t e = w / L, t = w - e * L;
-      uint32_t u = nz_hash(cld64<CL>(c.a_h, t), cld64<CL>(c.b_h, t), (uint32_t)idx[e]);
+      const uint32_t x = (uint32_t)idx[e];
+      if (c.bad && ((int32_t)x < 0 || x >= s.dim)) atomicOr(c.bad, 2u);
+      uint32_t u = nz_hash(cld64<CL>(c.a_h, t), cld64<CL>(c.b_h, t), x);
       atomicMin(&lds_m[t * K + range_bin(u, K)], u);
     }
   }
@@ -278,7 +287,7 @@ __device__ __forceinline__ void doph_regs(const Shape& s, const ConstView& c, co
 #pragma unroll
   for (int q = 0; q < P / 4; ++q) m4[q] = (v4u)(SL_EMPTY);
   wave_sync();
-  row_minima<G, PRE>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m, x0);
+  row_minima<G, PRE>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m, x0, c.bad);
   wave_sync();
 #pragma unroll
   for (int q = 0; q < P / 4; ++q) {

@@ -30,6 +30,7 @@ struct ConstView {
   const uint32_t* m2_t;  // [L] odd
   const uint64_t* a_r;   // [d] count-min multipliers (odd)
   const uint64_t* b_r;   // [d]
+  uint32_t* bad = nullptr;  // when set, hashing ORs 2 here on an index outside [0, dim)
 };
 
 struct HostConsts {
