@@ -186,6 +186,16 @@ SLASH_API slash_status slash_hash(const slash_index* index, slash_csr rows, uint
 SLASH_API slash_status slash_export_tables(const slash_index* index, uint32_t* ids_dev, uint32_t* seen_dev,
                                  void* stream);
 
+/* Create an index from tables exported earlier (with the same params):
+ * ids [L][2^B][R] and seen [L][2^B] device buffers are copied in; n_items is
+ * the number of ids assigned so far (the next insert continues from it).
+ * Together with slash_export_tables this saves and restores an index (the
+ * caller moves the buffers to storage).  The tables are taken as they are
+ * (not checked).  Errors: E_INVAL (params, NULL buffers), E_CAPACITY
+ * (n_items > 0xFFFFFFFE), E_NOMEM, E_DEVICE.  Synchronises `stream`. */
+SLASH_API slash_status slash_import_tables(const slash_params* params, const uint32_t* ids_dev, const uint32_t* seen_dev,
+                                 uint64_t n_items, void* stream, slash_index** out);
+
 SLASH_API slash_status slash_index_info_get(const slash_index* index, slash_index_info* info);
 
 /* Per-phase timing of the build that made `index`, measured with HIP events

@@ -101,6 +101,7 @@ def lib() -> C.CDLL:
             "slash_autotune": ([vp, CSR, u32, P(Schedule), vp], st),
             "slash_hash": ([vp, CSR, u32, vp, vp], st),
             "slash_export_tables": ([vp, vp, vp, vp], st),
+            "slash_import_tables": ([P(Params), vp, vp, u64, vp, P(vp)], st),
             "slash_index_info_get": ([vp, P(IndexInfo)], st),
             "slash_build_profile": ([vp, vp, u32, P(u32)], st),
             "slash_free": ([vp], None),
@@ -229,6 +230,14 @@ def slash_export_tables(index, stream=None):
     return ids, seen
 
 
+def slash_import_tables(params: Params, ids: torch.Tensor, seen: torch.Tensor, n_items: int, stream=None) -> C.c_void_p:
+    """New index over exported tables (ids [L][2^B][R], seen [L][2^B] device tensors)."""
+    out = C.c_void_p()
+    _check(lib().slash_import_tables(C.byref(params), _ptr(ids.contiguous()), _ptr(seen.contiguous()), n_items,
+                                     _stream(stream), C.byref(out)), "slash_import_tables")
+    return out
+
+
 def slash_index_info_get(index) -> dict:
     info = IndexInfo()
     _check(lib().slash_index_info_get(index, C.byref(info)), "slash_index_info_get")
@@ -334,7 +343,14 @@ class Index:
 
     def __init__(self, params: Params, indptr, indices, stream=None):
         self.params = params
-        self.handle = slash_build(params, indptr, indices, stream)
+        self.handle = slash_build(params, indptr, indices, stream) if indptr is not None else None
+
+    @classmethod
+    def from_tables(cls, params: Params, ids, seen, n_items: int, stream=None):
+        """Index restored from exported tables (see tables())."""
+        self = cls(params, None, None)
+        self.handle = slash_import_tables(params, ids, seen, n_items, stream)
+        return self
 
     def close(self):
         if getattr(self, "handle", None):

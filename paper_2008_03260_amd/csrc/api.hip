@@ -367,83 +367,6 @@ static int ceil_log2(uint64_t x) {
 
 static const uint32_t kHeavy = 16384;  // items one wave handles per bucket / chunk
 
-namespace {
-struct HeavyBucket {
-  uint32_t bucket, seen;
-  uint64_t off;
-  uint64_t len;
-};
-}  // namespace
-
-// Finish the buckets with more than kHeavy items: split into chunks, reduce
-// every chunk to its bottom-R, repeat on the candidate lists until a bucket's
-// candidates fit one wave, then write its reservoir.
-static slash_status finish_heavy(slash_index* ix, uint32_t t, const uint32_t* svals, std::vector<HeavyBucket> hv,
-                                 DBuf& candA, DBuf& candB, DBuf& workbuf, std::vector<std::vector<uint8_t>>& keep,
-                                 hipStream_t st) {
-  const Shape& s = ix->shape;
-  const uint32_t* src = svals;
-  bool useA = true;
-  while (!hv.empty()) {
-    std::vector<FinalWork> fin;
-    std::vector<ChunkWork> chk;
-    std::vector<HeavyBucket> next;
-    uint32_t slot = 0;
-    for (const HeavyBucket& h : hv) {
-      if (h.len <= kHeavy) {
-        fin.push_back(FinalWork{h.off, (uint32_t)h.len, h.bucket, h.seen, 0});
-        continue;
-      }
-      uint64_t nch = (h.len + kHeavy - 1) / kHeavy;
-      HeavyBucket nh{h.bucket, h.seen, (uint64_t)slot * s.R, nch * s.R};
-      for (uint64_t c = 0; c < nch; ++c) {
-        uint64_t off = h.off + c * kHeavy;
-        uint32_t len = (uint32_t)std::min<uint64_t>(kHeavy, h.off + h.len - off);
-        chk.push_back(ChunkWork{off, len, slot++});
-      }
-      next.push_back(nh);
-    }
-    size_t wbytes = fin.size() * sizeof(FinalWork) + chk.size() * sizeof(ChunkWork) + 64;
-    keep.emplace_back(wbytes);
-    uint8_t* host = keep.back().data();
-    memcpy(host, fin.data(), fin.size() * sizeof(FinalWork));
-    size_t chk_off = (fin.size() * sizeof(FinalWork) + 15) & ~(size_t)15;
-    memcpy(host + chk_off, chk.data(), chk.size() * sizeof(ChunkWork));
-    // work descriptors live in their own buffer per round
-    DBuf* wb = new DBuf();
-    if (!wb->get(wbytes)) {
-      delete wb;
-      return fail(SLASH_E_NOMEM, "heavy-bucket work list allocation failed");
-    }
-    HIP_TRY(hipMemcpyAsync(wb->p, host, wbytes, hipMemcpyHostToDevice, st));
-    const FinalWork* dfin = (const FinalWork*)wb->p;
-    const ChunkWork* dchk = (const ChunkWork*)((uint8_t*)wb->p + chk_off);
-    slash_status rs = SLASH_OK;
-    if (!fin.empty()) {
-      hipError_t e = launch_select_final(s, ix->cv, t, src, dfin, (uint32_t)fin.size(), tables(ix), st);
-      if (e != hipSuccess) rs = fail(SLASH_E_DEVICE, "select_final: %s", hipGetErrorString(e));
-    }
-    if (rs == SLASH_OK && !chk.empty()) {
-      DBuf& dst = useA ? candA : candB;
-      if (!dst.get((size_t)slot * s.R * 4)) rs = fail(SLASH_E_NOMEM, "candidate buffer allocation failed");
-      if (rs == SLASH_OK) {
-        hipError_t e = launch_select_chunks(s, ix->cv, t, src, dchk, (uint32_t)chk.size(), dst.as<uint32_t>(), st);
-        if (e != hipSuccess) rs = fail(SLASH_E_DEVICE, "select_chunks: %s", hipGetErrorString(e));
-      }
-      src = dst.as<uint32_t>();
-      useA = !useA;
-    }
-    // the round's descriptors must outlive its kernels
-    hipError_t e = hipStreamSynchronize(st);
-    delete wb;
-    if (rs != SLASH_OK) return rs;
-    if (e != hipSuccess) return fail(SLASH_E_DEVICE, "heavy round: %s", hipGetErrorString(e));
-    hv.swap(next);
-    (void)workbuf;
-  }
-  return SLASH_OK;
-}
-
 static slash_status alloc_tables(slash_index* ix) {
   const Shape& s = ix->shape;
   size_t n_ids = (size_t)s.L * s.nb * s.R;
@@ -485,12 +408,15 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table init: %s", hipGetErrorString(e)));
   }
   if (n > 0) {
-    DBuf keys, k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, candA, candB, workbuf;
+    DBuf keys, k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, hchunks, hfinals, hcount, hcand;
     size_t hist_n = sort_hist_entries(n);
     size_t part_n = std::max(sort_part_entries(hist_n), sort_part_entries(n)) + 16;
+    const size_t hcap = heavy_chunk_capacity(n, kHeavy);
     if (!keys.get((size_t)s.L * n * 4) || !k0.get(n * 4) || !v0.get(n * 4) || !k1.get(n * 4) || !v1.get(n * 4) ||
         !hist.get(hist_n * 4) || !part.get(part_n * 4) || !start.get((size_t)s.nb * 4) ||
-        !end.get((size_t)s.nb * 4) || !heavy.get((size_t)s.nb * 12) || !heavy_n.get(4))
+        !end.get((size_t)s.nb * 4) || !heavy.get((size_t)s.nb * 12) || !heavy_n.get(4) ||
+        !hchunks.get(hcap * sizeof(ChunkWork)) || !hfinals.get((n / kHeavy + 1) * sizeof(FinalWork)) ||
+        !hcount.get(4) || !hcand.get(hcap * s.R * 4))
       return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
     // the hash kernel also checks every index against [0, dim) (flag bit 2)
     ConstView cvb = ix->cv;
@@ -508,7 +434,8 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
     }
     SortBuffers sb{k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), hist.as<uint32_t>(),
                    part.as<uint32_t>()};
-    std::vector<std::vector<uint8_t>> keep;
+    // every table is enqueued back to back: heavy buckets are planned and
+    // finished on the device, so the host never waits between tables
     for (uint32_t t = 0; t < s.L; ++t) {
       uint32_t *sk = nullptr, *sv = nullptr;
       e = radix_sort(keys.as<uint32_t>() + (uint64_t)t * n, nullptr, n, (int)s.B, sb, &sk, &sv, st, &timer);
@@ -523,23 +450,13 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
         e = launch_select_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
                                 heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
       timer.end(PH_SELECT, st);
+      timer.begin(PH_HEAVY, st);
+      if (e == hipSuccess)
+        e = launch_heavy(s, ix->cv, t, sv, n, heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), kHeavy,
+                         hchunks.as<ChunkWork>(), hfinals.as<FinalWork>(), hcount.as<uint32_t>(), hcand.as<uint32_t>(),
+                         tables(ix), st);
+      timer.end(PH_HEAVY, st);
       if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build table %u: %s", t, hipGetErrorString(e)));
-      uint32_t nh = 0;
-      e = hipMemcpyAsync(&nh, heavy_n.p, 4, hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build table %u: %s", t, hipGetErrorString(e)));
-      if (nh) {
-        std::vector<uint32_t> hl((size_t)nh * 3);
-        e = hipMemcpy(hl.data(), heavy.p, hl.size() * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "heavy list: %s", hipGetErrorString(e)));
-        std::vector<HeavyBucket> hv;
-        for (uint32_t i = 0; i < nh; ++i) hv.push_back(HeavyBucket{hl[3 * i], hl[3 * i + 2], hl[3 * i + 1], hl[3 * i + 2]});
-        std::sort(hv.begin(), hv.end(), [](const HeavyBucket& a, const HeavyBucket& b) { return a.bucket < b.bucket; });
-        timer.begin(PH_HEAVY, st);
-        rs = finish_heavy(ix, t, sv, hv, candA, candB, workbuf, keep, st);
-        timer.end(PH_HEAVY, st);
-        if (rs != SLASH_OK) return bail(rs);
-      }
     }
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build: %s", hipGetErrorString(e)));
@@ -836,6 +753,38 @@ extern "C" slash_status slash_export_tables(const slash_index* ix, uint32_t* ids
   const Shape& s = ix->shape;
   if (ids) HIP_TRY(hipMemcpyAsync(ids, ix->ids, (size_t)s.L * s.nb * s.R * 4, hipMemcpyDeviceToDevice, st));
   if (seen) HIP_TRY(hipMemcpyAsync(seen, ix->seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st));
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_import_tables(const slash_params* params, const uint32_t* ids, const uint32_t* seen,
+                                           uint64_t n_items, void* stream, slash_index** out) {
+  if (!out) return fail(SLASH_E_INVAL, "out is NULL");
+  slash_status rs = check_params(params);
+  if (rs != SLASH_OK) return rs;
+  if (!ids || !seen) return fail(SLASH_E_INVAL, "table buffers are NULL");
+  if (n_items > 0xFFFFFFFEull) return fail(SLASH_E_CAPACITY, "more than 2^32-2 ids");
+  hipStream_t st = (hipStream_t)stream;
+  slash_index* ix = new (std::nothrow) slash_index();
+  if (!ix) return fail(SLASH_E_NOMEM, "host allocation failed");
+  ix->p = *params;
+  ix->shape = make_shape(*params);
+  ix->hc = derive_consts(*params);
+  auto bail = [&](slash_status s) {
+    destroy_index(ix);
+    return s;
+  };
+  if (hipGetDevice(&ix->device) != hipSuccess ||
+      hipDeviceGetAttribute(&ix->n_cu, hipDeviceAttributeMultiprocessorCount, ix->device) != hipSuccess)
+    return bail(fail(SLASH_E_DEVICE, "device query failed"));
+  if ((rs = upload_consts(ix, st)) != SLASH_OK) return bail(rs);
+  if ((rs = alloc_tables(ix)) != SLASH_OK) return bail(rs);
+  const Shape& s = ix->shape;
+  hipError_t e = hipMemcpyAsync(ix->ids, ids, (size_t)s.L * s.nb * s.R * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(ix->seen, seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table copy: %s", hipGetErrorString(e)));
+  ix->n_items = n_items;
+  *out = ix;
   return SLASH_OK;
 }
 

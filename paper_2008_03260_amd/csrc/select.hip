@@ -287,14 +287,63 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
   }
 }
 
+// Heavy buckets planned on the device (no host round trip): one block turns
+// the heavy list written by k_select_light into chunk work (kHeavy ids per
+// chunk, each reduced to a bottom-R list in its own candidate slot) and one
+// final item per bucket (its chunks' candidate lists, merged by one wave).
+__global__ void __launch_bounds__(256)
+    k_heavy_plan(const uint32_t* __restrict__ heavy_list, const uint32_t* __restrict__ heavy_n, uint32_t R,
+                 uint32_t chunk_len, ChunkWork* __restrict__ chunks, FinalWork* __restrict__ finals,
+                 uint32_t* __restrict__ n_chunks) {
+  __shared__ uint32_t part[4];
+  __shared__ uint32_t carry_sh;
+  const uint32_t nh = *heavy_n, tid = threadIdx.x, lane = lane_id(), wave = tid / SL_WAVE;
+  if (tid == 0) carry_sh = 0;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < nh; b0 += 256) {
+    const uint32_t i = b0 + tid;
+    uint32_t bucket = 0, off = 0, len = 0, nch = 0;
+    if (i < nh) {
+      bucket = heavy_list[3 * i];
+      off = heavy_list[3 * i + 1];
+      len = heavy_list[3 * i + 2];
+      nch = (len + chunk_len - 1) / chunk_len;
+    }
+    uint32_t inc = nch;
+    for (int o = 1; o < SL_WAVE; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, SL_WAVE);
+      if (lane >= (uint32_t)o) inc += y;
+    }
+    if (lane == SL_WAVE - 1) part[wave] = inc;
+    __syncthreads();
+    uint32_t before = carry_sh;
+    for (uint32_t w = 0; w < wave; ++w) before += part[w];
+    const uint32_t first = before + inc - nch;
+    if (i < nh) {
+      finals[i] = FinalWork{(uint64_t)first * R, nch * R, bucket, len, 0};
+      for (uint32_t c = 0; c < nch; ++c) {
+        const uint32_t o = c * chunk_len;
+        chunks[first + c] = ChunkWork{(uint64_t)off + o, min(chunk_len, len - o), first + c};
+      }
+    }
+    __syncthreads();
+    if (tid == 255) carry_sh = first + nch;
+    __syncthreads();
+  }
+  if (tid == 0) *n_chunks = carry_sh;
+}
+
+// Chunk and final reductions of the heavy buckets (work counts read on the device).
 __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     k_select_chunks(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ src,
-                    const ChunkWork* __restrict__ work, uint32_t n_work, uint32_t* __restrict__ dst) {
+                        const ChunkWork* __restrict__ work, const uint32_t* __restrict__ n_work,
+                        uint32_t* __restrict__ dst) {
   extern __shared__ uint64_t lds64[];
   const uint32_t wave = threadIdx.x / SL_WAVE;
   uint64_t* my = lds64 + wave * wl_words(s.R);
   const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
-  for (uint32_t wi = blockIdx.x * kSelWaves + wave; wi < n_work; wi += gridDim.x * kSelWaves) {
+  const uint32_t nw = *n_work;
+  for (uint32_t wi = blockIdx.x * kSelWaves + wave; wi < nw; wi += gridDim.x * kSelWaves) {
     ChunkWork cw = work[wi];
     WaveList w = wl_init(my, s.R);
     wl_stream(w, src, cw.off, cw.len, key, m1, m2);
@@ -303,20 +352,41 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
   }
 }
 
+// One work-group per heavy bucket: each wave reduces a contiguous quarter of
+// the bucket's chunk candidates to a bottom-R list, then wave 0 merges the
+// other waves' lists into its own and writes the reservoir.
 __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     k_select_final(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ src,
-                   const FinalWork* __restrict__ work, uint32_t n_work, TablesView tab) {
+                   const FinalWork* __restrict__ work, const uint32_t* __restrict__ n_work, TablesView tab) {
   extern __shared__ uint64_t lds64[];
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
   uint64_t* my = lds64 + wave * wl_words(s.R);
+  uint64_t* lists = lds64 + kSelWaves * wl_words(s.R);       // [kSelWaves][R]
+  uint32_t* counts = (uint32_t*)(lists + kSelWaves * s.R);  // [kSelWaves]
   const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
-  for (uint32_t wi = blockIdx.x * kSelWaves + wave; wi < n_work; wi += gridDim.x * kSelWaves) {
-    FinalWork fw = work[wi];
+  const uint32_t nw = *n_work;
+  for (uint32_t wi = blockIdx.x; wi < nw; wi += gridDim.x) {
+    const FinalWork fw = work[wi];
+    const uint32_t q = ((fw.len + kSelWaves - 1) / kSelWaves + SL_WAVE - 1) / SL_WAVE * SL_WAVE;
+    const uint32_t lo = min(fw.len, wave * q), hi = min(fw.len, lo + q);
     WaveList w = wl_init(my, s.R);
-    wl_stream(w, src, fw.off, fw.len, key, m1, m2);
-    wl_write(w, tab.ids + ((uint64_t)t * s.nb + fw.bucket) * s.R, s.R);
-    if (lane == 0) tab.seen[(uint64_t)t * s.nb + fw.bucket] = fw.seen;
-    wave_sync();
+    wl_stream(w, src, fw.off + lo, hi - lo, key, m1, m2);
+    for (uint32_t i = lane; i < s.R; i += SL_WAVE) lists[wave * s.R + i] = i < w.cnt ? w.a[i] : kNoKey;
+    if (lane == 0) counts[wave] = w.cnt;
+    __syncthreads();
+    if (wave == 0) {
+      for (uint32_t o = 1; o < kSelWaves; ++o) {
+        const uint32_t n_o = counts[o];
+        for (uint32_t i = 0; i < n_o; i += SL_WAVE) {
+          const bool v = i + lane < n_o;
+          wl_offer(w, v, v ? lists[o * s.R + i + lane] : kNoKey);
+        }
+      }
+      wl_flush(w);
+      wl_write(w, tab.ids + ((uint64_t)t * s.nb + fw.bucket) * s.R, s.R);
+      if (lane == 0) tab.seen[(uint64_t)t * s.nb + fw.bucket] = fw.seen;
+    }
+    __syncthreads();
   }
 }
 
@@ -486,21 +556,21 @@ hipError_t launch_select_light(const Shape& s, const ConstView& c, uint32_t t, c
   return hipGetLastError();
 }
 
-hipError_t launch_select_chunks(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
-                                const ChunkWork* work, uint32_t n_work, uint32_t* dst, hipStream_t st) {
-  if (n_work == 0) return hipSuccess;
-  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
-  hipLaunchKernelGGL(k_select_chunks, dim3(grid_for(n_work, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st,
-                     s, c, t, src, work, n_work, dst);
-  return hipGetLastError();
-}
+size_t heavy_chunk_capacity(uint64_t n, uint32_t chunk_len) { return (size_t)(2 * (n / chunk_len) + 2); }
 
-hipError_t launch_select_final(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
-                               const FinalWork* work, uint32_t n_work, TablesView tab, hipStream_t st) {
-  if (n_work == 0) return hipSuccess;
-  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
-  hipLaunchKernelGGL(k_select_final, dim3(grid_for(n_work, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st,
-                     s, c, t, src, work, n_work, tab);
+hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* svals, uint64_t n,
+                        const uint32_t* heavy_list, const uint32_t* heavy_n, uint32_t chunk_len, ChunkWork* chunks,
+                        FinalWork* finals, uint32_t* n_chunks, uint32_t* cand, TablesView tab, hipStream_t st) {
+  hipLaunchKernelGGL(k_heavy_plan, dim3(1), dim3(256), 0, st, heavy_list, heavy_n, s.R, chunk_len, chunks, finals,
+                     n_chunks);
+  const size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  const uint32_t max_chunks = (uint32_t)heavy_chunk_capacity(n, chunk_len);
+  hipLaunchKernelGGL(k_select_chunks, dim3(grid_for(max_chunks, kSelWaves, 4096)), dim3(kSelWaves * SL_WAVE), lds,
+                     st, s, c, t, svals, chunks, n_chunks, cand);
+  const uint32_t max_heavy = (uint32_t)(n / chunk_len + 1);
+  const size_t lds_f = lds + (size_t)kSelWaves * s.R * 8 + kSelWaves * 4;
+  hipLaunchKernelGGL(k_select_final, dim3(max_heavy < 1024 ? max_heavy : 1024), dim3(kSelWaves * SL_WAVE), lds_f, st,
+                     s, c, t, cand, finals, heavy_n, tab);
   return hipGetLastError();
 }
 

@@ -182,9 +182,6 @@ struct ChunkWork {
   uint32_t len;
   uint32_t dst;  // output slot (in units of R)
 };
-hipError_t launch_select_chunks(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
-                                const ChunkWork* work, uint32_t n_work, uint32_t* dst, hipStream_t st);
-// Final: items [off, off+len) of src -> reservoir of bucket b, seen = seen_v.
 struct FinalWork {
   uint64_t off;
   uint32_t len;
@@ -192,8 +189,15 @@ struct FinalWork {
   uint32_t seen;
   uint32_t pad;
 };
-hipError_t launch_select_final(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* src,
-                               const FinalWork* work, uint32_t n_work, TablesView tab, hipStream_t st);
+// Finish the heavy buckets listed by launch_select_light entirely on the
+// device: plan chunks of chunk_len ids, reduce each chunk to a bottom-R
+// candidate list (cand: heavy_chunk_capacity(n) * R ids), merge each bucket's
+// candidates into its reservoir.  No host synchronisation.
+size_t heavy_chunk_capacity(uint64_t n, uint32_t chunk_len);
+hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* svals, uint64_t n,
+                        const uint32_t* heavy_list, const uint32_t* heavy_n, uint32_t chunk_len, ChunkWork* chunks,
+                        FinalWork* finals, uint32_t* n_chunks, uint32_t* cand, TablesView tab, hipStream_t st);
+
 
 // Small insert (n rows, keys [L][n] as written by launch_hash_rows without
 // combining): one block per table sorts, groups and merges in LDS.

@@ -150,6 +150,29 @@ def test_insert_equals_bulk_build(api):
     assert idx.info()["n_items"] == 9000
 
 
+def test_tables_export_import_roundtrip(api):
+    # an index restored from its exported tables answers and grows exactly
+    # like the original
+    gp, op = params_pair(api, L=6, log2_buckets=8, R=12)
+    law, (ip, ix) = rows_of(6000, seed=17)
+    a = api.Index(gp, dev(ip[:5001]), dev(ix[: ip[5000]]))
+    ids, seen = a.tables()
+    b = api.Index.from_tables(gp, ids.clone(), seen.clone(), 5000)
+    assert b.info()["n_items"] == 5000
+    tail = (dev(ip[5000:] - ip[5000]), dev(ix[ip[5000]:]))
+    a.insert(*tail)
+    b.insert(*tail)
+    torch.cuda.synchronize()
+    for x, y in zip(a.tables(), b.tables()):
+        assert torch.equal(x, y)
+    check_tables(api, b, op, oracle.constants(op), ip, ix)
+    qi, qx, _, _ = law.queries(synth.derive(17, synth.STREAM_QUERY), 6000, 0, 50)
+    ra, rb = a.query(dev(qi), dev(qx), 10), b.query(dev(qi), dev(qx), 10)
+    assert torch.equal(ra[0], rb[0]) and torch.equal(ra[1], rb[1])
+    with pytest.raises(api.SlashError):
+        api.Index.from_tables(gp, ids, seen, 2**32)
+
+
 def test_invalid_rows_rejected(api):
     gp, op = params_pair(api, dim=1000, L=2, log2_buckets=4, R=3)
     for rows in ([[1, 2], []], [[1, 2], [1000]], [[-3]]):
