@@ -481,6 +481,15 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
 
 // ----------------------------------------------------------------- insert
 
+slash_status slash::reserve_insert_scratch(slash_index* ix, uint64_t rows) {
+  if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
+  if (!small_insert_ok(ix->shape, rows)) return SLASH_OK;
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (!grow(ix->ins_keys, (size_t)rows * ix->shape.L * 4) || !grow(ix->ins_seg, small_insert_scratch(ix->shape, rows)))
+    return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
+  return SLASH_OK;
+}
+
 extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev,
                                      void* stream) {
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");

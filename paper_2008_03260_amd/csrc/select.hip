@@ -439,103 +439,242 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
 }
 
 // Small insert batches (n <= kSmallInsert rows), two kernels after hashing:
-// k_insert_sort - one block per table sorts the table's (bucket, id) pairs in
-//   LDS (bitonic), finds the bucket runs with a block scan and writes the
-//   sorted pairs, the run starts and the run count to scratch;
-// k_insert_runs - one wave per run, over the whole GPU, merges the run into
-//   its reservoir.
+// k_insert_group - one block per table groups the table's n new (bucket, id)
+//   pairs by bucket in an LDS open-addressing table, then writes one run
+//   record (bucket, first item, length) per distinct bucket, the ids of each
+//   run contiguously, and zero-length records up to n;
+// k_insert_merge16 - sixteen lanes per run record, over the whole GPU: the
+//   group holds the bucket's reservoir in registers (E entries per lane, in
+//   ascending priority) and inserts each new id whose priority is below the
+//   current R-th one at its rank (group sum of per-lane counts, one shift).
+// The bottom-R set does not depend on the order in which ids arrive, so the
+// grouping order is free.
 constexpr uint32_t kSmallInsert = 4096;
+constexpr uint32_t kGroupThreads = 1024;
+constexpr uint32_t kGroupItems = kSmallInsert / kGroupThreads;  // items per thread
+constexpr uint32_t kMergeThreads = 256;
 
-__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
-    k_insert_sort(const uint32_t* __restrict__ keys, uint32_t n, uint32_t first_id, uint64_t* __restrict__ sorted,
-                  uint32_t* __restrict__ starts, uint32_t* __restrict__ runs) {
-  extern __shared__ uint64_t lds64[];
-  constexpr uint32_t NT = kSelWaves * SL_WAVE;
-  const uint32_t t = blockIdx.x;
-  uint32_t P = 1;
-  while (P < n) P <<= 1;
-  uint64_t* comp = lds64;                    // [P] (bucket << 32 | id)
-  uint32_t* scan = (uint32_t*)(lds64 + P);   // [NT + 1]
-  for (uint32_t i = threadIdx.x; i < P; i += NT)
-    comp[i] = i < n ? ((uint64_t)keys[(uint64_t)t * n + i] << 32) | (first_id + i) : ~0ull;
+__host__ __device__ inline uint32_t group_cap_log2(uint32_t n) {
+  uint32_t c = 6;  // at least 64 slots, at most half full
+  while ((1u << c) < 2 * n) ++c;
+  return c;
+}
+
+// Block-wide exclusive scan of one value per thread (kGroupThreads threads);
+// returns the prefix and writes the total to *total.
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const uint32_t lane = lane_id(), wave = threadIdx.x / SL_WAVE;
+  constexpr uint32_t NW = kGroupThreads / SL_WAVE;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < SL_WAVE; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, SL_WAVE);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == SL_WAVE - 1) wsum[wave] = x;
   __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P; i += NT) {
-        uint32_t l = i ^ j;
-        if (l > i) {
-          uint64_t a = comp[i], b = comp[l];
-          bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            comp[i] = b;
-            comp[l] = a;
-          }
-        }
+  if (wave == 0) {
+    uint32_t w = lane < NW ? wsum[lane] : 0u;
+#pragma unroll
+    for (int o = 1; o < (int)NW; o <<= 1) {
+      uint32_t y = __shfl_up(w, o, SL_WAVE);
+      if (lane >= (uint32_t)o) w += y;
+    }
+    if (lane < NW) wsum[lane] = w;  // inclusive
+  }
+  __syncthreads();
+  uint32_t before = wave ? wsum[wave - 1] : 0u;
+  *total = wsum[NW - 1];
+  return before + x - v;
+}
+
+__global__ void __launch_bounds__(kGroupThreads)
+    k_insert_group(const uint32_t* __restrict__ keys, uint32_t n, uint32_t first_id, uint2* __restrict__ recs,
+                   uint32_t* __restrict__ items) {
+  extern __shared__ uint32_t lds32[];
+  const uint32_t t = blockIdx.x, tid = threadIdx.x;
+  const uint32_t cl = group_cap_log2(n), cap = 1u << cl;
+  uint32_t* slot_key = lds32;          // [cap] bucket or EMPTY
+  uint32_t* slot_cnt = lds32 + cap;    // [cap] ids in the run, then its first item
+  uint32_t* wsum = lds32 + 2 * cap;    // [kGroupThreads / SL_WAVE]
+  for (uint32_t i = tid; i < cap; i += kGroupThreads) {
+    slot_key[i] = 0xFFFFFFFFu;
+    slot_cnt[i] = 0;
+  }
+  uint32_t key[kGroupItems];
+#pragma unroll
+  for (uint32_t j = 0; j < kGroupItems; ++j) {
+    uint32_t i = tid + j * kGroupThreads;
+    key[j] = i < n ? keys[(uint64_t)t * n + i] : 0u;
+  }
+  __syncthreads();
+  uint32_t slot[kGroupItems], rank[kGroupItems];
+#pragma unroll
+  for (uint32_t j = 0; j < kGroupItems; ++j) {
+    uint32_t i = tid + j * kGroupThreads;
+    if (i < n) {
+      // linear probing from a multiplicative hash of the bucket id; the table
+      // is at most half full, so a free or matching slot is always found
+      uint32_t h = (key[j] * 0x9E3779B1u) >> (32 - cl);
+      for (;;) {
+        uint32_t prev = atomicCAS(&slot_key[h], 0xFFFFFFFFu, key[j]);
+        if (prev == 0xFFFFFFFFu || prev == key[j]) break;
+        h = (h + 1) & (cap - 1);
       }
-      __syncthreads();
+      slot[j] = h;
+      rank[j] = atomicAdd(&slot_cnt[h], 1u);
     }
   }
-  uint64_t* out = sorted + (uint64_t)t * n;
-  for (uint32_t i = threadIdx.x; i < n; i += NT) out[i] = comp[i];
-  // run heads -> compacted starts (each thread owns a contiguous slice)
-  const uint32_t per = (n + NT - 1) / NT;
-  const uint32_t i0 = min(n, threadIdx.x * per), i1 = min(n, i0 + per);
-  uint32_t cnt = 0;
-  for (uint32_t i = i0; i < i1; ++i) cnt += (i == 0 || (comp[i] >> 32) != (comp[i - 1] >> 32)) ? 1u : 0u;
-  scan[threadIdx.x] = cnt;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (uint32_t x = 0; x < NT; ++x) {
-      uint32_t v = scan[x];
-      scan[x] = acc;
-      acc += v;
-    }
-    scan[NT] = acc;
+  // number the runs and place their ids: each thread owns a slice of slots
+  const uint32_t per = (cap + kGroupThreads - 1) / kGroupThreads;
+  const uint32_t s0 = min(cap, tid * per), s1 = min(cap, s0 + per);
+  uint32_t nrun = 0, nitem = 0;
+  for (uint32_t h = s0; h < s1; ++h) {
+    uint32_t c = slot_cnt[h];
+    nrun += c ? 1u : 0u;
+    nitem += c;
   }
+  uint32_t tot;
+  // both counts are <= 4096: scan them packed in one word
+  uint32_t pre = block_scan_excl((nrun << 16) | nitem, wsum, &tot);
+  uint32_t r = pre >> 16, o = pre & 0xFFFFu;
+  uint2* rec = recs + (uint64_t)t * n;
+  for (uint32_t h = s0; h < s1; ++h) {
+    uint32_t c = slot_cnt[h];
+    if (c) {
+      rec[r++] = make_uint2(slot_key[h], o | (c << 16));
+      slot_cnt[h] = o;
+      o += c;
+    }
+  }
+  for (uint32_t i = (tot >> 16) + tid; i < n; i += kGroupThreads) rec[i] = make_uint2(0u, 0u);
   __syncthreads();
-  uint32_t* st = starts + (uint64_t)t * (n + 1);
-  uint32_t o = scan[threadIdx.x];
-  for (uint32_t i = i0; i < i1; ++i)
-    if (i == 0 || (comp[i] >> 32) != (comp[i - 1] >> 32)) st[o++] = i;
-  if (threadIdx.x == 0) {
-    st[scan[NT]] = n;
-    runs[t] = scan[NT];
+  uint32_t* it = items + (uint64_t)t * n;
+#pragma unroll
+  for (uint32_t j = 0; j < kGroupItems; ++j) {
+    uint32_t i = tid + j * kGroupThreads;
+    if (i < n) it[slot_cnt[slot[j]] + rank[j]] = first_id + i;
   }
 }
 
-// Block (t, c) merges runs [c * kSelWaves, (c + 1) * kSelWaves) of table t.
-__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
-    k_insert_runs(Shape s, ConstView c, const uint64_t* __restrict__ sorted, const uint32_t* __restrict__ starts,
-                  const uint32_t* __restrict__ runs, uint32_t n, uint32_t chunks, TablesView tab) {
-  extern __shared__ uint64_t lds64[];
-  const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
-  const uint32_t t = blockIdx.x / chunks, ch = blockIdx.x - t * chunks;
-  const uint32_t g = ch * kSelWaves + wave;
-  if (g >= runs[t]) return;  // whole wave leaves together (g is wave-uniform)
-  uint64_t* my = lds64 + wave * wl_words(s.R);
-  const uint32_t* st = starts + (uint64_t)t * (n + 1);
-  const uint64_t* comp = sorted + (uint64_t)t * n;
-  const uint32_t s0 = st[g], e0 = st[g + 1];
-  const uint32_t b = (uint32_t)(comp[s0] >> 32);
-  const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
-  uint32_t* res = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
-  uint32_t* seen = tab.seen + (uint64_t)t * s.nb + b;
-  WaveList w = wl_init(my, s.R);
-  const uint32_t old = *seen;
-  const uint32_t fill = min(old, s.R);
-  for (uint32_t i = lane; i < fill; i += SL_WAVE) w.a[i] = prio_key(res[i], key, m1, m2);
-  w.cnt = fill;
-  wave_sync();
-  for (uint32_t i = s0; i < e0; i += SL_WAVE) {
-    uint32_t j = i + lane;
-    bool v = j < e0;
-    uint32_t id = v ? (uint32_t)comp[j] : 0u;
-    wl_offer(w, v, v ? prio_key(id, key, m1, m2) : kNoKey);
+// Entry e of lane g (0..15) of the group is reservoir position g * E + e.
+template <int E>
+__device__ __forceinline__ void load_row(const uint32_t* __restrict__ row, uint32_t R, uint32_t g, uint32_t (&v)[E]) {
+  if (R == 16u * E && E >= 2) {
+    const uint32_t* p = row + g * E;
+    if constexpr (E == 2) {
+      uint2 x = *(const uint2*)p;
+      v[0] = x.x;
+      v[1] = x.y;
+    } else {
+#pragma unroll
+      for (int q = 0; q < E / 4; ++q) {
+        uint4 x = ((const uint4*)p)[q];
+        v[4 * q] = x.x;
+        v[4 * q + 1] = x.y;
+        v[4 * q + 2] = x.z;
+        v[4 * q + 3] = x.w;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = g * E + e < R ? row[g * E + e] : 0xFFFFFFFFu;
   }
-  wl_flush(w);
-  wl_write(w, res, s.R);
-  if (lane == 0) *seen = old + (e0 - s0);
+}
+
+template <int E>
+__device__ __forceinline__ void store_row(uint32_t* __restrict__ row, uint32_t R, uint32_t g, const uint32_t (&v)[E]) {
+  if (R == 16u * E && E >= 2) {
+    uint32_t* p = row + g * E;
+    if constexpr (E == 2) {
+      *(uint2*)p = make_uint2(v[0], v[1]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < E / 4; ++q) ((uint4*)p)[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (g * E + e < R) row[g * E + e] = v[e];
+  }
+}
+
+template <int E>
+__global__ void __launch_bounds__(kMergeThreads)
+    k_insert_merge16(Shape s, ConstView c, const uint2* __restrict__ recs, const uint32_t* __restrict__ items,
+                     uint32_t n, TablesView tab) {
+  const uint32_t lane = lane_id(), g = lane & 15u, gbase = lane & ~15u;
+  const uint64_t run = ((uint64_t)blockIdx.x * kMergeThreads + threadIdx.x) >> 4;
+  // every condition below is uniform over the sixteen lanes of a group, so
+  // the group's shuffles only read lanes of the same group
+  if (run >= (uint64_t)s.L * n) return;
+  const uint32_t t = (uint32_t)(run / n);
+  const uint2 rec = recs[run];
+  const uint32_t len = rec.y >> 16;
+  if (len == 0) return;
+  const uint32_t start = rec.y & 0xFFFFu, b = rec.x, R = s.R;
+  const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  uint32_t* row = tab.ids + ((uint64_t)t * s.nb + b) * R;
+  uint32_t* seen = tab.seen + (uint64_t)t * s.nb + b;
+  const uint32_t* it = items + (uint64_t)t * n + start;
+  uint32_t v[E], p[E];
+  load_row<E>(row, R, g, v);
+  const uint32_t old = *seen;
+  uint32_t nid = g < len ? it[g] : 0u;
+  uint32_t fill = min(old, R);
+#pragma unroll
+  for (int e = 0; e < E; ++e) p[e] = priority(v[e], key, m1, m2);
+  // priority of the entry at position R - 1 (meaningful once fill == R)
+  const uint32_t last_lane = gbase + (R - 1) / E, last_e = (R - 1) % E;
+  auto last_prio = [&]() {
+    uint32_t x = p[0];
+#pragma unroll
+    for (int e = 1; e < E; ++e)
+      if ((uint32_t)e == last_e) x = p[e];
+    return __shfl(x, last_lane, SL_WAVE);
+  };
+  bool dirty = false;
+  for (uint32_t c0 = 0; c0 < len; c0 += 16) {
+    if (c0) nid = c0 + g < len ? it[c0 + g] : 0u;
+    const uint32_t nq = priority(nid, key, m1, m2);
+    const bool full = fill == R;
+    const uint32_t lim = full ? last_prio() : 0u;
+    const bool cand = c0 + g < len && (!full || nq < lim);
+    uint32_t gm = (uint32_t)((__ballot(cand) >> gbase) & 0xFFFFull);
+    while (gm) {
+      const uint32_t src = __builtin_ctz(gm);
+      gm &= gm - 1;
+      const uint32_t x = __shfl(nid, gbase + src, SL_WAVE), q = __shfl(nq, gbase + src, SL_WAVE);
+      // rank of q among the live entries
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) cnt += (g * E + e < fill && p[e] < q) ? 1u : 0u;
+      cnt += __shfl_xor(cnt, 1, 16);
+      cnt += __shfl_xor(cnt, 2, 16);
+      cnt += __shfl_xor(cnt, 4, 16);
+      cnt += __shfl_xor(cnt, 8, 16);
+      const uint32_t pos = cnt;
+      if (pos >= R) continue;  // below none of a full reservoir's entries
+      dirty = true;
+      const uint32_t pp = __shfl_up(p[E - 1], 1, 16), pv = __shfl_up(v[E - 1], 1, 16);
+#pragma unroll
+      for (int e = E - 1; e >= 0; --e) {
+        const uint32_t k = g * E + e;
+        const uint32_t lp = e ? p[e - 1] : pp, lv = e ? v[e - 1] : pv;
+        if (k > pos) {
+          p[e] = lp;
+          v[e] = lv;
+        } else if (k == pos) {
+          p[e] = q;
+          v[e] = x;
+        }
+      }
+      fill = min(R, fill + 1);
+    }
+  }
+  if (dirty) store_row<E>(row, R, g, v);
+  if (g == 0) *seen = old + len;
 }
 
 uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap) {
@@ -574,33 +713,36 @@ hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const ui
   return hipGetLastError();
 }
 
-size_t small_insert_lds(uint32_t n) {
-  uint32_t P = 1;
-  while (P < n) P <<= 1;
-  constexpr uint32_t NT = kSelWaves * SL_WAVE;
-  return (size_t)P * 8 + (NT + 1) * 4;
-}
-
 bool small_insert_ok(const Shape& s, uint64_t n) { return n >= 1 && n <= kSmallInsert; }
 
-size_t small_insert_scratch(const Shape& s, uint64_t n) {
-  return (size_t)s.L * n * 8 + (size_t)s.L * (n + 1) * 4 + (size_t)s.L * 4 + 64;
-}
+// run records [L][n] (uint2) then run ids [L][n]
+size_t small_insert_scratch(const Shape& s, uint64_t n) { return (size_t)s.L * n * 12 + 64; }
 
 hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
                                void* scratch, TablesView tab, hipStream_t st) {
-  uint64_t* sorted = (uint64_t*)scratch;
-  uint32_t* starts = (uint32_t*)(sorted + (size_t)s.L * n);
-  uint32_t* runs = starts + (size_t)s.L * (n + 1);
-  size_t lds = small_insert_lds(n);
-  hipLaunchKernelGGL(k_insert_sort, dim3(s.L), dim3(kSelWaves * SL_WAVE), lds, st, keys, n, first_id, sorted, starts,
-                     runs);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const uint32_t chunks = (n + kSelWaves - 1) / kSelWaves;
-  size_t l2 = (size_t)kSelWaves * wl_words(s.R) * 8;
-  hipLaunchKernelGGL(k_insert_runs, dim3(s.L * chunks), dim3(kSelWaves * SL_WAVE), l2, st, s, c, sorted, starts, runs,
-                     n, chunks, tab);
+  if (n == 0 || n > kSmallInsert) return hipErrorInvalidValue;
+  uint2* recs = (uint2*)scratch;
+  uint32_t* items = (uint32_t*)(recs + (size_t)s.L * n);
+  const size_t lds = ((size_t)2 << group_cap_log2(n)) * 4 + (kGroupThreads / SL_WAVE) * 4;
+  hipError_t e;
+  if (lds > 65536 &&
+      (e = hipFuncSetAttribute((const void*)k_insert_group, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+          hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_insert_group, dim3(s.L), dim3(kGroupThreads), lds, st, keys, n, first_id, recs, items);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const uint64_t lanes = (uint64_t)s.L * n * 16;
+  const dim3 grid((uint32_t)((lanes + kMergeThreads - 1) / kMergeThreads));
+  if (s.R <= 16)
+    hipLaunchKernelGGL(k_insert_merge16<1>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else if (s.R <= 32)
+    hipLaunchKernelGGL(k_insert_merge16<2>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else if (s.R <= 64)
+    hipLaunchKernelGGL(k_insert_merge16<4>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else if (s.R <= 128)
+    hipLaunchKernelGGL(k_insert_merge16<8>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else
+    hipLaunchKernelGGL(k_insert_merge16<16>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
   return hipGetLastError();
 }
 

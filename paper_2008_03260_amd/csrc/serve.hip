@@ -57,15 +57,14 @@ struct Slot {
   uint64_t epoch = 0;
   std::vector<Request> reqs;
   // device staging
-  int64_t* d_indptr = nullptr;
-  int32_t* d_idx = nullptr;
-  uint32_t* d_k = nullptr;
-  uint32_t* d_out = nullptr;  // ids then scores, [cap_q][k_max] each
-  // pinned host staging
-  int64_t* h_indptr = nullptr;
-  int32_t* h_idx = nullptr;
-  uint32_t* h_k = nullptr;
-  uint32_t* h_out = nullptr;
+  // request data of one launch, packed so that it moves in one copy:
+  // indptr [n + 1] (int64), k [n] (queries only), then the indices (int32)
+  // from a 256-byte boundary
+  char* d_in = nullptr;
+  char* h_in = nullptr;  // pinned
+  // query results of one launch: ids [n][k_max] then scores [n][k_max]
+  uint32_t* d_out = nullptr;
+  uint32_t* h_out = nullptr;  // pinned
   uint32_t cap_q = 0;
   uint64_t cap_nnz = 0;
   uint32_t first_id = 0;
@@ -102,38 +101,62 @@ void free_slot(Slot& s) {
   if (s.stream) (void)hipStreamSynchronize(s.stream);
   if (s.done) (void)hipEventDestroy(s.done);
   if (s.stream) (void)hipStreamDestroy(s.stream);
-  (void)hipFree(s.d_indptr);
-  (void)hipFree(s.d_idx);
-  (void)hipFree(s.d_k);
+  (void)hipFree(s.d_in);
   (void)hipFree(s.d_out);
-  (void)hipHostFree(s.h_indptr);
-  (void)hipHostFree(s.h_idx);
-  (void)hipHostFree(s.h_k);
+  (void)hipHostFree(s.h_in);
   (void)hipHostFree(s.h_out);
   s = Slot();
+}
+
+// Offsets of one launch's packed request data (see Slot::d_in).
+struct InLayout {
+  size_t k, idx, bytes;
+};
+InLayout in_layout(uint64_t n, uint64_t nnz, bool with_k) {
+  InLayout l;
+  l.k = (n + 1) * 8;
+  l.idx = (l.k + (with_k ? n * 4 : 0) + 255) & ~(size_t)255;
+  l.bytes = l.idx + nnz * 4;
+  return l;
 }
 
 // Device + pinned staging for up to cap_q queries / rows and cap_nnz indices.
 bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool with_out) {
   s.cap_q = cap_q;
   s.cap_nnz = cap_nnz;
+  const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
   if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
   if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
-  if (hipMalloc(&s.d_indptr, (cap_q + 1) * 8) != hipSuccess) return false;
-  if (hipMalloc(&s.d_idx, cap_nnz * 4) != hipSuccess) return false;
-  if (hipHostMalloc(&s.h_indptr, (cap_q + 1) * 8) != hipSuccess) return false;
-  if (hipHostMalloc(&s.h_idx, cap_nnz * 4) != hipSuccess) return false;
+  if (hipMalloc(&s.d_in, in_bytes) != hipSuccess) return false;
+  if (hipHostMalloc(&s.h_in, in_bytes) != hipSuccess) return false;
   if (with_out) {
-    if (hipMalloc(&s.d_k, cap_q * 4) != hipSuccess) return false;
     if (hipMalloc(&s.d_out, (size_t)cap_q * k_max * 8) != hipSuccess) return false;
-    if (hipHostMalloc(&s.h_k, cap_q * 4) != hipSuccess) return false;
     if (hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8) != hipSuccess) return false;
   }
   return true;
 }
 
+__global__ void k_touch(int64_t* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
+}
+
+// Run each transfer the slot will make once, at full size, and one kernel,
+// and wait: the runtime sets up a stream's hardware queue and copy engines on
+// first use, which would otherwise stall the first requests by milliseconds.
+bool warm_slot(Slot& s, uint32_t k_max, bool with_out) {
+  hipLaunchKernelGGL(k_touch, dim3(1), dim3(64), 0, s.stream, (int64_t*)s.d_in);
+  if (hipGetLastError() != hipSuccess) return false;
+  const size_t in_bytes = in_layout(s.cap_q, s.cap_nnz, with_out).bytes;
+  if (hipMemcpyAsync(s.d_in, s.h_in, in_bytes, hipMemcpyHostToDevice, s.stream) != hipSuccess) return false;
+  if (with_out &&
+      hipMemcpyAsync(s.h_out, s.d_out, (size_t)s.cap_q * k_max * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+    return false;
+  if (hipEventRecord(s.done, s.stream) != hipSuccess) return false;
+  return hipStreamSynchronize(s.stream) == hipSuccess;
+}
+
 uint64_t slot_bytes(uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max) {
-  return (uint64_t)(cap_q + 1) * 8 + cap_nnz * 4 + (uint64_t)cap_q * 4 + (uint64_t)cap_q * k_max * 8;
+  return in_layout(cap_q, cap_nnz, true).bytes + (uint64_t)cap_q * k_max * 8;
 }
 
 // Turn a finished slot into completions (called with the lock held).
@@ -151,7 +174,7 @@ void finish_slot(slash_server* srv, Slot& s) {
       c.kind = 0;
       c.k = r.k;
       const uint32_t* oi = s.h_out + q * km;
-      const uint32_t* os = s.h_out + (size_t)s.cap_q * km + q * km;
+      const uint32_t* os = s.h_out + s.reqs.size() * km + q * km;
       memcpy(c.ids, oi, r.k * 4);
       memcpy(c.scores, os, r.k * 4);
       c.t_submit_s = r.t_submit;
@@ -183,28 +206,29 @@ void finish_slot(slash_server* srv, Slot& s) {
 hipError_t launch_queries(slash_server* srv, Slot& s) {
   const uint32_t n = (uint32_t)s.reqs.size();
   const uint32_t km = srv->info.params.k_max;
+  uint64_t nnz = 0;
+  for (const Request& r : s.reqs) nnz += r.idx.size();
+  const InLayout l = in_layout(n, nnz, true);
+  int64_t* h_ip = (int64_t*)s.h_in;
+  uint32_t* h_k = (uint32_t*)(s.h_in + l.k);
+  int32_t* h_ix = (int32_t*)(s.h_in + l.idx);
   uint64_t off = 0;
-  s.h_indptr[0] = 0;
+  h_ip[0] = 0;
   for (uint32_t q = 0; q < n; ++q) {
     const Request& r = s.reqs[q];
-    memcpy(s.h_idx + off, r.idx.data(), r.idx.size() * 4);
+    memcpy(h_ix + off, r.idx.data(), r.idx.size() * 4);
     off += r.idx.size();
-    s.h_indptr[q + 1] = (int64_t)off;
-    s.h_k[q] = r.k;
+    h_ip[q + 1] = (int64_t)off;
+    h_k[q] = r.k;
   }
   hipError_t e;
   if (srv->have_insert && (e = hipStreamWaitEvent(s.stream, srv->last_insert, 0)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(s.d_indptr, s.h_indptr, (n + 1) * 8, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(s.d_idx, s.h_idx, off * 4, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(s.d_k, s.h_k, n * 4, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
-  slash_csr q{s.d_indptr, s.d_idx, n};
-  slash_status st = slash_query(srv->ix, q, s.d_k, 0, SLASH_FLAG_TRUSTED, s.d_out, s.d_out + (size_t)s.cap_q * km,
-                                s.stream);
+  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  slash_csr q{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), n};
+  slash_status st = slash_query(srv->ix, q, (const uint32_t*)(s.d_in + l.k), 0, SLASH_FLAG_TRUSTED, s.d_out,
+                                s.d_out + (size_t)n * km, s.stream);
   if (st != SLASH_OK) return hipErrorLaunchFailure;
-  if ((e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * km * 4, hipMemcpyDeviceToHost, s.stream)) != hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(s.h_out + (size_t)s.cap_q * km, s.d_out + (size_t)s.cap_q * km, (size_t)n * km * 4,
-                          hipMemcpyDeviceToHost, s.stream)) != hipSuccess)
+  if ((e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * km * 8, hipMemcpyDeviceToHost, s.stream)) != hipSuccess)
     return e;
   return hipEventRecord(s.done, s.stream);
 }
@@ -218,15 +242,14 @@ hipError_t launch_insert(slash_server* srv, Slot& s) {
     if (o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
   for (Slot& o : srv->ins)
     if (&o != &s && o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
-  memcpy(s.h_indptr, r.indptr.data(), (r.n_rows + 1) * 8);
-  memcpy(s.h_idx, r.idx.data(), r.idx.size() * 4);
-  if ((e = hipMemcpyAsync(s.d_indptr, s.h_indptr, (r.n_rows + 1) * 8, hipMemcpyHostToDevice, s.stream)) != hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(s.d_idx, s.h_idx, r.idx.size() * 4, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  const InLayout l = in_layout(r.n_rows, r.idx.size(), false);
+  memcpy(s.h_in, r.indptr.data(), (r.n_rows + 1) * 8);
+  memcpy(s.h_in + l.idx, r.idx.data(), r.idx.size() * 4);
+  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
   slash_index_info info;
   slash_index_info_get(srv->ix, &info);
   s.first_id = (uint32_t)info.n_items;
-  slash_csr rows{s.d_indptr, s.d_idx, r.n_rows};
+  slash_csr rows{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), r.n_rows};
   if (slash_insert(srv->ix, rows, SLASH_FLAG_TRUSTED, nullptr, s.stream) != SLASH_OK) return hipErrorLaunchFailure;
   if ((e = hipEventRecord(s.done, s.stream)) != hipSuccess) return e;
   srv->last_insert = s.done;
@@ -344,7 +367,7 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   const uint32_t ins_rows = 4096;
   const uint64_t ins_nnz = cfg->max_insert_nnz ? cfg->max_insert_nnz
                                                : std::max<uint64_t>((uint64_t)ins_rows * 64, 8ull * cfg->max_query_nnz);
-  const uint64_t ins_bytes = (uint64_t)(ins_rows + 1) * 8 + ins_nnz * 4;
+  const uint64_t ins_bytes = in_layout(ins_rows, ins_nnz, false).bytes;
   if (ins_bytes + per_slot > cfg->hbm_budget_bytes) {
     delete srv;
     return fail(SLASH_E_NOMEM, "HBM budget %llu below one batch slot (%llu bytes)",
@@ -357,6 +380,13 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     return fail(SLASH_E_NOMEM, "insert staging allocation failed");
   }
   srv->hbm_used = ins_bytes;
+  // the index's own scratch for the largest insert, so that no insert grows
+  // (and drains the device) while batches are in flight
+  if (slash_status rs = reserve_insert_scratch(ix, ins_rows); rs != SLASH_OK) {
+    free_slot(srv->ins[0]);
+    delete srv;
+    return rs;
+  }
   // a second insert slot when the budget still leaves room for a batch slot
   if (srv->hbm_used + ins_bytes + per_slot <= cfg->hbm_budget_bytes) {
     srv->ins.emplace_back();
@@ -382,6 +412,27 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     return fail(SLASH_E_NOMEM, "no batch slot fits the HBM budget");
   }
   srv->stats.peak_hbm_bytes = srv->hbm_used;
+  bool warm = true;
+  for (Slot& o : srv->ins) warm = warm && warm_slot(o, km, false);
+  for (Slot& o : srv->slots) warm = warm && warm_slot(o, km, true);
+  if (warm) {
+    // one single-index query through the first slot loads the query kernels
+    Slot& q = srv->slots[0];
+    const int64_t ip[2] = {0, 1};
+    const int32_t zero = 0;
+    const InLayout l = in_layout(1, 1, false);
+    warm = hipMemcpy(q.d_in, ip, sizeof ip, hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(q.d_in + l.idx, &zero, 4, hipMemcpyHostToDevice) == hipSuccess &&
+           slash_query(ix, slash_csr{(const int64_t*)q.d_in, (const int32_t*)(q.d_in + l.idx), 1}, nullptr, 1,
+                       SLASH_FLAG_TRUSTED, q.d_out, q.d_out + km, q.stream) == SLASH_OK &&
+           hipStreamSynchronize(q.stream) == hipSuccess;
+  }
+  if (!warm) {
+    for (Slot& o : srv->ins) free_slot(o);
+    for (Slot& o : srv->slots) free_slot(o);
+    delete srv;
+    return fail(SLASH_E_DEVICE, "server warm-up failed");
+  }
   srv->th = std::thread(scheduler, srv);
   *out = srv;
   return SLASH_OK;

@@ -239,4 +239,9 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
                                    const QueryArgs& a, uint32_t waves, uint32_t per_ticket, uint32_t grid,
                                    uint32_t* ticket, hipStream_t st);
 
+// Size the index's insert scratch for batches of up to `rows` rows now, so
+// that later inserts of at most that many rows allocate nothing and never
+// drain the device (a server calls this once at start).
+slash_status reserve_insert_scratch(slash_index* ix, uint64_t rows);
+
 }  // namespace slash

@@ -127,12 +127,15 @@ class RowLaw:
         self.spec = RowsSpec(key & (2**64 - 1), dim, 0 if index == "zipf" else 1, zipf_s,
                              0 if nnz == "poisson" else 1, nnz_a, nnz_b, max(1, nnz_lo), nnz_hi)
         self._ctx = lib().synth_ctx_new(C.byref(self.spec))
+        # held so that the destructor still works while the interpreter tears
+        # down module globals
+        self._free = lib().synth_ctx_free
         if not self._ctx:
             raise ValueError("invalid row law")
 
     def __del__(self):
         if getattr(self, "_ctx", None):
-            lib().synth_ctx_free(self._ctx)
+            self._free(self._ctx)
             self._ctx = None
 
     @property

@@ -150,6 +150,44 @@ def test_insert_equals_bulk_build(api):
     assert idx.info()["n_items"] == 9000
 
 
+@pytest.mark.parametrize("R", [1, 16, 24, 64, 100, 128, 256])
+def test_insert_small_batches_by_reservoir_size(api, R):
+    # batches of at most 4096 rows are grouped by bucket in LDS and merged by
+    # sixteen lanes per bucket holding the reservoir in registers (1 to 16
+    # entries per lane); one batch carries 2000 identical rows, so every table
+    # gets a run of 2000 ids in one bucket
+    gp, op = params_pair(api, L=3, log2_buckets=6, R=R)
+    _, (ip0, ix0) = rows_of(9000, seed=21)
+    dip, dix = csr_from_lists([[11, 22, 33, 44]] * 2000)
+    n0 = 3000
+    # rows: [0, 3000) base, then batches of 1, 4096 (with the 2000 duplicates
+    # in the middle), 17 and 4096 - 2000 + ... rows
+    parts = [(ip0[: n0 + 1], ix0[: ip0[n0]])]
+    cur = n0
+    for m in (1, 1000):
+        parts.append((ip0[cur: cur + m + 1] - ip0[cur], ix0[ip0[cur]: ip0[cur + m]]))
+        cur += m
+    parts.append((dip, dix))
+    for m in (1096, 17, 3886):
+        parts.append((ip0[cur: cur + m + 1] - ip0[cur], ix0[ip0[cur]: ip0[cur + m]]))
+        cur += m
+    ips, ixs, off = [np.zeros(1, np.int64)], [], 0
+    for pi, px in parts:
+        ips.append(pi[1:] + off)
+        ixs.append(px)
+        off += int(pi[-1])
+    ip, ix = np.concatenate(ips), np.concatenate(ixs)
+    idx = api.Index(gp, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    # insert batches: 1 row, then 1000 + 2000 duplicates + 1096 = 4096 rows,
+    # then 17, then 3886
+    bounds = [n0, n0 + 1, n0 + 1 + 4096, n0 + 1 + 4096 + 17, len(ip) - 1]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        idx.insert(dev(ip[a: b + 1] - ip[a]), dev(ix[ip[a]: ip[b]]))
+    torch.cuda.synchronize()
+    check_tables(api, idx, op, oracle.constants(op), ip, ix)
+    assert idx.info()["n_items"] == len(ip) - 1
+
+
 def test_tables_export_import_roundtrip(api):
     # an index restored from its exported tables answers and grows exactly
     # like the original
