@@ -78,6 +78,12 @@ def lib():
         L.oracle_query.argtypes = [P, vp, vp, vp, vp, vp, C.c_uint64, vp, C.c_uint32, C.c_uint32,
                                    vp, vp, C.c_int]
         L.oracle_aggregate.argtypes = [P, vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, C.c_int]
+        L.oracle_tk_sketch.argtypes = [P, vp, vp, C.c_uint64, vp]
+        L.oracle_tk_merge.argtypes = [P, vp, vp]
+        L.oracle_tk_build.argtypes = [P, vp, vp, vp, C.c_uint64, vp, vp]
+        L.oracle_tk_insert.argtypes = [P, vp, vp, vp, C.c_uint32, vp, vp, C.c_uint64]
+        L.oracle_tk_report.argtypes = [P, vp, C.c_uint32, C.c_uint32, vp, vp]
+        L.oracle_tk_query.argtypes = [P, vp, vp, vp, vp, C.c_uint64, vp, C.c_uint32, C.c_uint32, vp, vp]
         _lib = L
     return _lib
 
@@ -200,4 +206,74 @@ def aggregate(p: Params, cs, cand, k: int, k_max: int | None = None, exact: bool
     osc = np.zeros(k_max, dtype=np.uint32)
     _check(lib().oracle_aggregate(C.byref(p.c()), _p(cs), _p(c) if len(c) else None, len(c), k, k_max, _p(oi),
                                   _p(osc), 1 if exact else 0), "oracle_aggregate")
+    return oi, osc
+
+
+# ------------------------------------------------------------ Topkapi buckets
+# A sketch is an array [W, C, 2] of uint32 (heavy hitter, count) with
+# W = cm_rows and C = 2^log2_cm_width; empty cells are (EMPTY, 0).
+
+
+def tk_shape(p: Params) -> tuple:
+    return (p.cm_rows, 1 << p.log2_cm_width, 2)
+
+
+def tk_sketch(p: Params, cs, ids) -> np.ndarray:
+    """Sketch of the stream ids, inserted in the given order."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    sk = np.zeros(tk_shape(p), dtype=np.uint32)
+    _check(lib().oracle_tk_sketch(C.byref(p.c()), _p(cs), _p(ids) if len(ids) else None, len(ids), _p(sk)),
+           "oracle_tk_sketch")
+    return sk
+
+
+def tk_merge(p: Params, a, b) -> np.ndarray:
+    """Merge(a, b) of two sketches (a new array)."""
+    out = np.ascontiguousarray(a, dtype=np.uint32).copy()
+    b = np.ascontiguousarray(b, dtype=np.uint32)
+    _check(lib().oracle_tk_merge(C.byref(p.c()), _p(out), _p(b)), "oracle_tk_merge")
+    return out
+
+
+def tk_build(p: Params, cs, indptr, indices):
+    """Topkapi tables after pre-processing: cells [L, 2^B, W, C, 2], seen [L, 2^B]."""
+    indptr, indices = _csr(indptr, indices)
+    nb = 1 << p.log2_buckets
+    cells = np.zeros((p.L, nb) + tk_shape(p), dtype=np.uint32)
+    seen = np.zeros((p.L, nb), dtype=np.uint32)
+    _check(lib().oracle_tk_build(C.byref(p.c()), _p(cs), _p(indptr), _p(indices), len(indptr) - 1,
+                                 _p(cells), _p(seen)), "oracle_tk_build")
+    return cells, seen
+
+
+def tk_insert(p: Params, cs, cells, seen, first_id: int, indptr, indices):
+    """In-place streaming insert into Topkapi tables."""
+    indptr, indices = _csr(indptr, indices)
+    assert cells.flags.c_contiguous and seen.flags.c_contiguous
+    _check(lib().oracle_tk_insert(C.byref(p.c()), _p(cs), _p(cells), _p(seen), first_id, _p(indptr),
+                                  _p(indices), len(indptr) - 1), "oracle_tk_insert")
+
+
+def tk_report(p: Params, sk, k: int, k_max: int | None = None):
+    """Top-k (ids, counts) of one sketch, padded (EMPTY, 0)."""
+    k_max = k if k_max is None else k_max
+    sk = np.ascontiguousarray(sk, dtype=np.uint32)
+    oi = np.zeros(k_max, dtype=np.uint32)
+    osc = np.zeros(k_max, dtype=np.uint32)
+    _check(lib().oracle_tk_report(C.byref(p.c()), _p(sk), k, k_max, _p(oi), _p(osc)), "oracle_tk_report")
+    return oi, osc
+
+
+def tk_query(p: Params, cs, cells, qindptr, qindices, k: int, k_max: int | None = None, kq=None):
+    """Top-k (ids, counts) per query from Topkapi tables, rows of stride k_max."""
+    qindptr, qindices = _csr(qindptr, qindices)
+    k_max = k if k_max is None else k_max
+    nq = len(qindptr) - 1
+    oi = np.zeros((nq, k_max), dtype=np.uint32)
+    osc = np.zeros((nq, k_max), dtype=np.uint32)
+    kqa = None if kq is None else np.ascontiguousarray(kq, dtype=np.uint32)
+    cells = np.ascontiguousarray(cells, dtype=np.uint32)
+    _check(lib().oracle_tk_query(C.byref(p.c()), _p(cs), _p(cells), _p(qindptr), _p(qindices), nq,
+                                 _p(kqa) if kqa is not None else None, k, k_max, _p(oi), _p(osc)),
+           "oracle_tk_query")
     return oi, osc

@@ -487,3 +487,185 @@ EXPORT void oracle_priorities(const oracle_params* p, const uint64_t* cs, uint32
                               const uint32_t* ids, uint64_t n, uint32_t* out) {
   for (uint64_t i = 0; i < n; ++i) out[i] = prio(p, cs, t, ids[i]);
 }
+
+/* ------------------------------------------------- TopKAPI buckets */
+
+/* The paper replaces each bucket by a Topkapi sketch (Section 3.1; Appendix 2
+ * "Top-K-API Details"): W rows of C cells, each cell a (heavy hitter, count)
+ * pair, empty = (EMPTY, 0).  Here W = cm_rows, C = 2^log2_cm_width, and the
+ * row hashes are the count-min row hashes g_r above (one set shared by every
+ * bucket of every table, so that any two sketches can be merged).  A sketch
+ * is W * C cells of two uint32 words (heavy hitter, count); the tables are
+ * cells[L][2^B][W][C][2] and seen[L][2^B].
+ *
+ * Readings where Appendix 2 is silent: on insertion the empty-or-zero check
+ * comes before the match check; two different heavy hitters with equal
+ * counts merge to count 0 and the smaller id; the paper's threshold report is
+ * read as top-k by count over the heavy hitters of count >= 1, an id held by
+ * several rows scoring its largest count, ties by ascending id. */
+
+/* Appendix 2 "Insertion": in every row, the cell g_r(x) takes x with count 1
+ * when it is empty or its count is zero, counts up when it holds x, and
+ * counts down otherwise. */
+static void tk_insert_one(const oracle_params* p, const uint64_t* cs, uint32_t* sk, uint32_t x) {
+  uint32_t C = 1u << p->log2_cm_width;
+  for (uint32_t r = 0; r < p->cm_rows; ++r) {
+    uint32_t* cell = sk + 2 * ((uint64_t)r * C + cm_hash(p, cs, r, x));
+    if (cell[0] == EMPTY || cell[1] == 0) {
+      cell[0] = x;
+      cell[1] = 1;
+    } else if (cell[0] == x) {
+      cell[1] += 1;
+    } else {
+      cell[1] -= 1;
+    }
+  }
+}
+
+/* Appendix 2 "Merging": cell by cell, equal heavy hitters add their counts;
+ * otherwise the larger count wins and keeps the difference.  dst <- dst (+) src. */
+static void tk_merge_cells(uint32_t* dst, const uint32_t* src, uint64_t ncell) {
+  for (uint64_t c = 0; c < ncell; ++c) {
+    uint32_t h1 = dst[2 * c], c1 = dst[2 * c + 1], h2 = src[2 * c], c2 = src[2 * c + 1];
+    if (h1 == h2) {
+      dst[2 * c + 1] = c1 + c2;
+    } else if (c1 > c2) {
+      dst[2 * c + 1] = c1 - c2;
+    } else if (c2 > c1) {
+      dst[2 * c] = h2;
+      dst[2 * c + 1] = c2 - c1;
+    } else {
+      dst[2 * c] = h1 < h2 ? h1 : h2;
+      dst[2 * c + 1] = 0;
+    }
+  }
+}
+
+static uint64_t tk_cells(const oracle_params* p) { return (uint64_t)p->cm_rows << p->log2_cm_width; }
+
+static void tk_clear(uint32_t* sk, uint64_t ncell) {
+  for (uint64_t c = 0; c < ncell; ++c) {
+    sk[2 * c] = EMPTY;
+    sk[2 * c + 1] = 0;
+  }
+}
+
+/* One sketch of the stream ids[0..n), inserted in the given order. */
+EXPORT int oracle_tk_sketch(const oracle_params* p, const uint64_t* cs, const uint32_t* ids, uint64_t n,
+                            uint32_t* sk) {
+  if (!params_ok(p) || !cs || !sk) return O_EINVAL;
+  tk_clear(sk, tk_cells(p));
+  for (uint64_t i = 0; i < n; ++i) tk_insert_one(p, cs, sk, ids[i]);
+  return O_OK;
+}
+
+EXPORT int oracle_tk_merge(const oracle_params* p, uint32_t* dst, const uint32_t* src) {
+  if (!params_ok(p) || !dst || !src) return O_EINVAL;
+  tk_merge_cells(dst, src, tk_cells(p));
+  return O_OK;
+}
+
+/* Pre-processing with Topkapi buckets (Algorithm 1 with the sketch insert):
+ * ids in ascending order (the row order), each into bucket H_t(x) of every
+ * table t. */
+EXPORT int oracle_tk_build(const oracle_params* p, const uint64_t* cs, const int64_t* indptr,
+                           const int32_t* indices, uint64_t n, uint32_t* cells, uint32_t* seen) {
+  if (!params_ok(p) || !cs || !cells || !seen) return O_EINVAL;
+  if (n > 0xFFFFFFFEull) return O_ECAPACITY;
+  uint64_t nb = 1ull << p->log2_buckets, nc = tk_cells(p);
+  for (uint64_t s = 0; s < (uint64_t)p->L * nb; ++s) tk_clear(cells + 2 * nc * s, nc);
+  memset(seen, 0, sizeof(uint32_t) * p->L * nb);
+  uint32_t* bk = (uint32_t*)malloc(sizeof(uint32_t) * p->L);
+  if (!bk) return O_ENOMEM;
+  int rc = O_OK;
+  for (uint64_t r = 0; r < n && rc == O_OK; ++r) {
+    rc = oracle_hash_rows(p, cs, indptr, indices, r, r + 1, bk, NULL);
+    for (uint32_t t = 0; t < p->L && rc == O_OK; ++t) {
+      uint64_t s = t * nb + bk[t];
+      tk_insert_one(p, cs, cells + 2 * nc * s, (uint32_t)r);
+      seen[s] += 1;
+    }
+  }
+  free(bk);
+  return rc;
+}
+
+/* Streaming insertion into Topkapi buckets: new ids first_id, first_id+1, ...
+ * in row order, after everything already inserted. */
+EXPORT int oracle_tk_insert(const oracle_params* p, const uint64_t* cs, uint32_t* cells, uint32_t* seen,
+                            uint32_t first_id, const int64_t* indptr, const int32_t* indices, uint64_t n) {
+  if (!params_ok(p) || !cs || !cells || !seen) return O_EINVAL;
+  if ((uint64_t)first_id + n > 0xFFFFFFFEull) return O_ECAPACITY;
+  uint64_t nb = 1ull << p->log2_buckets, nc = tk_cells(p);
+  uint32_t* bk = (uint32_t*)malloc(sizeof(uint32_t) * p->L);
+  if (!bk) return O_ENOMEM;
+  int rc = O_OK;
+  for (uint64_t r = 0; r < n && rc == O_OK; ++r) {
+    rc = oracle_hash_rows(p, cs, indptr, indices, r, r + 1, bk, NULL);
+    for (uint32_t t = 0; t < p->L && rc == O_OK; ++t) {
+      uint64_t s = t * nb + bk[t];
+      tk_insert_one(p, cs, cells + 2 * nc * s, first_id + (uint32_t)r);
+      seen[s] += 1;
+    }
+  }
+  free(bk);
+  return rc;
+}
+
+/* Appendix 2 "Querying", read as top-k: every heavy hitter of count >= 1
+ * scores its largest count over the cells that hold it; the kk best by
+ * (count desc, id asc) go to out_ids / out_scores[0..k_max), padded with
+ * (EMPTY, 0). */
+EXPORT int oracle_tk_report(const oracle_params* p, const uint32_t* sk, uint32_t kk, uint32_t k_max,
+                            uint32_t* out_ids, uint32_t* out_scores) {
+  if (!params_ok(p) || !sk || !out_ids || !out_scores || kk > k_max) return O_EINVAL;
+  uint64_t nc = tk_cells(p), nd = 0;
+  scored_t* sc = (scored_t*)malloc(sizeof(scored_t) * (nc + 1));
+  if (!sc) return O_ENOMEM;
+  for (uint64_t c = 0; c < nc; ++c) {
+    uint32_t h = sk[2 * c], n = sk[2 * c + 1];
+    if (h == EMPTY || n == 0) continue;
+    uint64_t j = 0;
+    while (j < nd && sc[j].id != h) ++j;
+    if (j == nd) {
+      sc[nd].id = h;
+      sc[nd].score = n;
+      ++nd;
+    } else if (n > sc[j].score) {
+      sc[j].score = n;
+    }
+  }
+  qsort(sc, nd, sizeof(scored_t), cmp_scored);
+  for (uint32_t i = 0; i < k_max; ++i) {
+    int live = i < kk && i < nd;
+    out_ids[i] = live ? sc[i].id : EMPTY;
+    out_scores[i] = live ? sc[i].score : 0;
+  }
+  free(sc);
+  return O_OK;
+}
+
+/* Query with Topkapi buckets (Algorithm 2's per-node part): hash the query,
+ * fold the sketches of its L buckets into an empty sketch in table order,
+ * S <- Merge(S, T_t(H_t(q))) for t = 0 .. L-1, and report the top-k of S. */
+EXPORT int oracle_tk_query(const oracle_params* p, const uint64_t* cs, const uint32_t* cells, const int64_t* qindptr,
+                           const int32_t* qindices, uint64_t nq, const uint32_t* kq, uint32_t k, uint32_t k_max,
+                           uint32_t* out_ids, uint32_t* out_scores) {
+  if (!params_ok(p) || !cs || !cells || !out_ids || !out_scores || k_max == 0) return O_EINVAL;
+  uint64_t nb = 1ull << p->log2_buckets, nc = tk_cells(p);
+  uint32_t* bk = (uint32_t*)malloc(sizeof(uint32_t) * p->L);
+  uint32_t* sk = (uint32_t*)malloc(sizeof(uint32_t) * 2 * nc);
+  int rc = (bk && sk) ? O_OK : O_ENOMEM;
+  for (uint64_t q = 0; q < nq && rc == O_OK; ++q) {
+    uint32_t kk = kq ? kq[q] : k;
+    if (kk > k_max) { rc = O_EINVAL; break; }
+    rc = oracle_hash_rows(p, cs, qindptr, qindices, q, q + 1, bk, NULL);
+    if (rc != O_OK) break;
+    tk_clear(sk, nc);
+    for (uint32_t t = 0; t < p->L; ++t) tk_merge_cells(sk, cells + 2 * nc * (t * nb + bk[t]), nc);
+    rc = oracle_tk_report(p, sk, kk, k_max, out_ids + q * k_max, out_scores + q * k_max);
+  }
+  free(bk);
+  free(sk);
+  return rc;
+}
