@@ -69,7 +69,23 @@ typedef enum {
  *   dim >= 1; 1 <= K; 1 <= L; K * L <= 4096; 1 <= log2_buckets <= 30;
  *   1 <= R <= 256; 1 <= cm_rows <= 16; log2_cm_width <= 16 (0 means one
  *   counter); 1 <= k_max <= 1024; hash_mode 0 (one DOPH pass over K*L bins)
- *   or 1 (a DOPH pass of K bins per table). */
+ *   or 1 (a DOPH pass of K bins per table); bucket 0 or 1.
+ *
+ * bucket selects what a bucket holds:
+ *   0 - the R ids of smallest priority (bottom-R reservoir, Section 3 "Avoid
+ *       Skewed buckets"); queries aggregate with the count-min sketch of
+ *       cm_rows x 2^log2_cm_width counters.
+ *   1 - a Topkapi sketch (Section 3.1, Appendix 2) of cm_rows rows of
+ *       2^log2_cm_width (heavy hitter, count) cells, row r sending id x to
+ *       cell (a_r * x + b_r) >> (64 - log2_cm_width) (the count-min row
+ *       hash); R is not used.  Ids enter a bucket in ascending order; on
+ *       insertion a cell takes the id with count 1 when its count is 0,
+ *       counts up on a match and down otherwise.  A query folds its L bucket
+ *       sketches in table order (equal heavy hitters add; otherwise the
+ *       larger count wins and keeps the difference; equal counts give the
+ *       smaller id and count 0) and reports heavy hitters of count >= 1 by
+ *       (count desc, id asc), an id held by several rows scoring its largest
+ *       count.  Needs log2_cm_width <= 8 and cm_rows * 2^log2_cm_width <= 256. */
 typedef struct {
   uint32_t dim;           /* number of features D */
   uint32_t K;             /* hashes per table */
@@ -80,7 +96,7 @@ typedef struct {
   uint32_t log2_cm_width; /* log2 w: counters per count-min row */
   uint32_t k_max;         /* output row stride of queries */
   uint32_t hash_mode;     /* 0 or 1, see above */
-  uint32_t reserved;      /* must be 0 */
+  uint32_t bucket;        /* 0: bottom-R reservoir, 1: Topkapi sketch (see above) */
   uint64_t seed;          /* every hash constant derives from this (Section 3 "Design") */
 } slash_params;
 
@@ -132,7 +148,8 @@ SLASH_API slash_status slash_build(const slash_params* params, slash_csr data, v
 
 /* Insert rows (Section 3.1 streaming insert): ids n_items, n_items+1, ... in
  * row order; each touched bucket keeps the R smallest-priority ids of its old
- * content and the new ids, seen += number of new ids.  The result equals a
+ * content and the new ids (Topkapi buckets: the new ids enter the bucket's
+ * sketch in ascending order), seen += number of new ids.  The result equals a
  * bulk build over all rows inserted so far.  new_ids_dev (nullable) receives
  * the n_rows assigned ids.  Needs exclusive access to the index (no
  * concurrent query on another stream).  Validation (unless TRUSTED) happens
@@ -153,7 +170,9 @@ SLASH_API slash_status slash_insert(slash_index* index, slash_csr rows, uint32_t
  * candidates are ranked by their exact multiplicity among the probed slots
  * (at most L) instead of the estimate (the sketch-versus-exact comparison of
  * Section 6.2); scores are then the multiplicities.  One work-group per query,
- * no device allocation, asynchronous under TRUSTED. */
+ * no device allocation, asynchronous under TRUSTED.  Topkapi buckets: one
+ * wave per query folds the L bucket sketches and reports as described at
+ * slash_params (scores are merged counts; EXACT is E_UNSUPPORTED). */
 SLASH_API slash_status slash_query(const slash_index* index, slash_csr queries, const uint32_t* k_per_query_dev,
                          uint32_t k, uint32_t flags, uint32_t* ids_dev, uint32_t* scores_dev, void* stream);
 
@@ -181,8 +200,9 @@ SLASH_API slash_status slash_autotune(slash_index* index, slash_csr sample, uint
 SLASH_API slash_status slash_hash(const slash_index* index, slash_csr rows, uint32_t flags, uint32_t* buckets_dev,
                         void* stream);
 
-/* Copy the tables into caller device buffers: ids [L][2^B][R], seen [L][2^B]
- * (either may be NULL).  Asynchronous on `stream`. */
+/* Copy the tables into caller device buffers: ids [L][2^B][R] (Topkapi
+ * buckets: cells [L][2^B][cm_rows][2^log2_cm_width][2] as heavy hitter,
+ * count), seen [L][2^B] (either may be NULL).  Asynchronous on `stream`. */
 SLASH_API slash_status slash_export_tables(const slash_index* index, uint32_t* ids_dev, uint32_t* seen_dev,
                                  void* stream);
 

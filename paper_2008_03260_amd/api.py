@@ -33,7 +33,7 @@ class SlashError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("dim", "K", "L", "log2_buckets", "R", "cm_rows", "log2_cm_width",
-                                          "k_max", "hash_mode", "reserved")] + [("seed", C.c_uint64)]
+                                          "k_max", "hash_mode", "bucket")] + [("seed", C.c_uint64)]
 
     @classmethod
     def of(cls, **kw) -> "Params":
@@ -224,14 +224,20 @@ def slash_hash(index, indptr, indices, flags: int = 0, stream=None) -> torch.Ten
 def slash_export_tables(index, stream=None):
     info = slash_index_info_get(index)
     dev = torch.device("cuda", torch.cuda.current_device())
-    ids = torch.empty((info["L"], info["n_buckets"], info["R"]), dtype=torch.int32, device=dev)
+    if info["bucket"]:
+        # Topkapi cells: (heavy hitter, count) per cell of cm_rows x 2^log2_cm_width
+        shape = (info["L"], info["n_buckets"], info["cm_rows"], 1 << info["log2_cm_width"], 2)
+    else:
+        shape = (info["L"], info["n_buckets"], info["R"])
+    ids = torch.empty(shape, dtype=torch.int32, device=dev)
     seen = torch.empty((info["L"], info["n_buckets"]), dtype=torch.int32, device=dev)
     _check(lib().slash_export_tables(index, _ptr(ids), _ptr(seen), _stream(stream)), "slash_export_tables")
     return ids, seen
 
 
 def slash_import_tables(params: Params, ids: torch.Tensor, seen: torch.Tensor, n_items: int, stream=None) -> C.c_void_p:
-    """New index over exported tables (ids [L][2^B][R], seen [L][2^B] device tensors)."""
+    """New index over exported tables (ids [L][2^B][R] or Topkapi cells
+    [L][2^B][cm_rows][2^log2_cm_width][2], seen [L][2^B] device tensors)."""
     out = C.c_void_p()
     _check(lib().slash_import_tables(C.byref(params), _ptr(ids.contiguous()), _ptr(seen.contiguous()), n_items,
                                      _stream(stream), C.byref(out)), "slash_import_tables")

@@ -153,7 +153,9 @@ static slash_status check_params(const slash_params* p) {
   if (p->log2_cm_width > 16) return fail(SLASH_E_INVAL, "log2_cm_width must be <= 16");
   if (p->k_max < 1 || p->k_max > 1024) return fail(SLASH_E_INVAL, "k_max must be in [1, 1024]");
   if (p->hash_mode > 1) return fail(SLASH_E_INVAL, "hash_mode must be 0 or 1");
-  if (p->reserved != 0) return fail(SLASH_E_INVAL, "reserved must be 0");
+  if (p->bucket > 1) return fail(SLASH_E_INVAL, "bucket must be 0 or 1");
+  if (p->bucket == 1 && (p->log2_cm_width > 8 || (p->cm_rows << p->log2_cm_width) > 256))
+    return fail(SLASH_E_UNSUPPORTED, "Topkapi buckets need log2_cm_width <= 8 and cm_rows * 2^log2_cm_width <= 256");
   if (((uint64_t)p->L << p->log2_buckets) > (1ull << 32)) return fail(SLASH_E_UNSUPPORTED, "L * 2^B must be <= 2^32");
   if ((uint64_t)p->L * p->R > 65535) return fail(SLASH_E_UNSUPPORTED, "L * R must be <= 65535");
   return SLASH_OK;
@@ -240,6 +242,10 @@ static const uint32_t kTicketRing = 256;
 
 static TablesView tables(const slash_index* ix) { return TablesView{ix->ids, ix->seen}; }
 
+// 32-bit words a bucket occupies in the table array: R ids, or the Topkapi
+// sketch's cells of two words each.
+static uint64_t bucket_words(const Shape& s) { return s.bucket ? 2ull * (s.d << s.lw) : s.R; }
+
 static Shape make_shape(const slash_params& p) {
   Shape s;
   s.dim = p.dim;
@@ -252,6 +258,7 @@ static Shape make_shape(const slash_params& p) {
   s.lw = p.log2_cm_width;
   s.k_max = p.k_max;
   s.mode = p.hash_mode;
+  s.bucket = p.bucket;
   s.nb = 1u << p.log2_buckets;
   s.mshift = 0xFFu;
   if ((s.M & (s.M - 1)) == 0) {
@@ -369,7 +376,7 @@ static const uint32_t kHeavy = 16384;  // items one wave handles per bucket / ch
 
 static slash_status alloc_tables(slash_index* ix) {
   const Shape& s = ix->shape;
-  size_t n_ids = (size_t)s.L * s.nb * s.R;
+  size_t n_ids = (size_t)s.L * s.nb * bucket_words(s);
   ix->ids = (uint32_t*)dalloc(n_ids * 4);
   ix->seen = (uint32_t*)dalloc((size_t)s.L * s.nb * 4);
   ix->flag = (uint32_t*)dalloc(64);
@@ -403,7 +410,12 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
   const Shape& s = ix->shape;
   const uint64_t n = data.n_rows;
   {
-    hipError_t e = launch_fill_u32(ix->ids, SL_EMPTY, (uint64_t)s.L * s.nb * s.R, st);
+    // Topkapi tables of a non-empty build are written bucket by bucket
+    hipError_t e = hipSuccess;
+    if (!s.bucket)
+      e = launch_fill_u32(ix->ids, SL_EMPTY, (uint64_t)s.L * s.nb * s.R, st);
+    else if (n == 0)
+      e = launch_tk_clear(s, tables(ix), st);
     if (e == hipSuccess) e = launch_fill_u32(ix->seen, 0u, (uint64_t)s.L * s.nb, st);
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table init: %s", hipGetErrorString(e)));
   }
@@ -446,12 +458,18 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
       if (e == hipSuccess) e = launch_segment_bounds(sk, n, start.as<uint32_t>(), end.as<uint32_t>(), st);
       timer.end(PH_BOUNDS, st);
       timer.begin(PH_SELECT, st);
-      if (e == hipSuccess)
+      if (e == hipSuccess && s.bucket)
+        e = launch_tk_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
+                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
+      else if (e == hipSuccess)
         e = launch_select_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
                                 heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
       timer.end(PH_SELECT, st);
       timer.begin(PH_HEAVY, st);
-      if (e == hipSuccess)
+      if (e == hipSuccess && s.bucket)
+        e = launch_tk_heavy(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix),
+                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), (uint32_t)(n / kHeavy + 1), st);
+      else if (e == hipSuccess)
         e = launch_heavy(s, ix->cv, t, sv, n, heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), kHeavy,
                          hchunks.as<ChunkWork>(), hfinals.as<FinalWork>(), hcount.as<uint32_t>(), hcand.as<uint32_t>(),
                          tables(ix), st);
@@ -465,14 +483,14 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
   timer.collect(ix->phase_ms, ix->phase_n);
   {
     // algorithmic bytes: what each phase must read and write once
-    const double N = (double)n, L = s.L, NB = s.nb, R = s.R;
+    const double N = (double)n, L = s.L, NB = s.nb;
     const double passes = (s.B + 7) / 8;
     ix->phase_bytes[PH_VALIDATE] = 4.0 * nnz + 8.0 * (N + 1);
     ix->phase_bytes[PH_HASH] = 4.0 * nnz + 8.0 * (N + 1) + 4.0 * L * N;
     ix->phase_bytes[PH_UPSWEEP] = 4.0 * N * L * passes;
     ix->phase_bytes[PH_DOWNSWEEP] = L * (12.0 * N + (passes - 1) * 16.0 * N);
     ix->phase_bytes[PH_BOUNDS] = 4.0 * N * L + 8.0 * NB * L;
-    ix->phase_bytes[PH_SELECT] = L * (4.0 * N + 8.0 * NB + NB * (4.0 * R + 4.0));
+    ix->phase_bytes[PH_SELECT] = L * (4.0 * N + 8.0 * NB + NB * (4.0 * (double)bucket_words(s) + 4.0));
   }
   ix->n_items = n;
   *out = ix;
@@ -542,7 +560,10 @@ static slash_status query_prelude(const slash_index* ix, slash_csr q, const uint
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
   if (q.n_rows && (!ids || !scores)) return fail(SLASH_E_INVAL, "output pointers are NULL");
   if (!kq && k > ix->p.k_max) return fail(SLASH_E_INVAL, "k (%u) exceeds k_max (%u)", k, ix->p.k_max);
-  if (!query_supported(ix->shape, query_default_waves(ix->shape), (flags & SLASH_FLAG_EXACT) != 0))
+  if (ix->shape.bucket && (flags & SLASH_FLAG_EXACT))
+    return fail(SLASH_E_UNSUPPORTED, "exact counting needs reservoir buckets");
+  if (ix->shape.bucket ? !tk_supported(ix->shape)
+                       : !query_supported(ix->shape, query_default_waves(ix->shape), (flags & SLASH_FLAG_EXACT) != 0))
     return fail(SLASH_E_UNSUPPORTED, "query shape not supported (count-min or id set too large for LDS)");
   if (!(flags & SLASH_FLAG_TRUSTED))
     return validate_rows(const_cast<slash_index*>(ix), q, kq, st);
@@ -557,6 +578,10 @@ extern "C" slash_status slash_query(const slash_index* ix, slash_csr q, const ui
   if (q.n_rows == 0) return SLASH_OK;
   QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
   a.exact = (flags & SLASH_FLAG_EXACT) ? 1u : 0u;
+  if (ix->shape.bucket) {
+    HIP_TRY(launch_tk_query(ix->shape, ix->cv, tables(ix), a, st));
+    return SLASH_OK;
+  }
   // A batch too small to occupy the GPU runs each query with 16 waves
   // (shorter per-query latency); larger batches use the default width.
   uint32_t waves = query_default_waves(ix->shape);
@@ -658,6 +683,12 @@ extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q,
   if (rs != SLASH_OK) return rs;
   if (q.n_rows == 0) return SLASH_OK;
   slash_index* ix = const_cast<slash_index*>(cix);
+  if (ix->shape.bucket) {
+    // Topkapi buckets: one wave per query, hashing in the kernel
+    QueryArgs ta{q, kq, k, 1, ids, scores, nullptr};
+    HIP_TRY(launch_tk_query(ix->shape, ix->cv, tables(ix), ta, st));
+    return SLASH_OK;
+  }
   slash_schedule sc = default_schedule(ix);
   if (sched) {
     sc = *sched;
@@ -679,6 +710,11 @@ extern "C" slash_status slash_autotune(slash_index* ix, slash_csr sample, uint32
   slash_status rs = query_prelude(ix, sample, nullptr, k, 0, (uint32_t*)1, (uint32_t*)1, st);
   if (rs != SLASH_OK) return rs;
   if (sample.n_rows == 0) return fail(SLASH_E_INVAL, "empty tuning sample");
+  if (ix->shape.bucket) {
+    // one launch form only for Topkapi buckets: nothing to tune
+    if (best_out) *best_out = default_schedule(ix);
+    return SLASH_OK;
+  }
   const uint64_t n = sample.n_rows;
   const uint32_t km = ix->p.k_max;
   DBuf ref_i, ref_s, got_i, got_s;
@@ -760,7 +796,7 @@ extern "C" slash_status slash_export_tables(const slash_index* ix, uint32_t* ids
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
   hipStream_t st = (hipStream_t)stream;
   const Shape& s = ix->shape;
-  if (ids) HIP_TRY(hipMemcpyAsync(ids, ix->ids, (size_t)s.L * s.nb * s.R * 4, hipMemcpyDeviceToDevice, st));
+  if (ids) HIP_TRY(hipMemcpyAsync(ids, ix->ids, (size_t)s.L * s.nb * bucket_words(s) * 4, hipMemcpyDeviceToDevice, st));
   if (seen) HIP_TRY(hipMemcpyAsync(seen, ix->seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st));
   return SLASH_OK;
 }
@@ -788,7 +824,7 @@ extern "C" slash_status slash_import_tables(const slash_params* params, const ui
   if ((rs = upload_consts(ix, st)) != SLASH_OK) return bail(rs);
   if ((rs = alloc_tables(ix)) != SLASH_OK) return bail(rs);
   const Shape& s = ix->shape;
-  hipError_t e = hipMemcpyAsync(ix->ids, ids, (size_t)s.L * s.nb * s.R * 4, hipMemcpyDeviceToDevice, st);
+  hipError_t e = hipMemcpyAsync(ix->ids, ids, (size_t)s.L * s.nb * bucket_words(s) * 4, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(ix->seen, seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table copy: %s", hipGetErrorString(e)));
@@ -818,6 +854,6 @@ extern "C" slash_status slash_index_info_get(const slash_index* ix, slash_index_
   info->params = ix->p;
   info->n_items = ix->n_items;
   info->n_buckets = ix->shape.nb;
-  info->table_bytes = (uint64_t)ix->shape.L * ix->shape.nb * (ix->shape.R + 1) * 4;
+  info->table_bytes = (uint64_t)ix->shape.L * ix->shape.nb * (bucket_words(ix->shape) + 1) * 4;
   return SLASH_OK;
 }

@@ -731,6 +731,7 @@ hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_
     return e;
   hipLaunchKernelGGL(k_insert_group, dim3(s.L), dim3(kGroupThreads), lds, st, keys, n, first_id, recs, items);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (s.bucket) return launch_tk_runs(s, c, recs, items, n, tab, st);
   const uint64_t lanes = (uint64_t)s.L * n * 16;
   const dim3 grid((uint32_t)((lanes + kMergeThreads - 1) / kMergeThreads));
   if (s.R <= 16)
@@ -758,6 +759,7 @@ hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_head_scatter, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, skeys, n, segno, seg_start,
                      nseg);
+  if (s.bucket) return launch_tk_segments(s, c, skeys, svals, n, seg_start, nseg, tab, st);
   size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
   hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st, s, c,
                      skeys, svals, n, seg_start, nseg, tab);

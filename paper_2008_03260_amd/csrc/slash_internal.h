@@ -41,6 +41,7 @@ struct HostConsts {
 // Shape of an index as the kernels see it.
 struct Shape {
   uint32_t dim, K, L, M, B, R, d, lw, k_max, mode;
+  uint32_t bucket;  // 0: bottom-R reservoir of R ids; 1: Topkapi sketch of d x 2^lw cells
   uint32_t nb;     // 2^B
   uint32_t mshift; // M = 2^mshift when pow2, else 0xFF
 };
@@ -238,6 +239,23 @@ hipError_t launch_query(const Shape& s, const ConstView& c, const TablesView& ta
 hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const TablesView& tab,
                                    const QueryArgs& a, uint32_t waves, uint32_t per_ticket, uint32_t grid,
                                    uint32_t* ticket, hipStream_t st);
+
+// Topkapi buckets (bucket == 1): each bucket is d x 2^lw (heavy hitter,
+// count) cells, stored as uint2 in the table array.
+bool tk_supported(const Shape& s);
+hipError_t launch_tk_light(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* sv, const uint32_t* start,
+                           const uint32_t* end, TablesView tab, uint32_t heavy_t, uint32_t* heavy_list,
+                           uint32_t* heavy_n, hipStream_t st);
+hipError_t launch_tk_heavy(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* sv, const uint32_t* start,
+                           const uint32_t* end, TablesView tab, const uint32_t* heavy_list, const uint32_t* heavy_n,
+                           uint32_t max_heavy, hipStream_t st);
+hipError_t launch_tk_clear(const Shape& s, TablesView tab, hipStream_t st);
+hipError_t launch_tk_segments(const Shape& s, const ConstView& c, const uint32_t* sk, const uint32_t* sv, uint64_t n,
+                              const uint32_t* seg_start, const uint32_t* nseg, TablesView tab, hipStream_t st);
+hipError_t launch_tk_runs(const Shape& s, const ConstView& c, const uint2* recs, const uint32_t* items, uint32_t n,
+                          TablesView tab, hipStream_t st);
+hipError_t launch_tk_query(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
+                           hipStream_t st);
 
 // Size the index's insert scratch for batches of up to `rows` rows now, so
 // that later inserts of at most that many rows allocate nothing and never
