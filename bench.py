@@ -42,16 +42,16 @@ WIDE_MIX = dict(nnz_mode="lognormal", median=500, sigma=0.8, lo=50, hi=20000, f=
 
 WORKLOADS = {
     # tiny: N = 1e5, K=4, L=16, 2^16 buckets, R=32, count-min 4 x 1024, k = 10
-    "c0": dict(n=100_000, dim=1 << 20, K=4, L=16, B=16, R=32, d=4, lw=10, k=10, nq=1000, master=2020,
+    "c0": dict(n=100_000, dim=1 << 20, K=4, L=16, B=16, R=32, d=4, lw=10, k=10, nq=1000, master=2020, tk=(4, 3),
                law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=100_000,
                desc="tiny: N=1e5, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=16 B=16 R=32; CM 4x1024; k=10; 1000 queries f=0.2"),
     # one node's 200M-point shard
-    "c1": dict(n=200_000_000, dim=1 << 20, K=4, L=32, B=20, R=64, d=4, lw=12, k=10, nq=100_000, master=2021,
+    "c1": dict(n=200_000_000, dim=1 << 20, K=4, L=32, B=20, R=64, d=4, lw=12, k=10, nq=100_000, master=2021, tk=(4, 4),
                law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=1_000_000,
                desc="200M-point shard: N=2e8, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=32 B=20 R=64; CM 4x4096; "
                     "k=10; 100k queries f=0.2"),
     # denser, wider shard under serving
-    "c4": dict(n=20_000_000, dim=1 << 24, K=8, L=128, B=18, R=128, d=8, lw=14, k=100, nq=10_000, master=2024,
+    "c4": dict(n=20_000_000, dim=1 << 24, K=8, L=128, B=18, R=128, d=8, lw=14, k=100, nq=10_000, master=2024, tk=(8, 4),
                law=WIDE_LAW, q=dict(nnz_mode="lognormal", median=500, sigma=0.8, lo=50, hi=20000, f=(0.1, 0.4)),
                mix=WIDE_MIX, max_nnz=20000, max_insert_nnz=8_000_000, cpu_rows=100_000, mix_n=100_000,
                serve_rates=(1e3, 3e3, 1e4, 3e4),
@@ -241,6 +241,7 @@ def main():
     ap.add_argument("--plain-queries", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--no-topkapi", action="store_true", help="skip the Topkapi-bucket index")
     ap.add_argument("--serve-seconds", type=float, default=0.5, help="arrival window per serving rate")
     ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
     args = ap.parse_args()
@@ -413,6 +414,54 @@ def main():
     d = prof[dom]
     dom_gbs = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9 if d["total_ms"] > 0 else 0.0
     log("build phases: " + ", ".join(f"{k} {v['total_ms']:.1f} ms/{v['launches']}" for k, v in prof.items()))
+
+    # Topkapi buckets (Section 3.1, Appendix 2): the same rows, hash seed and
+    # planted queries, each bucket a sketch of tk_rows x 2^tk_lw (heavy
+    # hitter, count) cells (as many cells as reservoir slots) instead of the
+    # bottom-R reservoir
+    topkapi = None
+    if not args.no_topkapi:
+        tw, tlw = w["tk"]
+        tkp = api.Params.of(dim=w["dim"], K=w["K"], L=w["L"], log2_buckets=w["B"], R=1, cm_rows=tw,
+                            log2_cm_width=tlw, k_max=100, hash_mode=0, bucket=1, seed=seeds["index"])
+        tb, ti, tq = [], [], []
+        for rep in range(2):
+            e = [ev() for _ in range(4)]
+            e[0].record(stream)
+            th = api.slash_build(tkp, ip, ix, stream)
+            e[1].record(stream)
+            api.slash_insert(th, ins_ip, ins_ix, api.FLAG_TRUSTED, None, stream)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            tb.append(e[0].elapsed_time(e[1]))
+            ti.append(e[1].elapsed_time(e[2]))
+            if rep == 0:
+                api.slash_free(th)
+        tk_i, tk_s = api.slash_query_batched(th, qi, qx, w["k"], flags=api.FLAG_TRUSTED, stream=stream)
+        for _ in range(3):
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            api.slash_query_batched(th, qi, qx, w["k"], flags=api.FLAG_TRUSTED, out_ids=tk_i, out_scores=tk_s,
+                                    stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tq.append(e0.elapsed_time(e1))
+        tk_got = api.as_u32(tk_i)[:, : w["k"]]
+        tprof = api.slash_build_profile(th)
+        api.slash_free(th)
+        cells = tw << tlw
+        topkapi = {"cells_per_bucket": f"{tw} x {1 << tlw}", "build_ms": tb[-1],
+                   "build_inserts_per_s": w["n"] / (tb[-1] / 1e3), "insert_batch_rows_per_s": 4096 / (ti[-1] / 1e3),
+                   "batched_queries_per_s": w["nq"] / (min(tq) / 1e3),
+                   "recall_at_10": float(np.mean([s_ in row for s_, row in zip(src.tolist(), tk_got.tolist())])),
+                   "table_bytes": w["L"] * (1 << w["B"]) * cells * 8,
+                   # per query: the row, the L sketches (8 B per cell), the output
+                   "query_alg_bytes_per_query": (4 * int(qi_h[-1]) + 8 * w["nq"]) / w["nq"] + w["L"] * cells * 8
+                   + 8 * w["k"],
+                   "build_phases": {k: {"launches": v["launches"], "total_ms": v["total_ms"]} for k, v in tprof.items()}}
+        log(f"topkapi buckets ({topkapi['cells_per_bucket']} cells): build {tb[-1]:.1f} ms, insert(4096) "
+            f"{ti[-1]:.2f} ms, {topkapi['batched_queries_per_s']:,.0f} q/s, recall@10 {topkapi['recall_at_10']:.4f}")
+        del tk_i, tk_s
     # achievable HBM bandwidth: a plain device copy of 4 GiB (read + write)
     src_t = torch.empty(1 << 30, dtype=torch.int32, device=dev)
     dst_t = torch.empty_like(src_t)
@@ -452,6 +501,7 @@ def main():
         "build_phases": prof,
         "batched_mix": mix,
         "exact_counting": exact,
+        "topkapi_buckets": topkapi,
         "serve": serve,
         "stream_copy_gbs": copy_gbs,
     }

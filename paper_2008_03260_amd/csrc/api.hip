@@ -420,7 +420,7 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table init: %s", hipGetErrorString(e)));
   }
   if (n > 0) {
-    DBuf keys, k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, hchunks, hfinals, hcount, hcand;
+    DBuf keys, k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, hchunks, hfinals, hcount, hcand, tkh;
     size_t hist_n = sort_hist_entries(n);
     size_t part_n = std::max(sort_part_entries(hist_n), sort_part_entries(n)) + 16;
     const size_t hcap = heavy_chunk_capacity(n, kHeavy);
@@ -428,7 +428,8 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
         !hist.get(hist_n * 4) || !part.get(part_n * 4) || !start.get((size_t)s.nb * 4) ||
         !end.get((size_t)s.nb * 4) || !heavy.get((size_t)s.nb * 12) || !heavy_n.get(4) ||
         !hchunks.get(hcap * sizeof(ChunkWork)) || !hfinals.get((n / kHeavy + 1) * sizeof(FinalWork)) ||
-        !hcount.get(4) || !hcand.get(hcap * s.R * 4))
+        !hcount.get(4) || !hcand.get(hcap * s.R * 4) ||
+        (s.bucket && !tkh.get(tk_heavy_scratch_words(s, n / kHeavy + 1) * 4)))
       return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
     // the hash kernel also checks every index against [0, dim) (flag bit 2)
     ConstView cvb = ix->cv;
@@ -460,7 +461,7 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
       timer.begin(PH_SELECT, st);
       if (e == hipSuccess && s.bucket)
         e = launch_tk_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
-                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
+                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), tkh.as<uint32_t>(), st);
       else if (e == hipSuccess)
         e = launch_select_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
                                 heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
@@ -468,7 +469,7 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
       timer.begin(PH_HEAVY, st);
       if (e == hipSuccess && s.bucket)
         e = launch_tk_heavy(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix),
-                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), (uint32_t)(n / kHeavy + 1), st);
+                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), n, tkh.as<uint32_t>(), st);
       else if (e == hipSuccess)
         e = launch_heavy(s, ix->cv, t, sv, n, heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), kHeavy,
                          hchunks.as<ChunkWork>(), hfinals.as<FinalWork>(), hcount.as<uint32_t>(), hcand.as<uint32_t>(),

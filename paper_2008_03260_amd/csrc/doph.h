@@ -219,7 +219,7 @@ __device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const Cons
   }
   wave_sync();
   // non-empty mask, G bins per ballot; any_all: is any bin of the row non-empty
-  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
   bool any_all = false;
   for (uint32_t base = 0; base < M; base += G) {
     uint32_t b = base + gl;
@@ -304,7 +304,7 @@ __device__ __forceinline__ void doph_regs(const Shape& s, const ConstView& c, co
 #pragma unroll
   for (int j = 0; j < P; ++j)
     if (h[j] != SL_EMPTY) last = h[j];
-  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
   const uint64_t bal = (ballot64(first != SL_EMPTY) >> gshift) & gmask;
   // rotate so that bit i stands for lane (gl + i) mod G
   const uint64_t rot = gl ? (((bal >> gl) | (bal << (G - gl))) & gmask) : bal;

@@ -243,12 +243,17 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
 // Topkapi buckets (bucket == 1): each bucket is d x 2^lw (heavy hitter,
 // count) cells, stored as uint2 in the table array.
 bool tk_supported(const Shape& s);
+// Build of one table from its sorted ids: buckets of at most heavy_t ids
+// (light), then the listed heavier ones.  heavy_t must be the heavy kernels'
+// chunk length (16384); scratch holds tk_heavy_scratch_words(s, n / 16384 + 1)
+// words; hpar is its start.
+size_t tk_heavy_scratch_words(const Shape& s, uint64_t max_heavy);
 hipError_t launch_tk_light(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* sv, const uint32_t* start,
                            const uint32_t* end, TablesView tab, uint32_t heavy_t, uint32_t* heavy_list,
-                           uint32_t* heavy_n, hipStream_t st);
+                           uint32_t* heavy_n, uint32_t* hpar, hipStream_t st);
 hipError_t launch_tk_heavy(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* sv, const uint32_t* start,
                            const uint32_t* end, TablesView tab, const uint32_t* heavy_list, const uint32_t* heavy_n,
-                           uint32_t max_heavy, hipStream_t st);
+                           uint64_t n, uint32_t* scratch, hipStream_t st);
 hipError_t launch_tk_clear(const Shape& s, TablesView tab, hipStream_t st);
 hipError_t launch_tk_segments(const Shape& s, const ConstView& c, const uint32_t* sk, const uint32_t* sv, uint64_t n,
                               const uint32_t* seg_start, const uint32_t* nseg, TablesView tab, hipStream_t st);

@@ -29,7 +29,6 @@ namespace slash {
 namespace {
 
 constexpr uint32_t kTkWaves = 4;       // waves per block (one bucket / run / query each)
-constexpr uint32_t kTkHeavyThreads = 1024;
 
 __device__ __forceinline__ uint32_t tk_cells(const Shape& s) { return s.d << s.lw; }
 
@@ -83,13 +82,16 @@ __device__ __forceinline__ void tk_write(const TkAcc& a, uint2* __restrict__ cel
 
 __device__ __forceinline__ uint32_t tk_ncp(uint32_t nc) { return (nc + 63) & ~63u; }
 
+// 32-bit parity words of a sketch (one bit per cell).
+__device__ __forceinline__ uint32_t tk_pw(uint32_t nc) { return (nc + 31) / 32; }
+
 // Build, buckets of at most heavy_t ids: one wave per bucket over the
 // table's sorted ids (ascending within a bucket); every bucket of the table
 // is written, empty ones as empty sketches.  Heavier buckets are listed.
 __global__ void __launch_bounds__(kTkWaves * SL_WAVE)
     k_tk_light(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ sv, const uint32_t* __restrict__ start,
                const uint32_t* __restrict__ end, TablesView tab, uint32_t heavy_t, uint32_t* __restrict__ heavy_list,
-               uint32_t* __restrict__ heavy_n) {
+               uint32_t* __restrict__ heavy_n, uint32_t* __restrict__ hpar) {
   extern __shared__ uint32_t lds32[];
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
   const uint32_t nc = tk_cells(s), ncp = tk_ncp(nc);
@@ -97,7 +99,11 @@ __global__ void __launch_bounds__(kTkWaves * SL_WAVE)
   for (uint32_t b = blockIdx.x * kTkWaves + wave; b < s.nb; b += gridDim.x * kTkWaves) {
     const uint32_t s0 = start[b], e0 = end[b];
     if (e0 - s0 > heavy_t) {
-      if (lane == 0) heavy_list[atomicAdd(heavy_n, 1u)] = b;
+      if (lane == 0) {
+        const uint32_t h = atomicAdd(heavy_n, 1u);
+        heavy_list[h] = b;
+        for (uint32_t w = 0; w < tk_pw(nc); ++w) hpar[(uint64_t)h * tk_pw(nc) + w] = 0;
+      }
       continue;
     }
     tk_clear(a, nc, lane, SL_WAVE);
@@ -110,25 +116,130 @@ __global__ void __launch_bounds__(kTkWaves * SL_WAVE)
   }
 }
 
-// Build, listed heavy buckets: one block of kTkHeavyThreads per bucket.
-__global__ void __launch_bounds__(kTkHeavyThreads)
-    k_tk_heavy(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ sv, const uint32_t* __restrict__ start,
-               const uint32_t* __restrict__ end, TablesView tab, const uint32_t* __restrict__ heavy_list,
-               const uint32_t* __restrict__ heavy_n) {
+// Build, listed heavy buckets (more than heavy_t ids).  A bucket's ids are
+// ascending in the sorted order (the radix sort is stable and the build's
+// values are the row numbers), so a cell's two largest ids are its last two
+// in that order.  What the final state needs beyond them is only whether the
+// cell's count is odd, and a parity adds up without atomics:
+//   k_tk_heavy_chunks - chunks of kTkChunk ids, spread over the grid, XOR
+//     one bit per (id, row) into per-thread parity words, reduce them over
+//     the block and XOR them into the bucket's global parity words; the
+//     block holding a bucket's last chunk also scans the bucket backwards,
+//     a block-width of ids at a time with LDS atomics, until every cell has
+//     two hits (or the bucket's start), and stores each cell's hits (capped
+//     at 2), largest and second largest;
+//   k_tk_heavy_final - per cell: no hit -> empty; odd parity -> (largest, 1);
+//     even -> (second largest, 0).
+constexpr uint32_t kTkChunk = 16384;
+constexpr uint32_t kTkChunkThreads = 256;
+
+template <int P>  // 64-bit parity words per thread (cells / 64, rounded up)
+__global__ void __launch_bounds__(kTkChunkThreads)
+    k_tk_heavy_chunks(Shape s, ConstView c, const uint32_t* __restrict__ sv, const uint32_t* __restrict__ start,
+                      const uint32_t* __restrict__ end, const uint32_t* __restrict__ heavy_list,
+                      const uint32_t* __restrict__ heavy_n, uint32_t* __restrict__ hpar, uint32_t* __restrict__ htop) {
   extern __shared__ uint32_t lds32[];
-  const uint32_t nc = tk_cells(s), ncp = tk_ncp(nc), tid = threadIdx.x;
-  const TkAcc a = tk_acc(lds32, ncp);
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / SL_WAVE;
+  constexpr uint32_t NW = kTkChunkThreads / SL_WAVE;
+  const uint32_t nc = tk_cells(s), ncp = tk_ncp(nc), pw = tk_pw(nc);
+  uint32_t* wpar = lds32;                    // [NW][2 * P] per-wave parity
+  uint32_t* flag = lds32 + NW * 2 * P;       // [1] some cell still lacks two hits
+  const TkAcc a = tk_acc(lds32 + NW * 2 * P + 2, ncp);
   const uint32_t nh = *heavy_n;
-  for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+  uint64_t base = 0;  // chunks of the buckets before h
+  for (uint32_t h = 0; h < nh; ++h) {
     const uint32_t b = heavy_list[h];
     const uint32_t s0 = start[b], e0 = end[b];
-    tk_clear(a, nc, tid, kTkHeavyThreads);
-    __syncthreads();
-    tk_add(s, c, a, sv, s0 + tid, e0, kTkHeavyThreads);
-    __syncthreads();
-    tk_write(a, (uint2*)tab.ids + ((uint64_t)t * s.nb + b) * nc, nc, true, tid, kTkHeavyThreads);
-    if (tid == 0) tab.seen[(uint64_t)t * s.nb + b] = e0 - s0;
-    __syncthreads();
+    const uint32_t nch = (e0 - s0 + kTkChunk - 1) / kTkChunk;
+    // this block's chunks of bucket h: global chunk numbers = blockIdx.x (mod grid)
+    uint64_t j0 = (blockIdx.x + gridDim.x - (uint32_t)(base % gridDim.x)) % gridDim.x;
+    for (uint64_t j = j0; j < nch; j += gridDim.x) {
+      const uint32_t c0 = s0 + (uint32_t)j * kTkChunk, c1 = min(e0, c0 + kTkChunk);
+      uint64_t par[P];
+#pragma unroll
+      for (int w = 0; w < P; ++w) par[w] = 0;
+      for (uint32_t i = c0 + tid; i < c1; i += kTkChunkThreads) {
+        const uint32_t x = sv[i];
+        for (uint32_t r = 0; r < s.d; ++r) {
+          const uint32_t ci = (r << s.lw) | cm_hash(c.a_r[r], c.b_r[r], x, s.lw);
+#pragma unroll
+          for (int w = 0; w < P; ++w) par[w] ^= (ci >> 6) == (uint32_t)w ? (1ull << (ci & 63)) : 0ull;
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < P; ++w) {
+        uint32_t lo = (uint32_t)par[w], hi = (uint32_t)(par[w] >> 32);
+#pragma unroll
+        for (int o = SL_WAVE / 2; o > 0; o >>= 1) {
+          lo ^= __shfl_xor(lo, o, SL_WAVE);
+          hi ^= __shfl_xor(hi, o, SL_WAVE);
+        }
+        if (lane == 0) {
+          wpar[wave * 2 * P + 2 * w] = lo;
+          wpar[wave * 2 * P + 2 * w + 1] = hi;
+        }
+      }
+      __syncthreads();
+      if (tid < pw) {
+        uint32_t v = 0;
+        for (uint32_t q = 0; q < NW; ++q) v ^= wpar[q * 2 * P + tid];
+        if (v) atomicXor(&hpar[(uint64_t)h * pw + tid], v);
+      }
+      __syncthreads();
+      if (j + 1 == nch) {
+        // the bucket's two largest ids per cell, from its end backwards
+        tk_clear(a, nc, tid, kTkChunkThreads);
+        __syncthreads();
+        for (uint32_t stop = e0; stop > s0;) {
+          const uint32_t from = stop > s0 + kTkChunkThreads ? stop - kTkChunkThreads : s0;
+          if (from + tid < stop) {
+            const uint32_t x = sv[from + tid];
+            for (uint32_t r = 0; r < s.d; ++r) {
+              const uint32_t ci = (r << s.lw) | cm_hash(c.a_r[r], c.b_r[r], x, s.lw);
+              atomicAdd(&a.cnt[ci], 1u);
+              const uint32_t prev = atomicMax(&a.top1[ci], x);
+              atomicMax(&a.top2[ci], min(prev, x));
+            }
+          }
+          if (tid == 0) *flag = 0;
+          __syncthreads();
+          for (uint32_t i = tid; i < nc; i += kTkChunkThreads)
+            if (a.cnt[i] < 2) *flag = 1;
+          __syncthreads();
+          const uint32_t more = *flag;
+          __syncthreads();
+          if (!more) break;
+          stop = from;
+        }
+        uint32_t* top = htop + (uint64_t)h * nc * 3;
+        for (uint32_t i = tid; i < nc; i += kTkChunkThreads) {
+          top[3 * i] = min(a.cnt[i], 2u);
+          top[3 * i + 1] = a.top1[i];
+          top[3 * i + 2] = a.top2[i];
+        }
+        __syncthreads();
+      }
+    }
+    base += nch;
+  }
+}
+
+__global__ void __launch_bounds__(kTkChunkThreads)
+    k_tk_heavy_final(Shape s, uint32_t t, const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
+                     TablesView tab, const uint32_t* __restrict__ heavy_list, const uint32_t* __restrict__ heavy_n,
+                     const uint32_t* __restrict__ hpar, const uint32_t* __restrict__ htop) {
+  const uint32_t nc = tk_cells(s), pw = tk_pw(nc), nh = *heavy_n;
+  for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    const uint32_t b = heavy_list[h];
+    uint2* cells = (uint2*)tab.ids + ((uint64_t)t * s.nb + b) * nc;
+    const uint32_t* top = htop + (uint64_t)h * nc * 3;
+    for (uint32_t i = threadIdx.x; i < nc; i += kTkChunkThreads) {
+      const uint32_t odd = (hpar[(uint64_t)h * pw + (i >> 5)] >> (i & 31)) & 1u;
+      cells[i] = top[3 * i] == 0 ? make_uint2(SL_EMPTY, 0u)
+                 : odd           ? make_uint2(top[3 * i + 1], 1u)
+                                 : make_uint2(top[3 * i + 2], 0u);
+    }
+    if (threadIdx.x == 0) tab.seen[(uint64_t)t * s.nb + b] = end[b] - start[b];
   }
 }
 
@@ -339,18 +450,42 @@ bool tk_supported(const Shape& s) {
 
 hipError_t launch_tk_light(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* sv, const uint32_t* start,
                            const uint32_t* end, TablesView tab, uint32_t heavy_t, uint32_t* heavy_list,
-                           uint32_t* heavy_n, hipStream_t st) {
+                           uint32_t* heavy_n, uint32_t* hpar, hipStream_t st) {
   hipLaunchKernelGGL(k_tk_light, dim3(tk_grid(s.nb, kTkWaves, 16384)), dim3(kTkWaves * SL_WAVE),
-                     kTkWaves * tk_acc_lds(s), st, s, c, t, sv, start, end, tab, heavy_t, heavy_list, heavy_n);
+                     kTkWaves * tk_acc_lds(s), st, s, c, t, sv, start, end, tab, heavy_t, heavy_list, heavy_n, hpar);
   return hipGetLastError();
+}
+
+size_t tk_heavy_scratch_words(const Shape& s, uint64_t max_heavy) {
+  const uint64_t nc = s.d << s.lw;
+  return (size_t)max_heavy * ((nc + 31) / 32 + 3 * nc);
 }
 
 hipError_t launch_tk_heavy(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* sv, const uint32_t* start,
                            const uint32_t* end, TablesView tab, const uint32_t* heavy_list, const uint32_t* heavy_n,
-                           uint32_t max_heavy, hipStream_t st) {
-  const uint32_t grid = max_heavy < 1 ? 1 : (max_heavy < 1024 ? max_heavy : 1024);
-  hipLaunchKernelGGL(k_tk_heavy, dim3(grid), dim3(kTkHeavyThreads), tk_acc_lds(s), st, s, c, t, sv, start, end, tab,
-                     heavy_list, heavy_n);
+                           uint64_t n, uint32_t* scratch, hipStream_t st) {
+  // heavy buckets hold more than kTkChunk ids each, so there are at most
+  // n / kTkChunk of them and at most 2 n / kTkChunk chunks
+  const uint64_t max_heavy = n / kTkChunk + 1;
+  const uint32_t nc = s.d << s.lw;
+  uint32_t* hpar = scratch;
+  uint32_t* htop = scratch + max_heavy * ((nc + 31) / 32);
+  const uint32_t P = (nc + 63) / 64;
+  const uint32_t grid = tk_grid(2 * (n / kTkChunk) + 2, 1, 2048);
+  const size_t lds = (size_t)((kTkChunkThreads / SL_WAVE) * 2 * P + 2) * 4 + tk_acc_lds(s);
+  if (P <= 1)
+    hipLaunchKernelGGL(k_tk_heavy_chunks<1>, dim3(grid), dim3(kTkChunkThreads), lds, st, s, c, sv, start, end,
+                       heavy_list, heavy_n, hpar, htop);
+  else if (P <= 2)
+    hipLaunchKernelGGL(k_tk_heavy_chunks<2>, dim3(grid), dim3(kTkChunkThreads), lds, st, s, c, sv, start, end,
+                       heavy_list, heavy_n, hpar, htop);
+  else
+    hipLaunchKernelGGL(k_tk_heavy_chunks<4>, dim3(grid), dim3(kTkChunkThreads), lds, st, s, c, sv, start, end,
+                       heavy_list, heavy_n, hpar, htop);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tk_heavy_final, dim3(tk_grid(max_heavy, 1, 1024)), dim3(kTkChunkThreads), 0, st, s, t, start,
+                     end, tab, heavy_list, heavy_n, hpar, htop);
   return hipGetLastError();
 }
 
