@@ -125,8 +125,8 @@ typedef struct {
  * resident work-groups per CU).  Any schedule gives identical results. */
 typedef struct {
   uint32_t waves_per_query;  /* 1, 2, 4, 8 or 16 */
-  uint32_t queries_per_ticket;
-  uint32_t groups_per_cu;    /* 0 = as many as fit */
+  uint32_t queries_per_ticket; /* 0 = one work-group per query (no work counter) */
+  uint32_t groups_per_cu;    /* persistent form: 0 = as many as fit */
   uint32_t reserved;
 } slash_schedule;
 
@@ -178,10 +178,11 @@ SLASH_API slash_status slash_query(const slash_index* index, slash_csr queries, 
 
 /* Same results as slash_query (bit-exact) through the batched path: every
  * query is first hashed by the row-parallel hash kernel into an index-owned
- * bucket-id buffer (grown on demand), then one persistent launch whose
- * resident work-groups take queries from a device work counter answers
- * them, with the schedule `sched` (NULL = the tuned schedule for this index,
- * see slash_autotune).  Both launches are recorded once into a HIP graph and
+ * bucket-id buffer (grown on demand), then one launch answers them: a
+ * persistent one whose resident work-groups take queries from a device work
+ * counter, or (queries_per_ticket = 0) one work-group per query, with the
+ * schedule `sched` (NULL = the tuned schedule for this index, see
+ * slash_autotune).  Both launches are recorded once into a HIP graph and
  * replayed.  Batched calls on one index share that buffer: issue them on one
  * stream (or otherwise order them). */
 SLASH_API slash_status slash_query_batched(const slash_index* index, slash_csr queries, const uint32_t* k_per_query_dev,

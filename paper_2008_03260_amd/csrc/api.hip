@@ -614,11 +614,14 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   int occ = 0;
   HIP_TRY(query_occupancy(s, waves, &occ, a.exact != 0));
   if (occ < 1) occ = 1;
+  // queries_per_ticket 0: the grid-stride kernel, one work-group per query
+  const bool plain = sc.queries_per_ticket == 0;
   uint32_t per_cu = sc.groups_per_cu ? std::min<uint32_t>(sc.groups_per_cu, (uint32_t)occ) : (uint32_t)occ;
   uint32_t grid = per_cu * (uint32_t)ix->n_cu;
   uint64_t max_grid = (a.q.n_rows + std::max(1u, sc.queries_per_ticket) - 1) / std::max(1u, sc.queries_per_ticket);
   if (grid > max_grid) grid = (uint32_t)std::max<uint64_t>(1, max_grid);
-  uint32_t per_ticket = std::max(1u, sc.queries_per_ticket);
+  uint32_t per_ticket = plain ? 0u : std::max(1u, sc.queries_per_ticket);
+  if (plain) grid = (uint32_t)std::min<uint64_t>(a.q.n_rows, 1u << 30);
   std::lock_guard<std::mutex> lk(ix->mu);
   const size_t need = (size_t)a.q.n_rows * s.L * 4;
   if (!grow(ix->qbk, need)) return fail(SLASH_E_NOMEM, "batched bucket-id buffer");
@@ -629,7 +632,9 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   void* hash_fn = hash_rowmajor_kernel(s, &hash_threads, &hash_lds);
   if (!hash_fn) return fail(SLASH_E_DEVICE, "hash kernel attributes");
   const uint32_t hash_grid = hash_rowmajor_grid(s, a.q.n_rows);
-  uint64_t gkey = ((uint64_t)a.exact << 63) | ((uint64_t)waves << 48) | ((uint64_t)per_ticket << 32) | grid;
+  // the plain form's grid follows the batch size and is updated in place (its
+  // grid-stride loop is correct for any grid)
+  uint64_t gkey = ((uint64_t)a.exact << 63) | ((uint64_t)waves << 48) | ((uint64_t)per_ticket << 32) | (plain ? 0u : grid);
   GraphSlot& g = ix->graphs[gkey];
   Shape sh = s;
   ConstView cv = ix->cv;
@@ -638,6 +643,7 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   uint32_t zero = 0;
   uint64_t one = 1;
   void* run_args[] = {&sh, &cv, &tv, &qa, &per_ticket, &ticket};
+  void* plain_args[] = {&sh, &cv, &tv, &qa};
   uint32_t* tk = ticket;
   void* fill_args[] = {&tk, &zero, &one};
   slash_csr hq = a.q;
@@ -650,11 +656,11 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   hp.sharedMemBytes = (unsigned)hash_lds;
   hp.kernelParams = hash_args;
   hipKernelNodeParams rp{};
-  rp.func = persistent_query_kernel(s, waves, a.exact != 0);
+  rp.func = plain ? plain_query_kernel(s, waves, a.exact != 0) : persistent_query_kernel(s, waves, a.exact != 0);
   rp.gridDim = dim3(grid);
   rp.blockDim = dim3(waves * SL_WAVE);
   rp.sharedMemBytes = (unsigned)query_lds_bytes(s, waves, a.exact != 0);
-  rp.kernelParams = run_args;
+  rp.kernelParams = plain ? plain_args : run_args;
   hipKernelNodeParams fp{};
   fp.func = fill_kernel_ptr();
   fp.gridDim = dim3(1);
@@ -737,12 +743,13 @@ extern "C" slash_status slash_autotune(slash_index* ix, slash_csr sample, uint32
   float best_ms = 1e30f;
   slash_schedule best = default_schedule(ix);
   const uint32_t wv[] = {1, 2, 4, 8, 16};
-  const uint32_t tk[] = {1, 2, 8};
+  const uint32_t tk[] = {0, 1, 2, 8};  // 0: one work-group per query, no work counter
   const uint32_t gpc[] = {0, 2};
   for (uint32_t w : wv) {
     if (!query_supported(ix->shape, w)) continue;
     for (uint32_t t : tk)
       for (uint32_t g : gpc) {
+        if (t == 0 && g != 0) continue;  // the plain form has no resident-group count
         slash_schedule sc{w, t, g, 0};
         QueryArgs ga{sample, nullptr, k, 1, got_i.as<uint32_t>(), got_s.as<uint32_t>(), nullptr};
         rs = run_batched(ix, ga, sc, st);  // warm-up + correctness

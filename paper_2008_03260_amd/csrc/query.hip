@@ -116,11 +116,16 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     for (uint32_t t = lane; t < s.L; t += SL_WAVE) bk[t] = table_bucket<CL>(s, c, h, t);
   }
   __syncthreads();
-  // 1. gather the probed reservoirs and count every occurrence
+  // 1. gather the probed reservoirs and count every occurrence.  The slot
+  //    arithmetic (a division by R per slot) is redone for every query: left
+  //    to itself the compiler keeps it across queries in registers, which at
+  //    the occupancy this kernel runs at means spilling it to scratch.
+  uint32_t tid_q = tid;
+  asm volatile("" : "+v"(tid_q));
   uint32_t id[SPT];
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
-    uint32_t sl = tid + i * NT;
+    uint32_t sl = tid_q + i * NT;
     id[i] = SL_EMPTY;
     if (sl < slots) {
       uint32_t t = sl / s.R, j = sl - t * s.R;
@@ -369,13 +374,18 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   __syncthreads();
 }
 
-// Register budget: at least 4 waves per SIMD (at most 128 VGPRs) for the
-// 4-wave groups, whose LDS lets 7 of them share a CU.
-template <int WAVES>
-constexpr int query_min_waves() { return WAVES <= 4 ? 4 : 1; }
+// Register budget per SIMD: the LDS of a query group (about 22 KB for the
+// 200M shard) lets 7 groups share a CU, so 4-wave groups with up to 8 slots
+// per thread are held to 72 VGPRs (7 waves per SIMD); with 16 slots that
+// would spill, so they keep 128 (4 waves), as do 2-wave groups (their LDS
+// allows 3.5 per SIMD).
+template <int WAVES, int SPT>
+constexpr int query_min_waves() {
+  return WAVES == 4 ? (SPT <= 8 ? 7 : 4) : (WAVES == 2 ? 4 : (WAVES == 1 ? 2 : 1));
+}
 
 template <int WAVES, int SPT, bool CL, bool EX>
-__global__ void __launch_bounds__(WAVES * SL_WAVE, query_min_waves<WAVES>())
+__global__ void __launch_bounds__(WAVES * SL_WAVE, (query_min_waves<WAVES, SPT>()))
     k_query(Shape s, ConstView c, TablesView tab, QueryArgs a) {
   extern __shared__ uint32_t lds[];
   const QLayout lay = q_layout(s, EX);
@@ -386,7 +396,7 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE, query_min_waves<WAVES>())
 }
 
 template <int WAVES, int SPT, bool CL, bool EX>
-__global__ void __launch_bounds__(WAVES * SL_WAVE, query_min_waves<WAVES>())
+__global__ void __launch_bounds__(WAVES * SL_WAVE, (query_min_waves<WAVES, SPT>()))
     k_query_persistent(Shape s, ConstView c, TablesView tab, QueryArgs a, uint32_t per_ticket, uint32_t* ticket) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t base_sh;
@@ -548,6 +558,11 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
 void* persistent_query_kernel(const Shape& s, uint32_t waves, bool exact) {
   const KPair* k = pick(s, waves, exact);
   return k ? const_cast<void*>(k->persistent) : nullptr;
+}
+
+void* plain_query_kernel(const Shape& s, uint32_t waves, bool exact) {
+  const KPair* k = pick(s, waves, exact);
+  return k ? const_cast<void*>(k->plain) : nullptr;
 }
 
 // Occupancy of the persistent kernel: resident work-groups per CU.

@@ -163,6 +163,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
 void* fill_kernel_ptr();
 // Kernel entry of the persistent query kernel for `waves` waves per query.
 void* persistent_query_kernel(const Shape& s, uint32_t waves, bool exact = false);
+// The grid-stride form (one work-group per query, no work counter), with
+// arguments (Shape, ConstView, TablesView, QueryArgs).
+void* plain_query_kernel(const Shape& s, uint32_t waves, bool exact = false);
 hipError_t launch_validate_indices(const int32_t* idx, uint64_t n, uint32_t dim, uint32_t* flag, hipStream_t st);
 hipError_t launch_item_ids(uint32_t* vals, uint32_t first_id, uint64_t n_rows, uint64_t items, hipStream_t st);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t first, uint64_t n, hipStream_t st);

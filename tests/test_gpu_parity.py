@@ -336,7 +336,9 @@ def test_query_counter_overflow_recount(api, lw):
                                    dict(waves_per_query=2, queries_per_ticket=3),
                                    dict(waves_per_query=4, queries_per_ticket=8, groups_per_cu=1),
                                    dict(waves_per_query=8, queries_per_ticket=1),
-                                   dict(waves_per_query=16, queries_per_ticket=2)])
+                                   dict(waves_per_query=16, queries_per_ticket=2),
+                                   dict(waves_per_query=4, queries_per_ticket=0),
+                                   dict(waves_per_query=16, queries_per_ticket=0)])
 def test_batched_equals_plain(api, qsetup, sched):
     idx, op, cs, oids, oseen, qi, qx = qsetup
     a = idx.query(dev(qi), dev(qx), 10)
@@ -344,6 +346,18 @@ def test_batched_equals_plain(api, qsetup, sched):
         b = idx.query_batched(dev(qi), dev(qx), 10, schedule=sched)
         torch.cuda.synchronize()
         assert (u32(a[0]) == u32(b[0])).all() and (u32(a[1]) == u32(b[1])).all()
+
+
+def test_batched_one_group_per_query_follows_batch_size(api, qsetup):
+    # the one-group-per-query form updates its recorded grid to each batch
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    sched = dict(waves_per_query=4, queries_per_ticket=0)
+    for n in (len(qi) - 1, 37, 1, len(qi) - 1):
+        sip, six = qi[: n + 1], qx[: qi[n]]
+        a = idx.query(dev(sip), dev(six), 10)
+        b = idx.query_batched(dev(sip), dev(six), 10, schedule=sched)
+        torch.cuda.synchronize()
+        assert (u32(a[0]) == u32(b[0])).all() and (u32(a[1]) == u32(b[1])).all(), n
 
 
 def test_autotune_and_batched_default(api, qsetup):
