@@ -162,14 +162,13 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       if (lane == 0) atomicAdd(&misc[7], live);
     }
     __syncthreads();
+    // the counter sum and the 8-bit estimates are read in the same pass; the
+    // estimates are redone below in the rare case the sum shows an overflow
     {
       uint32_t sum = 0;
       for (uint32_t e = tid; e < lay.cm_words; e += NT) sum = __builtin_amdgcn_sad_u8(cmw[e], 0u, sum);
       for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, SL_WAVE);
       if (lane == 0) atomicAdd(&misc[6], sum);
-    }
-    __syncthreads();
-    if (misc[6] == s.d * misc[7]) {
       for (uint32_t r = 0; r < s.d; ++r) {
         const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
 #pragma unroll
@@ -178,8 +177,11 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
           est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
         }
       }
-      __syncthreads();
-    } else {
+    }
+    __syncthreads();
+    if (misc[6] != s.d * misc[7]) {
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
       for (uint32_t r = 0; r < s.d; ++r) {
         const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
         for (uint32_t e = tid; e < lay.cm16_words; e += NT) cmw[e] = 0;
