@@ -246,7 +246,7 @@ def main():
     ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
