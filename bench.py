@@ -496,7 +496,8 @@ def main():
                      "kernel": dom, "launches": d["launches"], "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
                      "alg_bytes_per_launch": d["alg_bytes"] / d["launches"]},
         "query_roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": q_gbs / HBM_PEAK_GBS, "kernel": "k_query_persistent",
+                           "frac": q_gbs / HBM_PEAK_GBS,
+                           "kernel": "k_query" if sched and sched.get("queries_per_ticket") == 0 else "k_query_persistent",
                            "alg_bytes_per_query": alg_q / w["nq"]},
         "build_phases": prof,
         "batched_mix": mix,
