@@ -75,6 +75,18 @@ def test_inserts_close_epochs(api, setup):
     # queries submitted before an insert see the index without it; those
     # after see it (the inserted index equals a bulk build on the union)
     law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    check_epochs(api, setup, params)
+
+
+def test_inserts_close_epochs_topkapi_buckets(api, setup):
+    # the same with Topkapi buckets (4 x 16 cells per bucket)
+    params = api.Params.of(dim=1 << 20, K=4, L=16, log2_buckets=12, R=1, cm_rows=4, log2_cm_width=4, k_max=100,
+                           bucket=1, seed=synth.derive(31, synth.STREAM_INDEX))
+    check_epochs(api, setup, params)
+
+
+def check_epochs(api, setup, params):
+    law, _, ip, ix, n0, n1, qi, qx, kq = setup
     before = standalone(api, params, ip, ix, n0, qi, qx, kq)
     after = standalone(api, params, ip, ix, n0 + n1, qi, qx, kq)
     idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
