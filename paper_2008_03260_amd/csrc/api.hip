@@ -374,6 +374,8 @@ static int ceil_log2(uint64_t x) {
 
 static const uint32_t kHeavy = 16384;  // items one wave handles per bucket / chunk
 
+static slash_status reserve_small_inserts(slash_index* ix);
+
 static slash_status alloc_tables(slash_index* ix) {
   const Shape& s = ix->shape;
   size_t n_ids = (size_t)s.L * s.nb * bucket_words(s);
@@ -494,11 +496,20 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
     ix->phase_bytes[PH_SELECT] = L * (4.0 * N + 8.0 * NB + NB * (4.0 * (double)bucket_words(s) + 4.0));
   }
   ix->n_items = n;
+  // scratch for insert batches of up to 4096 rows, so that the first insert
+  // allocates nothing
+  if ((rs = reserve_small_inserts(ix)) != SLASH_OK) return bail(rs);
   *out = ix;
   return SLASH_OK;
 }
 
 // ----------------------------------------------------------------- insert
+
+static slash_status reserve_small_inserts(slash_index* ix) {
+  uint64_t rows = 4096;
+  while (rows > 1 && !small_insert_ok(ix->shape, rows)) rows /= 2;
+  return slash::reserve_insert_scratch(ix, rows);
+}
 
 slash_status slash::reserve_insert_scratch(slash_index* ix, uint64_t rows) {
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
@@ -837,6 +848,7 @@ extern "C" slash_status slash_import_tables(const slash_params* params, const ui
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table copy: %s", hipGetErrorString(e)));
   ix->n_items = n_items;
+  if ((rs = reserve_small_inserts(ix)) != SLASH_OK) return bail(rs);
   *out = ix;
   return SLASH_OK;
 }

@@ -40,8 +40,14 @@ __device__ __forceinline__ void hash_row(const Shape& s, const ConstView& c, con
 // hashes one row at a time (64 / G rows per wave at once) and stages its L
 // bucket ids in LDS; the block then writes every table's rpc ids as one
 // contiguous run (keys are table-major).
+// Waves per SIMD the register budget is held to: the 8-bins-per-lane form
+// (M = 128) is cut from 108 to 96 VGPRs, one more wave per SIMD (the block's
+// LDS allows five); the others keep what they need.
+template <int P>
+constexpr int hash_min_waves() { return P == 8 ? 5 : 1; }
+
 template <int G, int P, bool CL>
-__global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE)
+__global__ void __launch_bounds__(kMaxHashWaves * SL_WAVE, hash_min_waves<P>())
     k_hash_rows(Shape s, ConstView c, slash_csr rows, uint32_t* __restrict__ keys, uint64_t key_stride,
                 int combine, uint32_t rpc) {
   extern __shared__ uint32_t lds[];

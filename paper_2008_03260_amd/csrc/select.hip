@@ -238,7 +238,8 @@ __device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __re
   wave_sync();
 }
 
-__global__ void __launch_bounds__(kSelWaves * SL_WAVE)
+// 8 waves per SIMD (64 VGPRs): the wave-per-bucket loop is latency-bound
+__global__ void __launch_bounds__(kSelWaves * SL_WAVE, 8)
     k_select_light(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ svals,
                    const uint32_t* __restrict__ start, const uint32_t* __restrict__ end, TablesView tab,
                    uint32_t heavy_t, uint32_t* heavy_list, uint32_t* heavy_n) {
