@@ -75,6 +75,39 @@ __host__ __device__ inline QLayout q_layout(const Shape& s, bool exact = false) 
   return o;
 }
 
+// Outputs per query up to which the top-k is taken by repeated maximum
+// extraction instead of the radix select.
+constexpr uint32_t kFewK = 16;
+
+// One DPP step of a 64-bit max: y = x of the lane `ctrl` selects.
+template <int CTRL>
+__device__ __forceinline__ uint64_t max_dpp(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)x, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, false);
+  const uint64_t y = ((uint64_t)hi << 32) | lo;
+  return y > x ? y : x;
+}
+
+// Maximum over the wave, returned to every lane.  Within each row of 16
+// lanes: swap neighbours, swap pairs (quad permutations), mirror each half
+// row, mirror the row (DPP moves, no LDS); then the four row maxima are read
+// from lanes 0, 16, 32 and 48.
+__device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
+  x = max_dpp<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x = max_dpp<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x = max_dpp<0x141>(x);  // row_half_mirror
+  x = max_dpp<0x140>(x);  // row_mirror
+  uint64_t m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, 16 * r);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), 16 * r);
+    const uint64_t y = ((uint64_t)hi << 32) | lo;
+    m = y > m ? y : m;
+  }
+  return m;
+}
+
 // Slot of an id in the id set: high bits of a multiplicative hash.
 __device__ __forceinline__ uint32_t hs_slot(uint32_t id, uint32_t log2_size) {
   return (id * 0x9E3779B1u) >> (32 - log2_size);
@@ -287,6 +320,49 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   const uint32_t kk = min(kq, total);
   uint32_t* oid = a.out_ids + (uint64_t)q * s.k_max;
   uint32_t* osc = a.out_scores + (uint64_t)q * s.k_max;
+  if (kk <= kFewK) {
+    // 4'. few outputs: every wave takes its kk largest keys by repeated
+    //     maximum extraction, then wave 0 takes the kk largest of those.
+    //     Keys are distinct, so the order is exactly (estimate desc, id asc).
+    uint64_t* wtop = (uint64_t*)hist;  // [WAVES][kFewK]
+    uint32_t r = 0;
+    for (; r < kk; ++r) {
+      uint64_t m = 0;
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) m = key[i] > m ? key[i] : m;
+      m = wave_max64(m);
+      if (m == 0) break;
+#pragma unroll
+      for (int i = 0; i < SPT; ++i)
+        if (key[i] == m) key[i] = 0;
+      if (lane == 0) wtop[wave * kFewK + r] = m;
+    }
+    if (lane == 0)
+      for (; r < kFewK; ++r) wtop[wave * kFewK + r] = 0;
+    __syncthreads();
+    if (wave == 0) {
+      constexpr int PER = WAVES * kFewK / SL_WAVE > 0 ? WAVES * kFewK / SL_WAVE : 1;
+      uint64_t v[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const uint32_t e = lane + i * SL_WAVE;
+        v[i] = e < WAVES * kFewK ? wtop[e] : 0;
+      }
+      for (uint32_t o = 0; o < kk; ++o) {
+        uint64_t m = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) m = v[i] > m ? v[i] : m;
+        m = wave_max64(m);
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+          if (v[i] == m) v[i] = 0;
+        if (lane == 0) {
+          oid[o] = ~(uint32_t)m;
+          osc[o] = (uint32_t)(m >> 32);
+        }
+      }
+    }
+  } else {
   // 4. threshold key.  MSD radix select over 8-bit digits of
   //    (estimate << 32 | ~id), starting at the estimate's low byte when every
   //    estimate is below 256.  Once the estimate E of the kk-th key is known,
@@ -368,6 +444,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       oid[r] = ~(uint32_t)x;
       osc[r] = (uint32_t)(x >> 32);
     }
+  }
   }
   for (uint32_t e = kk + tid; e < s.k_max; e += NT) {
     oid[e] = SL_EMPTY;
