@@ -24,7 +24,7 @@ namespace {
 constexpr uint32_t kMaxSpt = 16;     // reservoir slots per thread
 
 struct QLayout {
-  uint32_t cst, doph, buckets, cm, hist, sel, misc, total;  // offsets in 32-bit words
+  uint32_t cst, doph, buckets, cm, hist, sel, misc, ticket, total;  // offsets in 32-bit words
   uint32_t cm_words, cm16_words, hs_size, cst_words, tie_cap;
   bool cst_fit;
 };
@@ -71,7 +71,10 @@ __host__ __device__ inline QLayout q_layout(const Shape& s, bool exact = false) 
   o.sel = o.hist + 512;
   if (o.sel & 1) o.sel++;
   o.misc = o.sel + 2 * s.k_max;
-  o.total = o.misc + 16;
+  // the persistent form's ticket word lives here too: a static LDS variable
+  // would shift the dynamic region by 4 bytes and misalign its 64-bit slots
+  o.ticket = o.misc + 16;
+  o.total = o.ticket + 2;
   return o;
 }
 
@@ -320,49 +323,59 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   const uint32_t kk = min(kq, total);
   uint32_t* oid = a.out_ids + (uint64_t)q * s.k_max;
   uint32_t* osc = a.out_scores + (uint64_t)q * s.k_max;
-  if (kk <= kFewK) {
-    // 4'. few outputs: every wave takes its kk largest keys by repeated
-    //     maximum extraction, then wave 0 takes the kk largest of those.
-    //     Keys are distinct, so the order is exactly (estimate desc, id asc).
-    uint64_t* wtop = (uint64_t*)hist;  // [WAVES][kFewK]
-    uint32_t r = 0;
-    for (; r < kk; ++r) {
-      uint64_t m = 0;
+  // 4'. few outputs: a lower bound B of the kk-th largest key prunes the
+  //     rest.  Within a wave the kk largest lane maxima are kk distinct keys,
+  //     so the kk-th of them is at most the kk-th largest key of the group;
+  //     B is the largest such bound over the waves.  The keys >= B (at least
+  //     kk) are collected and ranked directly when they fit, else the radix
+  //     select below runs.  Keys are distinct: the order is exactly
+  //     (estimate desc, id asc).
+  bool done = false;
+  if (kk > 0 && kk <= kFewK) {
+    uint64_t lm = 0;
 #pragma unroll
-      for (int i = 0; i < SPT; ++i) m = key[i] > m ? key[i] : m;
-      m = wave_max64(m);
+    for (int i = 0; i < SPT; ++i) lm = key[i] > lm ? key[i] : lm;
+    uint64_t kth = 0;
+    for (uint32_t r = 0; r < kk; ++r) {
+      const uint64_t m = wave_max64(lm);
+      kth = m;  // 0 once the wave has fewer than kk non-empty lanes
       if (m == 0) break;
-#pragma unroll
-      for (int i = 0; i < SPT; ++i)
-        if (key[i] == m) key[i] = 0;
-      if (lane == 0) wtop[wave * kFewK + r] = m;
+      if (lm == m) lm = 0;
     }
-    if (lane == 0)
-      for (; r < kFewK; ++r) wtop[wave * kFewK + r] = 0;
+    uint64_t* bound = (uint64_t*)(misc + 8);  // cleared with misc
+    if (lane == 0 && kth) atomicMax((unsigned long long*)bound, (unsigned long long)kth);
     __syncthreads();
-    if (wave == 0) {
-      constexpr int PER = WAVES * kFewK / SL_WAVE > 0 ? WAVES * kFewK / SL_WAVE : 1;
-      uint64_t v[PER];
+    const uint64_t B = *bound;
+    uint64_t* cbf = (uint64_t*)(lds + lay.cm);  // the id set is no longer needed
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const uint32_t e = lane + i * SL_WAVE;
-        v[i] = e < WAVES * kFewK ? wtop[e] : 0;
+    for (int i = 0; i < SPT; ++i) {
+      const bool in = key[i] != 0 && key[i] >= B;
+      const uint64_t m = ballot64(in);
+      if (m) {
+        uint32_t base = 0;
+        if (lane == (uint32_t)__builtin_ctzll(m)) base = atomicAdd(&misc[10], (uint32_t)__builtin_popcountll(m));
+        base = __shfl(base, __builtin_ctzll(m), SL_WAVE);
+        const uint32_t p = base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
+        if (in && p < lay.tie_cap) cbf[p] = key[i];
       }
-      for (uint32_t o = 0; o < kk; ++o) {
-        uint64_t m = 0;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) m = v[i] > m ? v[i] : m;
-        m = wave_max64(m);
-#pragma unroll
-        for (int i = 0; i < PER; ++i)
-          if (v[i] == m) v[i] = 0;
-        if (lane == 0) {
-          oid[o] = ~(uint32_t)m;
-          osc[o] = (uint32_t)(m >> 32);
+    }
+    __syncthreads();
+    const uint32_t ns = misc[10];
+    if (ns <= lay.tie_cap) {
+      for (uint32_t e = tid; e < ns; e += NT) {
+        const uint64_t x = cbf[e];
+        uint32_t r = 0;
+        for (uint32_t j = 0; j < ns; ++j) r += cbf[j] > x ? 1u : 0u;
+        if (r < kk) {
+          oid[r] = ~(uint32_t)x;
+          osc[r] = (uint32_t)(x >> 32);
         }
       }
+      done = true;
     }
-  } else {
+    __syncthreads();
+  }
+  if (!done) {
   // 4. threshold key.  MSD radix select over 8-bit digits of
   //    (estimate << 32 | ~id), starting at the estimate's low byte when every
   //    estimate is below 256.  Once the estimate E of the kk-th key is known,
@@ -478,8 +491,8 @@ template <int WAVES, int SPT, bool CL, bool EX>
 __global__ void __launch_bounds__(WAVES * SL_WAVE, (query_min_waves<WAVES, SPT>()))
     k_query_persistent(Shape s, ConstView c, TablesView tab, QueryArgs a, uint32_t per_ticket, uint32_t* ticket) {
   extern __shared__ uint32_t lds[];
-  __shared__ uint32_t base_sh;
   const QLayout lay = q_layout(s, EX);
+  uint32_t& base_sh = lds[lay.ticket];
   const ConstView cl = CL ? stage_consts(s, c, lds + lay.cst, WAVES * SL_WAVE) : c;
   const uint64_t n = a.q.n_rows;
   // the next ticket is taken while the current one is answered, so the
