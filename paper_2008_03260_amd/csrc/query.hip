@@ -111,6 +111,11 @@ __device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
   return m;
 }
 
+// Entries of the small distinct-id table (used when at most half as many
+// slots have an estimate of 2 or more).
+constexpr uint32_t kSmallSetLog2 = 9;
+constexpr uint32_t kSmallSet = 1u << kSmallSetLog2;
+
 // Slot of an id in the id set: high bits of a multiplicative hash.
 __device__ __forceinline__ uint32_t hs_slot(uint32_t id, uint32_t log2_size) {
   return (id * 0x9E3779B1u) >> (32 - log2_size);
@@ -213,9 +218,16 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
           est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
         }
       }
+      // slots whose id may occur more than once (estimate >= 2)
+      uint32_t multi = 0;
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) multi += id[i] != SL_EMPTY && est[i] >= 2 ? 1u : 0u;
+      for (int o = 32; o > 0; o >>= 1) multi += __shfl_xor(multi, o, SL_WAVE);
+      if (lane == 0) atomicAdd(&misc[11], multi);
     }
     __syncthreads();
-    if (misc[6] != s.d * misc[7]) {
+    const bool overflow = misc[6] != s.d * misc[7];
+    if (overflow) {
 #pragma unroll
       for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
       for (uint32_t r = 0; r < s.d; ++r) {
@@ -240,22 +252,29 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     }
 #pragma unroll
     for (int i = 0; i < SPT; ++i) key[i] = id[i] != SL_EMPTY ? ((uint64_t)est[i] << 32) | (uint32_t)~id[i] : 0ull;
-    // 3. distinct ids: the first insertion into the LDS id set represents the id
-    for (uint32_t e = tid; e < lay.hs_size; e += NT) hs[e] = SL_EMPTY;
+    // 3. distinct ids.  The count-min estimate is never below the true
+    //    count, so an id whose estimate is 1 occurs once and represents
+    //    itself; only the others go through the LDS id set, where the first
+    //    insertion represents the id.  When few slots need it (the usual
+    //    case) a small table is used, which is cheaper to clear.
+    const bool small = !overflow && kSmallSet < lay.hs_size && misc[11] <= kSmallSet / 2;
+    const uint32_t set_size = small ? kSmallSet : lay.hs_size;
+    const uint32_t set_log2 = small ? kSmallSetLog2 : hs_log2;
+    for (uint32_t e = tid; e < set_size; e += NT) hs[e] = SL_EMPTY;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
       if (id[i] != SL_EMPTY) {
-        uint32_t h = hs_slot(id[i], hs_log2);
-        bool rep = false;
-        for (;;) {
+        bool rep = est[i] == 1;
+        uint32_t h = hs_slot(id[i], set_log2);
+        while (!rep) {
           uint32_t prev = atomicCAS(&hs[h], SL_EMPTY, id[i]);
           if (prev == SL_EMPTY) {
             rep = true;
             break;
           }
           if (prev == id[i]) break;
-          h = (h + 1) & hs_mask;
+          h = (h + 1) & (set_size - 1);
         }
         if (rep) {
           ++nrep;
