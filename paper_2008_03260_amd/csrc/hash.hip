@@ -1,5 +1,7 @@
 // Hash kernels (Section 2.2 DOPH, Section 2.3 table addresses), input
 // validation and small utility kernels.
+#include <algorithm>
+
 #include "doph.h"
 
 namespace slash {
@@ -304,7 +306,11 @@ hipError_t launch_hash_rows(const Shape& s, const ConstView& c, slash_csr rows, 
                             int combine, hipStream_t st) {
   if (rows.n_rows == 0) return hipSuccess;
   if (!hash_shape_ok(s)) return hipErrorInvalidValue;
-  const uint32_t rpc = hash_rpc(s);
+  // a small batch (an insert) takes shorter chunks so that it spreads over
+  // about a thousand blocks instead of a few dozen
+  uint32_t rpc = hash_rpc(s);
+  const uint64_t want = (rows.n_rows + 1023) / 1024;
+  if (want < rpc) rpc = (uint32_t)std::max<uint64_t>(std::min<uint64_t>(16, rpc), want);
   const size_t stage = (size_t)s.L * (rpc + 1) * 4 + (size_t)const_lds_words(s) * 4;
   const uint32_t nw = hash_waves(s, stage);
   const size_t lds = hash_lds(s, nw, stage);
