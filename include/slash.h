@@ -263,7 +263,9 @@ typedef struct {
   uint32_t max_batch;         /* queries per device batch */
   uint32_t max_inflight;      /* device batches in flight (>= 1) */
   uint32_t queue_capacity;    /* pending requests accepted before E_BUSY */
-  uint32_t max_wait_us;       /* a partial batch is launched after this wait */
+  uint32_t max_wait_us;       /* 0: a batch launches as soon as a slot is free; else a batch that is
+                                 neither full nor followed by an insert waits until its oldest
+                                 query has waited this long */
   uint32_t max_query_nnz;     /* largest query row accepted */
   uint32_t max_insert_nnz;    /* indices one insert request may carry (0: max(4096 * 64, 8 * max_query_nnz)) */
 } slash_serve_config;
@@ -286,7 +288,7 @@ typedef struct {
 typedef struct {
   uint64_t queries_done, inserts_done, rows_inserted, batches, rejected_busy, rejected_nomem;
   uint64_t peak_inflight, peak_hbm_bytes;
-  double busy_s;
+  double busy_s; /* seconds with device work in flight (host clock) */
 } slash_serve_stats;
 
 SLASH_API slash_status slash_serve_start(slash_index* index, const slash_serve_config* cfg, slash_server** out);

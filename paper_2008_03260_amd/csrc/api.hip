@@ -522,8 +522,12 @@ slash_status slash::reserve_insert_scratch(slash_index* ix, uint64_t rows) {
 
 extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev,
                                      void* stream) {
+  return slash::insert_rows(ix, rows, flags, new_ids_dev, (hipStream_t)stream, InsertGate{});
+}
+
+slash_status slash::insert_rows(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev,
+                                hipStream_t st, const InsertGate& gate) {
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
-  hipStream_t st = (hipStream_t)stream;
   const uint64_t n = rows.n_rows;
   if (n == 0) return SLASH_OK;
   if (ix->n_items + n > 0xFFFFFFFFull) return fail(SLASH_E_CAPACITY, "ids would exceed 0xFFFFFFFE");
@@ -538,7 +542,7 @@ extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t f
       return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
     HIP_TRY(launch_hash_rows(s, ix->cv, rows, ix->ins_keys.as<uint32_t>(), n, 0, st));
     HIP_TRY(launch_insert_small(s, ix->cv, ix->ins_keys.as<uint32_t>(), (uint32_t)n, first, ix->ins_seg.p, tables(ix),
-                                st));
+                                st, gate));
     if (new_ids_dev) HIP_TRY(launch_iota_u32(new_ids_dev, first, n, st));
     ix->n_items += n;
     return SLASH_OK;
@@ -559,7 +563,7 @@ extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t f
   int bits = (int)s.B + ceil_log2(s.L);
   HIP_TRY(radix_sort(ix->ins_keys.as<uint32_t>(), ix->ins_vals.as<uint32_t>(), items, bits, sb, &sk, &sv, st));
   HIP_TRY(launch_insert_merge(s, ix->cv, sk, sv, items, ix->ins_seg.as<uint32_t>(), ix->ins_part.as<uint32_t>(),
-                              tables(ix), st));
+                              tables(ix), st, gate));
   if (new_ids_dev) HIP_TRY(launch_iota_u32(new_ids_dev, first, n, st));
   ix->n_items += n;
   return SLASH_OK;

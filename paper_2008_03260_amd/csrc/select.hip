@@ -720,7 +720,7 @@ bool small_insert_ok(const Shape& s, uint64_t n) { return n >= 1 && n <= kSmallI
 size_t small_insert_scratch(const Shape& s, uint64_t n) { return (size_t)s.L * n * 12 + 64; }
 
 hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
-                               void* scratch, TablesView tab, hipStream_t st) {
+                               void* scratch, TablesView tab, hipStream_t st, const InsertGate& gate) {
   if (n == 0 || n > kSmallInsert) return hipErrorInvalidValue;
   uint2* recs = (uint2*)scratch;
   uint32_t* items = (uint32_t*)(recs + (size_t)s.L * n);
@@ -732,6 +732,7 @@ hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_
     return e;
   hipLaunchKernelGGL(k_insert_group, dim3(s.L), dim3(kGroupThreads), lds, st, keys, n, first_id, recs, items);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = gate(st)) != hipSuccess) return e;
   if (s.bucket) return launch_tk_runs(s, c, recs, items, n, tab, st);
   const uint64_t lanes = (uint64_t)s.L * n * 16;
   const dim3 grid((uint32_t)((lanes + kMergeThreads - 1) / kMergeThreads));
@@ -749,7 +750,8 @@ hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_
 }
 
 hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys, const uint32_t* svals,
-                               uint64_t n, uint32_t* seg_scratch, uint32_t* part, TablesView tab, hipStream_t st) {
+                               uint64_t n, uint32_t* seg_scratch, uint32_t* part, TablesView tab, hipStream_t st,
+                               const InsertGate& gate) {
   if (n == 0) return hipSuccess;
   // seg_scratch: [0, n) flags -> segment numbers, [n, 2n) starts, [2n] count
   uint32_t* segno = seg_scratch;
@@ -760,6 +762,7 @@ hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_head_scatter, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, skeys, n, segno, seg_start,
                      nseg);
+  if ((e = gate(st)) != hipSuccess) return e;
   if (s.bucket) return launch_tk_segments(s, c, skeys, svals, n, seg_start, nseg, tab, st);
   size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
   hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st, s, c,

@@ -10,13 +10,20 @@
 //     FIFO that fits the slot (continuous batching: no waiting for a full
 //     batch while the device has room), copies them in, runs slash_query on
 //     the slot's stream and copies the results back;
-//   - an insert at the head of the FIFO closes the current epoch: it is
-//     ordered after every in-flight batch and insert (stream waits on their
-//     events) and every later batch waits on it, so a query of epoch e sees
-//     exactly the inserts submitted before it, without blocking the host.
-//     Two insert staging slots let the next insert be queued behind a
-//     running one, so the device runs epochs back to back;
-//   - finished work is detected with events and turned into completions.
+//   - an insert at the head of the FIFO closes the current epoch: it runs
+//     after every in-flight insert, its kernels that write the tables run
+//     after the query kernels of every in-flight batch (stream waits on their
+//     events; hashing and grouping the new rows may overlap those queries),
+//     and the query kernels of every later batch wait on it, so a query of
+//     epoch e sees exactly the inserts submitted before it, without blocking
+//     the host.  Only kernels wait: request data is copied in before the
+//     wait, and an insert does not wait for the result copies of earlier
+//     batches.  Up to four insert staging slots let later inserts queue
+//     behind a running one, so the device runs epochs back to back;
+//   - with max_wait_us > 0, a batch that is neither full nor followed by an
+//     insert is held back until its oldest query has waited that long;
+//   - finished work is detected with events (polled without sleeping while
+//     work is in flight) and turned into completions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +46,10 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Insert staging slots a server keeps at most (inserts queued on the device
+// behind the one running).
+constexpr size_t kInsertSlots = 4;
+
 struct Request {
   uint64_t ticket = 0;
   uint32_t kind = 0;  // 0 query, 1 insert
@@ -51,7 +62,8 @@ struct Request {
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t done = nullptr;   // everything the slot launched has finished
+  hipEvent_t kdone = nullptr;  // query slots: the query kernels have finished
   bool busy = false;
   uint32_t kind = 0;
   uint64_t epoch = 0;
@@ -100,6 +112,7 @@ namespace {
 void free_slot(Slot& s) {
   if (s.stream) (void)hipStreamSynchronize(s.stream);
   if (s.done) (void)hipEventDestroy(s.done);
+  if (s.kdone) (void)hipEventDestroy(s.kdone);
   if (s.stream) (void)hipStreamDestroy(s.stream);
   (void)hipFree(s.d_in);
   (void)hipFree(s.d_out);
@@ -127,6 +140,7 @@ bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool 
   const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
   if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
   if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
+  if (with_out && hipEventCreateWithFlags(&s.kdone, hipEventDisableTiming) != hipSuccess) return false;
   if (hipMalloc(&s.d_in, in_bytes) != hipSuccess) return false;
   if (hipHostMalloc(&s.h_in, in_bytes) != hipSuccess) return false;
   if (with_out) {
@@ -159,8 +173,9 @@ uint64_t slot_bytes(uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max) {
   return in_layout(cap_q, cap_nnz, true).bytes + (uint64_t)cap_q * k_max * 8;
 }
 
-// Turn a finished slot into completions (called with the lock held).
-void finish_slot(slash_server* srv, Slot& s) {
+// Turn a finished slot into completions (called with the lock held); status
+// is SLASH_E_DEVICE when the slot's work failed on the device.
+void finish_slot(slash_server* srv, Slot& s, int32_t status) {
   const uint32_t km = srv->info.params.k_max;
   double t = now_s();
   if (s.kind == 0) {
@@ -170,7 +185,7 @@ void finish_slot(slash_server* srv, Slot& s) {
       memset(&c, 0, sizeof c);
       c.ticket = r.ticket;
       c.epoch = s.epoch;
-      c.status = SLASH_OK;
+      c.status = status;
       c.kind = 0;
       c.k = r.k;
       const uint32_t* oi = s.h_out + q * km;
@@ -188,7 +203,7 @@ void finish_slot(slash_server* srv, Slot& s) {
     memset(&c, 0, sizeof c);
     c.ticket = r.ticket;
     c.epoch = s.epoch;
-    c.status = SLASH_OK;
+    c.status = status;
     c.kind = 1;
     c.n_ids = r.n_rows;
     c.first_id = s.first_id;
@@ -222,60 +237,102 @@ hipError_t launch_queries(slash_server* srv, Slot& s) {
     h_k[q] = r.k;
   }
   hipError_t e;
-  if (srv->have_insert && (e = hipStreamWaitEvent(s.stream, srv->last_insert, 0)) != hipSuccess) return e;
+  // the request copy may overlap the insert that opened this epoch; the
+  // query kernels may not
   if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  if (srv->have_insert && (e = hipStreamWaitEvent(s.stream, srv->last_insert, 0)) != hipSuccess) return e;
   slash_csr q{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), n};
   slash_status st = slash_query(srv->ix, q, (const uint32_t*)(s.d_in + l.k), 0, SLASH_FLAG_TRUSTED, s.d_out,
                                 s.d_out + (size_t)n * km, s.stream);
   if (st != SLASH_OK) return hipErrorLaunchFailure;
+  if ((e = hipEventRecord(s.kdone, s.stream)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * km * 8, hipMemcpyDeviceToHost, s.stream)) != hipSuccess)
     return e;
   return hipEventRecord(s.done, s.stream);
 }
 
-// Apply an insert after every in-flight batch and insert; later batches wait
-// on it.
+// The table writes of a served insert wait for the query kernels of every
+// batch in flight when it is launched (its gate).
+hipError_t wait_query_kernels(void* ctx, hipStream_t st) {
+  slash_server* srv = (slash_server*)ctx;
+  for (Slot& o : srv->slots)
+    if (o.busy) {
+      const hipError_t e = hipStreamWaitEvent(st, o.kdone, 0);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+// Apply an insert after every in-flight insert (they share the index's insert
+// scratch); its table writes also wait for the query kernels of every
+// in-flight batch, while its hashing and grouping may run beside them.  The
+// kernels of later batches wait on it.  The rows are copied in first.
 hipError_t launch_insert(slash_server* srv, Slot& s) {
   const Request& r = s.reqs[0];
   hipError_t e;
-  for (Slot& o : srv->slots)
-    if (o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
-  for (Slot& o : srv->ins)
-    if (&o != &s && o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
   const InLayout l = in_layout(r.n_rows, r.idx.size(), false);
   memcpy(s.h_in, r.indptr.data(), (r.n_rows + 1) * 8);
   memcpy(s.h_in + l.idx, r.idx.data(), r.idx.size() * 4);
   if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
+  for (Slot& o : srv->ins)
+    if (&o != &s && o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
   slash_index_info info;
   slash_index_info_get(srv->ix, &info);
   s.first_id = (uint32_t)info.n_items;
   slash_csr rows{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), r.n_rows};
-  if (slash_insert(srv->ix, rows, SLASH_FLAG_TRUSTED, nullptr, s.stream) != SLASH_OK) return hipErrorLaunchFailure;
+  if (insert_rows(srv->ix, rows, SLASH_FLAG_TRUSTED, nullptr, s.stream, InsertGate{wait_query_kernels, srv}) !=
+      SLASH_OK)
+    return hipErrorLaunchFailure;
   if ((e = hipEventRecord(s.done, s.stream)) != hipSuccess) return e;
   srv->last_insert = s.done;
   srv->have_insert = true;
   return hipSuccess;
 }
 
+// Queries at the head of the FIFO that one batch slot could take, and
+// whether an insert ends that run (then waiting cannot make the batch larger).
+void head_run(const slash_server* srv, const Slot& s, uint32_t max_batch, uint32_t* n, bool* full) {
+  uint64_t nnz = 0;
+  uint32_t c = 0;
+  *full = false;
+  for (const Request& r : srv->pending) {
+    if (r.kind != 0 || c >= std::min(max_batch, s.cap_q) || nnz + r.idx.size() > s.cap_nnz) {
+      *full = true;
+      break;
+    }
+    nnz += r.idx.size();
+    ++c;
+  }
+  *n = c;
+  *full = *full || c >= std::min(max_batch, s.cap_q);
+}
+
 void scheduler(slash_server* srv) {
   (void)hipSetDevice(srv->device);
   const uint32_t max_batch = srv->cfg.max_batch;
+  const double max_wait = srv->cfg.max_wait_us * 1e-6;
+  std::vector<std::pair<Slot*, hipError_t>> finished;
+  double busy_since = -1.0;
   std::unique_lock<std::mutex> lk(srv->mu);
   for (;;) {
-    // 1. retire finished work
-    bool progressed = false;
-    for (Slot& s : srv->slots)
-      if (s.busy && hipEventQuery(s.done) == hipSuccess) {
-        finish_slot(srv, s);
-        progressed = true;
-      }
-    for (Slot& s : srv->ins)
-      if (s.busy && hipEventQuery(s.done) == hipSuccess) {
-        finish_slot(srv, s);
-        progressed = true;
-      }
-    if (progressed) srv->cv.notify_all();
+    // 1. retire finished work.  Slots, events and streams belong to this
+    //    thread, so the events are queried without the lock.
+    lk.unlock();
+    finished.clear();
+    for (std::vector<Slot>* group : {&srv->slots, &srv->ins})
+      for (Slot& s : *group)
+        if (s.busy) {
+          const hipError_t q = hipEventQuery(s.done);
+          if (q != hipErrorNotReady) finished.emplace_back(&s, q);
+        }
+    lk.lock();
+    for (auto& [s, q] : finished) {
+      if (q != hipSuccess) srv->dev_err = q;
+      finish_slot(srv, *s, q == hipSuccess ? SLASH_OK : SLASH_E_DEVICE);
+    }
+    if (!finished.empty()) srv->cv.notify_all();
     // 2. admit the head of the FIFO
+    double wake_at = 0.0;
     while (!srv->pending.empty()) {
       Request& head = srv->pending.front();
       if (head.kind == 1) {
@@ -309,6 +366,16 @@ void scheduler(slash_server* srv) {
         }
       if (!free_s) break;
       Slot& s = *free_s;
+      if (max_wait > 0 && !srv->stopping) {
+        uint32_t run = 0;
+        bool full = false;
+        head_run(srv, s, max_batch, &run, &full);
+        const double due = head.t_submit + max_wait;
+        if (!full && now_s() < due) {
+          wake_at = due;  // hold the partial batch back
+          break;
+        }
+      }
       s.reqs.clear();
       uint64_t nnz = 0;
       while (!srv->pending.empty() && s.reqs.size() < std::min(max_batch, s.cap_q)) {
@@ -333,12 +400,22 @@ void scheduler(slash_server* srv) {
     bool busy = false;
     for (Slot& s : srv->ins) busy |= s.busy;
     for (Slot& s : srv->slots) busy |= s.busy;
+    // host time with device work in flight
+    const double t = now_s();
+    if (busy && busy_since < 0) busy_since = t;
+    if (!busy && busy_since >= 0) {
+      srv->stats.busy_s += t - busy_since;
+      busy_since = -1.0;
+    }
     if (srv->stopping && srv->pending.empty() && !busy) break;
     if (busy) {
-      // device work in flight: poll its events without sleeping long
+      // device work in flight: poll its events again at once (a sleep would
+      // add the timer slack, tens of microseconds, to every completion)
       lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      std::this_thread::yield();
       lk.lock();
+    } else if (wake_at > 0) {
+      srv->cv.wait_for(lk, std::chrono::duration<double>(std::max(0.0, wake_at - t)));
     } else {
       srv->cv.wait_for(lk, std::chrono::milliseconds(1), [&] { return srv->stopping || !srv->pending.empty(); });
     }
@@ -387,15 +464,16 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     delete srv;
     return rs;
   }
-  // a second insert slot when the budget still leaves room for a batch slot
-  if (srv->hbm_used + ins_bytes + per_slot <= cfg->hbm_budget_bytes) {
+  // up to three more insert slots while the budget still leaves room for a
+  // batch slot
+  while (srv->ins.size() < kInsertSlots && srv->hbm_used + ins_bytes + per_slot <= cfg->hbm_budget_bytes) {
     srv->ins.emplace_back();
-    if (alloc_slot(srv->ins[1], ins_rows, ins_nnz, km, false)) {
-      srv->hbm_used += ins_bytes;
-    } else {
-      free_slot(srv->ins[1]);
+    if (!alloc_slot(srv->ins.back(), ins_rows, ins_nnz, km, false)) {
+      free_slot(srv->ins.back());
       srv->ins.pop_back();
+      break;
     }
+    srv->hbm_used += ins_bytes;
   }
   for (uint32_t i = 0; i < cfg->max_inflight && srv->hbm_used + per_slot <= cfg->hbm_budget_bytes; ++i) {
     srv->slots.emplace_back();

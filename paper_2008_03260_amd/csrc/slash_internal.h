@@ -203,16 +203,27 @@ hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const ui
                         FinalWork* finals, uint32_t* n_chunks, uint32_t* cand, TablesView tab, hipStream_t st);
 
 
+// A hook an insert calls on its stream after the kernels that read only the
+// new rows and the insert scratch (hashing, grouping, sorting) and before the
+// first kernel that writes the tables; a server makes the table writes wait
+// for in-flight queries there.  Returns the first error of what it enqueued.
+struct InsertGate {
+  hipError_t (*fn)(void* ctx, hipStream_t st) = nullptr;
+  void* ctx = nullptr;
+  hipError_t operator()(hipStream_t st) const { return fn ? fn(ctx, st) : hipSuccess; }
+};
+
 // Small insert (n rows, keys [L][n] as written by launch_hash_rows without
-// combining): one block per table sorts, groups and merges in LDS.
+// combining): one block per table groups the (bucket, id) pairs in LDS, then
+// one kernel merges every touched bucket's run into its reservoir.
 bool small_insert_ok(const Shape& s, uint64_t n);
 size_t small_insert_scratch(const Shape& s, uint64_t n);
 hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
-                               void* scratch, TablesView tab, hipStream_t st);
+                               void* scratch, TablesView tab, hipStream_t st, const InsertGate& gate = {});
 // Insert merge: sorted combined keys (t*nb+b) with new ids -> merged reservoirs.
 hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys,
                                const uint32_t* svals, uint64_t n, uint32_t* seg_scratch,
-                               uint32_t* part, TablesView tab, hipStream_t st);
+                               uint32_t* part, TablesView tab, hipStream_t st, const InsertGate& gate = {});
 
 // Query kernels.
 struct QueryArgs {
@@ -269,5 +280,9 @@ hipError_t launch_tk_query(const Shape& s, const ConstView& c, const TablesView&
 // that later inserts of at most that many rows allocate nothing and never
 // drain the device (a server calls this once at start).
 slash_status reserve_insert_scratch(slash_index* ix, uint64_t rows);
+
+// slash_insert with a gate before the table writes (see InsertGate).
+slash_status insert_rows(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev, hipStream_t st,
+                         const InsertGate& gate);
 
 }  // namespace slash

@@ -71,6 +71,29 @@ def test_served_results_equal_standalone(api, setup):
     idx.close()
 
 
+def test_max_wait_holds_partial_batches(api, setup):
+    # with a long max_wait the scheduler launches only full batches (and the
+    # last one once its oldest query has waited); results are unchanged
+    law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    ref_i, ref_s = standalone(api, params, ip, ix, n0, qi, qx, kq)
+    idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=64 << 20, max_batch=64, max_inflight=3,
+                                max_wait_us=50_000)
+    nq = len(qi) - 1
+    tickets = {api.slash_serve_submit_query(srv, qx[qi[q]:qi[q + 1]], int(kq[q])): q for q in range(nq)}
+    got = []
+    while len(got) < nq:
+        got += api.slash_serve_poll(srv)
+    stats = api.slash_serve_stop(srv)
+    assert stats["queries_done"] == nq and stats["batches"] <= -(-nq // 64) + 2
+    assert stats["busy_s"] > 0
+    for c in got:
+        q = tickets[c["ticket"]]
+        k = int(kq[q])
+        assert c["status"] == 0 and (c["ids"] == ref_i[q, :k]).all() and (c["scores"] == ref_s[q, :k]).all()
+    idx.close()
+
+
 def test_inserts_close_epochs(api, setup):
     # queries submitted before an insert see the index without it; those
     # after see it (the inserted index equals a bulk build on the union)
