@@ -9,11 +9,15 @@
 //   3. count-min: d rows of w counters in LDS, incremented with LDS atomics;
 //      8-bit counters, and a 16-bit recount one row at a time for a query
 //      whose counts overflow a byte (a counter never exceeds L * R <= 65535);
-//   4. estimate = min over rows; duplicates of an id are folded by an LDS
-//      open-addressing set so each distinct id is ranked once;
-//   5. the k-th largest key (estimate << 32 | ~id) is found by an MSD radix
-//      select over 8-bit digits, the winners are ranked by counting and
-//      written with stride k_max, padded with (EMPTY, 0).
+//   4. estimate = min over rows; for k <= 16 a lower bound of the k-th
+//      largest key (estimate << 32 | ~id) from the waves' lane maxima leaves
+//      a few dozen candidates, whose duplicate slots are dropped and which
+//      are ranked directly;
+//   5. otherwise duplicates of an id are folded by an LDS open-addressing
+//      set so each distinct id is ranked once, the k-th largest key is found
+//      by an MSD radix select over 8-bit digits, and the winners are ranked
+//      by counting.  Results are written with stride k_max, padded with
+//      (EMPTY, 0).
 // The persistent form loops over queries taken from a device work counter.
 #include "doph.h"
 
@@ -64,9 +68,9 @@ __host__ __device__ inline QLayout q_layout(const Shape& s, bool exact = false) 
   // the id set reuses the count-min region once the estimates are read
   uint32_t region = o.cm_words > o.cm16_words ? o.cm_words : o.cm16_words;
   if (o.hs_size * per > region) region = o.hs_size * per;
-  // keys with the kk-th estimate or above, ranked directly when at most this
-  // many (collected into the count-min region, free by then)
-  o.tie_cap = region / 2 < 128 ? region / 2 : 128;
+  // keys ranked directly when at most this many (collected into the
+  // count-min region, free by then, beside one de-duplicated copy)
+  o.tie_cap = region / 4 < 128 ? region / 4 : 128;
   o.hist = o.cm + region;
   o.sel = o.hist + 512;
   if (o.sel & 1) o.sel++;
@@ -175,6 +179,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   }
   uint64_t key[SPT];
   uint32_t nrep = 0, emax = 0;
+  bool overflow = false;
   if constexpr (!EX) {
     // 2. count-min with 8-bit counters.  Every live slot adds one to each of
     //    the d rows, so without overflow the counters sum to d * live; an
@@ -226,7 +231,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       if (lane == 0) atomicAdd(&misc[11], multi);
     }
     __syncthreads();
-    const bool overflow = misc[6] != s.d * misc[7];
+    overflow = misc[6] != s.d * misc[7];
     if (overflow) {
 #pragma unroll
       for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
@@ -252,38 +257,6 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     }
 #pragma unroll
     for (int i = 0; i < SPT; ++i) key[i] = id[i] != SL_EMPTY ? ((uint64_t)est[i] << 32) | (uint32_t)~id[i] : 0ull;
-    // 3. distinct ids.  The count-min estimate is never below the true
-    //    count, so an id whose estimate is 1 occurs once and represents
-    //    itself; only the others go through the LDS id set, where the first
-    //    insertion represents the id.  When few slots need it (the usual
-    //    case) a small table is used, which is cheaper to clear.
-    const bool small = !overflow && kSmallSet < lay.hs_size && misc[11] <= kSmallSet / 2;
-    const uint32_t set_size = small ? kSmallSet : lay.hs_size;
-    const uint32_t set_log2 = small ? kSmallSetLog2 : hs_log2;
-    for (uint32_t e = tid; e < set_size; e += NT) hs[e] = SL_EMPTY;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < SPT; ++i) {
-      if (id[i] != SL_EMPTY) {
-        bool rep = est[i] == 1;
-        uint32_t h = hs_slot(id[i], set_log2);
-        while (!rep) {
-          uint32_t prev = atomicCAS(&hs[h], SL_EMPTY, id[i]);
-          if (prev == SL_EMPTY) {
-            rep = true;
-            break;
-          }
-          if (prev == id[i]) break;
-          h = (h + 1) & (set_size - 1);
-        }
-        if (rep) {
-          ++nrep;
-          emax = max(emax, (uint32_t)(key[i] >> 32));
-        } else {
-          key[i] = 0;
-        }
-      }
-    }
   } else {
     // 2'. exact variant: the id set also counts the occurrences of each id
     //     (its multiplicity among the probed slots, at most L); the slot that
@@ -324,6 +297,114 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       }
     }
   }
+  uint32_t kq = a.kq ? a.kq[q] : a.k;
+  if (kq > s.k_max) kq = s.k_max;
+  uint32_t kk = kq;  // outputs written; fewer when there are fewer distinct ids
+  uint32_t* oid = a.out_ids + (uint64_t)q * s.k_max;
+  uint32_t* osc = a.out_scores + (uint64_t)q * s.k_max;
+  // 3'. few outputs: a lower bound B of the kq-th largest distinct key prunes
+  //     the rest.  Keys of one id are equal, so in the count-min variant an
+  //     id may still hold several slots here.  Within a wave, taking the
+  //     largest lane maximum kq times, and each time retiring every lane that
+  //     holds it, yields kq distinct keys, so the last of them is at most the
+  //     kq-th largest distinct key of the group; B is the largest such bound
+  //     over the waves.  The keys >= B (every distinct key of the top kq, with
+  //     their copies) are collected, one copy of each is kept and the copies
+  //     ranked directly when they fit; otherwise, or when no wave holds kq
+  //     distinct keys, the general path below runs.  The order is exactly
+  //     (estimate desc, id asc).
+  bool done = false;
+  if (kq > 0 && kq <= kFewK) {
+    uint64_t lm = 0;
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) lm = key[i] > lm ? key[i] : lm;
+    uint64_t kth = 0;
+    for (uint32_t r = 0; r < kq; ++r) {
+      const uint64_t m = wave_max64(lm);
+      kth = m;  // 0 once the wave has fewer than kq distinct lane maxima
+      if (m == 0) break;
+      if (lm == m) lm = 0;
+    }
+    uint64_t* bound = (uint64_t*)(misc + 8);  // cleared with misc
+    if (lane == 0 && kth) atomicMax((unsigned long long*)bound, (unsigned long long)kth);
+    __syncthreads();
+    const uint64_t B = *bound;
+    if (B != 0) {
+      uint64_t* cbf = (uint64_t*)(lds + lay.cm);  // the sketch is no longer needed
+      uint64_t* uq = cbf + lay.tie_cap;             // one copy of each collected key
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) {
+        const bool in = key[i] != 0 && key[i] >= B;
+        const uint64_t m = ballot64(in);
+        if (m) {
+          uint32_t base = 0;
+          if (lane == (uint32_t)__builtin_ctzll(m)) base = atomicAdd(&misc[10], (uint32_t)__builtin_popcountll(m));
+          base = __shfl(base, __builtin_ctzll(m), SL_WAVE);
+          const uint32_t p = base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
+          if (in && p < lay.tie_cap) cbf[p] = key[i];
+        }
+      }
+      __syncthreads();
+      const uint32_t ns = misc[10];
+      if (ns <= lay.tie_cap) {
+        for (uint32_t e = tid; e < ns; e += NT) {
+          const uint64_t x = cbf[e];
+          bool copy = false;
+          for (uint32_t j = 0; j < e; ++j) copy |= cbf[j] == x;
+          uq[e] = copy ? 0ull : x;
+        }
+        __syncthreads();
+        for (uint32_t e = tid; e < ns; e += NT) {
+          const uint64_t x = uq[e];
+          if (x == 0) continue;
+          uint32_t r = 0;
+          for (uint32_t j = 0; j < ns; ++j) r += uq[j] > x ? 1u : 0u;
+          if (r < kq) {
+            oid[r] = ~(uint32_t)x;
+            osc[r] = (uint32_t)(x >> 32);
+          }
+        }
+        done = true;
+      }
+      __syncthreads();
+    }
+  }
+  if (!done) {
+  if constexpr (!EX) {
+    // 3. distinct ids.  The count-min estimate is never below the true
+    //    count, so an id whose estimate is 1 occurs once and represents
+    //    itself; only the others go through the LDS id set, where the first
+    //    insertion represents the id.  When few slots need it (the usual
+    //    case) a small table is used, which is cheaper to clear.
+    const bool small = !overflow && kSmallSet < lay.hs_size && misc[11] <= kSmallSet / 2;
+    const uint32_t set_size = small ? kSmallSet : lay.hs_size;
+    const uint32_t set_log2 = small ? kSmallSetLog2 : hs_log2;
+    for (uint32_t e = tid; e < set_size; e += NT) hs[e] = SL_EMPTY;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      if (key[i] != 0) {
+        const uint32_t idi = ~(uint32_t)key[i];
+        bool rep = (key[i] >> 32) == 1;
+        uint32_t h = hs_slot(idi, set_log2);
+        while (!rep) {
+          uint32_t prev = atomicCAS(&hs[h], SL_EMPTY, idi);
+          if (prev == SL_EMPTY) {
+            rep = true;
+            break;
+          }
+          if (prev == idi) break;
+          h = (h + 1) & (set_size - 1);
+        }
+        if (rep) {
+          ++nrep;
+          emax = max(emax, (uint32_t)(key[i] >> 32));
+        } else {
+          key[i] = 0;
+        }
+      }
+    }
+  }
   {
     uint32_t v = nrep, m = emax;
     for (int o = 32; o > 0; o >>= 1) {
@@ -337,64 +418,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   }
   __syncthreads();
   const uint32_t total = misc[0];
-  uint32_t kq = a.kq ? a.kq[q] : a.k;
-  if (kq > s.k_max) kq = s.k_max;
-  const uint32_t kk = min(kq, total);
-  uint32_t* oid = a.out_ids + (uint64_t)q * s.k_max;
-  uint32_t* osc = a.out_scores + (uint64_t)q * s.k_max;
-  // 4'. few outputs: a lower bound B of the kk-th largest key prunes the
-  //     rest.  Within a wave the kk largest lane maxima are kk distinct keys,
-  //     so the kk-th of them is at most the kk-th largest key of the group;
-  //     B is the largest such bound over the waves.  The keys >= B (at least
-  //     kk) are collected and ranked directly when they fit, else the radix
-  //     select below runs.  Keys are distinct: the order is exactly
-  //     (estimate desc, id asc).
-  bool done = false;
-  if (kk > 0 && kk <= kFewK) {
-    uint64_t lm = 0;
-#pragma unroll
-    for (int i = 0; i < SPT; ++i) lm = key[i] > lm ? key[i] : lm;
-    uint64_t kth = 0;
-    for (uint32_t r = 0; r < kk; ++r) {
-      const uint64_t m = wave_max64(lm);
-      kth = m;  // 0 once the wave has fewer than kk non-empty lanes
-      if (m == 0) break;
-      if (lm == m) lm = 0;
-    }
-    uint64_t* bound = (uint64_t*)(misc + 8);  // cleared with misc
-    if (lane == 0 && kth) atomicMax((unsigned long long*)bound, (unsigned long long)kth);
-    __syncthreads();
-    const uint64_t B = *bound;
-    uint64_t* cbf = (uint64_t*)(lds + lay.cm);  // the id set is no longer needed
-#pragma unroll
-    for (int i = 0; i < SPT; ++i) {
-      const bool in = key[i] != 0 && key[i] >= B;
-      const uint64_t m = ballot64(in);
-      if (m) {
-        uint32_t base = 0;
-        if (lane == (uint32_t)__builtin_ctzll(m)) base = atomicAdd(&misc[10], (uint32_t)__builtin_popcountll(m));
-        base = __shfl(base, __builtin_ctzll(m), SL_WAVE);
-        const uint32_t p = base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
-        if (in && p < lay.tie_cap) cbf[p] = key[i];
-      }
-    }
-    __syncthreads();
-    const uint32_t ns = misc[10];
-    if (ns <= lay.tie_cap) {
-      for (uint32_t e = tid; e < ns; e += NT) {
-        const uint64_t x = cbf[e];
-        uint32_t r = 0;
-        for (uint32_t j = 0; j < ns; ++j) r += cbf[j] > x ? 1u : 0u;
-        if (r < kk) {
-          oid[r] = ~(uint32_t)x;
-          osc[r] = (uint32_t)(x >> 32);
-        }
-      }
-      done = true;
-    }
-    __syncthreads();
-  }
-  if (!done) {
+  kk = min(kq, total);
   // 4. threshold key.  MSD radix select over 8-bit digits of
   //    (estimate << 32 | ~id), starting at the estimate's low byte when every
   //    estimate is below 256.  Once the estimate E of the kk-th key is known,
