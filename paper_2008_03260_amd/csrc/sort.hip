@@ -1,6 +1,6 @@
 // Device LSD radix sort (key-value, uint32) and exclusive scan.
 //
-// Each pass: (1) every tile of 4096 keys counts its digits in LDS, counts are
+// Each pass: (1) every tile of 8192 keys counts its digits in LDS, counts are
 // stored digit-major; (2) an exclusive scan of the counts gives every
 // (digit, tile) its output offset; (3) every tile ranks its keys stably (a
 // wave ranks 64 keys at once by matching digits with ballots; waves own
