@@ -48,6 +48,8 @@ WORKLOADS = {
     # one node's 200M-point shard
     "c1": dict(n=200_000_000, dim=1 << 20, K=4, L=32, B=20, R=64, d=4, lw=12, k=10, nq=100_000, master=2021, tk=(4, 4),
                law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=1_000_000,
+               # (L, R, log2 count-min width) of the --recall-sweep indexes
+               recall_points=((32, 128, 12), (32, 256, 14), (64, 128, 14), (64, 256, 14), (128, 128, 14)),
                desc="200M-point shard: N=2e8, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=32 B=20 R=64; CM 4x4096; "
                     "k=10; 100k queries f=0.2"),
     # denser, wider shard under serving
@@ -242,6 +244,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-topkapi", action="store_true", help="skip the Topkapi-bucket index")
+    ap.add_argument("--recall-sweep", action="store_true",
+                    help="also build indexes with more slots or tables and report recall@10 against queries/s")
     ap.add_argument("--serve-seconds", type=float, default=0.5, help="arrival window per serving rate")
     ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
     args = ap.parse_args()
@@ -462,6 +466,42 @@ def main():
         log(f"topkapi buckets ({topkapi['cells_per_bucket']} cells): build {tb[-1]:.1f} ms, insert(4096) "
             f"{ti[-1]:.2f} ms, {topkapi['batched_queries_per_s']:,.0f} q/s, recall@10 {topkapi['recall_at_10']:.4f}")
         del tk_i, tk_s
+    # recall against query cost (optional): the same rows and planted queries
+    # on indexes with more slots per table or more tables; L * R is at most
+    # 16384, the most one query work-group gathers
+    recall_sweep = None
+    if args.recall_sweep:
+        recall_sweep = []
+        for L_, R_, lw_ in w.get("recall_points", ()):
+            p_ = api.Params.of(dim=w["dim"], K=w["K"], L=L_, log2_buckets=w["B"], R=R_, cm_rows=w["d"],
+                               log2_cm_width=lw_, k_max=100, hash_mode=0, seed=seeds["index"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h_ = api.slash_build(p_, ip, ix, stream)
+            torch.cuda.synchronize()
+            tb_ = time.perf_counter() - t0
+            pt = {"L": L_, "R": R_, "cm": f"{w['d']} x {1 << lw_}", "build_wall_ms": tb_ * 1e3}
+            for name, fl in (("count_min", 0), ("exact", api.FLAG_EXACT)):
+                oi_, os_ = api.slash_query_batched(h_, qi, qx, w["k"], flags=api.FLAG_TRUSTED | fl, stream=stream)
+                tq_ = []
+                for _ in range(3):
+                    e0, e1 = ev(), ev()
+                    e0.record(stream)
+                    api.slash_query_batched(h_, qi, qx, w["k"], flags=api.FLAG_TRUSTED | fl, out_ids=oi_,
+                                            out_scores=os_, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    tq_.append(e0.elapsed_time(e1))
+                got_ = api.as_u32(oi_)[:, : w["k"]]
+                pt[name] = {"batched_queries_per_s": w["nq"] / (min(tq_) / 1e3),
+                            "recall_at_10": float(np.mean([s_ in row for s_, row in zip(src.tolist(), got_.tolist())]))}
+                del oi_, os_
+            api.slash_free(h_)
+            log(f"recall point L={L_} R={R_} cm {pt['cm']}: count-min {pt['count_min']['batched_queries_per_s']:,.0f} "
+                f"q/s recall@10 {pt['count_min']['recall_at_10']:.4f}; exact {pt['exact']['batched_queries_per_s']:,.0f} "
+                f"q/s recall@10 {pt['exact']['recall_at_10']:.4f}")
+            recall_sweep.append(pt)
+
     # achievable HBM bandwidth: a plain device copy of 4 GiB (read + write)
     src_t = torch.empty(1 << 30, dtype=torch.int32, device=dev)
     dst_t = torch.empty_like(src_t)
@@ -506,6 +546,8 @@ def main():
         "serve": serve,
         "stream_copy_gbs": copy_gbs,
     }
+    if recall_sweep is not None:
+        res["recall_sweep"] = recall_sweep
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(w, law, seeds)
