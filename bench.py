@@ -49,7 +49,7 @@ WORKLOADS = {
     "c1": dict(n=200_000_000, dim=1 << 20, K=4, L=32, B=20, R=64, d=4, lw=12, k=10, nq=100_000, master=2021, tk=(4, 4),
                law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=1_000_000,
                # (L, R, log2 count-min width) of the --recall-sweep indexes
-               recall_points=((32, 128, 12), (32, 256, 14), (64, 128, 14), (64, 256, 14), (128, 128, 14)),
+               recall_points=((32, 64, 12), (32, 128, 12), (32, 256, 14), (64, 128, 14), (64, 256, 14), (128, 128, 14)),
                desc="200M-point shard: N=2e8, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=32 B=20 R=64; CM 4x4096; "
                     "k=10; 100k queries f=0.2"),
     # denser, wider shard under serving

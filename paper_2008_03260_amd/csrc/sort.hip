@@ -17,9 +17,10 @@ namespace {
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / SL_WAVE;
 constexpr int kItems = 16;                 // per thread
-constexpr int kTile = kThreads * kItems;   // 4096
+constexpr int kTile = kThreads * kItems;   // 8192
 constexpr int kSubTile = kTile / kWaves;   // 1024 per wave
 constexpr int kRounds = kSubTile / SL_WAVE;
+constexpr int kUpRounds = 1;  // digits counted with one atomic per wave before the per-lane atomics
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   const uint32_t lane = lane_id();
@@ -98,20 +99,25 @@ __global__ void __launch_bounds__(kThreads)
       k[j] = i < n ? keys[i] : 0u;
     }
   }
-  // Counts need no ranks: each key adds one with an LDS atomic, except that a
-  // wave whose valid keys all share one digit (runs of one heavy bucket) adds
-  // them with a single atomic.
+  // Counts need no ranks: each key adds one with an LDS atomic.  Skewed
+  // buckets make many lanes of a wave share a digit, and LDS atomics to one
+  // address serialise, so the lanes sharing the digits of the first
+  // kUpRounds remaining lanes add them with one atomic per digit first.
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const bool v = full || base + (uint64_t)j * kThreads + threadIdx.x < n;
     const uint32_t d = (k[j] >> shift) & dmask;
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-    const uint64_t valid = ballot64(v);
-    if (ballot64(v && d == d0) == valid) {
-      if (valid && lane == (uint32_t)__builtin_ctzll(valid)) atomicAdd(&cnt[d0], (uint32_t)__builtin_popcountll(valid));
-    } else if (v) {
-      atomicAdd(&cnt[d], 1u);
+    uint64_t rest = ballot64(v);
+#pragma unroll
+    for (int round = 0; round < kUpRounds; ++round) {
+      if (rest == 0) break;
+      const uint32_t first = (uint32_t)__builtin_ctzll(rest);
+      const uint32_t d0 = __builtin_amdgcn_readlane(d, first);
+      const uint64_t m = ballot64(((rest >> lane) & 1) && d == d0);
+      if (lane == first) atomicAdd(&cnt[d0], (uint32_t)__builtin_popcountll(m));
+      rest &= ~m;
     }
+    if ((rest >> lane) & 1) atomicAdd(&cnt[d], 1u);
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < nd; d += kThreads) hist[(uint64_t)d * n_tiles + blockIdx.x] = cnt[d];
