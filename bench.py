@@ -56,7 +56,7 @@ WORKLOADS = {
     "c4": dict(n=20_000_000, dim=1 << 24, K=8, L=128, B=18, R=128, d=8, lw=14, k=100, nq=10_000, master=2024, tk=(8, 4),
                law=WIDE_LAW, q=dict(nnz_mode="lognormal", median=500, sigma=0.8, lo=50, hi=20000, f=(0.1, 0.4)),
                mix=WIDE_MIX, max_nnz=20000, max_insert_nnz=8_000_000, cpu_rows=100_000, mix_n=100_000,
-               serve_rates=(1e3, 3e3, 1e4, 3e4),
+               serve_rates=(1e3, 3e3, 1e4, 3e4), serve_seconds=1.0,
                desc="wide shard: N=2e7, D=2^24, nnz~lognormal(median 500, sigma 0.8) in [50, 20000], uniform "
                     "indices; K=8 L=128 B=18 R=128; CM 8x16384; k=100; 10k queries f~U[0.1,0.4]"),
 }
@@ -184,8 +184,9 @@ def cpu_parallel(op, cs, ids, seen, ip, ix, qi, qx, k, single_qps, max_procs=16)
 def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4, 1e5, 3e5, 1e6, 2e6)):
     """Open-loop Poisson arrivals against the continuous-batching server on
     the resident index: 90% queries (the batched mix), 10% inserts of 1-4096
-    new rows.  Latency = completion - scheduled arrival.  An untimed 0.2 s
-    window at the lowest rate runs first (its inserts stay in the index)."""
+    new rows.  Latency = completion - scheduled arrival.  Each rate offers
+    `seconds` of arrivals, at most 400k requests.  An untimed 0.2 s window at
+    the lowest rate runs first (its inserts stay in the index)."""
     import synth
     out = []
     next_row = w["n"] + 4096 * 64
@@ -246,7 +247,9 @@ def main():
     ap.add_argument("--no-topkapi", action="store_true", help="skip the Topkapi-bucket index")
     ap.add_argument("--recall-sweep", action="store_true",
                     help="also build indexes with more slots or tables and report recall@10 against queries/s")
-    ap.add_argument("--serve-seconds", type=float, default=0.5, help="arrival window per serving rate")
+    ap.add_argument("--serve-seconds", type=float, default=None,
+                    help="arrival window per serving rate (default: the workload's, 10 s for the 200M shard; "
+                         "a point is capped at 400k requests)")
     ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -403,7 +406,8 @@ def main():
 
     serve = None
     if not args.no_serve:
-        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, args.serve_seconds, seeds,
+        secs = args.serve_seconds if args.serve_seconds is not None else w.get("serve_seconds", 10.0)
+        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, secs, seeds,
                             **({"rates": w["serve_rates"]} if "serve_rates" in w else {}))
 
     # query kernel: algorithmic bytes per query = the query row 4*nnz + 8,
