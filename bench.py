@@ -542,7 +542,11 @@ def main():
         "query_roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": q_gbs / HBM_PEAK_GBS,
                            "kernel": "k_query" if sched and sched.get("queries_per_ticket") == 0 else "k_query_persistent",
-                           "alg_bytes_per_query": alg_q / w["nq"]},
+                           "alg_bytes_per_query": alg_q / w["nq"],
+                           # random gathers: one reservoir row of 4R bytes per table and query
+                           "random_gathers_per_s": w["nq"] * w["L"] / (q_ms.mean() / 1e3),
+                           "gather_bytes": 4 * w["R"],
+                           "gather_peak_per_s": HBM_PEAK_GBS * 1e9 / (4 * w["R"])},
         "build_phases": prof,
         "batched_mix": mix,
         "exact_counting": exact,
