@@ -51,6 +51,40 @@ __device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
   return x;
 }
 
+// Ascending bitonic sort of one 32-bit key per lane across the wave.
+__device__ __forceinline__ uint32_t wave_sort32(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= SL_WAVE; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t y = (uint32_t)__shfl_xor((int)x, j, SL_WAVE);
+      const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+      x = keep_min ? min(x, y) : max(x, y);
+    }
+  }
+  return x;
+}
+
+// Inverse of an odd number modulo 2^32 (Newton's iteration; m * m = 1 mod 8
+// gives 3 correct bits, each step doubles them).
+__device__ __forceinline__ uint32_t inv_odd(uint32_t m) {
+  uint32_t v = m;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v *= 2u - m * v;
+  return v;
+}
+
+// The id whose priority (the bijection `priority`) is p; im1 and im2 are the
+// inverses of m1 and m2.  Each step of the priority undone in reverse order.
+__device__ __forceinline__ uint32_t priority_inverse(uint32_t p, uint32_t key, uint32_t im1, uint32_t im2) {
+  uint32_t x = p ^ (p >> 15) ^ (p >> 30);
+  x *= im2;
+  x ^= x >> 16;
+  x *= im1;
+  return x ^ key;
+}
+
 // Number of entries of sorted arr[0..n) below x.
 __device__ __forceinline__ uint32_t lower_bound64(const uint64_t* arr, uint32_t n, uint64_t x) {
   uint32_t lo = 0, hi = n;
@@ -154,13 +188,14 @@ __host__ __device__ constexpr uint32_t wl_words(uint32_t R) { return 2 * R + SL_
 
 // Bottom-R of a bucket of at most 64·kC ids (R <= 64), all held in registers:
 // an MSD radix select over 8-bit digits of the priority finds the R-th
-// smallest priority (priorities of one table are distinct), the R keys at or
-// below it are compacted into LDS and sorted across the wave once.  Writes R
-// slots of out (EMPTY past the bucket's size).
+// smallest priority (priorities of one table are distinct), the R kept
+// priorities are compacted into LDS and sorted across the wave once, and each
+// id is recovered from its priority by the inverse bijection (im1, im2: the
+// inverses of m1, m2).  Writes R slots of out (EMPTY past the bucket's size).
 template <int kC>
 __device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __restrict__ src, uint64_t off,
                                              uint32_t n, uint32_t R, uint32_t key, uint32_t m1, uint32_t m2,
-                                             uint32_t* __restrict__ out) {
+                                             uint32_t im1, uint32_t im2, uint32_t* __restrict__ out) {
   const uint32_t lane = lane_id();
   uint32_t id[kC];
 #pragma unroll
@@ -221,20 +256,23 @@ __device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __re
       }
     }
   }
-  // compact the kept keys (exactly min(n, R)) and sort them once
+  // compact the kept priorities (exactly min(n, R)) and sort them once; the
+  // filler 0xFFFFFFFF may equal a kept priority, which changes nothing since
+  // the first `base` sorted values are the kept ones either way
+  uint32_t* kept = (uint32_t*)lds;
   uint32_t base = 0;
 #pragma unroll
   for (int c = 0; c < kC; ++c) {
     const bool keep = id[c] != SL_EMPTY && pr[c] <= upper;
     const uint64_t m = ballot64(keep);
     const uint32_t pos = base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
-    if (keep && pos < SL_WAVE) lds[pos] = ((uint64_t)pr[c] << 32) | id[c];
+    if (keep && pos < SL_WAVE) kept[pos] = pr[c];
     base += (uint32_t)__builtin_popcountll(m);
   }
   wave_sync();
-  uint64_t x = lane < min(base, (uint32_t)SL_WAVE) ? lds[lane] : kNoKey;
-  x = wave_sort64(x);
-  if (lane < R) out[lane] = lane < base ? (uint32_t)x : SL_EMPTY;
+  uint32_t x = lane < min(base, (uint32_t)SL_WAVE) ? kept[lane] : 0xFFFFFFFFu;
+  x = wave_sort32(x);
+  if (lane < R) out[lane] = lane < base ? priority_inverse(x, key, im1, im2) : SL_EMPTY;
   wave_sync();
 }
 
@@ -247,6 +285,7 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE, 8)
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
   uint64_t* my = lds64 + wave * wl_words(s.R);
   const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  const uint32_t im1 = inv_odd(m1), im2 = inv_odd(m2);
   const uint32_t nwaves = gridDim.x * kSelWaves;
   // the bounds of the wave's next bucket are loaded while this one is reduced
   uint32_t b = blockIdx.x * kSelWaves + wave;
@@ -265,9 +304,9 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE, 8)
     uint32_t* out = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
     if (n <= 8 * SL_WAVE && s.R <= SL_WAVE) {
       if (n <= 4 * SL_WAVE)
-        select_small<4>(my, svals, s0, n, s.R, key, m1, m2, out);
+        select_small<4>(my, svals, s0, n, s.R, key, m1, m2, im1, im2, out);
       else
-        select_small<8>(my, svals, s0, n, s.R, key, m1, m2, out);
+        select_small<8>(my, svals, s0, n, s.R, key, m1, m2, im1, im2, out);
       if (lane == 0) tab.seen[(uint64_t)t * s.nb + b] = n;
       continue;
     }
