@@ -17,39 +17,18 @@ namespace slash {
 namespace {
 
 constexpr int kSelWaves = 4;
-constexpr uint64_t kNoKey = ~0ull;
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // filler above every priority but the largest, which ties
 
+// A wave's bottom-R list of priorities (distinct within a table; the id of a
+// priority is recovered by the inverse bijection when the list is written).
 struct WaveList {
-  uint64_t* a;    // current list [R]
-  uint64_t* b;    // merge target [R]
-  uint64_t* buf;  // pending entrants [64]
+  uint32_t* a;    // current list [R], ascending
+  uint32_t* b;    // merge target [R]
+  uint32_t* buf;  // pending entrants [64]
   uint32_t cnt;   // live entries of a (uniform)
   uint32_t nbuf;  // live entries of buf (uniform)
   uint32_t R;
 };
-
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
-  uint32_t lo = __shfl_xor((uint32_t)x, m, SL_WAVE);
-  uint32_t hi = __shfl_xor((uint32_t)(x >> 32), m, SL_WAVE);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Ascending bitonic sort of one key per lane across the wave.
-__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= SL_WAVE; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      uint64_t y = shfl_xor64(x, j);
-      bool up = (lane & k) == 0;
-      bool lower = (lane & j) == 0;
-      bool keep_min = lower == up;
-      x = keep_min ? (x < y ? x : y) : (x < y ? y : x);
-    }
-  }
-  return x;
-}
 
 // Ascending bitonic sort of one 32-bit key per lane across the wave.
 __device__ __forceinline__ uint32_t wave_sort32(uint32_t x) {
@@ -86,7 +65,7 @@ __device__ __forceinline__ uint32_t priority_inverse(uint32_t p, uint32_t key, u
 }
 
 // Number of entries of sorted arr[0..n) below x.
-__device__ __forceinline__ uint32_t lower_bound64(const uint64_t* arr, uint32_t n, uint64_t x) {
+__device__ __forceinline__ uint32_t lower_bound32(const uint32_t* arr, uint32_t n, uint32_t x) {
   uint32_t lo = 0, hi = n;
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
@@ -101,24 +80,24 @@ __device__ __forceinline__ uint32_t lower_bound64(const uint64_t* arr, uint32_t 
 __device__ __forceinline__ void wl_flush(WaveList& w) {
   if (w.nbuf == 0) return;
   const uint32_t lane = lane_id();
-  uint64_t x = lane < w.nbuf ? w.buf[lane] : kNoKey;
+  uint32_t x = lane < w.nbuf ? w.buf[lane] : kNoKey;
   wave_sync();
-  x = wave_sort64(x);
+  x = wave_sort32(x);
   w.buf[lane] = x;
   wave_sync();
   // new position of each pending key
   if (lane < w.nbuf) {
-    uint32_t pos = lane + lower_bound64(w.a, w.cnt, x);
+    uint32_t pos = lane + lower_bound32(w.a, w.cnt, x);
     if (pos < w.R) w.b[pos] = x;
   }
   // new position of each listed key
   for (uint32_t i = lane; i < w.cnt; i += SL_WAVE) {
-    uint64_t y = w.a[i];
-    uint32_t pos = i + lower_bound64(w.buf, w.nbuf, y);
+    uint32_t y = w.a[i];
+    uint32_t pos = i + lower_bound32(w.buf, w.nbuf, y);
     if (pos < w.R) w.b[pos] = y;
   }
   wave_sync();
-  uint64_t* t = w.a;
+  uint32_t* t = w.a;
   w.a = w.b;
   w.b = t;
   w.cnt = min(w.R, w.cnt + w.nbuf);
@@ -126,8 +105,8 @@ __device__ __forceinline__ void wl_flush(WaveList& w) {
 }
 
 // Offer one key per lane (valid lanes only).
-__device__ __forceinline__ void wl_offer(WaveList& w, bool valid, uint64_t key) {
-  uint64_t thr = w.cnt < w.R ? kNoKey : w.a[w.R - 1];
+__device__ __forceinline__ void wl_offer(WaveList& w, bool valid, uint32_t key) {
+  uint32_t thr = w.cnt < w.R ? kNoKey : w.a[w.R - 1];
   bool pass = valid && (w.cnt < w.R || key < thr);
   uint64_t m = ballot64(pass);
   uint32_t np = (uint32_t)__builtin_popcountll(m);
@@ -136,10 +115,6 @@ __device__ __forceinline__ void wl_offer(WaveList& w, bool valid, uint64_t key) 
   if (pass) w.buf[w.nbuf + (uint32_t)__builtin_popcountll(m & lanemask_lt())] = key;
   wave_sync();
   w.nbuf += np;
-}
-
-__device__ __forceinline__ uint64_t prio_key(uint32_t id, uint32_t key, uint32_t m1, uint32_t m2) {
-  return ((uint64_t)priority(id, key, m1, m2) << 32) | id;
 }
 
 // Stream ids src[off .. off+len) (EMPTY entries skipped) through the list.
@@ -160,17 +135,20 @@ __device__ __forceinline__ void wl_stream(WaveList& w, const uint32_t* __restric
     for (int c = 0; c < kChunks; ++c) {
       if (i + (uint64_t)c * SL_WAVE >= len) break;  // wave-uniform
       const bool v = id[c] != SL_EMPTY;
-      wl_offer(w, v, v ? prio_key(id[c], key, m1, m2) : kNoKey);
+      wl_offer(w, v, v ? priority(id[c], key, m1, m2) : kNoKey);
     }
   }
   wl_flush(w);
 }
 
-__device__ __forceinline__ void wl_write(const WaveList& w, uint32_t* __restrict__ out, uint32_t R) {
-  for (uint32_t i = lane_id(); i < R; i += SL_WAVE) out[i] = i < w.cnt ? (uint32_t)w.a[i] : SL_EMPTY;
+// Write the list's ids (im1, im2: inverses of the table's m1, m2).
+__device__ __forceinline__ void wl_write(const WaveList& w, uint32_t* __restrict__ out, uint32_t R, uint32_t key,
+                                         uint32_t im1, uint32_t im2) {
+  for (uint32_t i = lane_id(); i < R; i += SL_WAVE)
+    out[i] = i < w.cnt ? priority_inverse(w.a[i], key, im1, im2) : SL_EMPTY;
 }
 
-__device__ __forceinline__ WaveList wl_init(uint64_t* lds, uint32_t R) {
+__device__ __forceinline__ WaveList wl_init(uint32_t* lds, uint32_t R) {
   WaveList w;
   w.a = lds;
   w.b = lds + R;
@@ -181,10 +159,13 @@ __device__ __forceinline__ WaveList wl_init(uint64_t* lds, uint32_t R) {
   return w;
 }
 
-// Per-wave LDS (u64 words): the list, its merge target and the entrant
-// buffer; at least 128 words, which the small-bucket select uses as a
-// 256-bin histogram.
-__host__ __device__ constexpr uint32_t wl_words(uint32_t R) { return 2 * R + SL_WAVE > 128 ? 2 * R + SL_WAVE : 128; }
+// Per-wave LDS (u32 words): the list, its merge target and the entrant
+// buffer; at least 256 words, which the small-bucket select uses as a
+// 256-bin histogram; a multiple of 4 so that every wave's region is 16-byte
+// aligned.
+__host__ __device__ constexpr uint32_t wl_words(uint32_t R) {
+  return ((2 * R + SL_WAVE > 256 ? 2 * R + SL_WAVE : 256) + 3) & ~3u;
+}
 
 // Bottom-R of a bucket of at most 64·kC ids (R <= 64), all held in registers:
 // an MSD radix select over 8-bit digits of the priority finds the R-th
@@ -193,7 +174,7 @@ __host__ __device__ constexpr uint32_t wl_words(uint32_t R) { return 2 * R + SL_
 // id is recovered from its priority by the inverse bijection (im1, im2: the
 // inverses of m1, m2).  Writes R slots of out (EMPTY past the bucket's size).
 template <int kC>
-__device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __restrict__ src, uint64_t off,
+__device__ __forceinline__ void select_small(uint32_t* lds, const uint32_t* __restrict__ src, uint64_t off,
                                              uint32_t n, uint32_t R, uint32_t key, uint32_t m1, uint32_t m2,
                                              uint32_t im1, uint32_t im2, uint32_t* __restrict__ out) {
   const uint32_t lane = lane_id();
@@ -209,7 +190,7 @@ __device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __re
   // upper bound (inclusive) of the kept priorities
   uint32_t upper = 0xFFFFFFFFu;
   if (n > R) {
-    uint32_t* hist = (uint32_t*)lds;
+    uint32_t* hist = lds;
     uint32_t need = R, prefix = 0;
     for (int shift = 24; shift >= 0; shift -= 8) {
       const uint32_t hi_mask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
@@ -259,7 +240,7 @@ __device__ __forceinline__ void select_small(uint64_t* lds, const uint32_t* __re
   // compact the kept priorities (exactly min(n, R)) and sort them once; the
   // filler 0xFFFFFFFF may equal a kept priority, which changes nothing since
   // the first `base` sorted values are the kept ones either way
-  uint32_t* kept = (uint32_t*)lds;
+  uint32_t* kept = lds;
   uint32_t base = 0;
 #pragma unroll
   for (int c = 0; c < kC; ++c) {
@@ -281,9 +262,9 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE, 8)
     k_select_light(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ svals,
                    const uint32_t* __restrict__ start, const uint32_t* __restrict__ end, TablesView tab,
                    uint32_t heavy_t, uint32_t* heavy_list, uint32_t* heavy_n) {
-  extern __shared__ uint64_t lds64[];
+  extern __shared__ uint32_t lds32[];
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
-  uint64_t* my = lds64 + wave * wl_words(s.R);
+  uint32_t* my = lds32 + wave * wl_words(s.R);
   const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
   const uint32_t im1 = inv_odd(m1), im2 = inv_odd(m2);
   const uint32_t nwaves = gridDim.x * kSelWaves;
@@ -321,7 +302,7 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE, 8)
     }
     WaveList w = wl_init(my, s.R);
     wl_stream(w, svals, s0, n, key, m1, m2);
-    wl_write(w, out, s.R);
+    wl_write(w, out, s.R, key, im1, im2);
     if (lane == 0) tab.seen[(uint64_t)t * s.nb + b] = n;
     wave_sync();
   }
@@ -378,16 +359,17 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     k_select_chunks(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ src,
                         const ChunkWork* __restrict__ work, const uint32_t* __restrict__ n_work,
                         uint32_t* __restrict__ dst) {
-  extern __shared__ uint64_t lds64[];
+  extern __shared__ uint32_t lds32[];
   const uint32_t wave = threadIdx.x / SL_WAVE;
-  uint64_t* my = lds64 + wave * wl_words(s.R);
+  uint32_t* my = lds32 + wave * wl_words(s.R);
   const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  const uint32_t im1 = inv_odd(m1), im2 = inv_odd(m2);
   const uint32_t nw = *n_work;
   for (uint32_t wi = blockIdx.x * kSelWaves + wave; wi < nw; wi += gridDim.x * kSelWaves) {
     ChunkWork cw = work[wi];
     WaveList w = wl_init(my, s.R);
     wl_stream(w, src, cw.off, cw.len, key, m1, m2);
-    wl_write(w, dst + (uint64_t)cw.dst * s.R, s.R);
+    wl_write(w, dst + (uint64_t)cw.dst * s.R, s.R, key, im1, im2);
     wave_sync();
   }
 }
@@ -398,12 +380,13 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
 __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     k_select_final(Shape s, ConstView c, uint32_t t, const uint32_t* __restrict__ src,
                    const FinalWork* __restrict__ work, const uint32_t* __restrict__ n_work, TablesView tab) {
-  extern __shared__ uint64_t lds64[];
+  extern __shared__ uint32_t lds32[];
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
-  uint64_t* my = lds64 + wave * wl_words(s.R);
-  uint64_t* lists = lds64 + kSelWaves * wl_words(s.R);       // [kSelWaves][R]
-  uint32_t* counts = (uint32_t*)(lists + kSelWaves * s.R);  // [kSelWaves]
+  uint32_t* my = lds32 + wave * wl_words(s.R);
+  uint32_t* lists = lds32 + kSelWaves * wl_words(s.R);  // [kSelWaves][R] priorities
+  uint32_t* counts = lists + kSelWaves * s.R;           // [kSelWaves]
   const uint32_t key = c.key_t[t], m1 = c.m1_t[t], m2 = c.m2_t[t];
+  const uint32_t im1 = inv_odd(m1), im2 = inv_odd(m2);
   const uint32_t nw = *n_work;
   for (uint32_t wi = blockIdx.x; wi < nw; wi += gridDim.x) {
     const FinalWork fw = work[wi];
@@ -423,7 +406,7 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
         }
       }
       wl_flush(w);
-      wl_write(w, tab.ids + ((uint64_t)t * s.nb + fw.bucket) * s.R, s.R);
+      wl_write(w, tab.ids + ((uint64_t)t * s.nb + fw.bucket) * s.R, s.R, key, im1, im2);
       if (lane == 0) tab.seen[(uint64_t)t * s.nb + fw.bucket] = fw.seen;
     }
     __syncthreads();
@@ -453,9 +436,9 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     k_insert_merge(Shape s, ConstView c, const uint32_t* __restrict__ sk, const uint32_t* __restrict__ sv,
                    uint64_t n, const uint32_t* __restrict__ seg_start, const uint32_t* __restrict__ nseg,
                    TablesView tab) {
-  extern __shared__ uint64_t lds64[];
+  extern __shared__ uint32_t lds32[];
   const uint32_t wave = threadIdx.x / SL_WAVE, lane = lane_id();
-  uint64_t* my = lds64 + wave * wl_words(s.R);
+  uint32_t* my = lds32 + wave * wl_words(s.R);
   const uint32_t ns = *nseg;
   for (uint32_t g = blockIdx.x * kSelWaves + wave; g < ns; g += gridDim.x * kSelWaves) {
     const uint32_t s0 = seg_start[g];
@@ -468,11 +451,11 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE)
     WaveList w = wl_init(my, s.R);
     const uint32_t old = *seen;
     const uint32_t fill = min(old, s.R);
-    for (uint32_t i = lane; i < fill; i += SL_WAVE) w.a[i] = prio_key(res[i], key, m1, m2);
+    for (uint32_t i = lane; i < fill; i += SL_WAVE) w.a[i] = priority(res[i], key, m1, m2);
     w.cnt = fill;
     wave_sync();
     wl_stream(w, sv, s0, e0 - s0, key, m1, m2);
-    wl_write(w, res, s.R);
+    wl_write(w, res, s.R, key, inv_odd(m1), inv_odd(m2));
     if (lane == 0) *seen = old + (e0 - s0);
     wave_sync();
   }
@@ -729,7 +712,7 @@ uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap) {
 hipError_t launch_select_light(const Shape& s, const ConstView& c, uint32_t t, const uint32_t* svals,
                                const uint32_t* start, const uint32_t* end, TablesView tab, uint32_t heavy_t,
                                uint32_t* heavy_list, uint32_t* heavy_n, hipStream_t st) {
-  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 4;
   hipLaunchKernelGGL(k_select_light, dim3(grid_for(s.nb, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st,
                      s, c, t, svals, start, end, tab, heavy_t, heavy_list, heavy_n);
   return hipGetLastError();
@@ -742,12 +725,12 @@ hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const ui
                         FinalWork* finals, uint32_t* n_chunks, uint32_t* cand, TablesView tab, hipStream_t st) {
   hipLaunchKernelGGL(k_heavy_plan, dim3(1), dim3(256), 0, st, heavy_list, heavy_n, s.R, chunk_len, chunks, finals,
                      n_chunks);
-  const size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  const size_t lds = (size_t)kSelWaves * wl_words(s.R) * 4;
   const uint32_t max_chunks = (uint32_t)heavy_chunk_capacity(n, chunk_len);
   hipLaunchKernelGGL(k_select_chunks, dim3(grid_for(max_chunks, kSelWaves, 4096)), dim3(kSelWaves * SL_WAVE), lds,
                      st, s, c, t, svals, chunks, n_chunks, cand);
   const uint32_t max_heavy = (uint32_t)(n / chunk_len + 1);
-  const size_t lds_f = lds + (size_t)kSelWaves * s.R * 8 + kSelWaves * 4;
+  const size_t lds_f = lds + (size_t)kSelWaves * s.R * 4 + kSelWaves * 4;
   hipLaunchKernelGGL(k_select_final, dim3(max_heavy < 1024 ? max_heavy : 1024), dim3(kSelWaves * SL_WAVE), lds_f, st,
                      s, c, t, cand, finals, heavy_n, tab);
   return hipGetLastError();
@@ -803,7 +786,7 @@ hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_
                      nseg);
   if ((e = gate(st)) != hipSuccess) return e;
   if (s.bucket) return launch_tk_segments(s, c, skeys, svals, n, seg_start, nseg, tab, st);
-  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 8;
+  size_t lds = (size_t)kSelWaves * wl_words(s.R) * 4;
   hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st, s, c,
                      skeys, svals, n, seg_start, nseg, tab);
   return hipGetLastError();
