@@ -402,7 +402,7 @@ void* fill_kernel_ptr() { return (void*)k_fill; }
 
 hipError_t launch_segment_bounds(const uint32_t* skeys, uint64_t n, uint32_t* start, uint32_t* end, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segment_bounds, dim3(grid_for((n + 7) / 8, 256, 16384)), dim3(256), 0, st, skeys, n, start,
+  hipLaunchKernelGGL(k_segment_bounds, dim3(grid_for((n + 7) / 8, 256, 65536)), dim3(256), 0, st, skeys, n, start,
                      end);
   return hipGetLastError();
 }
