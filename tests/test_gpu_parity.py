@@ -115,6 +115,25 @@ def test_build_heavy_buckets(api):
     check_tables(api, idx, op, oracle.constants(op), ip, ix)
 
 
+@pytest.mark.parametrize("R", [37, 64, 100])
+def test_build_bucket_sizes_at_select_boundaries(api, R):
+    # groups of identical rows fill one bucket per table with exactly n ids:
+    # sizes on either side of every select path's limit (the register path
+    # for 256 and 512 ids, the streaming list, the chunked heavy path above
+    # 16384 ids), with random rows around them
+    sizes = [1, 37, 63, 64, 65, 100, 255, 256, 257, 511, 512, 513, 16384, 16385]
+    gp, op = params_pair(api, L=4, log2_buckets=14, R=R)
+    _, (ip0, ix0) = rows_of(2000, seed=12)
+    groups = []
+    for g, n in enumerate(sizes):
+        groups += [[5000 + 16 * g + j for j in range(5)]] * n
+    gip, gix = csr_from_lists(groups)
+    ip = np.concatenate([ip0, ip0[-1] + gip[1:]])
+    ix = np.concatenate([ix0, gix])
+    idx = api.Index(gp, dev(ip), dev(ix))
+    check_tables(api, idx, op, oracle.constants(op), ip, ix)
+
+
 def test_build_ragged_and_tiny(api):
     for n in (1, 2, 63, 64, 65, 4097):
         gp, op = params_pair(api, L=3, log2_buckets=4, R=5)
