@@ -289,22 +289,18 @@ hipError_t launch_insert(slash_server* srv, Slot& s) {
   return hipSuccess;
 }
 
-// Queries at the head of the FIFO that one batch slot could take, and
-// whether an insert ends that run (then waiting cannot make the batch larger).
-void head_run(const slash_server* srv, const Slot& s, uint32_t max_batch, uint32_t* n, bool* full) {
+// Whether the queries at the head of the FIFO fill one batch of slot s, or
+// an insert ends their run (then waiting cannot make the batch larger).
+bool head_run_full(const slash_server* srv, const Slot& s, uint32_t max_batch) {
+  const uint32_t cap = std::min(max_batch, s.cap_q);
   uint64_t nnz = 0;
   uint32_t c = 0;
-  *full = false;
   for (const Request& r : srv->pending) {
-    if (r.kind != 0 || c >= std::min(max_batch, s.cap_q) || nnz + r.idx.size() > s.cap_nnz) {
-      *full = true;
-      break;
-    }
+    if (r.kind != 0 || c >= cap || nnz + r.idx.size() > s.cap_nnz) return true;
     nnz += r.idx.size();
     ++c;
   }
-  *n = c;
-  *full = *full || c >= std::min(max_batch, s.cap_q);
+  return c >= cap;
 }
 
 void scheduler(slash_server* srv) {
@@ -367,11 +363,8 @@ void scheduler(slash_server* srv) {
       if (!free_s) break;
       Slot& s = *free_s;
       if (max_wait > 0 && !srv->stopping) {
-        uint32_t run = 0;
-        bool full = false;
-        head_run(srv, s, max_batch, &run, &full);
         const double due = head.t_submit + max_wait;
-        if (!full && now_s() < due) {
+        if (!head_run_full(srv, s, max_batch) && now_s() < due) {
           wake_at = due;  // hold the partial batch back
           break;
         }
