@@ -68,8 +68,15 @@ typedef enum {
  * L").  Constraints checked by every call:
  *   dim >= 1; 1 <= K; 1 <= L; K * L <= 4096; 1 <= log2_buckets <= 30;
  *   1 <= R <= 256; 1 <= cm_rows <= 16; log2_cm_width <= 16 (0 means one
- *   counter); 1 <= k_max <= 1024; hash_mode 0 (one DOPH pass over K*L bins)
- *   or 1 (a DOPH pass of K bins per table); bucket 0 or 1.
+ *   counter); 1 <= k_max <= 1024; bucket 0 or 1; hash_mode:
+ *   0 - one densified one-permutation pass (Section 2.2) over K*L equal range
+ *       bins of one nonzero hash; table t takes bins [tK, tK + K);
+ *   1 - a DOPH pass of K bins per table, each table with its own nonzero
+ *       hash;
+ *   2 - classic MinHash with K*L independent hash functions (Section 2.2;
+ *       the L x K seeds of Section 4 "Initialization"): value j is the
+ *       minimum over the row of its own nonzero hash, no densification;
+ *       K*L times the hashing work of mode 0.
  *
  * bucket selects what a bucket holds:
  *   0 - the R ids of smallest priority (bottom-R reservoir, Section 3 "Avoid
@@ -95,7 +102,7 @@ typedef struct {
   uint32_t cm_rows;       /* d: count-min rows */
   uint32_t log2_cm_width; /* log2 w: counters per count-min row */
   uint32_t k_max;         /* output row stride of queries */
-  uint32_t hash_mode;     /* 0 or 1, see above */
+  uint32_t hash_mode;     /* 0, 1 or 2, see above */
   uint32_t bucket;        /* 0: bottom-R reservoir, 1: Topkapi sketch (see above) */
   uint64_t seed;          /* every hash constant derives from this (Section 3 "Design") */
 } slash_params;
@@ -182,7 +189,9 @@ SLASH_API slash_status slash_query(const slash_index* index, slash_csr queries, 
  * persistent one whose resident work-groups take queries from a device work
  * counter, or (queries_per_ticket = 0) one work-group per query, with the
  * schedule `sched` (NULL = the tuned schedule for this index, see
- * slash_autotune).  Both launches are recorded once into a HIP graph and
+ * slash_autotune; when schedules of several query-size classes are tuned,
+ * the batch's mean row size picks the nearest class, which reads its first
+ * and last row offsets with a copy that synchronises `stream`).  Both launches are recorded once into a HIP graph and
  * replayed.  Batched calls on one index share that buffer: issue them on one
  * stream (or otherwise order them). */
 SLASH_API slash_status slash_query_batched(const slash_index* index, slash_csr queries, const uint32_t* k_per_query_dev,
@@ -211,9 +220,12 @@ SLASH_API slash_status slash_export_tables(const slash_index* index, uint32_t* i
  * ids [L][2^B][R] and seen [L][2^B] device buffers are copied in; n_items is
  * the number of ids assigned so far (the next insert continues from it).
  * Together with slash_export_tables this saves and restores an index (the
- * caller moves the buffers to storage).  The tables are taken as they are
- * (not checked).  Errors: E_INVAL (params, NULL buffers), E_CAPACITY
- * (n_items > 0xFFFFFFFE), E_NOMEM, E_DEVICE.  Synchronises `stream`. */
+ * caller moves the buffers to storage).  Reservoir tables are checked: the
+ * first min(R, seen) slots of every bucket must hold ids below n_items and
+ * the slots past them EMPTY, as a build or insert leaves them (Topkapi cells
+ * are taken as they are).  Errors: E_INVAL (params, NULL buffers, tables
+ * failing the check), E_CAPACITY (n_items > 0xFFFFFFFE), E_NOMEM, E_DEVICE.
+ * Synchronises `stream`. */
 SLASH_API slash_status slash_import_tables(const slash_params* params, const uint32_t* ids_dev, const uint32_t* seen_dev,
                                  uint64_t n_items, void* stream, slash_index** out);
 
@@ -242,11 +254,20 @@ SLASH_API const char* slash_last_error(void);
 
 /* Route the library's device allocations through caller functions (e.g. a
  * framework's caching allocator).  alloc_fn returns NULL on failure.  Pass
- * NULLs to restore hipMalloc/hipFree.  Not thread-safe against concurrent
- * allocation. */
+ * NULLs to restore hipMalloc/hipFree.  Set it before any index exists (a
+ * block is always freed through the allocator that made it only while the
+ * setting is unchanged).  Not thread-safe against concurrent allocation.
+ *
+ * With the default allocator the library keeps the device blocks it frees
+ * (build scratch, the tables of freed indexes) and reuses them for later
+ * allocations of up to their size, since allocating and freeing tens of GB
+ * costs more than a build's kernels.  An allocation that fails releases the
+ * cache of its device and is retried; slash_release_cache() returns every
+ * cached block to the device now (also done by slash_set_allocator). */
 typedef void* (*slash_alloc_fn)(size_t bytes, void* ctx);
 typedef void (*slash_free_fn)(void* ptr, void* ctx);
 SLASH_API slash_status slash_set_allocator(slash_alloc_fn alloc_fn, slash_free_fn free_fn, void* ctx);
+SLASH_API void slash_release_cache(void);
 
 /* -------------------------------------------------------------- serving */
 

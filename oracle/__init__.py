@@ -24,7 +24,7 @@ def build_lib() -> str:
     """Compile the oracle (plain C, -O2) in-tree; always recompiles."""
     src = os.path.join(_HERE, "slash_oracle.c")
     tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src])
+    subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
     os.replace(tmp, _SO)
     return _SO
 
@@ -71,8 +71,6 @@ def lib():
         L.oracle_priority.restype = C.c_uint32
         L.oracle_priority.argtypes = [P, vp, C.c_uint32, C.c_uint32]
         L.oracle_priorities.argtypes = [P, vp, C.c_uint32, vp, C.c_uint64, vp]
-        L.oracle_bottom_r.restype = C.c_uint32
-        L.oracle_bottom_r.argtypes = [P, vp, C.c_uint32, vp, C.c_uint64, vp]
         L.oracle_build.argtypes = [P, vp, vp, vp, C.c_uint64, vp, vp]
         L.oracle_insert.argtypes = [P, vp, vp, vp, C.c_uint32, vp, vp, C.c_uint64]
         L.oracle_query.argtypes = [P, vp, vp, vp, vp, vp, C.c_uint64, vp, C.c_uint32, C.c_uint32,
@@ -83,6 +81,8 @@ def lib():
         L.oracle_tk_build.argtypes = [P, vp, vp, vp, C.c_uint64, vp, vp]
         L.oracle_tk_insert.argtypes = [P, vp, vp, vp, C.c_uint32, vp, vp, C.c_uint64]
         L.oracle_tk_report.argtypes = [P, vp, C.c_uint32, C.c_uint32, vp, vp]
+        L.oracle_jaccard_knn.argtypes = [vp, vp, C.c_uint64, vp, vp, C.c_uint64, C.c_uint32, vp, vp, vp]
+        L.oracle_mean_cosine.argtypes = [vp, vp, C.c_uint64, vp, vp, C.c_uint64, vp, C.c_uint32, C.c_uint32, vp, vp]
         L.oracle_tk_query.argtypes = [P, vp, vp, vp, vp, C.c_uint64, vp, C.c_uint32, C.c_uint32, vp, vp]
         _lib = L
     return _lib
@@ -110,7 +110,7 @@ def _check(rc: int, what: str):
 
 def layout(p: Params) -> dict:
     """Offsets of each constant group in the flat table (same order as the C code)."""
-    n_h = p.L if p.hash_mode else 1
+    n_h = p.M if p.hash_mode == 2 else (p.L if p.hash_mode else 1)
     o = {"a_h": 0}
     o["b_h"] = n_h
     o["dir"] = 2 * n_h
@@ -155,13 +155,6 @@ def priorities(p: Params, cs, t: int, ids) -> np.ndarray:
     out = np.zeros(len(ids), dtype=np.uint32)
     lib().oracle_priorities(C.byref(p.c()), _p(cs), t, _p(ids), len(ids), _p(out))
     return out
-
-
-def bottom_r(p: Params, cs, t: int, ids) -> np.ndarray:
-    ids = np.ascontiguousarray(ids, dtype=np.uint32)
-    out = np.zeros(max(1, p.R), dtype=np.uint32)
-    f = lib().oracle_bottom_r(C.byref(p.c()), _p(cs), t, _p(ids), len(ids), _p(out))
-    return out[:f]
 
 
 def build(p: Params, cs, indptr, indices):
@@ -277,3 +270,38 @@ def tk_query(p: Params, cs, cells, qindptr, qindices, k: int, k_max: int | None 
                                  _p(kqa) if kqa is not None else None, k, k_max, _p(oi), _p(osc)),
            "oracle_tk_query")
     return oi, osc
+
+
+# ------------------------------------------------------- quality references
+
+
+def jaccard_knn(indptr, indices, qindptr, qindices, k: int):
+    """Brute-force Jaccard k nearest rows per query, ties by ascending id:
+    (ids [nq, k], intersection sizes [nq, k], union sizes [nq, k]); slots past
+    the data size hold (EMPTY, 0, 0)."""
+    indptr, indices = _csr(indptr, indices)
+    qindptr, qindices = _csr(qindptr, qindices)
+    n, nq = len(indptr) - 1, len(qindptr) - 1
+    oi = np.zeros((nq, k), dtype=np.uint32)
+    on = np.zeros((nq, k), dtype=np.uint32)
+    ou = np.zeros((nq, k), dtype=np.uint32)
+    _check(lib().oracle_jaccard_knn(_p(indptr), _p(indices) if len(indices) else None, n, _p(qindptr),
+                                    _p(qindices) if len(qindices) else None, nq, k, _p(oi), _p(on), _p(ou)),
+           "oracle_jaccard_knn")
+    return oi, on, ou
+
+
+def mean_cosine(indptr, indices, qindptr, qindices, ids, k: int):
+    """Per query: mean cosine similarity of the first k non-EMPTY ids of its
+    row of `ids` (0 when there are none), and how many there were."""
+    indptr, indices = _csr(indptr, indices)
+    qindptr, qindices = _csr(qindptr, qindices)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    nq = len(qindptr) - 1
+    assert ids.shape[0] == nq and ids.ndim == 2
+    mean = np.zeros(nq, dtype=np.float64)
+    cnt = np.zeros(nq, dtype=np.uint32)
+    _check(lib().oracle_mean_cosine(_p(indptr), _p(indices) if len(indices) else None, len(indptr) - 1,
+                                    _p(qindptr), _p(qindices) if len(qindices) else None, nq, _p(ids),
+                                    ids.shape[1], k, _p(mean), _p(cnt)), "oracle_mean_cosine")
+    return mean, cnt

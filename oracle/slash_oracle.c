@@ -25,7 +25,9 @@
  *     seed, drawn in a fixed order (oracle_constants);
  *   - nonzero hash u(i) = hi32(a_h * i + b_h), bin = hi32(u * M) over
  *     M = K * L contiguous range bins (hash_mode 0), or per table K bins with
- *     a per-table (a_h, b_h) (hash_mode 1);
+ *     a per-table (a_h, b_h) (hash_mode 1), or classic MinHash with M
+ *     independent hash functions, one (a_h, b_h) each and no bins
+ *     (hash_mode 2);
  *   - densification direction is a fixed bit per bin, the walk is circular
  *     over the pre-densification minima;
  *   - bucket id = (sum_j a_tj * h[tK + j] + b_t) >> (64 - B), mod 2^64;
@@ -34,6 +36,7 @@
  *   - count-min row hash g_r(c) = (a_r * c + b_r) >> (64 - log2 w);
  *   - top-k by (estimate desc, id asc), padded with (0xFFFFFFFF, 0).
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -58,7 +61,7 @@ typedef struct {
 static layout_t layout(const oracle_params* p) {
   layout_t o;
   uint64_t M = (uint64_t)p->K * p->L;
-  o.n_h = p->hash_mode ? p->L : 1;
+  o.n_h = p->hash_mode == 2 ? (uint64_t)p->K * p->L : (p->hash_mode ? p->L : 1);
   o.a_h = 0;
   o.b_h = o.a_h + o.n_h;
   o.dir = o.b_h + o.n_h;
@@ -90,17 +93,17 @@ static int params_ok(const oracle_params* p) {
   if (p->dim == 0 || p->K == 0 || p->L == 0 || p->R == 0 || p->cm_rows == 0) return 0;
   if (p->log2_buckets == 0 || p->log2_buckets > 32) return 0;
   if (p->log2_cm_width > 32) return 0;
-  if (p->hash_mode > 1) return 0;
+  if (p->hash_mode > 2) return 0;
   return 1;
 }
 
 /* The paper shares one random seed among all workers so every node derives
  * the same L x K hash functions (Section 3, "Design"; Section 4
- * "Initialization").  Draw order: (1) a_h|1, b_h (once, or per table in
- * hash_mode 1, interleaved); (2) one direction bit (top bit) per bin; (3) per
- * table K odd multipliers then one offset; (4) per table the priority key and
- * two odd 32-bit multipliers; (5) per count-min row an odd multiplier and an
- * offset. */
+ * "Initialization").  Draw order: (1) a_h|1, b_h (once; per table in
+ * hash_mode 1; per hash function in hash_mode 2; interleaved); (2) one
+ * direction bit (top bit) per bin; (3) per table K odd multipliers then one
+ * offset; (4) per table the priority key and two odd 32-bit multipliers;
+ * (5) per count-min row an odd multiplier and an offset. */
 EXPORT int oracle_constants(const oracle_params* p, uint64_t* out) {
   if (!params_ok(p) || !out) return O_EINVAL;
   layout_t o = layout(p);
@@ -156,7 +159,11 @@ static void densify(const uint32_t* m, uint32_t* h, uint32_t n, const uint64_t* 
 /* DOPH values h[0..M) of one row (Section 2.2): every nonzero index i is
  * hashed once, u(i) = hi32(a_h * i + b_h); the hash range is split into M
  * equal bins; each bin keeps the smallest value that falls in it; empty bins
- * are densified.  hash_mode 1 runs this per table with K bins. */
+ * are densified.  hash_mode 1 runs this per table with K bins.  hash_mode 2
+ * is the classic MinHash of Section 2.2 with the L x K seeds of Section 4
+ * "Initialization": value j is min over the row of u_j(i) =
+ * hi32(a_h[j] * i + b_h[j]), a 2-universal stand-in for the j-th random
+ * permutation; nothing is binned, so nothing is densified. */
 static void doph(const oracle_params* p, const uint64_t* cs, const int32_t* idx, uint64_t nnz,
                  uint32_t* m, uint32_t* h) {
   layout_t o = layout(p);
@@ -170,6 +177,14 @@ static void doph(const oracle_params* p, const uint64_t* cs, const int32_t* idx,
       if (u < m[bin]) m[bin] = u;
     }
     densify(m, h, M, cs + o.dir);
+  } else if (p->hash_mode == 2) {
+    for (uint32_t j = 0; j < M; ++j) {
+      for (uint64_t e = 0; e < nnz; ++e) {
+        uint32_t u = hi32(cs[o.a_h + j] * (uint64_t)(uint32_t)idx[e] + cs[o.b_h + j]);
+        if (u < m[j]) m[j] = u;
+      }
+      h[j] = m[j];
+    }
   } else {
     for (uint32_t t = 0; t < p->L; ++t) {
       uint32_t* mt = m + (uint64_t)t * p->K;
@@ -254,23 +269,6 @@ static int cmp_item(const void* a, const void* b) {
   if (x->bucket != y->bucket) return x->bucket < y->bucket ? -1 : 1;
   if (x->pri != y->pri) return x->pri < y->pri ? -1 : 1;
   return 0;
-}
-
-/* The min(R, n) ids of smallest priority among ids[0..n) (table t), written in
- * ascending priority order; returns how many were written. */
-EXPORT uint32_t oracle_bottom_r(const oracle_params* p, const uint64_t* cs, uint32_t t,
-                                const uint32_t* ids, uint64_t n, uint32_t* out) {
-  item_t* it = (item_t*)malloc(sizeof(item_t) * (n ? n : 1));
-  for (uint64_t i = 0; i < n; ++i) {
-    it[i].bucket = 0;
-    it[i].pri = prio(p, cs, t, ids[i]);
-    it[i].id = ids[i];
-  }
-  qsort(it, n, sizeof(item_t), cmp_item);
-  uint32_t f = (uint32_t)(n < p->R ? n : p->R);
-  for (uint32_t i = 0; i < f; ++i) out[i] = it[i].id;
-  free(it);
-  return f;
 }
 
 /* Pre-processing (Algorithm 1): every vector x, with id = its row number, is
@@ -667,5 +665,165 @@ EXPORT int oracle_tk_query(const oracle_params* p, const uint64_t* cs, const uin
   }
   free(bk);
   free(sk);
+  return rc;
+}
+
+/* ------------------------------------------------- quality references */
+
+/* Not part of what the GPU computes: the exact neighbours the method
+ * approximates, and the quality measure the paper reports.
+ *   - Similarity is Jaccard, |x ∩ y| / |x ∪ y| (Section 2.2; the printed
+ *     formula's denominator is read as |x| + |y| - x.y).  A row is a set:
+ *     order and repeats inside a row do not count.
+ *   - S@k (Section 6, evaluation metrics) is the mean cosine similarity,
+ *     |x ∩ y| / sqrt(|x| |y|) for binary vectors, of the returned neighbours
+ *     to the query. */
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Sorted copy of a row with repeats dropped; returns its size. */
+static uint64_t row_set(const int32_t* idx, uint64_t nnz, int32_t* out) {
+  memcpy(out, idx, sizeof(int32_t) * nnz);
+  qsort(out, nnz, sizeof(int32_t), cmp_i32);
+  uint64_t m = 0;
+  for (uint64_t e = 0; e < nnz; ++e)
+    if (m == 0 || out[m - 1] != out[e]) out[m++] = out[e];
+  return m;
+}
+
+/* |a ∩ b| of two sorted sets. */
+static uint64_t inter_size(const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb) {
+  uint64_t i = 0, j = 0, c = 0;
+  while (i < na && j < nb) {
+    if (a[i] < b[j]) {
+      ++i;
+    } else if (b[j] < a[i]) {
+      ++j;
+    } else {
+      ++c;
+      ++i;
+      ++j;
+    }
+  }
+  return c;
+}
+
+typedef struct {
+  uint64_t inter, uni;
+  uint32_t id;
+} jac_t;
+
+/* Jaccard descending (i1/u1 > i2/u2 compared as i1*u2 > i2*u1, exact), then
+ * id ascending. */
+static int cmp_jac(const void* a, const void* b) {
+  const jac_t* x = (const jac_t*)a;
+  const jac_t* y = (const jac_t*)b;
+  uint64_t l = x->inter * y->uni, r = y->inter * x->uni;
+  if (l != r) return l > r ? -1 : 1;
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+/* Sets of all rows of a CSR matrix, stored back to back; offs[n + 1]. */
+static int32_t* csr_sets(const int64_t* indptr, const int32_t* indices, uint64_t n, uint64_t* offs) {
+  uint64_t total = (uint64_t)(indptr[n] - indptr[0]);
+  int32_t* sets = (int32_t*)malloc(sizeof(int32_t) * (total ? total : 1));
+  if (!sets) return NULL;
+  offs[0] = 0;
+  for (uint64_t r = 0; r < n; ++r) {
+    uint64_t nnz = (uint64_t)(indptr[r + 1] - indptr[r]);
+    offs[r + 1] = offs[r] + row_set(indices + indptr[r], nnz, sets + offs[r]);
+  }
+  return sets;
+}
+
+/* Brute-force k nearest rows of each query by Jaccard similarity, ties by
+ * ascending id (row number).  Output rows of stride k: ids, and the exact
+ * similarity as the pair (|x ∩ y|, |x ∪ y|); slots past the data size hold
+ * (EMPTY, 0, 0). */
+EXPORT int oracle_jaccard_knn(const int64_t* indptr, const int32_t* indices, uint64_t n, const int64_t* qindptr,
+                              const int32_t* qindices, uint64_t nq, uint32_t k, uint32_t* out_ids,
+                              uint32_t* out_inter, uint32_t* out_union) {
+  if (!indptr || !qindptr || !out_ids || !out_inter || !out_union || n > 0xFFFFFFFEull) return O_EINVAL;
+  uint64_t* offs = (uint64_t*)malloc(sizeof(uint64_t) * (n + 1));
+  jac_t* sc = (jac_t*)malloc(sizeof(jac_t) * (n ? n : 1));
+  int32_t* sets = offs ? csr_sets(indptr, indices, n, offs) : NULL;
+  int rc = (offs && sc && sets) ? O_OK : O_ENOMEM;
+  int32_t* qs = NULL;
+  for (uint64_t q = 0; q < nq && rc == O_OK; ++q) {
+    uint64_t qn = (uint64_t)(qindptr[q + 1] - qindptr[q]);
+    free(qs);
+    qs = (int32_t*)malloc(sizeof(int32_t) * (qn ? qn : 1));
+    if (!qs) {
+      rc = O_ENOMEM;
+      break;
+    }
+    uint64_t qm = row_set(qindices + qindptr[q], qn, qs);
+    for (uint64_t r = 0; r < n; ++r) {
+      uint64_t xm = offs[r + 1] - offs[r];
+      uint64_t in = inter_size(qs, qm, sets + offs[r], xm);
+      sc[r].inter = in;
+      sc[r].uni = qm + xm - in;
+      sc[r].id = (uint32_t)r;
+    }
+    qsort(sc, n, sizeof(jac_t), cmp_jac);
+    for (uint32_t i = 0; i < k; ++i) {
+      int live = i < n;
+      out_ids[q * k + i] = live ? sc[i].id : EMPTY;
+      out_inter[q * k + i] = live ? (uint32_t)sc[i].inter : 0;
+      out_union[q * k + i] = live ? (uint32_t)sc[i].uni : 0;
+    }
+  }
+  free(qs);
+  free(offs);
+  free(sc);
+  free(sets);
+  return rc;
+}
+
+/* S@k terms per query: the mean cosine similarity between query q and the
+ * rows ids[q * stride + 0 .. k) that are not EMPTY (out_mean[q]; 0 when none
+ * is), and how many there were (out_count[q]).  The caller averages over
+ * queries. */
+EXPORT int oracle_mean_cosine(const int64_t* indptr, const int32_t* indices, uint64_t n, const int64_t* qindptr,
+                              const int32_t* qindices, uint64_t nq, const uint32_t* ids, uint32_t stride, uint32_t k,
+                              double* out_mean, uint32_t* out_count) {
+  if (!indptr || !qindptr || !ids || !out_mean || !out_count || k > stride) return O_EINVAL;
+  int rc = O_OK;
+  for (uint64_t q = 0; q < nq && rc == O_OK; ++q) {
+    uint64_t qn = (uint64_t)(qindptr[q + 1] - qindptr[q]);
+    int32_t* qs = (int32_t*)malloc(sizeof(int32_t) * (qn ? qn : 1));
+    if (!qs) {
+      rc = O_ENOMEM;
+      break;
+    }
+    uint64_t qm = row_set(qindices + qindptr[q], qn, qs);
+    double sum = 0.0;
+    uint32_t cnt = 0;
+    for (uint32_t i = 0; i < k && rc == O_OK; ++i) {
+      uint32_t id = ids[q * stride + i];
+      if (id == EMPTY) continue;
+      if (id >= n) {
+        rc = O_EINVAL;
+        break;
+      }
+      uint64_t xn = (uint64_t)(indptr[id + 1] - indptr[id]);
+      int32_t* xs = (int32_t*)malloc(sizeof(int32_t) * (xn ? xn : 1));
+      if (!xs) {
+        rc = O_ENOMEM;
+        break;
+      }
+      uint64_t xm = row_set(indices + indptr[id], xn, xs);
+      uint64_t in = inter_size(qs, qm, xs, xm);
+      sum += (double)in / sqrt((double)qm * (double)xm);
+      ++cnt;
+      free(xs);
+    }
+    free(qs);
+    out_mean[q] = cnt ? sum / cnt : 0.0;
+    out_count[q] = cnt;
+  }
   return rc;
 }

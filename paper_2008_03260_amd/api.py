@@ -107,6 +107,7 @@ def lib() -> C.CDLL:
             "slash_free": ([vp], None),
             "slash_last_error": ([], C.c_char_p),
             "slash_set_allocator": ([vp, vp, vp], st),
+            "slash_release_cache": ([], None),
             "slash_serve_start": ([vp, P(ServeConfig), P(vp)], st),
             "slash_serve_submit_query": ([vp, vp, u32, u32, P(u64)], st),
             "slash_serve_submit_insert": ([vp, vp, vp, u32, P(u64)], st),
@@ -265,6 +266,11 @@ def slash_build_profile(index) -> dict:
 def slash_free(index):
     if index:
         lib().slash_free(index)
+
+
+def slash_release_cache():
+    """Return the device blocks the library keeps for reuse to the device."""
+    lib().slash_release_cache()
 
 
 # ------------------------------------------------------------- serving

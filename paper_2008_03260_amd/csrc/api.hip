@@ -44,15 +44,7 @@ static slash_alloc_fn g_alloc = nullptr;
 static slash_free_fn g_free = nullptr;
 static void* g_alloc_ctx = nullptr;
 
-extern "C" slash_status slash_set_allocator(slash_alloc_fn a, slash_free_fn f, void* ctx) {
-  if ((a == nullptr) != (f == nullptr)) return fail(SLASH_E_INVAL, "allocator and free must both be set or both NULL");
-  g_alloc = a;
-  g_free = f;
-  g_alloc_ctx = ctx;
-  return SLASH_OK;
-}
-
-static void* dalloc(size_t bytes) {
+static void* dalloc_raw(size_t bytes) {
   if (bytes == 0) bytes = 4;
   if (g_alloc) return g_alloc(bytes, g_alloc_ctx);
   void* p = nullptr;
@@ -63,12 +55,107 @@ static void* dalloc(size_t bytes) {
   return p;
 }
 
-static void dfree(void* p) {
+static void dfree_raw(void* p) {
   if (!p) return;
   if (g_free)
     g_free(p, g_alloc_ctx);
   else
     (void)hipFree(p);
+}
+
+// Cache of freed device blocks (default allocator only).  A 200M-row build
+// needs about 38 GB of scratch and 8.6 GB of tables; hipMalloc and hipFree of
+// that much take longer than the build's kernels, so freed blocks are kept
+// and handed to later allocations of up to their size (best fit, at most
+// twice the request).  Every block is idle when it enters the cache: scratch
+// is returned after its stream has synchronised, index memory after the
+// device has drained.  When an allocation fails, the cache of that device is
+// released and the allocation retried.  slash_release_cache() frees it.
+namespace {
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  int device;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+std::map<void*, std::pair<size_t, int>> g_live;  // blocks handed out by the cache path
+
+void release_cache(int device, bool all_devices) {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (size_t i = 0; i < g_cache.size();) {
+      if (all_devices || g_cache[i].device == device) {
+        drop.push_back(g_cache[i].p);
+        g_cache[i] = g_cache.back();
+        g_cache.pop_back();
+      } else {
+        ++i;
+      }
+    }
+  }
+  for (void* p : drop) (void)hipFree(p);
+}
+}  // namespace
+
+static void* dalloc(size_t bytes) {
+  if (bytes == 0) bytes = 4;
+  if (g_alloc) return dalloc_raw(bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    size_t best = g_cache.size();
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+      const CachedBlock& b = g_cache[i];
+      if (b.device == dev && b.bytes >= bytes && b.bytes / 2 <= bytes &&
+          (best == g_cache.size() || b.bytes < g_cache[best].bytes))
+        best = i;
+    }
+    if (best != g_cache.size()) {
+      CachedBlock b = g_cache[best];
+      g_cache[best] = g_cache.back();
+      g_cache.pop_back();
+      g_live[b.p] = {b.bytes, b.device};
+      return b.p;
+    }
+  }
+  void* p = dalloc_raw(bytes);
+  if (!p) {
+    release_cache(dev, false);
+    p = dalloc_raw(bytes);
+  }
+  if (p) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_live[p] = {bytes, dev};
+  }
+  return p;
+}
+
+static void dfree(void* p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_live.find(p);
+    if (it != g_live.end()) {
+      g_cache.push_back(CachedBlock{p, it->second.first, it->second.second});
+      g_live.erase(it);
+      return;
+    }
+  }
+  dfree_raw(p);
+}
+
+extern "C" void slash_release_cache(void) { release_cache(0, true); }
+
+extern "C" slash_status slash_set_allocator(slash_alloc_fn a, slash_free_fn f, void* ctx) {
+  if ((a == nullptr) != (f == nullptr)) return fail(SLASH_E_INVAL, "allocator and free must both be set or both NULL");
+  release_cache(0, true);
+  g_alloc = a;
+  g_free = f;
+  g_alloc_ctx = ctx;
+  return SLASH_OK;
 }
 
 // RAII device buffer for scratch.
@@ -88,6 +175,15 @@ struct DBuf {
   }
   template <class T>
   T* as() const { return (T*)p; }
+};
+
+// Synchronises a stream when it goes out of scope.  Declared after the
+// scratch buffers of a call, it runs before they return to the cache, so no
+// block re-enters the cache while queued work may still use it (error paths
+// included).
+struct SyncOnExit {
+  hipStream_t st;
+  ~SyncOnExit() { (void)hipStreamSynchronize(st); }
 };
 
 // Grow index-owned scratch.  Work queued earlier on another stream may still
@@ -110,7 +206,8 @@ static uint64_t sm64(uint64_t& s) {
 }
 
 // One seed gives every hash function (Section 3 "Design", Section 4
-// "Initialization").  Draw order: nonzero-hash pair(s); one direction bit per
+// "Initialization").  Draw order: nonzero-hash pair(s) (one, one per table,
+// or one per MinHash function, by hash mode); one direction bit per
 // bin; per table K odd multipliers then an offset; per table priority key and
 // two odd 32-bit multipliers; per count-min row an odd multiplier and an
 // offset.
@@ -118,7 +215,7 @@ static HostConsts derive_consts(const slash_params& p) {
   HostConsts h;
   uint64_t s = p.seed;
   const uint32_t M = p.K * p.L;
-  const uint32_t n_h = p.hash_mode ? p.L : 1;
+  const uint32_t n_h = p.hash_mode == 2 ? M : (p.hash_mode ? p.L : 1);
   for (uint32_t t = 0; t < n_h; ++t) {
     h.a_h.push_back(sm64(s) | 1u);
     h.b_h.push_back(sm64(s));
@@ -152,7 +249,7 @@ static slash_status check_params(const slash_params* p) {
   if (p->cm_rows < 1 || p->cm_rows > 16) return fail(SLASH_E_INVAL, "cm_rows must be in [1, 16]");
   if (p->log2_cm_width > 16) return fail(SLASH_E_INVAL, "log2_cm_width must be <= 16");
   if (p->k_max < 1 || p->k_max > 1024) return fail(SLASH_E_INVAL, "k_max must be in [1, 1024]");
-  if (p->hash_mode > 1) return fail(SLASH_E_INVAL, "hash_mode must be 0 or 1");
+  if (p->hash_mode > 2) return fail(SLASH_E_INVAL, "hash_mode must be 0, 1 or 2");
   if (p->bucket > 1) return fail(SLASH_E_INVAL, "bucket must be 0 or 1");
   if (p->bucket == 1 && (p->log2_cm_width > 8 || (p->cm_rows << p->log2_cm_width) > 256))
     return fail(SLASH_E_UNSUPPORTED, "Topkapi buckets need log2_cm_width <= 8 and cm_rows * 2^log2_cm_width <= 256");
@@ -428,6 +525,7 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
   }
   if (n > 0) {
     DBuf keys, k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, hchunks, hfinals, hcount, hcand, tkh;
+    SyncOnExit drain{st};
     size_t hist_n = sort_hist_entries(n);
     size_t part_n = std::max(sort_part_entries(hist_n), sort_part_entries(n)) + 16;
     const size_t hcap = heavy_chunk_capacity(n, kHeavy);
@@ -720,11 +818,27 @@ extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q,
   if (sched) {
     sc = *sched;
   } else {
+    int n_tuned = 0, only = -1;
     for (int c = 0; c < 4; ++c)
       if (ix->has_tuned[c]) {
-        sc = ix->tuned[c];
-        break;
+        ++n_tuned;
+        only = c;
       }
+    if (n_tuned == 1) {
+      sc = ix->tuned[only];
+    } else if (n_tuned > 1) {
+      // several size classes tuned: the batch's mean row size picks one (the
+      // nearest tuned class)
+      int64_t ends[2];
+      HIP_TRY(hipMemcpyAsync(&ends[0], q.indptr, 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(&ends[1], q.indptr + q.n_rows, 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      const int cls = (int)size_class((double)(ends[1] - ends[0]) / (double)q.n_rows);
+      int best = -1;
+      for (int c = 0; c < 4; ++c)
+        if (ix->has_tuned[c] && (best < 0 || std::abs(c - cls) < std::abs(best - cls))) best = c;
+      sc = ix->tuned[best];
+    }
   }
   QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
   a.exact = (flags & SLASH_FLAG_EXACT) ? 1u : 0u;
@@ -745,6 +859,7 @@ extern "C" slash_status slash_autotune(slash_index* ix, slash_csr sample, uint32
   const uint64_t n = sample.n_rows;
   const uint32_t km = ix->p.k_max;
   DBuf ref_i, ref_s, got_i, got_s;
+  SyncOnExit drain{st};
   if (!ref_i.get(n * km * 4) || !ref_s.get(n * km * 4) || !got_i.get(n * km * 4) || !got_s.get(n * km * 4))
     return fail(SLASH_E_NOMEM, "autotune buffers");
   QueryArgs ra{sample, nullptr, k, 1, ref_i.as<uint32_t>(), ref_s.as<uint32_t>(), nullptr};
@@ -854,8 +969,16 @@ extern "C" slash_status slash_import_tables(const slash_params* params, const ui
   const Shape& s = ix->shape;
   hipError_t e = hipMemcpyAsync(ix->ids, ids, (size_t)s.L * s.nb * bucket_words(s) * 4, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(ix->seen, seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st);
+  // reservoir tables: a bucket's first min(R, seen) slots hold assigned ids,
+  // the rest are EMPTY (queries read every non-EMPTY slot)
+  uint32_t f = 0;
+  if (e == hipSuccess && !s.bucket) e = launch_fill_u32(ix->flag, 0u, 1, st);
+  if (e == hipSuccess && !s.bucket) e = launch_check_tables(ix->ids, ix->seen, (uint64_t)s.L * s.nb, s.R, n_items, ix->flag, st);
+  if (e == hipSuccess && !s.bucket) e = hipMemcpyAsync(&f, ix->flag, 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table copy: %s", hipGetErrorString(e)));
+  if (f & 8u) return bail(fail(SLASH_E_INVAL, "imported tables: a bucket holds an EMPTY or unassigned id in its first "
+                                             "min(R, seen) slots, or an id past them"));
   ix->n_items = n_items;
   if ((rs = reserve_small_inserts(ix)) != SLASH_OK) return bail(rs);
   *out = ix;

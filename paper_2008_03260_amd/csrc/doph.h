@@ -33,10 +33,14 @@ __host__ __device__ constexpr uint32_t mask_words(uint32_t M) { return ((M + 63)
 // LDS words one wave needs for doph_wave: minima[M] + densified[M] + mask.
 __host__ __device__ constexpr uint32_t doph_lds_words(uint32_t M) { return 2 * M + mask_words(M); }
 
+// Nonzero-hash constant pairs (a_h, b_h): one for the single DOPH pass
+// (mode 0), one per table (mode 1), one per MinHash function (mode 2).
+__host__ __device__ inline uint32_t n_hash_pairs(const Shape& s) { return s.mode == 2 ? s.M : (s.mode ? s.L : 1u); }
+
 // 32-bit LDS words of the staged hash constants: u64 a_h, b_h, a_tj, b_t,
 // a_r, b_r, then the u32 direction words.
 __host__ __device__ inline uint32_t const_words(const Shape& s) {
-  uint32_t n_h = s.mode ? s.L : 1;
+  uint32_t n_h = n_hash_pairs(s);
   return 2 * (2 * n_h + s.M + s.L + 2 * s.d) + (s.M + 31) / 32 + 1;
 }
 
@@ -50,7 +54,7 @@ constexpr uint32_t kConstCapWords = 4096;
 // the u32 direction words), so it is copied as const_words(s) flat words,
 // every load of a thread issued before its stores.
 __device__ inline ConstView stage_consts(const Shape& s, const ConstView& c, uint32_t* dst, uint32_t nthreads) {
-  const uint32_t n_h = s.mode ? s.L : 1;
+  const uint32_t n_h = n_hash_pairs(s);
   const uint32_t W = const_words(s);
   const uint32_t* src = (const uint32_t*)c.a_h;
   for (uint32_t base = 0; base < W; base += 4 * nthreads) {
@@ -207,6 +211,16 @@ __device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const Cons
   wave_sync();
   if (s.mode == 0) {
     row_minima<G>(s, cld64<CL>(c.a_h, 0), cld64<CL>(c.b_h, 0), idx, nnz, gl, lds_m, nullptr, c.bad);
+  } else if (s.mode == 2) {
+    // classic MinHash: value j is the minimum of u_j over the row; lanes take
+    // (function, nonzero) pairs function-major, so a lane keeps its function's
+    // constants across consecutive nonzeros
+    for (uint32_t w = gl; w < nnz * M; w += G) {
+      const uint32_t j = w / nnz, e = w - j * nnz;
+      const uint32_t x = (uint32_t)idx[e];
+      if (c.bad && ((int32_t)x < 0 || x >= s.dim)) atomicOr(c.bad, 2u);
+      atomicMin(&lds_m[j], nz_hash(cld64<CL>(c.a_h, j), cld64<CL>(c.b_h, j), x));
+    }
   } else {
     const uint32_t L = s.L, K = s.K;
     for (uint32_t w = gl; w < nnz * L; w += G) {
@@ -243,8 +257,10 @@ __device__ __forceinline__ const uint32_t* doph_group(const Shape& s, const Cons
   for (uint32_t b = gl; b < M; b += G) {
     uint32_t v = m3[b];
     if (v == SL_EMPTY) {
-      uint32_t lo = s.mode == 0 ? 0u : (b / s.K) * s.K;
-      uint32_t n = s.mode == 0 ? M : s.K;
+      // densification domain: every bin (mode 0), the table's K bins (mode
+      // 1); a MinHash function (mode 2) is its own domain and stays EMPTY
+      uint32_t lo = s.mode == 0 ? 0u : (s.mode == 1 ? (b / s.K) * s.K : b);
+      uint32_t n = s.mode == 0 ? M : (s.mode == 1 ? s.K : 1u);
       if (s.mode == 0 ? any_all : domain_any(k3, lo, n)) {
         bool right = (cld32<CL>(c.dirw, b >> 5) >> (b & 31)) & 1u;
         uint32_t src = right ? find_right(k3, lo, n, b) : find_left(k3, lo, n, b);

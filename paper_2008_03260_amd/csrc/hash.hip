@@ -294,6 +294,24 @@ __global__ void k_item_ids(uint32_t* v, uint32_t first, uint64_t n_rows, uint64_
     v[i] = first + (uint32_t)(i % n_rows);
 }
 
+// Imported reservoir tables: the first min(R, seen) slots of a bucket hold
+// ids below n_items, the rest are EMPTY (what a build or insert leaves, and
+// what a query relies on: it reads every non-EMPTY slot).  ORs 8 into *flag
+// on a violation.
+__global__ void k_check_tables(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ seen, uint64_t n_buckets,
+                               uint32_t R, uint64_t n_items, uint32_t* flag) {
+  const uint64_t total = n_buckets * R;
+  bool bad = false;
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total; x += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = x / R;
+    const uint32_t j = (uint32_t)(x - b * R);
+    const uint32_t fill = min(R, seen[b]);
+    const uint32_t v = ids[x];
+    bad |= j < fill ? (v == SL_EMPTY || (uint64_t)v >= n_items) : v != SL_EMPTY;
+  }
+  if (bad) atomicOr(flag, 8u);
+}
+
 uint32_t grid_for(uint64_t work, uint32_t block, uint32_t cap = 65536) {
   uint64_t g = (work + block - 1) / block;
   if (g < 1) g = 1;
@@ -395,6 +413,14 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t first, uint64_t n, hipStream_t 
 hipError_t launch_item_ids(uint32_t* vals, uint32_t first_id, uint64_t n_rows, uint64_t items, hipStream_t st) {
   if (items == 0) return hipSuccess;
   hipLaunchKernelGGL(k_item_ids, dim3(grid_for(items, 256, 8192)), dim3(256), 0, st, vals, first_id, n_rows, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_tables(const uint32_t* ids, const uint32_t* seen, uint64_t n_buckets, uint32_t R,
+                               uint64_t n_items, uint32_t* flag, hipStream_t st) {
+  if (n_buckets == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_tables, dim3(grid_for(n_buckets * R, 256, 65536)), dim3(256), 0, st, ids, seen,
+                     n_buckets, R, n_items, flag);
   return hipGetLastError();
 }
 

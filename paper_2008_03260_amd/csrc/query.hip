@@ -82,6 +82,15 @@ __host__ __device__ inline QLayout q_layout(const Shape& s, bool exact = false) 
   return o;
 }
 
+// The layout's 64-bit slots (keys collected in the count-min region, the
+// radix-select buffer, the top-k bound at misc + 8) must sit on 8-byte
+// boundaries: a misaligned 64-bit LDS atomic faults.  Checked on the host
+// before any launch.
+__host__ __device__ inline bool q_layout_aligned(const QLayout& o) {
+  return (o.cm % 2) == 0 && (o.sel % 2) == 0 && (o.misc % 2) == 0 && ((o.misc + 8) % 2) == 0 &&
+         (o.doph % 2) == 0 && o.total <= kLdsWords;
+}
+
 // Outputs per query up to which the top-k is taken by repeated maximum
 // extraction instead of the radix select.
 constexpr uint32_t kFewK = 16;
@@ -642,6 +651,7 @@ size_t query_lds_bytes(const Shape& s, uint32_t waves, bool exact) {
 bool query_supported(const Shape& s, uint32_t waves, bool exact) {
   if (!pick(s, waves, exact)) return false;
   if (s.L * s.R > 65535u) return false;
+  if (!q_layout_aligned(q_layout(s, exact))) return false;
   return query_lds_bytes(s, waves, exact) <= (size_t)kLdsWords * 4;
 }
 

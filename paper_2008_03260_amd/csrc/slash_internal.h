@@ -169,6 +169,11 @@ void* plain_query_kernel(const Shape& s, uint32_t waves, bool exact = false);
 hipError_t launch_validate_indices(const int32_t* idx, uint64_t n, uint32_t dim, uint32_t* flag, hipStream_t st);
 hipError_t launch_item_ids(uint32_t* vals, uint32_t first_id, uint64_t n_rows, uint64_t items, hipStream_t st);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t first, uint64_t n, hipStream_t st);
+// Check imported reservoir tables ([n_buckets][R] ids, [n_buckets] seen):
+// ORs 8 into *flag unless every bucket's first min(R, seen) slots hold ids
+// below n_items and the rest are EMPTY.
+hipError_t launch_check_tables(const uint32_t* ids, const uint32_t* seen, uint64_t n_buckets, uint32_t R,
+                               uint64_t n_items, uint32_t* flag, hipStream_t st);
 
 // Per-bucket [start, end) of a sorted key array (start/end pre-zeroed, nb entries).
 hipError_t launch_segment_bounds(const uint32_t* skeys, uint64_t n, uint32_t* start, uint32_t* end,

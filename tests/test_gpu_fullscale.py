@@ -9,9 +9,12 @@ what it can compute one by one, plus properties that hold at any size:
   priority is below the reservoir's largest; every reservoir is sorted by
   priority, every stored id hashes (oracle) to its bucket, fill = min(R, seen),
   and seen sums to N per table;
-* sampled query rows equal the count-min top-k recomputed by the oracle's
-  query arithmetic over the stored reservoirs of the probed buckets (a
-  consistency property; the reservoirs themselves are checked above).
+* sampled query rows (64 planted queries on the plain path; 1000 queries of
+  the batched mix through the autotuned batched path and 1000 planted
+  queries in bench.py's launch form) equal the count-min top-k recomputed by
+  the oracle's query arithmetic over the stored reservoirs of the buckets the
+  oracle hashes them to (a consistency property; the reservoirs themselves
+  are checked above).
 """
 import numpy as np
 import pytest
@@ -39,7 +42,7 @@ def shard():
     law = synth.RowLaw(synth.derive(MASTER, synth.STREAM_DATA), 1 << 20)
     ip, ix = law.gpu_rows(0, N)
     seed = synth.derive(MASTER, synth.STREAM_INDEX)
-    gp = api.Params.of(k_max=10, seed=seed, **KW)
+    gp = api.Params.of(k_max=100, seed=seed, **KW)
     op = oracle.Params(seed=seed, **KW)
     idx = api.Index(gp, ip, ix)
     ids, seen = idx.tables()
@@ -101,17 +104,50 @@ def test_sampled_rows_bottom_r(shard):
         assert int(mb[pos[y], t]) == b, "stored id does not hash to its bucket"
 
 
+def _oracle_answers(api, idx_tables, op, cs, qi, qx, kq):
+    """The oracle's count-min top-k of each query over the stored reservoirs
+    of its probed buckets (bucket ids from the oracle's own hash)."""
+    ids, seen = idx_tables
+    bk = oracle.hash_rows(op, cs, qi, qx)
+    nq = len(qi) - 1
+    tt = torch.arange(op.L, device=ids.device).view(1, -1).expand(nq, -1)
+    bb = torch.from_numpy(bk.astype(np.int64)).to(ids.device)
+    res = api.as_u32(ids[tt, bb])            # [nq, L, R]
+    fil = np.minimum(api.as_u32(seen[tt, bb]), op.R)  # [nq, L]
+    wi = np.zeros((nq, 100), dtype=np.uint32)
+    ws = np.zeros((nq, 100), dtype=np.uint32)
+    for q in range(nq):
+        cand = np.concatenate([res[q, t, : fil[q, t]] for t in range(op.L)])
+        wi[q], ws[q] = oracle.aggregate(op, cs, cand, int(kq[q]), k_max=100)
+    return wi, ws
+
+
 def test_sampled_queries_consistent_with_tables(shard):
     api, law, idx, ids, seen, op, cs = shard
     qi, qx, src, _ = law.queries(synth.derive(MASTER, synth.STREAM_QUERY), N, 0, 64)
     gi, gs = idx.query(torch.from_numpy(qi).cuda(), torch.from_numpy(qx).cuda(), 10)
-    gb, gsn = api.as_u32(gi), api.as_u32(gs)
-    bk = oracle.hash_rows(op, cs, qi, qx)
-    for q in range(len(qi) - 1):
-        cand = []
-        for t in range(op.L):
-            b = int(bk[q, t])
-            fill = min(op.R, int(seen[t, b].item()))
-            cand.append(ids[t, b, :fill].cpu().numpy().view(np.uint32))
-        wi, ws = oracle.aggregate(op, cs, np.concatenate(cand), 10)
-        assert (gb[q] == wi).all() and (gsn[q] == ws).all()
+    wi, ws = _oracle_answers(api, (ids, seen), op, cs, qi, qx, np.full(64, 10))
+    assert (api.as_u32(gi) == wi).all() and (api.as_u32(gs) == ws).all()
+
+
+def test_batched_mix_autotuned_consistent_with_tables(shard):
+    # 1000 queries of the batched mix (lognormal nnz, 10-40% replaced, k in
+    # {1, 10, 100}) through the batched path with the tuned schedule, as
+    # bench.py runs it
+    api, law, idx, ids, seen, op, cs = shard
+    qi, qx, src, kq = law.queries(synth.derive(MASTER, synth.STREAM_QUERY) ^ 0x5EED, N, 0, 1000,
+                                  nnz_mode="lognormal", median=40, sigma=1.0, lo=5, hi=2000, f=(0.1, 0.4),
+                                  kmix=(1, 10, 100))
+    dqi, dqx = torch.from_numpy(qi).cuda(), torch.from_numpy(qx).cuda()
+    sched = idx.autotune(dqi, dqx, 100)
+    gi, gs = idx.query_batched(dqi, dqx, 0, k_per_query=torch.from_numpy(kq.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    wi, ws = _oracle_answers(api, (ids, seen), op, cs, qi, qx, kq)
+    assert (api.as_u32(gi) == wi).all() and (api.as_u32(gs) == ws).all(), sched
+    # the planted-query workload's launch form (4 waves, one group per query)
+    qi, qx, src, _ = law.queries(synth.derive(MASTER, synth.STREAM_QUERY), N, 0, 1000)
+    gi, gs = idx.query_batched(torch.from_numpy(qi).cuda(), torch.from_numpy(qx).cuda(), 10,
+                               schedule=dict(waves_per_query=4, queries_per_ticket=0))
+    torch.cuda.synchronize()
+    wi, ws = _oracle_answers(api, (ids, seen), op, cs, qi, qx, np.full(1000, 10))
+    assert (api.as_u32(gi) == wi).all() and (api.as_u32(gs) == ws).all()

@@ -60,6 +60,9 @@ HASH_SHAPES = [
     dict(K=4, L=16, hash_mode=1),           # per-table DOPH
     dict(K=5, L=3, hash_mode=1),
     dict(K=64, L=64, log2_buckets=12),      # M = 4096, the largest
+    dict(K=4, L=16, hash_mode=2),           # classic MinHash, 64 functions
+    dict(K=3, L=7, hash_mode=2),
+    dict(K=16, L=64, log2_buckets=12, hash_mode=2),  # 1024 functions, constants in global memory
 ]
 
 
@@ -92,8 +95,9 @@ def check_tables(api, idx, op, cs, ip, ix):
 
 
 @pytest.mark.parametrize("shape", [dict(), dict(L=16, log2_buckets=12, R=32), dict(K=2, L=5, log2_buckets=3, R=7),
-                                   dict(hash_mode=1, L=6), dict(R=1), dict(R=130, log2_buckets=6)],
-                         ids=["base", "wide", "tiny-buckets", "mode1", "R1", "R130"])
+                                   dict(hash_mode=1, L=6), dict(hash_mode=2, L=6), dict(R=1),
+                                   dict(R=130, log2_buckets=6)],
+                         ids=["base", "wide", "tiny-buckets", "mode1", "mode2", "R1", "R130"])
 def test_build_parity(api, shape):
     gp, op = params_pair(api, **shape)
     _, (ip, ix) = rows_of(20000, seed=5)
@@ -251,7 +255,7 @@ def test_invalid_rows_rejected(api):
 def test_invalid_params_rejected(api):
     ip, ix = csr_from_lists([[1]])
     for bad in (dict(K=0), dict(L=0), dict(R=0), dict(log2_buckets=0), dict(log2_buckets=31), dict(k_max=0),
-                dict(hash_mode=2), dict(cm_rows=0), dict(log2_cm_width=17)):
+                dict(hash_mode=3), dict(cm_rows=0), dict(log2_cm_width=17)):
         gp, _ = params_pair(api, **bad)
         with pytest.raises(api.SlashError) as e:
             api.Index(gp, dev(ip), dev(ix))
@@ -453,3 +457,132 @@ def test_wide_config_end_to_end(api, log2_buckets):
     assert (u32(gi) == ei).all() and (u32(gs) == es).all()
     if log2_buckets == 6:
         assert int(oseen.min()) > 128  # every reservoir full
+
+
+# ------------------------------------------ the 200M-shard query instance
+
+
+@pytest.fixture(scope="module")
+def headline(api):
+    # The query shape of the 200M-point shard (K=4, L=32, R=64, count-min
+    # 4 x 4096, k_max = 100) on 200k rows with 2^10 buckets per table, so the
+    # mean bucket load (195) matches the shard's (191) and most reservoirs
+    # are full: a query aggregates about 2048 slots, 8 per thread of the
+    # 4-wave kernels.  Queries follow the batched mix (lognormal nnz, 10-40%
+    # replaced, k drawn from {1, 10, 100}).
+    master = 2021
+    gp, op = params_pair(api, k_max=100, K=4, L=32, log2_buckets=10, R=64, cm_rows=4, log2_cm_width=12,
+                         seed=synth.derive(master, synth.STREAM_INDEX))
+    law = synth.RowLaw(synth.derive(master, synth.STREAM_DATA), 1 << 20)
+    n = 200_000
+    ip, ix = law.rows(0, n)
+    qi, qx, src, kq = law.queries(synth.derive(master, synth.STREAM_QUERY), n, 0, 400, nnz_mode="lognormal",
+                                  median=40, sigma=1.0, lo=5, hi=2000, f=(0.1, 0.4), kmix=(1, 10, 100))
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    assert np.mean(np.minimum(oseen, op.R)) > 0.9 * op.R  # most reservoirs full
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=100, kq=kq)
+    return idx, op, cs, oids, oseen, qi, qx, kq, wi, ws
+
+
+def test_headline_shape_tables(api, headline):
+    idx, op, cs, oids, oseen, *_ = headline
+    gi, gsn = idx.tables()
+    assert (u32(gsn) == oseen).all()
+    assert (u32(gi) == oids).all()
+
+
+@pytest.mark.parametrize("sched", [None, dict(waves_per_query=4, queries_per_ticket=0),
+                                   dict(waves_per_query=4, queries_per_ticket=1),
+                                   dict(waves_per_query=4, queries_per_ticket=8, groups_per_cu=2),
+                                   dict(waves_per_query=16, queries_per_ticket=0)],
+                         ids=["plain", "4w-grid", "4w-persistent", "4w-persistent-8", "16w-grid"])
+def test_headline_shape_query_parity(api, headline, sched):
+    # plain slash_query, and the batched path in the launch forms bench.py
+    # uses, against the oracle element by element (k in {1, 10, 100})
+    idx, op, cs, oids, oseen, qi, qx, kq, wi, ws = headline
+    kd = dev(kq.view(np.int32))
+    if sched is None:
+        gi, gs = idx.query(dev(qi), dev(qx), 0, k_per_query=kd)
+    else:
+        for _ in range(2):  # the second call replays the recorded graph
+            gi, gs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=kd, schedule=sched)
+            torch.cuda.synchronize()
+            assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+
+
+def test_headline_shape_autotuned(api, headline):
+    idx, op, cs, oids, oseen, qi, qx, kq, wi, ws = headline
+    best = idx.autotune(dev(qi), dev(qx), 100)
+    gi, gs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
+    torch.cuda.synchronize()
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all(), best
+    # k = 10 for every query (the planted-query workload)
+    w10, s10 = oracle.query(op, cs, oids, oseen, qi, qx, 10, k_max=100)
+    gi, gs = idx.query_batched(dev(qi), dev(qx), 10, schedule=dict(waves_per_query=4, queries_per_ticket=0))
+    torch.cuda.synchronize()
+    assert (u32(gi) == w10).all() and (u32(gs) == s10).all()
+
+
+def test_headline_shape_exact(api, headline):
+    idx, op, cs, oids, oseen, qi, qx, kq, wi, ws = headline
+    ei, es = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=100, kq=kq, exact=True)
+    gi, gs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)), flags=api.FLAG_EXACT,
+                               schedule=dict(waves_per_query=4, queries_per_ticket=0))
+    torch.cuda.synchronize()
+    assert (u32(gi) == ei).all() and (u32(gs) == es).all()
+    # the count-min estimate is never below the exact count
+    assert (ws[:, 0] >= es[:, 0]).all()
+
+
+@pytest.mark.parametrize("k", [101, 500, 1024])
+def test_query_large_k(api, k):
+    # k above 100 up to the largest k_max: candidates from 16 tables of 64
+    # slots (at most 1024 distinct ids), so a query can fill its whole row
+    gp, op = params_pair(api, k_max=1024, L=16, log2_buckets=6, R=64, cm_rows=2, log2_cm_width=9)
+    law, (ip, ix) = rows_of(20000, seed=51)
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    qi, qx = ip[:65], ix[: ip[64]]
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, k, k_max=1024)
+    assert (wi[:, min(k, 500) - 1] != EMPTY).any()  # rows well past 100 entries are filled
+    gi, gs = idx.query(dev(qi), dev(qx), k)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+    bi, bs = idx.query_batched(dev(qi), dev(qx), k)
+    torch.cuda.synchronize()
+    assert (u32(bi) == wi).all() and (u32(bs) == ws).all()
+
+
+def test_query_classic_minhash_mode(api):
+    gp, op = params_pair(api, k_max=10, L=12, log2_buckets=9, R=16, hash_mode=2)
+    law, (ip, ix) = rows_of(8000, seed=61)
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    check_tables(api, idx, op, cs, ip, ix)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    qi, qx, _, _ = law.queries(synth.derive(61, synth.STREAM_QUERY), 8000, 0, 100)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 10)
+    gi, gs = idx.query(dev(qi), dev(qx), 10)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+
+
+def test_import_rejects_data_past_fill(api):
+    # a query reads a bucket's first min(R, seen) slots as the oracle does,
+    # which holds for imported tables only if the slots past that are empty:
+    # import checks it
+    gp, op = params_pair(api, L=3, log2_buckets=5, R=8)
+    _, (ip, ix) = rows_of(100, seed=71)
+    a = api.Index(gp, dev(ip), dev(ix))
+    ids, seen = a.tables()
+    sn = u32(seen)
+    t, b = np.argwhere(sn < op.R)[0]
+    bad = ids.clone()
+    bad[t, b, sn[t, b]] = 5
+    with pytest.raises(api.SlashError) as e:
+        api.Index.from_tables(gp, bad, seen, 100)
+    assert e.value.code == api.E_INVAL
+    ok = api.Index.from_tables(gp, ids, seen, 100)
+    assert ok.info()["n_items"] == 100

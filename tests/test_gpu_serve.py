@@ -1,8 +1,11 @@
 """Serving loop (continuous batching with epoch-ordered inserts): every
-served result equals the standalone result on the index state of its epoch."""
+served result equals the oracle's result on the index state of its epoch
+(the rows inserted before it), and the standalone result of the same
+library."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 torch = pytest.importorskip("torch")
@@ -40,6 +43,23 @@ def setup(api):
     return law, params, ip, ix, n0, n1, qi, qx, kq
 
 
+def oracle_params(params):
+    return oracle.Params(**{f: int(getattr(params, f)) for f in ("dim", "K", "L", "log2_buckets", "R", "cm_rows",
+                                                                 "log2_cm_width", "hash_mode", "seed")})
+
+
+def oracle_answers(params, ip, ix, n_rows, qi, qx, kq):
+    """(ids, scores) [nq, k_max] of the oracle on the first n_rows rows."""
+    op = oracle_params(params)
+    cs = oracle.constants(op)
+    sip, six = ip[: n_rows + 1], ix[: ip[n_rows]]
+    if params.bucket:
+        cells, _ = oracle.tk_build(op, cs, sip, six)
+        return oracle.tk_query(op, cs, cells, qi, qx, 0, k_max=params.k_max, kq=kq)
+    oids, oseen = oracle.build(op, cs, sip, six)
+    return oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=params.k_max, kq=kq)
+
+
 def standalone(api, params, ip, ix, n_rows, qi, qx, kq):
     idx = api.Index(params, dev(ip[: n_rows + 1]), dev(ix[: ip[n_rows]]))
     gi, gs = idx.query(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)))
@@ -63,6 +83,27 @@ def test_served_results_equal_standalone(api, setup):
         got += api.slash_serve_poll(srv)
     stats = api.slash_serve_stop(srv)
     assert stats["queries_done"] == len(tickets) and stats["batches"] >= 1
+    for c in got:
+        q = tickets[c["ticket"]]
+        k = int(kq[q])
+        assert c["status"] == 0 and c["epoch"] == 0 and c["k"] == k
+        assert (c["ids"] == ref_i[q, :k]).all() and (c["scores"] == ref_s[q, :k]).all()
+    idx.close()
+
+
+def test_served_results_equal_oracle(api, setup):
+    # every completion against the oracle's build of the same rows, with
+    # several batches in flight (small batches, four slots)
+    law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    ref_i, ref_s = oracle_answers(params, ip, ix, n0, qi, qx, kq)
+    idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=64 << 20, max_batch=16, max_inflight=4)
+    tickets = {api.slash_serve_submit_query(srv, qx[qi[q]:qi[q + 1]], int(kq[q])): q for q in range(len(qi) - 1)}
+    got = []
+    while len(got) < len(tickets):
+        got += api.slash_serve_poll(srv)
+    stats = api.slash_serve_stop(srv)
+    assert stats["batches"] > 4
     for c in got:
         q = tickets[c["ticket"]]
         k = int(kq[q])
@@ -110,8 +151,12 @@ def test_inserts_close_epochs_topkapi_buckets(api, setup):
 
 def check_epochs(api, setup, params):
     law, _, ip, ix, n0, n1, qi, qx, kq = setup
-    before = standalone(api, params, ip, ix, n0, qi, qx, kq)
-    after = standalone(api, params, ip, ix, n0 + n1, qi, qx, kq)
+    before = oracle_answers(params, ip, ix, n0, qi, qx, kq)
+    after = oracle_answers(params, ip, ix, n0 + n1, qi, qx, kq)
+    # the library's own standalone answers agree with the oracle too
+    for ref, n in ((before, n0), (after, n0 + n1)):
+        gi, gs = standalone(api, params, ip, ix, n, qi, qx, kq)
+        assert (gi == ref[0]).all() and (gs == ref[1]).all()
     idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
     srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=64 << 20, max_batch=64, max_inflight=4)
     nq = len(qi) - 1
@@ -167,6 +212,10 @@ def test_stop_drains_and_rejects(api, setup):
 
 
 def test_replay_open_loop(api, setup):
+    # open-loop arrivals with about a hundred inserts interleaved among the
+    # queries, several batches and inserts in flight at once: each query's
+    # returned ids equal the oracle's top-k on the rows inserted before it
+    # (submission order fixes its epoch: the inserts submitted before it)
     law, params, ip, ix, n0, n1, qi, qx, kq = setup
     idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
     srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=128 << 20, max_batch=256, max_inflight=4)
@@ -185,4 +234,34 @@ def test_replay_open_loop(api, setup):
     stats = api.slash_serve_stop(srv)
     assert (lat >= 0).all() and stats["queries_done"] == nq and stats["inserts_done"] == int(ins.sum())
     assert stats["rows_inserted"] == rows
+    assert int(ins.sum()) >= 50
+    # the oracle replays the same sequence: inserts grow its tables, each run
+    # of queries between two inserts is answered on the tables of that epoch
+    op = oracle_params(params)
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip[: n0 + 1], ix[: ip[n0]])
+    next_id, next_row, qn, i = n0, 0, 0, 0
+    while i < n:
+        if ins[i]:
+            m = int(sz[i])
+            sip = iip[next_row: next_row + m + 1] - iip[next_row]
+            six = iix[iip[next_row]: iip[next_row + m]]
+            oracle.insert(op, cs, oids, oseen, next_id, sip, six)
+            next_id += m
+            next_row += m
+            i += 1
+            continue
+        j = i
+        while j < n and not ins[j]:
+            j += 1
+        m = j - i  # queries qn .. qn + m of this epoch
+        sub_ip = q_ptr[qn: qn + m + 1] - q_ptr[qn]
+        sub_ix = q_idx[q_ptr[qn]: q_ptr[qn + m]]
+        wi, _ = oracle.query(op, cs, oids, oseen, sub_ip, sub_ix, 0, k_max=100, kq=q_k[qn: qn + m])
+        for r in range(m):
+            k = int(q_k[qn + r])
+            assert (ids[i + r, :k] == wi[r, :k]).all(), (i + r, k)
+            assert (ids[i + r, k:] == EMPTY).all()
+        qn += m
+        i = j
     idx.close()

@@ -23,7 +23,7 @@ def test_splitmix64_published_outputs():
     assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_constant_draw_order(mode):
     # The whole table is one SplitMix64 stream consumed in the documented order.
     p = oracle.Params(dim=1000, K=3, L=5, log2_buckets=7, R=4, cm_rows=3, log2_cm_width=6,
@@ -32,7 +32,7 @@ def test_constant_draw_order(mode):
     lay = oracle.layout(p)
     st = [int(x) for x in oracle.splitmix64_stream(p.seed, lay["total"])]
     it = iter(st)
-    n_h = p.L if mode else 1
+    n_h = p.M if mode == 2 else (p.L if mode else 1)
     for t in range(n_h):
         assert int(cs[lay["a_h"] + t]) == next(it) | 1
         assert int(cs[lay["b_h"] + t]) == next(it)
@@ -53,7 +53,7 @@ def test_constant_draw_order(mode):
 
 def test_invalid_params_rejected():
     for bad in (dict(K=0), dict(L=0), dict(R=0), dict(log2_buckets=0), dict(log2_buckets=33),
-                dict(cm_rows=0), dict(hash_mode=2), dict(dim=0)):
+                dict(cm_rows=0), dict(hash_mode=3), dict(dim=0)):
         p = oracle.Params(**bad)
         with pytest.raises(oracle.OracleError):
             oracle.constants(p)
@@ -86,6 +86,65 @@ def test_doph_hand_worked_per_table_mode():
     bk, hv = oracle.hash_rows(p, cs, ip, ix, with_h=True)
     assert hv[0].tolist() == m1["h"]
     assert bk[0].tolist() == m1["buckets"]
+
+
+def test_classic_minhash_hand_worked():
+    # hash_mode 2: M independent MinHash functions (Section 2.2 MinHash with
+    # the L x K seeds of Section 4 "Initialization"), no bins, no
+    # densification; the fixture derives every value by hand
+    g = load_golden("doph_hand.json")
+    p = params_from(g["params"])
+    p.hash_mode = 2
+    m2 = g["mode2"]
+    groups = dict(g["constants"])
+    groups.update(a_h=m2["a_h"], b_h=m2["b_h"], dir=m2["dir"])
+    cs = constants_with(p, **groups)
+    for c in m2["cases"]:
+        ip, ix = csr([c["row"]])
+        bk, hv = oracle.hash_rows(p, cs, ip, ix, with_h=True)
+        assert hv[0].tolist() == c["h"], c["name"]
+        assert bk[0].tolist() == c["buckets"], c["name"]
+
+
+def test_classic_minhash_collision_rate_is_jaccard():
+    # Section 2.2: Pr[min of x = min of y under a random permutation] is the
+    # Jaccard similarity; every one of the M functions is such a MinHash.
+    rng = np.random.default_rng(7)
+    x, y = _jaccard_pairs(rng, 1 << 20, 24, 8)  # J = 24 / 40 = 0.6
+    hits = tot = 0
+    for seed in range(200):
+        p = oracle.Params(dim=1 << 20, K=4, L=8, log2_buckets=16, hash_mode=2, seed=seed)
+        _, hv = oracle.hash_rows(p, oracle.constants(p), *csr([x, y]), with_h=True)
+        hits += int((hv[0] == hv[1]).sum())
+        tot += p.M
+    assert abs(hits / tot - 0.6) < 0.03, hits / tot
+
+
+def test_classic_minhash_functions_are_row_minima():
+    # each value is the minimum over the row of what the row's single
+    # elements hash to under the same function
+    p = oracle.Params(dim=5000, K=3, L=2, log2_buckets=20, hash_mode=2, seed=13)
+    cs = oracle.constants(p)
+    rng = np.random.default_rng(8)
+    rows = _rand_rows(rng, 30, p.dim)
+    singles = sorted({v for r in rows for v in r})
+    _, hs = oracle.hash_rows(p, cs, *csr([[v] for v in singles]), with_h=True)
+    u = {v: hs[i] for i, v in enumerate(singles)}
+    _, hv = oracle.hash_rows(p, cs, *csr(rows), with_h=True)
+    for r, vals in zip(rows, hv):
+        assert vals.tolist() == np.min(np.stack([u[i] for i in r]), axis=0).tolist()
+
+
+def test_classic_minhash_single_function_is_one_bin_doph():
+    # with K = L = 1 both families hash with the same first constant pair and
+    # keep the row minimum, so they agree
+    rng = np.random.default_rng(9)
+    rows = _rand_rows(rng, 50, 1 << 20)
+    out = []
+    for mode in (0, 2):
+        p = oracle.Params(dim=1 << 20, K=1, L=1, log2_buckets=12, hash_mode=mode, seed=17)
+        out.append(oracle.hash_rows(p, oracle.constants(p), *csr(rows)))
+    assert (out[0] == out[1]).all()
 
 
 def _rand_rows(rng, n, dim, lo=1, hi=60):
@@ -132,7 +191,7 @@ def test_doph_is_min_over_elements_bin_by_bin():
         assert hv[0, b] == min(members)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_hash_invariant_to_order_and_duplicates(mode):
     p = oracle.Params(dim=1 << 20, K=4, L=8, log2_buckets=16, hash_mode=mode, seed=3)
     cs = oracle.constants(p)
@@ -259,7 +318,7 @@ def _data(n, seed=9, dim=1 << 20):
     return law, law.rows(0, n)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_build_matches_brute_force(mode):
     p = oracle.Params(dim=1 << 20, K=2, L=4, log2_buckets=5, R=6, hash_mode=mode, seed=21)
     cs = oracle.constants(p)
