@@ -198,6 +198,27 @@ SLASH_API slash_status slash_query_batched(const slash_index* index, slash_csr q
                                  uint32_t k, uint32_t flags, uint32_t* ids_dev, uint32_t* scores_dev,
                                  const slash_schedule* sched, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results as slash_query_batched (bit-exact), with the same arguments, but
+ * the call allocates nothing.  Its kernels (row-parallel hash, then the
+ * query kernel in the schedule's form, launched directly rather than
+ * through a HIP graph) keep the batch's bucket ids and work counter in a
+ * statically sized device array of the library, 16 MiB per GPU (a work
+ * counter in a 256-byte head, then n_rows * L bucket ids), which each GPU
+ * the library runs on holds until the process ends.  A batch needing more
+ * (n_rows * L > 4,194,240) is refused with E_INVAL before anything is
+ * launched.  Every call on one GPU shares that GPU's array and keeps the
+ * last call's contents (the counter is cleared by each call with a fill
+ * kernel): calls that overlap on one GPU race, so issue them on one stream
+ * or otherwise order them.  Topkapi-bucket indexes use no scratch.  The
+ * caller still provides every input and output buffer.  Other errors as
+ * slash_query_batched. */
+SLASH_API slash_status slash_query_batched_static(const slash_index* index, slash_csr queries,
+                                                  const uint32_t* k_per_query_dev, uint32_t k, uint32_t flags,
+                                                  uint32_t* ids_dev, uint32_t* scores_dev,
+                                                  const slash_schedule* sched, void* stream);
+
 /* Time every candidate schedule on `sample` (device CSR of representative
  * queries, k as given) and keep the fastest per query-size class for
  * slash_query_batched.  Candidates that disagree with slash_query are

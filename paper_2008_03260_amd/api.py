@@ -98,6 +98,7 @@ def lib() -> C.CDLL:
             "slash_insert": ([vp, CSR, u32, vp, vp], st),
             "slash_query": ([vp, CSR, vp, u32, u32, vp, vp, vp], st),
             "slash_query_batched": ([vp, CSR, vp, u32, u32, vp, vp, P(Schedule), vp], st),
+            "slash_query_batched_static": ([vp, CSR, vp, u32, u32, vp, vp, P(Schedule), vp], st),
             "slash_autotune": ([vp, CSR, u32, P(Schedule), vp], st),
             "slash_hash": ([vp, CSR, u32, vp, vp], st),
             "slash_export_tables": ([vp, vp, vp, vp], st),
@@ -204,6 +205,20 @@ def slash_query_batched(index, indptr, indices, k: int, k_per_query=None, flags:
         sch = C.byref(Schedule(*[int(schedule.get(f, 0)) for f, _ in Schedule._fields_]))
     _check(lib().slash_query_batched(index, c, _ptr(k_per_query), k, flags, _ptr(oi), _ptr(osc), sch,
                                      _stream(stream)), "slash_query_batched")
+    return oi, osc
+
+
+def slash_query_batched_static(index, indptr, indices, k: int, k_per_query=None, flags: int = 0, schedule=None,
+                               out_ids=None, out_scores=None, stream=None):
+    """slash_query_batched without any device allocation by the library
+    (its scratch is a static device array; see include/slash.h)."""
+    c, keep = csr(indptr, indices)
+    oi, osc = _outputs(index, c.n_rows, out_ids, out_scores)
+    sch = None
+    if schedule is not None:
+        sch = C.byref(Schedule(*[int(schedule.get(f, 0)) for f, _ in Schedule._fields_]))
+    _check(lib().slash_query_batched_static(index, c, _ptr(k_per_query), k, flags, _ptr(oi), _ptr(osc), sch,
+                                            _stream(stream)), "slash_query_batched_static")
     return oi, osc
 
 

@@ -800,20 +800,11 @@ static slash_status run_batched(slash_index* ix, const QueryArgs& a0, const slas
   return SLASH_OK;
 }
 
-extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q, const uint32_t* kq, uint32_t k,
-                                            uint32_t flags, uint32_t* ids, uint32_t* scores,
-                                            const slash_schedule* sched, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  slash_status rs = query_prelude(cix, q, kq, k, flags, ids, scores, st);
-  if (rs != SLASH_OK) return rs;
-  if (q.n_rows == 0) return SLASH_OK;
-  slash_index* ix = const_cast<slash_index*>(cix);
-  if (ix->shape.bucket) {
-    // Topkapi buckets: one wave per query, hashing in the kernel
-    QueryArgs ta{q, kq, k, 1, ids, scores, nullptr};
-    HIP_TRY(launch_tk_query(ix->shape, ix->cv, tables(ix), ta, st));
-    return SLASH_OK;
-  }
+// Schedule of a batched call: the caller's, else the tuned one (several
+// tuned size classes: the batch's mean row size picks the nearest), else the
+// default.
+static slash_status batched_schedule(const slash_index* ix, slash_csr q, const slash_schedule* sched, hipStream_t st,
+                                     slash_schedule* out) {
   slash_schedule sc = default_schedule(ix);
   if (sched) {
     sc = *sched;
@@ -840,9 +831,112 @@ extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q,
       sc = ix->tuned[best];
     }
   }
+  *out = sc;
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_query_batched(const slash_index* cix, slash_csr q, const uint32_t* kq, uint32_t k,
+                                            uint32_t flags, uint32_t* ids, uint32_t* scores,
+                                            const slash_schedule* sched, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  slash_status rs = query_prelude(cix, q, kq, k, flags, ids, scores, st);
+  if (rs != SLASH_OK) return rs;
+  if (q.n_rows == 0) return SLASH_OK;
+  slash_index* ix = const_cast<slash_index*>(cix);
+  if (ix->shape.bucket) {
+    // Topkapi buckets: one wave per query, hashing in the kernel
+    QueryArgs ta{q, kq, k, 1, ids, scores, nullptr};
+    HIP_TRY(launch_tk_query(ix->shape, ix->cv, tables(ix), ta, st));
+    return SLASH_OK;
+  }
+  slash_schedule sc;
+  if ((rs = batched_schedule(ix, q, sched, st, &sc)) != SLASH_OK) return rs;
   QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
   a.exact = (flags & SLASH_FLAG_EXACT) ? 1u : 0u;
   return run_batched(ix, a, sc, st);
+}
+
+// ------------------------------------------------ allocation-free batched
+
+// Scratch of slash_query_batched_static: a work counter (word 0, padded to
+// 256 bytes) and the batch's bucket ids [n][L].  One copy per device, held
+// until the process ends.  Host code never uses this name as an address
+// (on the host it stands for the symbol, not device memory): the device
+// address comes from hipGetSymbolAddress, once per device.
+static constexpr size_t kStaticScratchWords = size_t(4) << 20;  // 16 MiB
+static constexpr uint32_t kStaticTicketWords = 64;
+static __device__ __align__(256) uint32_t scratch[kStaticScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+uint32_t* g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current device's scratch array (set up on the first
+// call on that device, with that device current).
+static slash_status static_scratch(uint32_t** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SLASH_E_UNSUPPORTED, "device %d beyond the static scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(SLASH_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_static_ptr[dev] = (uint32_t*)p;
+  }
+  *out = g_static_ptr[dev];
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_query_batched_static(const slash_index* cix, slash_csr q, const uint32_t* kq, uint32_t k,
+                                                   uint32_t flags, uint32_t* ids, uint32_t* scores,
+                                                   const slash_schedule* sched, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  slash_status rs = query_prelude(cix, q, kq, k, flags, ids, scores, st);
+  if (rs != SLASH_OK) return rs;
+  if (q.n_rows == 0) return SLASH_OK;
+  QueryArgs a{q, kq, k, 1, ids, scores, nullptr};
+  a.exact = (flags & SLASH_FLAG_EXACT) ? 1u : 0u;
+  const Shape& s = cix->shape;
+  if (s.bucket) {
+    // Topkapi buckets hash inside their query kernel: no scratch
+    HIP_TRY(launch_tk_query(s, cix->cv, tables(cix), a, st));
+    return SLASH_OK;
+  }
+  const uint64_t need = kStaticTicketWords + q.n_rows * (uint64_t)s.L;
+  if (need > kStaticScratchWords)
+    return fail(SLASH_E_INVAL, "batch of %llu queries needs %llu scratch words; the static scratch holds %llu "
+                               "(at most %llu queries of %u tables)",
+                (unsigned long long)q.n_rows, (unsigned long long)need, (unsigned long long)kStaticScratchWords,
+                (unsigned long long)((kStaticScratchWords - kStaticTicketWords) / s.L), s.L);
+  slash_schedule sc;
+  if ((rs = batched_schedule(cix, q, sched, st, &sc)) != SLASH_OK) return rs;
+  const uint32_t waves = sc.waves_per_query;
+  if (!query_supported(s, waves, a.exact != 0))
+    return fail(SLASH_E_UNSUPPORTED, "schedule with %u waves/query not supported", waves);
+  uint32_t* sp = nullptr;
+  if ((rs = static_scratch(&sp)) != SLASH_OK) return rs;
+  uint32_t* ticket = sp;
+  a.qbk = sp + kStaticTicketWords;
+  HIP_TRY(launch_hash_rowmajor(s, cix->cv, q, sp + kStaticTicketWords, st));
+  if (sc.queries_per_ticket == 0) {
+    HIP_TRY(launch_query_waves(s, cix->cv, tables(cix), a, waves, st));
+    return SLASH_OK;
+  }
+  int occ = 0;
+  HIP_TRY(query_occupancy(s, waves, &occ, a.exact != 0));
+  if (occ < 1) occ = 1;
+  const uint32_t per_ticket = sc.queries_per_ticket;
+  const uint32_t per_cu = sc.groups_per_cu ? std::min<uint32_t>(sc.groups_per_cu, (uint32_t)occ) : (uint32_t)occ;
+  uint64_t grid = (uint64_t)per_cu * (uint32_t)cix->n_cu;
+  grid = std::min<uint64_t>(grid, (q.n_rows + per_ticket - 1) / per_ticket);
+  // the work counter starts at zero (a fill kernel, not a memset)
+  HIP_TRY(launch_fill_u32(ticket, 0u, 1, st));
+  HIP_TRY(launch_query_persistent(s, cix->cv, tables(cix), a, waves, per_ticket, (uint32_t)std::max<uint64_t>(1, grid),
+                                  ticket, st));
+  return SLASH_OK;
 }
 
 extern "C" slash_status slash_autotune(slash_index* ix, slash_csr sample, uint32_t k, slash_schedule* best_out,
