@@ -43,11 +43,23 @@ WIDE_MIX = dict(nnz_mode="lognormal", median=500, sigma=0.8, lo=50, hi=20000, f=
 WORKLOADS = {
     # tiny: N = 1e5, K=4, L=16, 2^16 buckets, R=32, count-min 4 x 1024, k = 10
     "c0": dict(n=100_000, dim=1 << 20, K=4, L=16, B=16, R=32, d=4, lw=10, k=10, nq=1000, master=2020, tk=(4, 3),
-               law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=100_000,
+               law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=100_000, cpu_B=16,
+               # brute-force Jaccard top-10 of each query (set recall) is cheap at this size
+               set_recall=True,
+               recall_ops=((8, 16, 16, 64, 10), (10, 16, 32, 64, 12)),
                desc="tiny: N=1e5, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=16 B=16 R=32; CM 4x1024; k=10; 1000 queries f=0.2"),
     # one node's 200M-point shard
     "c1": dict(n=200_000_000, dim=1 << 20, K=4, L=32, B=20, R=64, d=4, lw=12, k=10, nq=100_000, master=2021, tk=(4, 4),
-               law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000, cpu_rows=1_000_000,
+               law=C1_LAW, q=C1_Q, mix=C1_MIX, max_nnz=2000,
+               # the oracle's sample: a 1M-row prefix with 2^12 buckets per table,
+               # so that buckets hold about as many ids as the shard's (244 vs
+               # 191) and a query aggregates about the same number of candidates
+               cpu_rows=1_000_000, cpu_B=12,
+               # (K, B, L, R, log2 count-min width) tried in order for the
+               # smallest index of the shard with recall@10 >= 0.9
+               # (K = 8 and 16 keep M = K * L a shape the hash kernel's register
+               # form covers)
+               recall_ops=((8, 20, 64, 128, 14), (16, 20, 64, 128, 14), (8, 20, 64, 256, 14)),
                # (L, R, log2 count-min width) of the --recall-sweep indexes
                recall_points=((32, 64, 12), (32, 128, 12), (32, 256, 14), (64, 128, 14), (64, 256, 14), (128, 128, 14)),
                desc="200M-point shard: N=2e8, D=2^20, nnz~Poisson(40), Zipf(1.1); K=4 L=32 B=20 R=64; CM 4x4096; "
@@ -55,7 +67,7 @@ WORKLOADS = {
     # denser, wider shard under serving
     "c4": dict(n=20_000_000, dim=1 << 24, K=8, L=128, B=18, R=128, d=8, lw=14, k=100, nq=10_000, master=2024, tk=(8, 4),
                law=WIDE_LAW, q=dict(nnz_mode="lognormal", median=500, sigma=0.8, lo=50, hi=20000, f=(0.1, 0.4)),
-               mix=WIDE_MIX, max_nnz=20000, max_insert_nnz=8_000_000, cpu_rows=100_000, mix_n=100_000,
+               mix=WIDE_MIX, max_nnz=20000, max_insert_nnz=8_000_000, cpu_rows=100_000, cpu_B=14, mix_n=100_000,
                serve_rates=(1e3, 3e3, 1e4, 3e4), serve_seconds=1.0,
                desc="wide shard: N=2e7, D=2^24, nnz~lognormal(median 500, sigma 0.8) in [50, 20000], uniform "
                     "indices; K=8 L=128 B=18 R=128; CM 8x16384; k=100; 10k queries f~U[0.1,0.4]"),
@@ -64,32 +76,56 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 
 
-# Which kernel each build phase is, its source file, and its row in the
-# committed counter summary (traffic is reported only while the kernel's
-# source is the one the counters were taken on).
+# Which kernel each build phase is and its source file; the committed counter
+# summary holds scaled FETCH_SIZE + WRITE_SIZE bytes per dispatch of each
+# kernel, reported only while the kernel's source is the one the counters
+# were taken on.
 PHASE_KERNEL = {"sort_downsweep": ("k_downsweep", "sort.hip"), "sort_upsweep": ("k_upsweep", "sort.hip"),
-                "hash": ("k_hash_rows", "hash.hip"), "select": ("k_select_light", "select.hip"),
-                "segment_bounds": ("k_segment_bounds", "hash.hip")}
+                "sort_scan": ("k_scan", "sort.hip"), "hash": ("k_hash_rows", "hash.hip"),
+                "select": ("k_select_light", "select.hip"), "segment_bounds": ("k_segment_bounds", "hash.hip"),
+                "heavy": ("k_select_chunks", "select.hip"), "validate": ("k_validate_rows", "hash.hip")}
+COUNTERS = os.path.join(ROOT, "profiles", "c1_hbm_counters.md")
 
 
-def counted_traffic(phase):
-    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the phase's kernel,
-    from profiles/c1_hbm_counters.md, or None if absent or stale."""
+def _counter_rows(path=COUNTERS):
+    """{kernel: (dispatches, traffic GB per dispatch)} of the counter summary,
+    keeping only kernels whose source hash still matches."""
     import hashlib
     import re
-    if phase not in PHASE_KERNEL:
-        return None
-    kern, src = PHASE_KERNEL[phase]
-    path = os.path.join(ROOT, "profiles", "c1_hbm_counters.md")
     if not os.path.exists(path):
-        return None
+        return {}
     txt = open(path).read()
-    m = re.search(r"csrc/%s sha256 ([0-9a-f]{64})" % re.escape(src), txt)
-    cur = hashlib.sha256(open(os.path.join(ROOT, "paper_2008_03260_amd", "csrc", src), "rb").read()).hexdigest()
-    if not m or m.group(1) != cur:
-        return None
-    row = re.search(r"^\| %s \| (\d+) \| ([\d.]+) \| ([\d.]+) \| ([\d.]+) \|" % re.escape(kern), txt, flags=re.M)
-    return float(row.group(4)) * 1e9 if row else None
+    fresh = {}
+    for src in set(v[1] for v in PHASE_KERNEL.values()) | {"query.hip"}:
+        m = re.search(r"csrc/%s sha256 ([0-9a-f]{64})" % re.escape(src), txt)
+        f = os.path.join(ROOT, "paper_2008_03260_amd", "csrc", src)
+        fresh[src] = bool(m) and m.group(1) == hashlib.sha256(open(f, "rb").read()).hexdigest()
+    rows = {}
+    for m in re.finditer(r"^\| (k_[\w<>, ]+?) \| (\d+) \| ([\d.]+) \| ([\d.]+) \| ([\d.]+) \|", txt, flags=re.M):
+        rows[m.group(1).split("<")[0].strip()] = (int(m.group(2)), float(m.group(5)))
+    src_of = {k: v[1] for k, v in PHASE_KERNEL.values()}
+    src_of["k_query"] = "query.hip"
+    return {k: v for k, v in rows.items() if fresh.get(src_of.get(k, ""), False)}
+
+
+def counted_traffic(kernel):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per dispatch of `kernel`, or None."""
+    r = _counter_rows().get(kernel)
+    return r[1] * 1e9 if r else None
+
+
+def counted_build_traffic(prof):
+    """Counted bytes of one whole build (every build kernel's bytes per
+    dispatch times its dispatches in this build), or None if any is missing."""
+    tot = 0.0
+    for ph, v in prof.items():
+        if not v["launches"] or ph not in PHASE_KERNEL:
+            continue
+        t = counted_traffic(PHASE_KERNEL[ph][0])
+        if t is None:
+            return None
+        tot += t * v["launches"]
+    return tot
 
 
 def log(msg):
@@ -98,38 +134,142 @@ def log(msg):
 
 def cpu_baseline(w, law, seeds, budget_s=20.0):
     """The plain CPU oracle, single-threaded, on a bounded sample of the same
-    workload: a prefix of the rows and a slice of the queries."""
+    workload: the first cpu_rows rows, indexed with 2^cpu_B buckets per table
+    (same K, L, R and count-min) so that a bucket holds about as many ids as
+    the full shard's and a query aggregates about as many candidates; then as
+    many distinct planted queries as the time budget allows."""
     import oracle
-    import synth
 
     n_rows = min(w["n"], w["cpu_rows"])
-    op = oracle.Params(dim=w["dim"], K=w["K"], L=w["L"], log2_buckets=w["B"], R=w["R"], cm_rows=w["d"],
+    op = oracle.Params(dim=w["dim"], K=w["K"], L=w["L"], log2_buckets=w["cpu_B"], R=w["R"], cm_rows=w["d"],
                        log2_cm_width=w["lw"], seed=seeds["index"])
     cs = oracle.constants(op)
     ip, ix = law.rows(0, n_rows)
     t0 = time.perf_counter()
     ids, seen = oracle.build(op, cs, ip, ix)
     t_build = time.perf_counter() - t0
-    nq = 200
+    nq = 20000
     qi, qx, _, _ = law.queries(seeds["query"], n_rows, 0, nq, **w["q"])
+    # candidates per query (the slots a query aggregates) on this index
+    bk = oracle.hash_rows(op, cs, qi[:1001], qx[: qi[1000]])
+    cand = float(np.mean(np.minimum(seen[np.arange(op.L)[None, :], bk], op.R).sum(axis=1)))
     t0 = time.perf_counter()
-    done = 0
-    while time.perf_counter() - t0 < max(1.0, budget_s - t_build) and done < 20 * nq:
-        oracle.query(op, cs, ids, seen, qi, qx, w["k"])
-        done += nq
+    done, chunk = 0, 250
+    while done + chunk <= nq and (done == 0 or time.perf_counter() - t0 < max(1.0, budget_s - t_build)):
+        sub_i = qi[done: done + chunk + 1] - qi[done]
+        sub_x = qx[qi[done]: qi[done + chunk]]
+        oracle.query(op, cs, ids, seen, sub_i, sub_x, w["k"])
+        done += chunk
     t_q = time.perf_counter() - t0
+    load = n_rows / (1 << w["cpu_B"])
     out = {
         "value": done / t_q, "unit": "queries/s", "cores": 1, "kind": "oracle",
-        "sample": f"oracle (single-threaded C, -O2) on the first {n_rows:,} rows of the same workload "
-                  f"(same K, L, B, R, count-min); {done} queries answered; build {n_rows / t_build:,.0f} rows/s",
-        "build_rows_per_s": n_rows / t_build,
+        "sample": f"oracle (single-threaded C, -O2) on the first {n_rows:,} rows of the same workload, "
+                  f"indexed with 2^{w['cpu_B']} buckets per table (same K, L, R, count-min; {load:.0f} ids per "
+                  f"bucket on average vs {w['n'] / (1 << w['B']):.0f} on the full shard); {done} distinct planted "
+                  f"queries, each answered once, {cand:.0f} candidates per query; build {n_rows / t_build:,.0f} rows/s",
+        "build_rows_per_s": n_rows / t_build, "candidates_per_query": cand,
         "nproc": os.cpu_count(), "cpu_model": cpu_model(),
     }
     try:
-        out["all_cores"] = cpu_parallel(op, cs, ids, seen, ip, ix, qi, qx, w["k"], done / t_q)
+        out["all_cores"] = cpu_parallel(op, cs, ids, seen, ip, ix, qi[: done + 1], qx[: qi[done]], w["k"], done / t_q)
     except Exception as e:  # a host without fork or with too little memory: report why
         out["all_cores"] = {"error": str(e)}
     return out
+
+
+# ------------------------------------------------------------ quality metrics
+# Measurement helpers (not the method): Jaccard and cosine of binary rows as
+# sets, Section 2.2 and the S@k of Section 6.
+
+
+def row_sets(fetch, ids):
+    """{id: sorted unique feature array} for the given ids; fetch(ids) returns
+    (indptr, indices) of those rows in order."""
+    u = np.unique(np.asarray(ids, dtype=np.int64))
+    if len(u) == 0:
+        return {}
+    ptr, idx = fetch(u)
+    return {int(r): np.unique(idx[ptr[i]:ptr[i + 1]]) for i, r in enumerate(u.tolist())}
+
+
+def device_fetch(ip_dev, ix_dev):
+    """fetch(ids) over a device CSR (torch tensors): gathers the rows on the
+    device and copies them to the host."""
+    import torch
+
+    def fetch(u):
+        ids = torch.from_numpy(u).to(ip_dev.device)
+        beg, end = ip_dev[ids], ip_dev[ids + 1]
+        lens = end - beg
+        ptr = torch.zeros(len(u) + 1, dtype=torch.int64, device=ip_dev.device)
+        torch.cumsum(lens, 0, out=ptr[1:])
+        pos = torch.arange(int(ptr[-1].item()), device=ip_dev.device)
+        row = torch.repeat_interleave(torch.arange(len(u), device=ip_dev.device), lens)
+        src = beg[row] + (pos - ptr[row])
+        return ptr.cpu().numpy(), ix_dev[src].cpu().numpy()
+    return fetch
+
+
+def host_fetch(ip, ix):
+    def fetch(u):
+        lens = ip[u + 1] - ip[u]
+        ptr = np.zeros(len(u) + 1, dtype=np.int64)
+        np.cumsum(lens, out=ptr[1:])
+        idx = np.concatenate([ix[ip[r]:ip[r + 1]] for r in u.tolist()]) if len(u) else np.zeros(0, np.int32)
+        return ptr, idx
+    return fetch
+
+
+def s_at_k(fetch, qi, qx, ids, k):
+    """S@k (Section 6): mean over queries of the mean cosine similarity
+    |x & q| / sqrt(|x| |q|) of its first k returned ids (EMPTY skipped; a
+    query with none counts 0)."""
+    ids = np.asarray(ids, dtype=np.uint32)[:, :k]
+    live = ids != 0xFFFFFFFF
+    sets = row_sets(fetch, ids[live])
+    vals = np.zeros(len(ids))
+    for q in range(len(ids)):
+        qs = np.unique(qx[qi[q]:qi[q + 1]])
+        cs = [np.intersect1d(qs, sets[int(r)], assume_unique=True).size / np.sqrt(len(qs) * len(sets[int(r)]))
+              for r in ids[q][live[q]].tolist()]
+        vals[q] = float(np.mean(cs)) if cs else 0.0
+    return float(np.mean(vals))
+
+
+def jaccard_top(ip, ix, qi, qx, k):
+    """Brute-force Jaccard top-k row ids per query (ties by ascending id),
+    over host CSR rows with distinct indices per row."""
+    import scipy.sparse as sp
+    n, nq = len(ip) - 1, len(qi) - 1
+    dim = int(max(ix.max(initial=0), qx.max(initial=0))) + 1
+    X = sp.csr_matrix((np.ones(len(ix), np.float64), ix, ip), shape=(n, dim))
+    X.sum_duplicates()
+    X.data[:] = 1.0
+    Q = sp.csr_matrix((np.ones(len(qx), np.float64), qx, qi), shape=(nq, dim))
+    Q.sum_duplicates()
+    Q.data[:] = 1.0
+    xs = np.asarray(X.sum(axis=1)).ravel()
+    qs = np.asarray(Q.sum(axis=1)).ravel()
+    inter = (Q @ X.T).tocsr()
+    out = np.zeros((nq, k), dtype=np.int64)
+    for q in range(nq):
+        a, b = inter.indptr[q], inter.indptr[q + 1]
+        cols, iv = inter.indices[a:b], inter.data[a:b]
+        jac = iv / (qs[q] + xs[cols] - iv)
+        order = np.lexsort((cols, -jac))[:k]
+        top = cols[order].tolist()
+        if len(top) < k:  # similarity 0: the smallest ids not already taken
+            taken = set(top)
+            top += [r for r in range(n) if r not in taken][: k - len(top)]
+        out[q] = top
+    return out
+
+
+def set_recall(returned, truth):
+    """Mean over queries of |returned top-k & true top-k| / k."""
+    k = truth.shape[1]
+    return float(np.mean([len(set(r[:k].tolist()) & set(t.tolist())) / k for r, t in zip(returned, truth)]))
 
 
 def cpu_model() -> str:
@@ -179,6 +319,105 @@ def cpu_parallel(op, cs, ids, seen, ip, ix, qi, qx, k, single_qps, max_procs=16)
     return {"value": sum(r[0] for r in res) / wall, "unit": "queries/s", "cores": procs,
             "sample": f"{procs} processes, {sum(r[0] for r in res)} queries over disjoint slices against the "
                       f"shared index of the first {n:,} rows"}
+
+
+def quality(api, h, qi, qx, qi_h, qx_h, fetch, n_sample, stream):
+    """S@1 and S@64 (Section 6) of the first n_sample planted queries, ranked
+    by the count-min estimate and by exact counting (Section 6.2)."""
+    n = min(n_sample, len(qi_h) - 1)
+    sip, six = qi[: n + 1], qx[: int(qi_h[n])]
+    out = {}
+    for name, fl in (("count_min", 0), ("exact", api.FLAG_EXACT)):
+        oi, _ = api.slash_query_batched(h, sip, six, 64, flags=api.FLAG_TRUSTED | fl, stream=stream)
+        ids = api.as_u32(oi)
+        out[name] = {"s_at_1": s_at_k(fetch, qi_h[: n + 1], qx_h, ids, 1),
+                     "s_at_64": s_at_k(fetch, qi_h[: n + 1], qx_h, ids, 64)}
+    out["queries"] = n
+    return out
+
+
+def recall_operating_point(api, w, ip, ix, ins_ip, ins_ix, qi, qx, qi_h, qx_h, src, seeds, fetch, stream, ev):
+    """The first index setting of w["recall_ops"] (K, B, L, R, log2 count-min
+    width; on the same rows and planted queries) whose count-min recall@10
+    reaches 0.9: its build (warm: the second build of the setting, scratch
+    reused), a 4096-row insert, the batched queries (autotuned; the first
+    batch after the build and insert, then the best of three warm batches),
+    one-at-a-time latency, exact-counting recall and S@k."""
+    import torch
+    tried = []
+    nq = len(qi_h) - 1
+    for (K, B, L, R, lw) in w["recall_ops"]:
+        p = api.Params.of(dim=w["dim"], K=K, L=L, log2_buckets=B, R=R, cm_rows=w["d"], log2_cm_width=lw, k_max=100,
+                          hash_mode=0, seed=seeds["index"])
+        api.slash_release_cache()
+        # the first build allocates (the timed build reuses its blocks) and is
+        # where the schedule is tuned, as for the headline configuration
+        h = api.slash_build(p, ip, ix, stream)
+        ns = min(20000, nq)
+        sched = api.slash_autotune(h, qi[: ns + 1], qx[: int(qi_h[ns])], w["k"], stream)
+        api.slash_free(h)
+        e = [ev() for _ in range(3)]
+        e[0].record(stream)
+        h = api.slash_build(p, ip, ix, stream)
+        e[1].record(stream)
+        api.slash_insert(h, ins_ip, ins_ix, api.FLAG_TRUSTED, None, stream)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        build_ms, ins_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+        prof = api.slash_build_profile(h)
+        tq = []
+        oi, osc = None, None
+        for rep in range(4):
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            oi, osc = api.slash_query_batched(h, qi, qx, w["k"], flags=api.FLAG_TRUSTED, schedule=sched, out_ids=oi,
+                                              out_scores=osc, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tq.append(e0.elapsed_time(e1))
+        got = api.as_u32(oi)[:, : w["k"]]
+        rec = float(np.mean([s_ in row for s_, row in zip(src.tolist(), got.tolist())]))
+        ex, _ = api.slash_query_batched(h, qi, qx, w["k"], flags=api.FLAG_TRUSTED | api.FLAG_EXACT, schedule=sched,
+                                        stream=stream)
+        ex_rec = float(np.mean([s_ in row for s_, row in zip(src.tolist(), api.as_u32(ex)[:, : w["k"]].tolist())]))
+        pt = {"K": K, "log2_buckets": B, "L": L, "R": R, "count_min": f"{w['d']} x {1 << lw}", "slots": L * R,
+              "recall_at_10": rec, "exact_recall_at_10": ex_rec,
+              "batched_queries_per_s": nq / (tq[0] / 1e3), "warm_batched_queries_per_s": nq / (min(tq[1:]) / 1e3),
+              "schedule": sched, "build_ms": build_ms,
+              "build_kernel_ms": sum(v["total_ms"] for v in prof.values()),
+              "build_inserts_per_s": w["n"] / (build_ms / 1e3), "insert_4096_ms": ins_ms,
+              "table_bytes": L * (1 << B) * (R + 1) * 4}
+        log(f"operating point K={K} B={B} L={L} R={R} cm {pt['count_min']}: recall@10 {rec:.4f} "
+            f"(exact {ex_rec:.4f}), {pt['batched_queries_per_s']:,.0f} q/s, build {build_ms:.1f} ms")
+        if rec < 0.9:
+            api.slash_free(h)
+            tried.append(pt)
+            continue
+        # one-at-a-time latency of the plain path (host-synchronised)
+        npl = min(2000, nq)
+        lat = np.empty(npl)
+        out_i = torch.empty((1, 100), dtype=torch.int32, device=qi.device)
+        out_s = torch.empty((1, 100), dtype=torch.int32, device=qi.device)
+        for i in range(min(100, npl)):
+            api.slash_query(h, qi[i:i + 2] - qi[i], qx[int(qi_h[i]):int(qi_h[i + 1])], w["k"], flags=api.FLAG_TRUSTED,
+                            out_ids=out_i, out_scores=out_s)
+        torch.cuda.synchronize()
+        for i in range(npl):
+            t = time.perf_counter()
+            api.slash_query(h, qi[i:i + 2] - qi[i], qx[int(qi_h[i]):int(qi_h[i + 1])], w["k"], flags=api.FLAG_TRUSTED,
+                            out_ids=out_i, out_scores=out_s)
+            torch.cuda.synchronize()
+            lat[i] = time.perf_counter() - t
+        pt["p50_latency_us"] = float(np.percentile(lat, 50) * 1e6)
+        pt["p99_latency_us"] = float(np.percentile(lat, 99) * 1e6)
+        pt["quality"] = quality(api, h, qi, qx, qi_h, qx_h, fetch, 2000, stream)
+        pt["build_phases"] = {k: {"launches": v["launches"], "total_ms": v["total_ms"]} for k, v in prof.items()}
+        pt["tried"] = tried
+        api.slash_free(h)
+        api.slash_release_cache()
+        return pt
+    api.slash_release_cache()
+    return {"found": False, "tried": tried}
 
 
 def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4, 1e5, 3e5, 1e6, 2e6)):
@@ -251,6 +490,8 @@ def main():
                     help="arrival window per serving rate (default: the workload's, 10 s for the 200M shard; "
                          "a point is capped at 400k requests)")
     ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
+    ap.add_argument("--no-operating-point", action="store_true",
+                    help="skip the search for the smallest index setting with recall@10 >= 0.9")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -324,6 +565,7 @@ def main():
     qps = w["nq"] * len(rec) / (q_ms.sum() / 1e3)
     got = api.as_u32(oi)[:, : w["k"]]
     recall = float(np.mean([s in row for s, row in zip(src.tolist(), got.tolist())]))
+    prof_timed = api.slash_build_profile(h)
     log(f"build {b_ms.mean():.1f} ms, insert(4096) {i_ms.mean():.2f} ms, batched query {q_ms.mean():.2f} ms, "
         f"recall@10 {recall:.4f}")
 
@@ -346,6 +588,25 @@ def main():
     log(f"exact counting: {exact['batched_queries_per_s']:,.0f} q/s, recall@10 {exact['recall_at_10']:.4f} "
         f"(count-min: {qps:,.0f} q/s, recall@10 {recall:.4f})")
     del ex_i, ex_s
+
+    # quality of the answers (Section 6): S@1 and S@64 with the sketch and
+    # with exact counting, on a sample of the planted queries; ids past the
+    # shard's rows are the inserted batch's
+    main_fetch, ins_fetch = device_fetch(ip, ix), device_fetch(ins_ip, ins_ix)
+
+    def fetch(u):
+        lo, hi = u[u < w["n"]], u[u >= w["n"]] - w["n"]
+        p1, x1 = main_fetch(lo) if len(lo) else (np.zeros(1, np.int64), np.zeros(0, np.int32))
+        p2, x2 = ins_fetch(hi) if len(hi) else (np.zeros(1, np.int64), np.zeros(0, np.int32))
+        return np.concatenate([p1, p2[1:] + p1[-1]]), np.concatenate([x1, x2])
+    qual = quality(api, h, qi, qx, qi_h, qx_h, fetch, 2000, stream)
+    if w.get("set_recall"):
+        # brute-force Jaccard top-10 over every row of the index (the shard
+        # and the inserted batch) against the returned top-10
+        hip, hix = law.rows(0, w["n"] + 4096)
+        truth = jaccard_top(hip, hix, qi_h, qx_h, 10)
+        qual["set_recall_at_10"] = {"count_min": set_recall(got, truth), "exact": set_recall(ex_got, truth)}
+    log(f"quality: {qual}")
 
     # one-at-a-time plain path: per-query latency, host-synchronised
     npl = min(args.plain_queries, w["nq"])
@@ -410,17 +671,34 @@ def main():
         serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, secs, seeds,
                             **({"rates": w["serve_rates"]} if "serve_rates" in w else {}))
 
+    # the smallest index setting of the same shard with recall@10 >= 0.9
+    op_point = None
+    if w.get("recall_ops") and not args.no_operating_point:
+        api.slash_free(h)
+        h = None
+        op_point = recall_operating_point(api, w, ip, ix, ins_ip, ins_ix, qi, qx, qi_h, qx_h, src, seeds, fetch,
+                                          stream, ev)
+
+    if h is not None:
+        api.slash_free(h)
+        h = None
+
     # query kernel: algorithmic bytes per query = the query row 4*nnz + 8,
     # per table the reservoir row 4*R (read whole, EMPTY-padded), output 8*k
     alg_q = 4 * (int(qi_h[-1])) + 8 * w["nq"] + w["nq"] * w["L"] * 4 * w["R"] + w["nq"] * 8 * w["k"]
     q_gbs = alg_q / (q_ms.mean() / 1e3) / 1e9
-    build_alg = 4 * nnz + 8 * w["n"] + w["L"] * (1 << w["B"]) * (4 * w["R"] + 4)
+    # the build's algorithmic bytes: read the CSR once (4 B per nonzero, 8 B
+    # per row bound), write the tables once (L * 2^B buckets of R ids and a
+    # seen count)
+    build_alg = 4 * nnz + 8 * (w["n"] + 1) + w["L"] * (1 << w["B"]) * (4 * w["R"] + 4)
     # build phases, timed by the library with HIP events on the build stream
-    prof = api.slash_build_profile(h)
-    api.slash_free(h)
+    prof = prof_timed
+    build_kernel_ms = sum(v["total_ms"] for v in prof.values())
+    build_gbs = build_alg / (build_kernel_ms / 1e3) / 1e9
     dom = max((k for k in prof if prof[k]["launches"]), key=lambda k: prof[k]["total_ms"])
     d = prof[dom]
-    dom_gbs = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9 if d["total_ms"] > 0 else 0.0
+    dom_own_gbs = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9 if d["total_ms"] > 0 else 0.0
+    dom_kernel = PHASE_KERNEL.get(dom, (dom, ""))[0]
     log("build phases: " + ", ".join(f"{k} {v['total_ms']:.1f} ms/{v['launches']}" for k, v in prof.items()))
 
     # Topkapi buckets (Section 3.1, Appendix 2): the same rows, hash seed and
@@ -506,6 +784,7 @@ def main():
                 f"q/s recall@10 {pt['exact']['recall_at_10']:.4f}")
             recall_sweep.append(pt)
 
+    api.slash_release_cache()
     # achievable HBM bandwidth: a plain device copy of 4 GiB (read + write)
     src_t = torch.empty(1 << 30, dtype=torch.int32, device=dev)
     dst_t = torch.empty_like(src_t)
@@ -527,6 +806,13 @@ def main():
         "config": {"workload": w["desc"], "queries_per_step": w["nq"], "rows": w["n"], "nnz": nnz,
                    "schedule": sched},
         "recall_at_10": recall,
+        # the headline configuration misses the metric's recall condition on
+        # this synthetic workload; recall_operating_point is the smallest
+        # setting of the same shard that meets it
+        "recall_met": recall >= 0.9,
+        "query_hbm_frac": q_gbs / HBM_PEAK_GBS,
+        "recall_operating_point": op_point,
+        "quality": qual,
         "p50_latency_us": float(np.percentile(lat, 50) * 1e6),
         "p99_latency_us": float(np.percentile(lat, 99) * 1e6),
         "plain_queries_per_s": npl / t_pl,
@@ -534,11 +820,24 @@ def main():
         "build_ms": float(b_ms.mean()),
         "insert_batch_rows_per_s": 4096 / (i_ms.mean() / 1e3),
         "batched_query_ms": float(q_ms.mean()),
+        "build_kernel_ms": build_kernel_ms,
         "build_algorithmic_hbm_frac": build_alg / (b_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": counted_traffic(dom),
-                     "kernel": dom, "launches": d["launches"], "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
-                     "alg_bytes_per_launch": d["alg_bytes"] / d["launches"]},
+        # the whole build (every kernel of one slash_build) against the
+        # build's algorithmic bytes: achieved = those bytes / summed kernel time
+        "roofline": {"bound": "hbm", "achieved": build_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": build_gbs / HBM_PEAK_GBS, "traffic": counted_build_traffic(prof),
+                     "kernel": "build: hash, radix sort, segment bounds, bottom-R select (all launches of one build)",
+                     "alg_bytes": build_alg, "kernel_ms": build_kernel_ms,
+                     "dominant_kernel": {
+                         "kernel": dom_kernel, "phase": dom, "launches": d["launches"],
+                         "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
+                         # the build's algorithmic bytes shared over this kernel's launches
+                         "method_bytes_per_launch": build_alg / d["launches"],
+                         "method_frac": build_alg / (d["total_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         # the bytes this kernel itself must move per launch
+                         "own_alg_bytes_per_launch": d["alg_bytes"] / d["launches"],
+                         "own_frac": dom_own_gbs / HBM_PEAK_GBS,
+                         "traffic": counted_traffic(dom_kernel)}},
         "query_roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": q_gbs / HBM_PEAK_GBS,
                            "kernel": "k_query" if sched and sched.get("queries_per_ticket") == 0 else "k_query_persistent",

@@ -250,6 +250,23 @@ SLASH_API slash_status slash_export_tables(const slash_index* index, uint32_t* i
 SLASH_API slash_status slash_import_tables(const slash_params* params, const uint32_t* ids_dev, const uint32_t* seen_dev,
                                  uint64_t n_items, void* stream, slash_index** out);
 
+/* Save an index to a file (the index stays valid): a 128-byte header
+ * (magic "SLASHIDX", format version 1, every slash_params field, n_items,
+ * the byte sizes of the two arrays and a 64-bit FNV-1a checksum of them),
+ * then the table array and the seen array exactly as slash_export_tables
+ * lays them out, little endian.  Copies the tables through 64 MiB of pinned
+ * host memory on `stream` and synchronises it.  Errors: E_INVAL (NULL
+ * arguments, file not writable), E_DEVICE. */
+SLASH_API slash_status slash_save(const slash_index* index, const char* path, void* stream);
+
+/* Load an index saved by slash_save: the parameters come from the file, the
+ * tables are copied to the device and checked as by slash_import_tables, and
+ * the next insert continues from the saved n_items.  Errors: E_INVAL (not a
+ * saved index, another format version, parameters that fail the checks of
+ * slash_build, a file whose size or checksum does not match its header,
+ * tables that fail the check), E_NOMEM, E_DEVICE.  Synchronises `stream`. */
+SLASH_API slash_status slash_load(const char* path, void* stream, slash_index** out);
+
 SLASH_API slash_status slash_index_info_get(const slash_index* index, slash_index_info* info);
 
 /* Per-phase timing of the build that made `index`, measured with HIP events

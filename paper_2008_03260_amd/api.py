@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
             "slash_export_tables": ([vp, vp, vp, vp], st),
             "slash_import_tables": ([P(Params), vp, vp, u64, vp, P(vp)], st),
             "slash_index_info_get": ([vp, P(IndexInfo)], st),
+            "slash_save": ([vp, C.c_char_p, vp], st),
+            "slash_load": ([C.c_char_p, vp, P(vp)], st),
             "slash_build_profile": ([vp, vp, u32, P(u32)], st),
             "slash_free": ([vp], None),
             "slash_last_error": ([], C.c_char_p),
@@ -260,6 +262,16 @@ def slash_import_tables(params: Params, ids: torch.Tensor, seen: torch.Tensor, n
     return out
 
 
+def slash_save(index, path: str, stream=None):
+    _check(lib().slash_save(index, os.fsencode(path), _stream(stream)), "slash_save")
+
+
+def slash_load(path: str, stream=None) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(lib().slash_load(os.fsencode(path), _stream(stream), C.byref(out)), "slash_load")
+    return out
+
+
 def slash_index_info_get(index) -> dict:
     info = IndexInfo()
     _check(lib().slash_index_info_get(index, C.byref(info)), "slash_index_info_get")
@@ -378,6 +390,18 @@ class Index:
         self = cls(params, None, None)
         self.handle = slash_import_tables(params, ids, seen, n_items, stream)
         return self
+
+    @classmethod
+    def load(cls, path: str, stream=None):
+        """Index loaded from a file written by save()."""
+        self = cls(None, None, None)
+        self.handle = slash_load(path, stream)
+        info = slash_index_info_get(self.handle)
+        self.params = Params.of(**{f: info[f] for f, _ in Params._fields_})
+        return self
+
+    def save(self, path: str, stream=None):
+        slash_save(self.handle, path, stream)
 
     def close(self):
         if getattr(self, "handle", None):

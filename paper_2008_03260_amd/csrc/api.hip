@@ -1038,43 +1038,220 @@ extern "C" slash_status slash_export_tables(const slash_index* ix, uint32_t* ids
   return SLASH_OK;
 }
 
-extern "C" slash_status slash_import_tables(const slash_params* params, const uint32_t* ids, const uint32_t* seen,
-                                           uint64_t n_items, void* stream, slash_index** out) {
-  if (!out) return fail(SLASH_E_INVAL, "out is NULL");
+// An index with derived constants and allocated (unfilled) tables, for the
+// import and load paths.
+static slash_status new_index(const slash_params* params, uint64_t n_items, hipStream_t st, slash_index** out) {
   slash_status rs = check_params(params);
   if (rs != SLASH_OK) return rs;
-  if (!ids || !seen) return fail(SLASH_E_INVAL, "table buffers are NULL");
   if (n_items > 0xFFFFFFFEull) return fail(SLASH_E_CAPACITY, "more than 2^32-2 ids");
-  hipStream_t st = (hipStream_t)stream;
   slash_index* ix = new (std::nothrow) slash_index();
   if (!ix) return fail(SLASH_E_NOMEM, "host allocation failed");
   ix->p = *params;
   ix->shape = make_shape(*params);
   ix->hc = derive_consts(*params);
-  auto bail = [&](slash_status s) {
-    destroy_index(ix);
-    return s;
-  };
   if (hipGetDevice(&ix->device) != hipSuccess ||
-      hipDeviceGetAttribute(&ix->n_cu, hipDeviceAttributeMultiprocessorCount, ix->device) != hipSuccess)
-    return bail(fail(SLASH_E_DEVICE, "device query failed"));
-  if ((rs = upload_consts(ix, st)) != SLASH_OK) return bail(rs);
-  if ((rs = alloc_tables(ix)) != SLASH_OK) return bail(rs);
+      hipDeviceGetAttribute(&ix->n_cu, hipDeviceAttributeMultiprocessorCount, ix->device) != hipSuccess) {
+    destroy_index(ix);
+    return fail(SLASH_E_DEVICE, "device query failed");
+  }
+  if ((rs = upload_consts(ix, st)) != SLASH_OK || (rs = alloc_tables(ix)) != SLASH_OK) {
+    destroy_index(ix);
+    return rs;
+  }
+  ix->n_items = n_items;
+  *out = ix;
+  return SLASH_OK;
+}
+
+// After the tables of an imported or loaded index are in place: check
+// reservoir tables (a bucket's first min(R, seen) slots hold assigned ids,
+// the rest are EMPTY, which queries rely on: they read every non-EMPTY slot)
+// and reserve the insert scratch.  Frees the index on error.
+static slash_status finish_index(slash_index* ix, hipStream_t st) {
+  const Shape& s = ix->shape;
+  uint32_t f = 0;
+  hipError_t e = hipSuccess;
+  if (!s.bucket) e = launch_fill_u32(ix->flag, 0u, 1, st);
+  if (e == hipSuccess && !s.bucket)
+    e = launch_check_tables(ix->ids, ix->seen, (uint64_t)s.L * s.nb, s.R, ix->n_items, ix->flag, st);
+  if (e == hipSuccess && !s.bucket) e = hipMemcpyAsync(&f, ix->flag, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  slash_status rs = SLASH_OK;
+  if (e != hipSuccess)
+    rs = fail(SLASH_E_DEVICE, "table copy: %s", hipGetErrorString(e));
+  else if (f & 8u)
+    rs = fail(SLASH_E_INVAL, "tables: a bucket holds an EMPTY or unassigned id in its first min(R, seen) slots, or "
+                             "an id past them");
+  else
+    rs = reserve_small_inserts(ix);
+  if (rs != SLASH_OK) destroy_index(ix);
+  return rs;
+}
+
+extern "C" slash_status slash_import_tables(const slash_params* params, const uint32_t* ids, const uint32_t* seen,
+                                           uint64_t n_items, void* stream, slash_index** out) {
+  if (!out) return fail(SLASH_E_INVAL, "out is NULL");
+  if (!ids || !seen) return fail(SLASH_E_INVAL, "table buffers are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  slash_index* ix = nullptr;
+  slash_status rs = new_index(params, n_items, st, &ix);
+  if (rs != SLASH_OK) return rs;
   const Shape& s = ix->shape;
   hipError_t e = hipMemcpyAsync(ix->ids, ids, (size_t)s.L * s.nb * bucket_words(s) * 4, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(ix->seen, seen, (size_t)s.L * s.nb * 4, hipMemcpyDeviceToDevice, st);
-  // reservoir tables: a bucket's first min(R, seen) slots hold assigned ids,
-  // the rest are EMPTY (queries read every non-EMPTY slot)
-  uint32_t f = 0;
-  if (e == hipSuccess && !s.bucket) e = launch_fill_u32(ix->flag, 0u, 1, st);
-  if (e == hipSuccess && !s.bucket) e = launch_check_tables(ix->ids, ix->seen, (uint64_t)s.L * s.nb, s.R, n_items, ix->flag, st);
-  if (e == hipSuccess && !s.bucket) e = hipMemcpyAsync(&f, ix->flag, 4, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table copy: %s", hipGetErrorString(e)));
-  if (f & 8u) return bail(fail(SLASH_E_INVAL, "imported tables: a bucket holds an EMPTY or unassigned id in its first "
-                                             "min(R, seen) slots, or an id past them"));
-  ix->n_items = n_items;
-  if ((rs = reserve_small_inserts(ix)) != SLASH_OK) return bail(rs);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    destroy_index(ix);
+    return fail(SLASH_E_DEVICE, "table copy: %s", hipGetErrorString(e));
+  }
+  if ((rs = finish_index(ix, st)) != SLASH_OK) return rs;
+  *out = ix;
+  return SLASH_OK;
+}
+
+// ------------------------------------------------------------ save / load
+
+// File layout (little endian): a 128-byte header, then the table array
+// ([L][2^B][R] ids, or [L][2^B][cm_rows][2^lw][2] Topkapi cells, uint32),
+// then seen [L][2^B] (uint32).  Header: magic "SLASHIDX", format version,
+// header bytes, the slash_params fields one by one (uint32 each, then the
+// uint64 seed), n_items, the byte sizes of the two arrays, and a 64-bit
+// FNV-1a checksum of both arrays.
+namespace {
+constexpr char kMagic[8] = {'S', 'L', 'A', 'S', 'H', 'I', 'D', 'X'};
+constexpr uint32_t kFormat = 1;
+constexpr size_t kHeaderBytes = 128;
+constexpr size_t kChunk = size_t(64) << 20;  // staging chunk (pinned host memory)
+
+struct FileHeader {
+  char magic[8];
+  uint32_t format, header_bytes;
+  uint32_t dim, K, L, log2_buckets, R, cm_rows, log2_cm_width, k_max, hash_mode, bucket;
+  uint64_t seed, n_items, table_bytes, seen_bytes, checksum;
+};
+static_assert(sizeof(FileHeader) <= kHeaderBytes, "header fits its 128 bytes");
+
+uint64_t fnv1a(uint64_t h, const uint8_t* p, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001B3ull;
+  }
+  return h;
+}
+constexpr uint64_t kFnvBasis = 0xCBF29CE484222325ull;
+
+struct File {
+  FILE* f = nullptr;
+  ~File() {
+    if (f) fclose(f);
+  }
+};
+struct Pinned {
+  void* p = nullptr;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+}  // namespace
+
+extern "C" slash_status slash_save(const slash_index* ix, const char* path, void* stream) {
+  if (!ix || !path) return fail(SLASH_E_INVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const Shape& s = ix->shape;
+  FileHeader h;
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, kMagic, 8);
+  h.format = kFormat;
+  h.header_bytes = (uint32_t)kHeaderBytes;
+  const slash_params& p = ix->p;
+  h.dim = p.dim, h.K = p.K, h.L = p.L, h.log2_buckets = p.log2_buckets, h.R = p.R, h.cm_rows = p.cm_rows;
+  h.log2_cm_width = p.log2_cm_width, h.k_max = p.k_max, h.hash_mode = p.hash_mode, h.bucket = p.bucket;
+  h.seed = p.seed;
+  h.n_items = ix->n_items;
+  h.table_bytes = (uint64_t)s.L * s.nb * bucket_words(s) * 4;
+  h.seen_bytes = (uint64_t)s.L * s.nb * 4;
+  File out;
+  out.f = fopen(path, "wb");
+  if (!out.f) return fail(SLASH_E_INVAL, "cannot open %s for writing", path);
+  uint8_t head[kHeaderBytes] = {};
+  if (fwrite(head, 1, kHeaderBytes, out.f) != kHeaderBytes) return fail(SLASH_E_INVAL, "write to %s failed", path);
+  Pinned buf;
+  HIP_TRY(hipHostMalloc(&buf.p, kChunk));
+  uint64_t sum = kFnvBasis;
+  const struct {
+    const uint32_t* src;
+    uint64_t bytes;
+  } parts[2] = {{ix->ids, h.table_bytes}, {ix->seen, h.seen_bytes}};
+  for (const auto& part : parts)
+    for (uint64_t off = 0; off < part.bytes; off += kChunk) {
+      const size_t n = (size_t)std::min<uint64_t>(kChunk, part.bytes - off);
+      HIP_TRY(hipMemcpyAsync(buf.p, (const uint8_t*)part.src + off, n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      sum = fnv1a(sum, (const uint8_t*)buf.p, n);
+      if (fwrite(buf.p, 1, n, out.f) != n) return fail(SLASH_E_INVAL, "write to %s failed", path);
+    }
+  h.checksum = sum;
+  memcpy(head, &h, sizeof h);
+  if (fseek(out.f, 0, SEEK_SET) != 0 || fwrite(head, 1, kHeaderBytes, out.f) != kHeaderBytes || fflush(out.f) != 0)
+    return fail(SLASH_E_INVAL, "write to %s failed", path);
+  return SLASH_OK;
+}
+
+extern "C" slash_status slash_load(const char* path, void* stream, slash_index** out) {
+  if (!path || !out) return fail(SLASH_E_INVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  File in;
+  in.f = fopen(path, "rb");
+  if (!in.f) return fail(SLASH_E_INVAL, "cannot open %s", path);
+  uint8_t head[kHeaderBytes];
+  FileHeader h;
+  if (fread(head, 1, kHeaderBytes, in.f) != kHeaderBytes) return fail(SLASH_E_INVAL, "%s: short header", path);
+  memcpy(&h, head, sizeof h);
+  if (memcmp(h.magic, kMagic, 8) != 0) return fail(SLASH_E_INVAL, "%s: not a saved index", path);
+  if (h.format != kFormat || h.header_bytes != kHeaderBytes)
+    return fail(SLASH_E_INVAL, "%s: format %u (header %u bytes) is not %u", path, h.format, h.header_bytes, kFormat);
+  slash_params p{};
+  p.dim = h.dim, p.K = h.K, p.L = h.L, p.log2_buckets = h.log2_buckets, p.R = h.R, p.cm_rows = h.cm_rows;
+  p.log2_cm_width = h.log2_cm_width, p.k_max = h.k_max, p.hash_mode = h.hash_mode, p.bucket = h.bucket;
+  p.seed = h.seed;
+  slash_status rs = check_params(&p);
+  if (rs != SLASH_OK) return fail(SLASH_E_INVAL, "%s: saved parameters: %s", path, slash_last_error());
+  const Shape s = make_shape(p);
+  if (h.table_bytes != (uint64_t)s.L * s.nb * bucket_words(s) * 4 || h.seen_bytes != (uint64_t)s.L * s.nb * 4)
+    return fail(SLASH_E_INVAL, "%s: array sizes do not match the saved parameters", path);
+  if (fseek(in.f, 0, SEEK_END) != 0) return fail(SLASH_E_INVAL, "%s: cannot seek", path);
+  const long long size = ftell(in.f);
+  if (size < 0 || (uint64_t)size != kHeaderBytes + h.table_bytes + h.seen_bytes)
+    return fail(SLASH_E_INVAL, "%s: %lld bytes, expected %llu", path, size,
+                (unsigned long long)(kHeaderBytes + h.table_bytes + h.seen_bytes));
+  if (fseek(in.f, (long)kHeaderBytes, SEEK_SET) != 0) return fail(SLASH_E_INVAL, "%s: cannot seek", path);
+  slash_index* ix = nullptr;
+  if ((rs = new_index(&p, h.n_items, st, &ix)) != SLASH_OK) return rs;
+  auto bail = [&](slash_status r) {
+    (void)hipStreamSynchronize(st);
+    destroy_index(ix);
+    return r;
+  };
+  Pinned buf;
+  if (hipHostMalloc(&buf.p, kChunk) != hipSuccess) return bail(fail(SLASH_E_NOMEM, "pinned staging buffer"));
+  uint64_t sum = kFnvBasis;
+  const struct {
+    uint32_t* dst;
+    uint64_t bytes;
+  } parts[2] = {{ix->ids, h.table_bytes}, {ix->seen, h.seen_bytes}};
+  for (const auto& part : parts)
+    for (uint64_t off = 0; off < part.bytes; off += kChunk) {
+      const size_t n = (size_t)std::min<uint64_t>(kChunk, part.bytes - off);
+      // the previous chunk's copy reads the staging buffer until it is done
+      if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(SLASH_E_DEVICE, "load: stream"));
+      if (fread(buf.p, 1, n, in.f) != n) return bail(fail(SLASH_E_INVAL, "%s: short read", path));
+      sum = fnv1a(sum, (const uint8_t*)buf.p, n);
+      if (hipMemcpyAsync((uint8_t*)part.dst + off, buf.p, n, hipMemcpyHostToDevice, st) != hipSuccess)
+        return bail(fail(SLASH_E_DEVICE, "load: copy"));
+    }
+  if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(SLASH_E_DEVICE, "load: stream"));
+  if (sum != h.checksum) return bail(fail(SLASH_E_INVAL, "%s: checksum mismatch", path));
+  if ((rs = finish_index(ix, st)) != SLASH_OK) return rs;
   *out = ix;
   return SLASH_OK;
 }

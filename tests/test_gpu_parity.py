@@ -586,3 +586,50 @@ def test_import_rejects_data_past_fill(api):
     assert e.value.code == api.E_INVAL
     ok = api.Index.from_tables(gp, ids, seen, 100)
     assert ok.info()["n_items"] == 100
+
+
+@pytest.mark.parametrize("bucket", [0, 1], ids=["reservoir", "topkapi"])
+def test_save_load_roundtrip(api, tmp_path, bucket):
+    # an index saved to a file and loaded back answers and grows exactly like
+    # the original; the header carries the parameters and sizes
+    import struct
+    kw = dict(L=6, log2_buckets=8, R=12) if bucket == 0 else dict(L=6, log2_buckets=8, R=1, cm_rows=2,
+                                                                   log2_cm_width=3)
+    gp, op = params_pair(api, k_max=16, hash_mode=2 if bucket == 0 else 0, **kw)
+    gp.bucket = bucket
+    law, (ip, ix) = rows_of(7000, seed=81)
+    a = api.Index(gp, dev(ip[:5001]), dev(ix[: ip[5000]]))
+    a.insert(dev(ip[5000:6001] - ip[5000]), dev(ix[ip[5000]: ip[6000]]))
+    path = str(tmp_path / "index.slash")
+    a.save(path)
+    raw = open(path, "rb").read()
+    magic, fmt, hb = struct.unpack_from("<8sII", raw, 0)
+    fields = struct.unpack_from("<10I", raw, 16)
+    seed, n_items, tb, sb = struct.unpack_from("<QQQQ", raw, 56)
+    assert magic == b"SLASHIDX" and fmt == 1 and hb == 128
+    assert fields == (gp.dim, gp.K, gp.L, gp.log2_buckets, gp.R, gp.cm_rows, gp.log2_cm_width, gp.k_max,
+                      gp.hash_mode, gp.bucket)
+    assert seed == gp.seed and n_items == 6000 and len(raw) == 128 + tb + sb
+    b = api.Index.load(path)
+    assert b.info()["n_items"] == 6000 and b.params.bucket == bucket
+    for x, y in zip(a.tables(), b.tables()):
+        assert torch.equal(x, y)
+    tail = (dev(ip[6000:] - ip[6000]), dev(ix[ip[6000]:]))
+    a.insert(*tail)
+    b.insert(*tail)
+    torch.cuda.synchronize()
+    for x, y in zip(a.tables(), b.tables()):
+        assert torch.equal(x, y)
+    qi, qx, _, _ = law.queries(synth.derive(81, synth.STREAM_QUERY), 7000, 0, 40)
+    ra, rb = a.query(dev(qi), dev(qx), 16), b.query(dev(qi), dev(qx), 16)
+    assert torch.equal(ra[0], rb[0]) and torch.equal(ra[1], rb[1])
+    if bucket == 0:
+        check_tables(api, b, op, oracle.constants(op), ip, ix)
+    # a damaged file is refused
+    for name, data in (("flipped", raw[:200] + bytes([raw[200] ^ 1]) + raw[201:]), ("short", raw[:-4]),
+                       ("magic", b"X" + raw[1:])):
+        bad = str(tmp_path / name)
+        open(bad, "wb").write(data)
+        with pytest.raises(api.SlashError) as e:
+            api.Index.load(bad)
+        assert e.value.code == api.E_INVAL, name
