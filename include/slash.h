@@ -311,16 +311,19 @@ SLASH_API void slash_release_cache(void);
 
 /* Continuous-batching server over a resident index (the query process is
  * online, Section 2.3).  A scheduler thread admits pending requests into
- * device batches while device memory and in-flight slots allow, runs up to
- * max_inflight batches concurrently on separate streams, and applies inserts
- * at epoch boundaries: a query admitted in epoch e sees exactly the inserts
- * submitted before it. */
+ * device batches as staging slots free up and launches them on one device
+ * stream in submission order, so a query admitted in epoch e sees exactly
+ * the inserts submitted before it; inserts queued back to back are applied
+ * in one launch (each still closes its own epoch).  Batch slots (device and
+ * pinned host staging for one batch) are added while requests wait for one,
+ * up to max_inflight, as long as the HBM budget and the device's free memory
+ * (checked when a slot is added, leaving 1 GiB free) allow. */
 #define SLASH_SERVE_MAX_K 128u /* largest k a served query may ask for */
 
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device bytes the server may hold for request data */
   uint32_t max_batch;         /* queries per device batch */
-  uint32_t max_inflight;      /* device batches in flight (>= 1) */
+  uint32_t max_inflight;      /* batch slots at most (>= 1): batches launched and not yet harvested */
   uint32_t queue_capacity;    /* pending requests accepted before E_BUSY */
   uint32_t max_wait_us;       /* 0: a batch launches as soon as a slot is free; else a batch that is
                                  neither full nor followed by an insert waits until its oldest

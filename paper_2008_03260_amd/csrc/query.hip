@@ -177,12 +177,17 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   uint32_t tid_q = tid;
   asm volatile("" : "+v"(tid_q));
   uint32_t id[SPT];
+  // slot -> (table, position): a shift when R is a power of two (uniform
+  // branch), else a division
+  const bool rpow = (s.R & (s.R - 1)) == 0;
+  const uint32_t rsh = (uint32_t)__builtin_ctz(s.R);
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
     uint32_t sl = tid_q + i * NT;
     id[i] = SL_EMPTY;
     if (sl < slots) {
-      uint32_t t = sl / s.R, j = sl - t * s.R;
+      const uint32_t t = rpow ? sl >> rsh : sl / s.R;
+      const uint32_t j = sl - t * s.R;
       id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
     }
   }

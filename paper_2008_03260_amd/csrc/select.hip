@@ -754,20 +754,21 @@ hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_
     return e;
   hipLaunchKernelGGL(k_insert_group, dim3(s.L), dim3(kGroupThreads), lds, st, keys, n, first_id, recs, items);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = gate(st)) != hipSuccess) return e;
-  if (s.bucket) return launch_tk_runs(s, c, recs, items, n, tab, st);
+  hipStream_t wst = st;
+  if ((e = gate(st, &wst)) != hipSuccess) return e;
+  if (s.bucket) return launch_tk_runs(s, c, recs, items, n, tab, wst);
   const uint64_t lanes = (uint64_t)s.L * n * 16;
   const dim3 grid((uint32_t)((lanes + kMergeThreads - 1) / kMergeThreads));
   if (s.R <= 16)
-    hipLaunchKernelGGL(k_insert_merge16<1>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+    hipLaunchKernelGGL(k_insert_merge16<1>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
   else if (s.R <= 32)
-    hipLaunchKernelGGL(k_insert_merge16<2>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+    hipLaunchKernelGGL(k_insert_merge16<2>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
   else if (s.R <= 64)
-    hipLaunchKernelGGL(k_insert_merge16<4>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+    hipLaunchKernelGGL(k_insert_merge16<4>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
   else if (s.R <= 128)
-    hipLaunchKernelGGL(k_insert_merge16<8>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+    hipLaunchKernelGGL(k_insert_merge16<8>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
   else
-    hipLaunchKernelGGL(k_insert_merge16<16>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+    hipLaunchKernelGGL(k_insert_merge16<16>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
   return hipGetLastError();
 }
 
@@ -784,10 +785,11 @@ hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_head_scatter, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, skeys, n, segno, seg_start,
                      nseg);
-  if ((e = gate(st)) != hipSuccess) return e;
-  if (s.bucket) return launch_tk_segments(s, c, skeys, svals, n, seg_start, nseg, tab, st);
+  hipStream_t wst = st;
+  if ((e = gate(st, &wst)) != hipSuccess) return e;
+  if (s.bucket) return launch_tk_segments(s, c, skeys, svals, n, seg_start, nseg, tab, wst);
   size_t lds = (size_t)kSelWaves * wl_words(s.R) * 4;
-  hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st, s, c,
+  hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, wst, s, c,
                      skeys, svals, n, seg_start, nseg, tab);
   return hipGetLastError();
 }

@@ -4,26 +4,29 @@
 // shard's tables resident in HBM and serves a stream of queries and inserts:
 //   - submit calls copy the request and append it to a FIFO (E_BUSY when the
 //     FIFO is full);
-//   - a scheduler thread owns `max_inflight` slots, each with its own stream
-//     and its own device staging memory carved from the HBM budget.  As soon
-//     as a slot is free it takes the longest run of queries at the head of the
-//     FIFO that fits the slot (continuous batching: no waiting for a full
-//     batch while the device has room), copies them in, runs slash_query on
-//     the slot's stream and copies the results back;
-//   - an insert at the head of the FIFO closes the current epoch: it runs
-//     after every in-flight insert, its kernels that write the tables run
-//     after the query kernels of every in-flight batch (stream waits on their
-//     events; hashing and grouping the new rows may overlap those queries),
-//     and the query kernels of every later batch wait on it, so a query of
-//     epoch e sees exactly the inserts submitted before it, without blocking
-//     the host.  Only kernels wait: request data is copied in before the
-//     wait, and an insert does not wait for the result copies of earlier
-//     batches.  Up to four insert staging slots let later inserts queue
-//     behind a running one, so the device runs epochs back to back;
+//   - a scheduler thread owns staging slots (device and pinned host memory
+//     for one batch each).  As soon as a slot is free it takes the longest
+//     run of queries at the head of the FIFO that fits the slot (continuous
+//     batching: no waiting for a full batch while the device has room),
+//     copies them in, runs slash_query and copies the results back;
+//   - query batches and the table-writing kernels of inserts go to one
+//     device stream in FIFO order, so a query admitted in epoch e sees
+//     exactly the inserts submitted before it: an insert at the head of the
+//     FIFO (with the inserts queued right behind it, merged into one launch
+//     while they fit its staging) writes the tables after the batches before
+//     it and before the batches after it.  Its preparation (copying the rows
+//     in, hashing them, grouping them by bucket) runs on a second stream
+//     beside the query batches before it, after the previous insert's table
+//     writes (inserts share the index's insert scratch);
+//   - query results are written by the query kernel straight into pinned,
+//     host-coherent memory (no copy back);
+//   - slots are added while work is waiting, up to max_inflight, as long as
+//     the HBM budget and the device's free memory (checked when a slot is
+//     added) allow;
 //   - with max_wait_us > 0, a batch that is neither full nor followed by an
 //     insert is held back until its oldest query has waited that long;
-//   - finished work is detected with events (polled without sleeping while
-//     work is in flight) and turned into completions.
+//   - finished work is detected with one event per launch (polled without
+//     sleeping while work is in flight) and turned into completions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,6 +52,8 @@ double now_s() {
 // Insert staging slots a server keeps at most (inserts queued on the device
 // behind the one running).
 constexpr size_t kInsertSlots = 4;
+// Device memory a server leaves free when it adds a batch slot.
+constexpr uint64_t kFreeReserve = uint64_t(1) << 30;
 
 struct Request {
   uint64_t ticket = 0;
@@ -61,22 +66,20 @@ struct Request {
 };
 
 struct Slot {
-  hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;   // everything the slot launched has finished
-  hipEvent_t kdone = nullptr;  // query slots: the query kernels have finished
+  hipEvent_t done = nullptr;  // everything the slot launched has finished
+  hipEvent_t prep = nullptr;  // inserts: the preparation kernels have finished
   bool busy = false;
   uint32_t kind = 0;
-  uint64_t epoch = 0;
+  uint64_t epoch = 0;  // queries: the epoch they see; inserts: the first request's epoch
   std::vector<Request> reqs;
-  // device staging
   // request data of one launch, packed so that it moves in one copy:
   // indptr [n + 1] (int64), k [n] (queries only), then the indices (int32)
   // from a 256-byte boundary
   char* d_in = nullptr;
   char* h_in = nullptr;  // pinned
-  // query results of one launch: ids [n][k_max] then scores [n][k_max]
-  uint32_t* d_out = nullptr;
-  uint32_t* h_out = nullptr;  // pinned
+  // query results of one launch, written by the kernel: ids [n][k_max] then
+  // scores [n][k_max] (pinned, host-coherent)
+  uint32_t* h_out = nullptr;
   uint32_t cap_q = 0;
   uint64_t cap_nnz = 0;
   uint32_t first_id = 0;
@@ -92,17 +95,23 @@ struct slash_server {
   std::condition_variable cv;
   std::deque<Request> pending;
   std::deque<slash_completion> done;
-  std::vector<Slot> slots;
-  std::vector<Slot> ins;  // insert staging + streams (one or two)
-  hipEvent_t last_insert = nullptr;
+  std::vector<Slot> slots;  // query batch staging
+  std::vector<Slot> ins;    // insert staging
+  hipStream_t stream = nullptr;  // query batches and table writes, in FIFO order
+  hipStream_t prep = nullptr;    // insert preparation
+  hipEvent_t last_insert = nullptr;  // table writes of the latest insert
   bool have_insert = false;
+  uint32_t cap_q = 0;
+  uint64_t cap_nnz = 0, per_slot = 0;
   uint64_t epoch = 0;
   uint64_t next_ticket = 0;
+  uint64_t next_id = 0;  // id of the next inserted row
   bool stopping = false;
   bool closed = false;
   std::thread th;
   slash_serve_stats stats{};
   uint64_t hbm_used = 0;
+  double grow_retry_at = 0;  // a slot that did not fit is retried after this time
   int device = 0;
   hipError_t dev_err = hipSuccess;
 };
@@ -110,12 +119,10 @@ struct slash_server {
 namespace {
 
 void free_slot(Slot& s) {
-  if (s.stream) (void)hipStreamSynchronize(s.stream);
+  if (s.done) (void)hipEventSynchronize(s.done);
   if (s.done) (void)hipEventDestroy(s.done);
-  if (s.kdone) (void)hipEventDestroy(s.kdone);
-  if (s.stream) (void)hipStreamDestroy(s.stream);
+  if (s.prep) (void)hipEventDestroy(s.prep);
   (void)hipFree(s.d_in);
-  (void)hipFree(s.d_out);
   (void)hipHostFree(s.h_in);
   (void)hipHostFree(s.h_out);
   s = Slot();
@@ -133,20 +140,18 @@ InLayout in_layout(uint64_t n, uint64_t nnz, bool with_k) {
   return l;
 }
 
-// Device + pinned staging for up to cap_q queries / rows and cap_nnz indices.
+// Device + pinned staging for up to cap_q queries / rows and cap_nnz indices
+// (query slots: plus host-coherent result memory the kernel writes).
 bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool with_out) {
   s.cap_q = cap_q;
   s.cap_nnz = cap_nnz;
   const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
-  if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
   if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
-  if (with_out && hipEventCreateWithFlags(&s.kdone, hipEventDisableTiming) != hipSuccess) return false;
+  if (!with_out && hipEventCreateWithFlags(&s.prep, hipEventDisableTiming) != hipSuccess) return false;
   if (hipMalloc(&s.d_in, in_bytes) != hipSuccess) return false;
   if (hipHostMalloc(&s.h_in, in_bytes) != hipSuccess) return false;
-  if (with_out) {
-    if (hipMalloc(&s.d_out, (size_t)cap_q * k_max * 8) != hipSuccess) return false;
-    if (hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8) != hipSuccess) return false;
-  }
+  if (with_out && hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8, hipHostMallocCoherent) != hipSuccess)
+    return false;
   return true;
 }
 
@@ -155,23 +160,20 @@ __global__ void k_touch(int64_t* p) {
 }
 
 // Run each transfer the slot will make once, at full size, and one kernel,
-// and wait: the runtime sets up a stream's hardware queue and copy engines on
-// first use, which would otherwise stall the first requests by milliseconds.
-bool warm_slot(Slot& s, uint32_t k_max, bool with_out) {
-  hipLaunchKernelGGL(k_touch, dim3(1), dim3(64), 0, s.stream, (int64_t*)s.d_in);
+// and wait: the runtime sets up the stream's hardware queue and copy engines
+// on first use, which would otherwise stall the first requests by
+// milliseconds.
+bool warm_slot(hipStream_t st, Slot& s, bool with_out) {
+  hipLaunchKernelGGL(k_touch, dim3(1), dim3(64), 0, st, (int64_t*)s.d_in);
   if (hipGetLastError() != hipSuccess) return false;
   const size_t in_bytes = in_layout(s.cap_q, s.cap_nnz, with_out).bytes;
-  if (hipMemcpyAsync(s.d_in, s.h_in, in_bytes, hipMemcpyHostToDevice, s.stream) != hipSuccess) return false;
-  if (with_out &&
-      hipMemcpyAsync(s.h_out, s.d_out, (size_t)s.cap_q * k_max * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
-    return false;
-  if (hipEventRecord(s.done, s.stream) != hipSuccess) return false;
-  return hipStreamSynchronize(s.stream) == hipSuccess;
+  if (hipMemcpyAsync(s.d_in, s.h_in, in_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+  if (hipEventRecord(s.done, st) != hipSuccess) return false;
+  return hipStreamSynchronize(st) == hipSuccess;
 }
 
-uint64_t slot_bytes(uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max) {
-  return in_layout(cap_q, cap_nnz, true).bytes + (uint64_t)cap_q * k_max * 8;
-}
+// Device bytes of one batch slot (its request data; results go to host memory).
+uint64_t slot_bytes(uint32_t cap_q, uint64_t cap_nnz) { return in_layout(cap_q, cap_nnz, true).bytes; }
 
 // Turn a finished slot into completions (called with the lock held); status
 // is SLASH_E_DEVICE when the slot's work failed on the device.
@@ -198,26 +200,32 @@ void finish_slot(slash_server* srv, Slot& s, int32_t status) {
     }
     srv->stats.queries_done += s.reqs.size();
   } else {
-    const Request& r = s.reqs[0];
-    slash_completion c;
-    memset(&c, 0, sizeof c);
-    c.ticket = r.ticket;
-    c.epoch = s.epoch;
-    c.status = status;
-    c.kind = 1;
-    c.n_ids = r.n_rows;
-    c.first_id = s.first_id;
-    c.t_submit_s = r.t_submit;
-    c.t_done_s = t;
-    srv->done.push_back(c);
-    srv->stats.inserts_done += 1;
-    srv->stats.rows_inserted += r.n_rows;
+    // merged inserts: each request closes its own epoch and gets its own ids
+    uint32_t first = s.first_id;
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+      const Request& r = s.reqs[i];
+      slash_completion c;
+      memset(&c, 0, sizeof c);
+      c.ticket = r.ticket;
+      c.epoch = s.epoch + i;
+      c.status = status;
+      c.kind = 1;
+      c.n_ids = r.n_rows;
+      c.first_id = first;
+      c.t_submit_s = r.t_submit;
+      c.t_done_s = t;
+      srv->done.push_back(c);
+      srv->stats.inserts_done += 1;
+      srv->stats.rows_inserted += r.n_rows;
+      first += r.n_rows;
+    }
   }
   s.reqs.clear();
   s.busy = false;
 }
 
-// Launch a query batch on slot s (lock not held; reqs already moved in).
+// Launch a query batch on slot s (lock not held; reqs already moved in):
+// copy in, query, copy out, one event.
 hipError_t launch_queries(slash_server* srv, Slot& s) {
   const uint32_t n = (uint32_t)s.reqs.size();
   const uint32_t km = srv->info.params.k_max;
@@ -236,71 +244,101 @@ hipError_t launch_queries(slash_server* srv, Slot& s) {
     h_ip[q + 1] = (int64_t)off;
     h_k[q] = r.k;
   }
+  hipStream_t st = srv->stream;
   hipError_t e;
-  // the request copy may overlap the insert that opened this epoch; the
-  // query kernels may not
-  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
-  if (srv->have_insert && (e = hipStreamWaitEvent(s.stream, srv->last_insert, 0)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
   slash_csr q{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), n};
-  slash_status st = slash_query(srv->ix, q, (const uint32_t*)(s.d_in + l.k), 0, SLASH_FLAG_TRUSTED, s.d_out,
-                                s.d_out + (size_t)n * km, s.stream);
-  if (st != SLASH_OK) return hipErrorLaunchFailure;
-  if ((e = hipEventRecord(s.kdone, s.stream)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * km * 8, hipMemcpyDeviceToHost, s.stream)) != hipSuccess)
-    return e;
-  return hipEventRecord(s.done, s.stream);
+  slash_status rs = slash_query(srv->ix, q, (const uint32_t*)(s.d_in + l.k), 0, SLASH_FLAG_TRUSTED, s.h_out,
+                                s.h_out + (size_t)n * km, st);
+  if (rs != SLASH_OK) return hipErrorLaunchFailure;
+  return hipEventRecord(s.done, st);
 }
 
-// The table writes of a served insert wait for the query kernels of every
-// batch in flight when it is launched (its gate).
-hipError_t wait_query_kernels(void* ctx, hipStream_t st) {
-  slash_server* srv = (slash_server*)ctx;
-  for (Slot& o : srv->slots)
-    if (o.busy) {
-      const hipError_t e = hipStreamWaitEvent(st, o.kdone, 0);
-      if (e != hipSuccess) return e;
-    }
-  return hipSuccess;
+// The table writes of a served insert go to the batch stream, after the
+// insert's preparation on the preparation stream (its gate).
+hipError_t insert_gate(void* ctx, hipStream_t st, hipStream_t* write_st) {
+  Slot* s = (Slot*)((void**)ctx)[0];
+  slash_server* srv = (slash_server*)((void**)ctx)[1];
+  hipError_t e = hipEventRecord(s->prep, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(srv->stream, s->prep, 0);
+  *write_st = srv->stream;
+  return e;
 }
 
-// Apply an insert after every in-flight insert (they share the index's insert
-// scratch); its table writes also wait for the query kernels of every
-// in-flight batch, while its hashing and grouping may run beside them.  The
-// kernels of later batches wait on it.  The rows are copied in first.
+// Apply the slot's inserts (one or more requests, their rows back to back):
+// copy, hash and group on the preparation stream after the previous insert's
+// table writes, then write the tables on the batch stream, after every batch
+// launched before and before every batch launched after.
 hipError_t launch_insert(slash_server* srv, Slot& s) {
-  const Request& r = s.reqs[0];
+  uint32_t rows = 0;
+  uint64_t nnz = 0;
+  for (const Request& r : s.reqs) {
+    rows += r.n_rows;
+    nnz += r.idx.size();
+  }
+  const InLayout l = in_layout(rows, nnz, false);
+  int64_t* h_ip = (int64_t*)s.h_in;
+  int32_t* h_ix = (int32_t*)(s.h_in + l.idx);
+  uint32_t row = 0;
+  uint64_t off = 0;
+  h_ip[0] = 0;
+  for (const Request& r : s.reqs) {
+    for (uint32_t i = 0; i < r.n_rows; ++i) h_ip[row + i + 1] = (int64_t)off + r.indptr[i + 1];
+    memcpy(h_ix + off, r.idx.data(), r.idx.size() * 4);
+    off += r.idx.size();
+    row += r.n_rows;
+  }
+  hipStream_t pst = srv->prep;
   hipError_t e;
-  const InLayout l = in_layout(r.n_rows, r.idx.size(), false);
-  memcpy(s.h_in, r.indptr.data(), (r.n_rows + 1) * 8);
-  memcpy(s.h_in + l.idx, r.idx.data(), r.idx.size() * 4);
-  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, s.stream)) != hipSuccess) return e;
-  for (Slot& o : srv->ins)
-    if (&o != &s && o.busy && (e = hipStreamWaitEvent(s.stream, o.done, 0)) != hipSuccess) return e;
-  slash_index_info info;
-  slash_index_info_get(srv->ix, &info);
-  s.first_id = (uint32_t)info.n_items;
-  slash_csr rows{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), r.n_rows};
-  if (insert_rows(srv->ix, rows, SLASH_FLAG_TRUSTED, nullptr, s.stream, InsertGate{wait_query_kernels, srv}) !=
-      SLASH_OK)
+  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, pst)) != hipSuccess) return e;
+  if (srv->have_insert && (e = hipStreamWaitEvent(pst, srv->last_insert, 0)) != hipSuccess) return e;
+  s.first_id = (uint32_t)srv->next_id;
+  srv->next_id += rows;
+  slash_csr csr{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), rows};
+  void* ctx[2] = {&s, srv};
+  if (insert_rows(srv->ix, csr, SLASH_FLAG_TRUSTED, nullptr, pst, InsertGate{insert_gate, ctx}) != SLASH_OK)
     return hipErrorLaunchFailure;
-  if ((e = hipEventRecord(s.done, s.stream)) != hipSuccess) return e;
+  if ((e = hipEventRecord(s.done, srv->stream)) != hipSuccess) return e;
   srv->last_insert = s.done;
   srv->have_insert = true;
   return hipSuccess;
 }
 
-// Whether the queries at the head of the FIFO fill one batch of slot s, or
-// an insert ends their run (then waiting cannot make the batch larger).
-bool head_run_full(const slash_server* srv, const Slot& s, uint32_t max_batch) {
-  const uint32_t cap = std::min(max_batch, s.cap_q);
+// Whether the queries at the head of the FIFO fill one batch, or an insert
+// ends their run (then waiting cannot make the batch larger).
+bool head_run_full(const slash_server* srv, uint32_t max_batch) {
+  const uint32_t cap = std::min(max_batch, srv->cap_q);
   uint64_t nnz = 0;
   uint32_t c = 0;
   for (const Request& r : srv->pending) {
-    if (r.kind != 0 || c >= cap || nnz + r.idx.size() > s.cap_nnz) return true;
+    if (r.kind != 0 || c >= cap || nnz + r.idx.size() > srv->cap_nnz) return true;
     nnz += r.idx.size();
     ++c;
   }
   return c >= cap;
+}
+
+// Add a batch slot while the budget and the device's free memory allow
+// (lock not held).  Returns the new slot or nullptr.
+Slot* grow_slots(slash_server* srv) {
+  if (srv->slots.size() >= srv->cfg.max_inflight) return nullptr;
+  if (srv->hbm_used + srv->per_slot > srv->cfg.hbm_budget_bytes) return nullptr;
+  if (now_s() < srv->grow_retry_at) return nullptr;
+  size_t free_b = 0, total_b = 0;
+  Slot s;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b < srv->per_slot + kFreeReserve ||
+      !alloc_slot(s, srv->cap_q, srv->cap_nnz, srv->info.params.k_max, true)) {
+    free_slot(s);
+    (void)hipGetLastError();
+    srv->grow_retry_at = now_s() + 0.01;
+    return nullptr;
+  }
+  srv->hbm_used += srv->per_slot;
+  srv->stats.peak_hbm_bytes = std::max(srv->stats.peak_hbm_bytes, srv->hbm_used);
+  // the vector's elements move: only the scheduler thread holds Slot
+  // references, and none across this call
+  srv->slots.push_back(s);
+  return &srv->slots.back();
 }
 
 void scheduler(slash_server* srv) {
@@ -311,8 +349,8 @@ void scheduler(slash_server* srv) {
   double busy_since = -1.0;
   std::unique_lock<std::mutex> lk(srv->mu);
   for (;;) {
-    // 1. retire finished work.  Slots, events and streams belong to this
-    //    thread, so the events are queried without the lock.
+    // 1. retire finished work.  Slots and events belong to this thread, so
+    //    the events are queried without the lock.
     lk.unlock();
     finished.clear();
     for (std::vector<Slot>* group : {&srv->slots, &srv->ins})
@@ -332,7 +370,7 @@ void scheduler(slash_server* srv) {
     while (!srv->pending.empty()) {
       Request& head = srv->pending.front();
       if (head.kind == 1) {
-        Slot* free_i = nullptr;  // inserts launch in FIFO order, each behind the last
+        Slot* free_i = nullptr;
         for (Slot& o : srv->ins)
           if (!o.busy) {
             free_i = &o;
@@ -341,13 +379,23 @@ void scheduler(slash_server* srv) {
         if (!free_i) break;
         Slot& s = *free_i;
         s.reqs.clear();
-        s.reqs.push_back(std::move(head));
-        srv->pending.pop_front();
+        // this insert and the inserts right behind it, while they fit the
+        // staging: one launch, each request still its own epoch
+        uint32_t rows = 0;
+        uint64_t nnz = 0;
+        while (!srv->pending.empty() && srv->pending.front().kind == 1) {
+          Request& r = srv->pending.front();
+          if (!s.reqs.empty() && (rows + r.n_rows > s.cap_q || nnz + r.idx.size() > s.cap_nnz)) break;
+          rows += r.n_rows;
+          nnz += r.idx.size();
+          s.reqs.push_back(std::move(r));
+          srv->pending.pop_front();
+        }
         s.kind = 1;
         s.busy = true;
-        s.epoch = ++srv->epoch;
+        s.epoch = srv->epoch + 1;
+        srv->epoch += s.reqs.size();
         srv->stats.batches++;
-        // slots, events and streams belong to this thread: launch unlocked
         lk.unlock();
         hipError_t e = launch_insert(srv, s);
         lk.lock();
@@ -360,11 +408,16 @@ void scheduler(slash_server* srv) {
           free_s = &s;
           break;
         }
-      if (!free_s) break;
+      if (!free_s) {
+        lk.unlock();
+        free_s = grow_slots(srv);
+        lk.lock();
+        if (!free_s) break;
+      }
       Slot& s = *free_s;
       if (max_wait > 0 && !srv->stopping) {
-        const double due = head.t_submit + max_wait;
-        if (!head_run_full(srv, s, max_batch) && now_s() < due) {
+        const double due = srv->pending.front().t_submit + max_wait;
+        if (!head_run_full(srv, max_batch) && now_s() < due) {
           wake_at = due;  // hold the partial batch back
           break;
         }
@@ -415,6 +468,17 @@ void scheduler(slash_server* srv) {
   }
 }
 
+void free_server(slash_server* srv) {
+  for (Slot& o : srv->slots) free_slot(o);
+  for (Slot& o : srv->ins) free_slot(o);
+  for (hipStream_t st : {srv->stream, srv->prep})
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  delete srv;
+}
+
 }  // namespace
 
 extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_config* cfg, slash_server** out) {
@@ -425,41 +489,50 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   srv->ix = ix;
   srv->cfg = *cfg;
   slash_index_info_get(ix, &srv->info);
+  srv->next_id = srv->info.n_items;
   (void)hipGetDevice(&srv->device);
   const uint32_t km = srv->info.params.k_max;
   // a batch holds max_batch queries of 64 indices on average, and at least
   // one query of max_query_nnz
-  const uint32_t cap_q = cfg->max_batch;
-  const uint64_t cap_nnz = std::max<uint64_t>((uint64_t)cap_q * 64, cfg->max_query_nnz);
-  const uint64_t per_slot = slot_bytes(cap_q, cap_nnz, km);
+  srv->cap_q = cfg->max_batch;
+  srv->cap_nnz = std::max<uint64_t>((uint64_t)srv->cap_q * 64, cfg->max_query_nnz);
+  srv->per_slot = slot_bytes(srv->cap_q, srv->cap_nnz);
   // insert staging: 4096 rows of max_insert_nnz indices in total (default
   // the larger of 64 per row and 8 * max_query_nnz)
   const uint32_t ins_rows = 4096;
   const uint64_t ins_nnz = cfg->max_insert_nnz ? cfg->max_insert_nnz
                                                : std::max<uint64_t>((uint64_t)ins_rows * 64, 8ull * cfg->max_query_nnz);
   const uint64_t ins_bytes = in_layout(ins_rows, ins_nnz, false).bytes;
-  if (ins_bytes + per_slot > cfg->hbm_budget_bytes) {
+  if (ins_bytes + srv->per_slot > cfg->hbm_budget_bytes) {
     delete srv;
     return fail(SLASH_E_NOMEM, "HBM budget %llu below one batch slot (%llu bytes)",
-                (unsigned long long)cfg->hbm_budget_bytes, (unsigned long long)(ins_bytes + per_slot));
+                (unsigned long long)cfg->hbm_budget_bytes, (unsigned long long)(ins_bytes + srv->per_slot));
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b < ins_bytes + srv->per_slot) {
+    delete srv;
+    return fail(SLASH_E_NOMEM, "free device memory below one batch slot and the insert staging");
+  }
+  if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&srv->prep, hipStreamNonBlocking) != hipSuccess) {
+    free_server(srv);
+    return fail(SLASH_E_DEVICE, "stream creation failed");
   }
   srv->ins.emplace_back();
   if (!alloc_slot(srv->ins[0], ins_rows, ins_nnz, km, false)) {
-    free_slot(srv->ins[0]);
-    delete srv;
+    free_server(srv);
     return fail(SLASH_E_NOMEM, "insert staging allocation failed");
   }
   srv->hbm_used = ins_bytes;
   // the index's own scratch for the largest insert, so that no insert grows
   // (and drains the device) while batches are in flight
   if (slash_status rs = reserve_insert_scratch(ix, ins_rows); rs != SLASH_OK) {
-    free_slot(srv->ins[0]);
-    delete srv;
+    free_server(srv);
     return rs;
   }
   // up to three more insert slots while the budget still leaves room for a
   // batch slot
-  while (srv->ins.size() < kInsertSlots && srv->hbm_used + ins_bytes + per_slot <= cfg->hbm_budget_bytes) {
+  while (srv->ins.size() < kInsertSlots && srv->hbm_used + ins_bytes + srv->per_slot <= cfg->hbm_budget_bytes) {
     srv->ins.emplace_back();
     if (!alloc_slot(srv->ins.back(), ins_rows, ins_nnz, km, false)) {
       free_slot(srv->ins.back());
@@ -468,26 +541,20 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     }
     srv->hbm_used += ins_bytes;
   }
-  for (uint32_t i = 0; i < cfg->max_inflight && srv->hbm_used + per_slot <= cfg->hbm_budget_bytes; ++i) {
-    srv->slots.emplace_back();
-    if (!alloc_slot(srv->slots.back(), cap_q, cap_nnz, km, true)) {
-      free_slot(srv->slots.back());
-      srv->slots.pop_back();
-      break;
-    }
-    srv->hbm_used += per_slot;
-  }
-  if (srv->slots.empty()) {
-    for (Slot& o : srv->ins) free_slot(o);
-    delete srv;
+  // one batch slot now; more are added while work waits for them
+  srv->slots.reserve(cfg->max_inflight);
+  srv->slots.emplace_back();
+  if (!alloc_slot(srv->slots[0], srv->cap_q, srv->cap_nnz, km, true)) {
+    free_server(srv);
     return fail(SLASH_E_NOMEM, "no batch slot fits the HBM budget");
   }
+  srv->hbm_used += srv->per_slot;
   srv->stats.peak_hbm_bytes = srv->hbm_used;
   bool warm = true;
-  for (Slot& o : srv->ins) warm = warm && warm_slot(o, km, false);
-  for (Slot& o : srv->slots) warm = warm && warm_slot(o, km, true);
+  for (Slot& o : srv->ins) warm = warm && warm_slot(srv->prep, o, false);
+  warm = warm && warm_slot(srv->stream, srv->slots[0], true);
   if (warm) {
-    // one single-index query through the first slot loads the query kernels
+    // one single-index query loads the query kernels
     Slot& q = srv->slots[0];
     const int64_t ip[2] = {0, 1};
     const int32_t zero = 0;
@@ -495,13 +562,11 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     warm = hipMemcpy(q.d_in, ip, sizeof ip, hipMemcpyHostToDevice) == hipSuccess &&
            hipMemcpy(q.d_in + l.idx, &zero, 4, hipMemcpyHostToDevice) == hipSuccess &&
            slash_query(ix, slash_csr{(const int64_t*)q.d_in, (const int32_t*)(q.d_in + l.idx), 1}, nullptr, 1,
-                       SLASH_FLAG_TRUSTED, q.d_out, q.d_out + km, q.stream) == SLASH_OK &&
-           hipStreamSynchronize(q.stream) == hipSuccess;
+                       SLASH_FLAG_TRUSTED, q.h_out, q.h_out + km, srv->stream) == SLASH_OK &&
+           hipStreamSynchronize(srv->stream) == hipSuccess;
   }
   if (!warm) {
-    for (Slot& o : srv->ins) free_slot(o);
-    for (Slot& o : srv->slots) free_slot(o);
-    delete srv;
+    free_server(srv);
     return fail(SLASH_E_DEVICE, "server warm-up failed");
   }
   srv->th = std::thread(scheduler, srv);
@@ -588,9 +653,7 @@ extern "C" slash_status slash_serve_stop(slash_server* srv, slash_serve_stats* s
   if (srv->th.joinable()) srv->th.join();
   hipError_t err = srv->dev_err;
   if (stats) *stats = srv->stats;
-  for (Slot& s : srv->slots) free_slot(s);
-  for (Slot& o : srv->ins) free_slot(o);
-  delete srv;
+  free_server(srv);
   if (err != hipSuccess) return fail(SLASH_E_DEVICE, "serve: %s", hipGetErrorString(err));
   return SLASH_OK;
 }

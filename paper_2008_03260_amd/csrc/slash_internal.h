@@ -208,14 +208,20 @@ hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const ui
                         FinalWork* finals, uint32_t* n_chunks, uint32_t* cand, TablesView tab, hipStream_t st);
 
 
-// A hook an insert calls on its stream after the kernels that read only the
-// new rows and the insert scratch (hashing, grouping, sorting) and before the
-// first kernel that writes the tables; a server makes the table writes wait
-// for in-flight queries there.  Returns the first error of what it enqueued.
+// A hook an insert calls on its stream `st` after the kernels that read only
+// the new rows and the insert scratch (hashing, grouping, sorting) and
+// before the first kernel that writes the tables.  It may enqueue waits and
+// may name another stream for the table-writing kernels (*write_st, preset
+// to st): a server runs the preparation beside its query batches and the
+// table writes in the order of its batches.  Returns the first error of what
+// it enqueued.
 struct InsertGate {
-  hipError_t (*fn)(void* ctx, hipStream_t st) = nullptr;
+  hipError_t (*fn)(void* ctx, hipStream_t st, hipStream_t* write_st) = nullptr;
   void* ctx = nullptr;
-  hipError_t operator()(hipStream_t st) const { return fn ? fn(ctx, st) : hipSuccess; }
+  hipError_t operator()(hipStream_t st, hipStream_t* write_st) const {
+    *write_st = st;
+    return fn ? fn(ctx, st, write_st) : hipSuccess;
+  }
 };
 
 // Small insert (n rows, keys [L][n] as written by launch_hash_rows without
