@@ -332,15 +332,36 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     uint64_t lm = 0;
 #pragma unroll
     for (int i = 0; i < SPT; ++i) lm = key[i] > lm ? key[i] : lm;
-    uint64_t kth = 0;
-    for (uint32_t r = 0; r < kq; ++r) {
-      const uint64_t m = wave_max64(lm);
-      kth = m;  // 0 once the wave has fewer than kq distinct lane maxima
-      if (m == 0) break;
-      if (lm == m) lm = 0;
-    }
     uint64_t* bound = (uint64_t*)(misc + 8);  // cleared with misc
-    if (lane == 0 && kth) atomicMax((unsigned long long*)bound, (unsigned long long)kth);
+    // With several waves, the lane maxima go through LDS and wave 0 alone
+    // takes the rounds, each of its lanes offering the largest of the lane
+    // maxima at its position in every wave (the other waves skip the rounds;
+    // the extracted keys are still distinct keys of the group, so the last
+    // one is still a lower bound).  The buffer sits after the collection
+    // area in the free sketch region.
+    const bool shared = WAVES > 1 && 4 * lay.tie_cap + 2 * NT <= lay.hist - lay.cm;
+    if (shared) {
+      uint64_t* lmv = (uint64_t*)(lds + lay.cm) + 2 * lay.tie_cap;
+      lmv[tid] = lm;
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int w = 1; w < WAVES; ++w) {
+          const uint64_t x = lmv[lane + w * SL_WAVE];
+          lm = x > lm ? x : lm;
+        }
+      }
+    }
+    if (!shared || wave == 0) {
+      uint64_t kth = 0;
+      for (uint32_t r = 0; r < kq; ++r) {
+        const uint64_t m = wave_max64(lm);
+        kth = m;  // 0 once the wave has fewer than kq distinct lane maxima
+        if (m == 0) break;
+        if (lm == m) lm = 0;
+      }
+      if (lane == 0 && kth) atomicMax((unsigned long long*)bound, (unsigned long long)kth);
+    }
     __syncthreads();
     const uint64_t B = *bound;
     if (B != 0) {
