@@ -76,55 +76,55 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 
 
-# Which kernel each build phase is and its source file; the committed counter
-# summary holds scaled FETCH_SIZE + WRITE_SIZE bytes per dispatch of each
-# kernel, reported only while the kernel's source is the one the counters
-# were taken on.
-PHASE_KERNEL = {"sort_downsweep": ("k_downsweep", "sort.hip"), "sort_upsweep": ("k_upsweep", "sort.hip"),
-                "sort_scan": ("k_scan", "sort.hip"), "hash": ("k_hash_rows", "hash.hip"),
-                "select": ("k_select_light", "select.hip"), "segment_bounds": ("k_segment_bounds", "hash.hip"),
-                "heavy": ("k_select_chunks", "select.hip"), "validate": ("k_validate_rows", "hash.hip")}
+# Which source file each build phase's kernels (and the query kernel) live
+# in.  The committed counter summary holds scaled FETCH_SIZE + WRITE_SIZE
+# bytes per launch of each phase; a row is used only while its source is the
+# one the counters were taken on.
+PHASE_SRC = {"validate": "hash.hip", "hash": "hash.hip", "sort_upsweep": "sort.hip", "sort_scan": "sort.hip",
+             "sort_downsweep": "sort.hip", "segment_bounds": "hash.hip", "select": "select.hip",
+             "heavy": "select.hip", "query": "query.hip"}
+PHASE_KERNEL = {"sort_downsweep": "k_downsweep", "sort_upsweep": "k_upsweep", "hash": "k_hash_rows",
+                "select": "k_select_light", "segment_bounds": "k_segment_bounds", "query": "k_query"}
 COUNTERS = os.path.join(ROOT, "profiles", "c1_hbm_counters.md")
 
 
 def _counter_rows(path=COUNTERS):
-    """{kernel: (dispatches, traffic GB per dispatch)} of the counter summary,
-    keeping only kernels whose source hash still matches."""
+    """{phase: traffic bytes per launch} of the counter summary, keeping only
+    rows whose source file still hashes to the recorded sha256."""
     import hashlib
     import re
     if not os.path.exists(path):
         return {}
     txt = open(path).read()
     fresh = {}
-    for src in set(v[1] for v in PHASE_KERNEL.values()) | {"query.hip"}:
+    for src in set(PHASE_SRC.values()):
         m = re.search(r"csrc/%s sha256 ([0-9a-f]{64})" % re.escape(src), txt)
         f = os.path.join(ROOT, "paper_2008_03260_amd", "csrc", src)
         fresh[src] = bool(m) and m.group(1) == hashlib.sha256(open(f, "rb").read()).hexdigest()
     rows = {}
-    for m in re.finditer(r"^\| (k_[\w<>, ]+?) \| (\d+) \| ([\d.]+) \| ([\d.]+) \| ([\d.]+) \|", txt, flags=re.M):
-        rows[m.group(1).split("<")[0].strip()] = (int(m.group(2)), float(m.group(5)))
-    src_of = {k: v[1] for k, v in PHASE_KERNEL.values()}
-    src_of["k_query"] = "query.hip"
-    return {k: v for k, v in rows.items() if fresh.get(src_of.get(k, ""), False)}
+    for m in re.finditer(r"^\| (\w+) \| [^|]+ \| (\d+) \| ([\d.]+) \| ([\d.]+) \| ([\d.]+) \|", txt, flags=re.M):
+        ph = m.group(1)
+        if ph in PHASE_SRC and fresh[PHASE_SRC[ph]]:
+            rows[ph] = float(m.group(5)) * 1e9
+    return rows
 
 
-def counted_traffic(kernel):
-    """Scaled FETCH_SIZE + WRITE_SIZE bytes per dispatch of `kernel`, or None."""
-    r = _counter_rows().get(kernel)
-    return r[1] * 1e9 if r else None
+def counted_traffic(phase):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of a phase, or None."""
+    return _counter_rows().get(phase)
 
 
 def counted_build_traffic(prof):
-    """Counted bytes of one whole build (every build kernel's bytes per
-    dispatch times its dispatches in this build), or None if any is missing."""
+    """Counted bytes of one whole build (each phase's bytes per launch times
+    its launches in this build), or None if any phase is missing."""
+    rows = _counter_rows()
     tot = 0.0
     for ph, v in prof.items():
-        if not v["launches"] or ph not in PHASE_KERNEL:
+        if not v["launches"]:
             continue
-        t = counted_traffic(PHASE_KERNEL[ph][0])
-        if t is None:
+        if ph not in rows:
             return None
-        tot += t * v["launches"]
+        tot += rows[ph] * v["launches"]
     return tot
 
 
@@ -698,7 +698,7 @@ def main():
     dom = max((k for k in prof if prof[k]["launches"]), key=lambda k: prof[k]["total_ms"])
     d = prof[dom]
     dom_own_gbs = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9 if d["total_ms"] > 0 else 0.0
-    dom_kernel = PHASE_KERNEL.get(dom, (dom, ""))[0]
+    dom_kernel = PHASE_KERNEL.get(dom, dom)
     log("build phases: " + ", ".join(f"{k} {v['total_ms']:.1f} ms/{v['launches']}" for k, v in prof.items()))
 
     # Topkapi buckets (Section 3.1, Appendix 2): the same rows, hash seed and
@@ -837,9 +837,12 @@ def main():
                          # the bytes this kernel itself must move per launch
                          "own_alg_bytes_per_launch": d["alg_bytes"] / d["launches"],
                          "own_frac": dom_own_gbs / HBM_PEAK_GBS,
-                         "traffic": counted_traffic(dom_kernel)}},
+                         "traffic": counted_traffic(dom)}},
         "query_roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": q_gbs / HBM_PEAK_GBS,
+                           # counted bytes of one 100k-query launch (the 4-wave kernel), see
+                           # profiles/c1_query_counters.md for why writes exceed the output
+                           "traffic": counted_traffic("query") if w["nq"] == 100_000 else None,
                            "kernel": "k_query" if sched and sched.get("queries_per_ticket") == 0 else "k_query_persistent",
                            "alg_bytes_per_query": alg_q / w["nq"],
                            # random gathers: one reservoir row of 4R bytes per table and query
