@@ -489,6 +489,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="arrival window per serving rate (default: the workload's, 10 s for the 200M shard; "
                          "a point is capped at 400k requests)")
+    ap.add_argument("--serve-rates", default=None,
+                    help="comma-separated offered request rates of the serving sweep (default: the workload's)")
     ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
     ap.add_argument("--no-operating-point", action="store_true",
                     help="skip the search for the smallest index setting with recall@10 >= 0.9")
@@ -668,8 +670,10 @@ def main():
     serve = None
     if not args.no_serve:
         secs = args.serve_seconds if args.serve_seconds is not None else w.get("serve_seconds", 10.0)
-        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, secs, seeds,
-                            **({"rates": w["serve_rates"]} if "serve_rates" in w else {}))
+        rates = w.get("serve_rates")
+        if args.serve_rates:
+            rates = tuple(float(x) for x in args.serve_rates.split(","))
+        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, secs, seeds, **({"rates": rates} if rates else {}))
 
     # the smallest index setting of the same shard with recall@10 >= 0.9
     op_point = None

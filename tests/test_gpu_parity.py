@@ -633,3 +633,43 @@ def test_save_load_roundtrip(api, tmp_path, bucket):
         with pytest.raises(api.SlashError) as e:
             api.Index.load(bad)
         assert e.value.code == api.E_INVAL, name
+
+
+def test_wide_config_full_bucket_count(api):
+    # the wide configuration's own table shape (K=8, L=128, 2^18 buckets,
+    # R=128: 17 GB of reservoirs) on 20000 of its rows: seen everywhere, the
+    # fill of every bucket, the reservoir of every non-empty bucket, and 48
+    # queries of the k mix (count-min 8 x 16384, 16384 slots per query)
+    free, _ = torch.cuda.mem_get_info()
+    if free < (64 << 30):
+        pytest.skip("needs ~64 GB of free device memory")
+    master = 2024
+    gp, op = params_pair(api, k_max=100, dim=1 << 24, K=8, L=128, log2_buckets=18, R=128, cm_rows=8,
+                         log2_cm_width=14, seed=synth.derive(master, synth.STREAM_INDEX))
+    law = synth.RowLaw(synth.derive(master, synth.STREAM_DATA), 1 << 24, index="uniform", nnz="lognormal",
+                       nnz_a=500.0, nnz_b=0.8, nnz_lo=50, nnz_hi=20000)
+    n = 20000
+    ip, ix = law.rows(0, n)
+    qi, qx, src, kq = law.queries(synth.derive(master, synth.STREAM_QUERY), n, 0, 48, nnz_mode="lognormal",
+                                  median=500, sigma=0.8, lo=50, hi=20000, f=(0.1, 0.4), kmix=(1, 10, 100))
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    gi, gsn = idx.tables()
+    assert (u32(gsn) == oseen).all()
+    for t in range(op.L):  # slots in use per bucket = min(R, seen), for every bucket
+        live = (gi[t] != -1).sum(dim=1)
+        assert torch.equal(live, torch.clamp(gsn[t].to(live.dtype), max=op.R))
+    tt, bb = np.nonzero(oseen)
+    got = u32(gi[torch.from_numpy(tt).cuda(), torch.from_numpy(bb).cuda()])
+    assert (got == oids[tt, bb]).all()
+    del gi, gsn
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=100, kq=kq)
+    del oids
+    kd = dev(kq.view(np.int32))
+    gi, gs = idx.query(dev(qi), dev(qx), 0, k_per_query=kd)
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+    bi, bs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=kd)
+    torch.cuda.synchronize()
+    assert (u32(bi) == wi).all() and (u32(bs) == ws).all()
+    idx.close()
