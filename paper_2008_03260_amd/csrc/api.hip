@@ -513,13 +513,11 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
   if ((rs = validate_rows(ix, data, nullptr, st, &timer, &nnz, false)) != SLASH_OK) return bail(rs);
   const Shape& s = ix->shape;
   const uint64_t n = data.n_rows;
-  {
-    // Topkapi tables of a non-empty build are written bucket by bucket
-    hipError_t e = hipSuccess;
-    if (!s.bucket)
-      e = launch_fill_u32(ix->ids, SL_EMPTY, (uint64_t)s.L * s.nb * s.R, st);
-    else if (n == 0)
-      e = launch_tk_clear(s, tables(ix), st);
+  if (n == 0) {
+    // a non-empty build writes every bucket's slots (or cells) and seen
+    // count in its select pass, so only an empty one clears the tables
+    hipError_t e = s.bucket ? launch_tk_clear(s, tables(ix), st)
+                            : launch_fill_u32(ix->ids, SL_EMPTY, (uint64_t)s.L * s.nb * s.R, st);
     if (e == hipSuccess) e = launch_fill_u32(ix->seen, 0u, (uint64_t)s.L * s.nb, st);
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table init: %s", hipGetErrorString(e)));
   }
@@ -554,15 +552,23 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
                    part.as<uint32_t>()};
     // every table is enqueued back to back: heavy buckets are planned and
     // finished on the device, so the host never waits between tables
+    // the packed sort (ids below 2^28, keys below 2^20) writes the bucket
+    // runs itself; otherwise the sorted keys are scanned for them
+    const bool packed = packed_sort_ok(n, (int)s.B);
     for (uint32_t t = 0; t < s.L; ++t) {
       uint32_t *sk = nullptr, *sv = nullptr;
-      e = radix_sort(keys.as<uint32_t>() + (uint64_t)t * n, nullptr, n, (int)s.B, sb, &sk, &sv, st, &timer);
-      if (e == hipSuccess) e = launch_fill_u32(start.as<uint32_t>(), 0u, s.nb, st);
+      const uint32_t* tkeys = keys.as<uint32_t>() + (uint64_t)t * n;
+      e = launch_fill_u32(start.as<uint32_t>(), 0u, s.nb, st);
       if (e == hipSuccess) e = launch_fill_u32(end.as<uint32_t>(), 0u, s.nb, st);
       if (e == hipSuccess) e = launch_fill_u32(heavy_n.as<uint32_t>(), 0u, 1, st);
-      timer.begin(PH_BOUNDS, st);
-      if (e == hipSuccess) e = launch_segment_bounds(sk, n, start.as<uint32_t>(), end.as<uint32_t>(), st);
-      timer.end(PH_BOUNDS, st);
+      if (e == hipSuccess && packed) {
+        e = radix_sort_runs(tkeys, n, (int)s.B, sb, start.as<uint32_t>(), end.as<uint32_t>(), &sv, st, &timer);
+      } else if (e == hipSuccess) {
+        e = radix_sort(tkeys, nullptr, n, (int)s.B, sb, &sk, &sv, st, &timer);
+        timer.begin(PH_BOUNDS, st);
+        if (e == hipSuccess) e = launch_segment_bounds(sk, n, start.as<uint32_t>(), end.as<uint32_t>(), st);
+        timer.end(PH_BOUNDS, st);
+      }
       timer.begin(PH_SELECT, st);
       if (e == hipSuccess && s.bucket)
         e = launch_tk_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavyTk,
@@ -590,12 +596,27 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
   {
     // algorithmic bytes: what each phase must read and write once
     const double N = (double)n, L = s.L, NB = s.nb;
-    const double passes = (s.B + 7) / 8;
+    const int passes = (int)(s.B + 7) / 8;
     ix->phase_bytes[PH_VALIDATE] = 4.0 * nnz + 8.0 * (N + 1);
     ix->phase_bytes[PH_HASH] = 4.0 * nnz + 8.0 * (N + 1) + 4.0 * L * N;
-    ix->phase_bytes[PH_UPSWEEP] = 4.0 * N * L * passes;
-    ix->phase_bytes[PH_DOWNSWEEP] = L * (12.0 * N + (passes - 1) * 16.0 * N);
-    ix->phase_bytes[PH_BOUNDS] = 4.0 * N * L + 8.0 * NB * L;
+    if (packed_sort_ok(n, (int)s.B)) {
+      // counts read 4 B keys, then 2 B low halves (digits below bit 16) or
+      // 4 B words; a scatter reads 4 B keys (first pass) or 6 B packed items
+      // and writes 6 B packed items, or 4 B ids (last pass) and the runs
+      double up = 0, down = 0;
+      for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p, bits = std::min(8, (int)s.B - shift);
+        up += p == 0 ? 4.0 : (shift + bits <= 16 ? 2.0 : 4.0);
+        down += (p == 0 ? 4.0 : 6.0) + (p + 1 == passes ? 4.0 : 6.0);
+      }
+      ix->phase_bytes[PH_UPSWEEP] = up * N * L;
+      ix->phase_bytes[PH_DOWNSWEEP] = down * N * L;
+      ix->phase_bytes[PH_BOUNDS] = 8.0 * NB * L;  // the runs, written once
+    } else {
+      ix->phase_bytes[PH_UPSWEEP] = 4.0 * N * L * passes;
+      ix->phase_bytes[PH_DOWNSWEEP] = L * (12.0 * N + (passes - 1) * 16.0 * N);
+      ix->phase_bytes[PH_BOUNDS] = 4.0 * N * L + 8.0 * NB * L;
+    }
     ix->phase_bytes[PH_SELECT] = L * (4.0 * N + 8.0 * NB + NB * (4.0 * (double)bucket_words(s) + 4.0));
   }
   ix->n_items = n;

@@ -271,16 +271,10 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE, 8)
   // the bounds of the wave's next bucket are loaded while this one is reduced
   uint32_t b = blockIdx.x * kSelWaves + wave;
   uint32_t s_next = 0, e_next = 0;
-  if (b < s.nb) {
-    s_next = start[b];
-    e_next = end[b];
-  }
+  if (b < s.nb) bucket_run(start, end, b, s_next, e_next);
   for (; b < s.nb; b += nwaves) {
     const uint32_t s0 = s_next, e0 = e_next;
-    if (b + nwaves < s.nb) {
-      s_next = start[b + nwaves];
-      e_next = end[b + nwaves];
-    }
+    if (b + nwaves < s.nb) bucket_run(start, end, b + nwaves, s_next, e_next);
     const uint32_t n = e0 - s0;
     uint32_t* out = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
     if (n <= 8 * SL_WAVE && s.R <= SL_WAVE) {

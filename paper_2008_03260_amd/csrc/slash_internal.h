@@ -155,6 +155,24 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
                       SortBuffers& b, uint32_t** keys_out, uint32_t** vals_out, hipStream_t st,
                       PhaseTimer* timer = nullptr);
 
+// The build's sort: n ids (the positions 0..n-1) by their keys' bits
+// [0, nbits), carried as 6 bytes per item; needs packed_sort_ok(n, nbits).
+// Writes the ids in key order to *ids_out (one of b.k0 / b.k1) and each key's
+// run [start[key], end[key]); keys with no items keep what start and end held
+// (fill both with 0).
+bool packed_sort_ok(uint64_t n, int nbits);
+hipError_t radix_sort_runs(const uint32_t* keys_in, uint64_t n, int nbits, SortBuffers& b, uint32_t* start,
+                           uint32_t* end, uint32_t** ids_out, hipStream_t st, PhaseTimer* timer = nullptr);
+
+// Bounds [s0, e0) of a bucket's run as the build wrote them (an empty run as
+// (0, 0); any e0 <= s0 is taken as empty).
+__device__ __forceinline__ void bucket_run(const uint32_t* start, const uint32_t* end, uint32_t b, uint32_t& s0,
+                                           uint32_t& e0) {
+  s0 = start[b];
+  e0 = end[b];
+  if (e0 <= s0) s0 = e0 = 0;
+}
+
 // Exclusive scan of n uint32 (in place), scratch `part` of sort_part_entries(n).
 hipError_t exclusive_scan(uint32_t* data, uint64_t n, uint32_t* part, hipStream_t st);
 

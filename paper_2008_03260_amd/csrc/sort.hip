@@ -1,13 +1,27 @@
-// Device LSD radix sort (key-value, uint32) and exclusive scan.
+// Device LSD radix sort and exclusive scan.
 //
 // Each pass: (1) every tile of 8192 keys counts its digits in LDS, counts are
 // stored digit-major; (2) an exclusive scan of the counts gives every
 // (digit, tile) its output offset; (3) every tile ranks its keys stably (a
 // wave ranks 64 keys at once by matching digits with ballots; waves own
 // consecutive sub-tiles), stages them in LDS in digit order and writes each
-// digit's run contiguously.  No global atomics, so the output is
-// deterministic.  The scatter visits tiles in XCD-contiguous order so that
-// the short runs that neighbouring tiles write for one digit meet in one L2.
+// digit's run contiguously.  The scatter visits tiles in XCD-contiguous order
+// so that the short runs that neighbouring tiles write for one digit meet in
+// one L2.
+//
+// Two item forms.  The general form moves a uint32 key and a uint32 value
+// (no global atomics: the output is deterministic).  The build's packed form
+// (ids below 2^28, keys below 2^20) moves 6 bytes per item: the key's low 16
+// bits in a uint16 array and a uint32 word holding key bits 16-19 above a
+// 28-bit id; its first pass reads the hash keys with the ids implicit, and its
+// last pass writes the ids alone plus each key's [start, end) run (a key
+// changes between neighbours inside a tile's digit run: a plain store; at the
+// edges of a run it may continue in another tile, so the edge items' keys are
+// written to a side array and a small pass over the (digit, tile) runs
+// compares each run's first and last key with its global neighbours), so no
+// sorted keys are written and no pass over all items finds the runs.  No
+// atomics: a Zipf head bucket spans thousands of tiles, and device-wide
+// atomics on its two words serialised the pass.
 #include "slash_internal.h"
 
 namespace slash {
@@ -49,38 +63,82 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return off + inc - v;
 }
 
-// Keys (and values) of one wave's sub-tile: every load is issued before any
-// is used, unpredicated when the tile is full.
-template <bool WITH_VALS>
-__device__ __forceinline__ void load_subtile(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                             uint64_t sbase, uint64_t n, bool full, uint32_t (&key)[kRounds],
-                                             uint32_t (&val)[kRounds]) {
+// Input and output item forms of a scatter pass.
+enum { IN_KV = 0, IN_KEYS = 1, IN_PACKED = 2 };    // key+value, keys (values = positions), packed
+enum { OUT_KV = 0, OUT_PACKED = 1, OUT_IDS = 2 };  // key+value, packed, ids + key runs
+constexpr uint32_t kIdBits = 28, kIdMask = (1u << kIdBits) - 1;
+
+struct ScatterIO {
+  const uint32_t* kin;  // IN_KV, IN_KEYS: keys
+  const uint32_t* vin;  // IN_KV: values
+  const uint16_t* lin;  // IN_PACKED: low key halves
+  const uint32_t* win;  // IN_PACKED: words
+  uint32_t* kout;       // OUT_KV: keys
+  uint32_t* vout;       // OUT_KV: values; OUT_IDS: ids
+  uint16_t* lout;       // OUT_PACKED: low key halves
+  uint32_t* wout;       // OUT_PACKED: words
+  uint32_t* start;      // OUT_IDS: first position of each key whose run starts inside a tile's digit run
+  uint32_t* end;        // OUT_IDS: one past its last position, likewise
+  uint32_t* edge;       // OUT_IDS: keys at the first and last position of every (digit, tile) run
+};
+
+__device__ __forceinline__ uint32_t packed_key(uint16_t lo, uint32_t w) { return (uint32_t)lo | ((w >> kIdBits) << 16); }
+
+// Keys and values of one wave's sub-tile: every load is issued before any is
+// used, unpredicated when the tile is full.
+template <int IN>
+__device__ __forceinline__ void load_subtile(const ScatterIO& io, uint64_t sbase, uint64_t n, bool full,
+                                             uint32_t (&key)[kRounds], uint32_t (&val)[kRounds]) {
   const uint32_t lane = lane_id();
+  if (IN == IN_PACKED) {
+    uint16_t lo[kRounds];
+    uint32_t w[kRounds];
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) lo[r] = io.lin[sbase + (uint64_t)r * SL_WAVE + lane];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) w[r] = io.win[sbase + (uint64_t)r * SL_WAVE + lane];
+    } else {
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const uint64_t i = sbase + (uint64_t)r * SL_WAVE + lane;
+        lo[r] = i < n ? io.lin[i] : (uint16_t)0;
+        w[r] = i < n ? io.win[i] : 0u;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      key[r] = packed_key(lo[r], w[r]);
+      val[r] = w[r] & kIdMask;
+    }
+    return;
+  }
   if (full) {
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) key[r] = kin[sbase + (uint64_t)r * SL_WAVE + lane];
-    if (WITH_VALS) {
+    for (int r = 0; r < kRounds; ++r) key[r] = io.kin[sbase + (uint64_t)r * SL_WAVE + lane];
+    if (IN == IN_KV) {
 #pragma unroll
-      for (int r = 0; r < kRounds; ++r) val[r] = vin[sbase + (uint64_t)r * SL_WAVE + lane];
+      for (int r = 0; r < kRounds; ++r) val[r] = io.vin[sbase + (uint64_t)r * SL_WAVE + lane];
     }
   } else {
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       const uint64_t i = sbase + (uint64_t)r * SL_WAVE + lane;
-      key[r] = i < n ? kin[i] : 0u;
-      if (WITH_VALS) val[r] = i < n ? vin[i] : 0u;
+      key[r] = i < n ? io.kin[i] : 0u;
+      if (IN == IN_KV) val[r] = i < n ? io.vin[i] : 0u;
     }
   }
-  if (!WITH_VALS) {
+  if (IN == IN_KEYS) {
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) val[r] = (uint32_t)(sbase + (uint64_t)r * SL_WAVE + lane);
   }
 }
 
-template <int BITS>
+// Digit counts of one tile.  T = uint32_t: keys (HI: packed words, whose
+// key bits 16-19 sit above the id); T = uint16_t: packed low key halves.
+template <int BITS, typename T, bool HI>
 __global__ void __launch_bounds__(kThreads)
-    k_upsweep(const uint32_t* __restrict__ keys, uint64_t n, int shift, uint32_t* __restrict__ hist,
-              uint32_t n_tiles) {
+    k_upsweep(const T* __restrict__ keys, uint64_t n, int shift, uint32_t* __restrict__ hist, uint32_t n_tiles) {
   __shared__ uint32_t cnt[256];
   constexpr uint32_t nd = 1u << BITS, dmask = nd - 1;
   for (uint32_t d = threadIdx.x; d < nd; d += kThreads) cnt[d] = 0;
@@ -96,8 +154,12 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
-      k[j] = i < n ? keys[i] : 0u;
+      k[j] = i < n ? (uint32_t)keys[i] : 0u;
     }
+  }
+  if (HI) {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) k[j] = (k[j] >> kIdBits) << 16;
   }
   // Counts need no ranks: each key adds one with an LDS atomic.  Skewed
   // buckets make many lanes of a wave share a digit, and LDS atomics to one
@@ -123,11 +185,9 @@ __global__ void __launch_bounds__(kThreads)
   for (uint32_t d = threadIdx.x; d < nd; d += kThreads) hist[(uint64_t)d * n_tiles + blockIdx.x] = cnt[d];
 }
 
-template <int BITS>
+template <int BITS, int IN, int OUT>
 __global__ void __launch_bounds__(kThreads)
-    k_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t n, int shift,
-                const uint32_t* __restrict__ offs, uint32_t n_tiles, uint32_t* __restrict__ kout,
-                uint32_t* __restrict__ vout) {
+    k_downsweep(ScatterIO io, uint64_t n, int shift, const uint32_t* __restrict__ offs, uint32_t n_tiles) {
   __shared__ uint32_t wcnt[kWaves][256];
   __shared__ uint32_t tile_off[256];
   __shared__ uint32_t goff[256];  // output offset of the digit's run, minus its tile offset
@@ -141,10 +201,9 @@ __global__ void __launch_bounds__(kThreads)
   const uint64_t sbase = tbase + (uint64_t)wave * kSubTile;
   const bool full = tbase + kTile <= n;
   uint32_t key[kRounds], val[kRounds], loc[kRounds];
-  if (vin)
-    load_subtile<true>(kin, vin, sbase, n, full, key, val);
-  else
-    load_subtile<false>(kin, vin, sbase, n, full, key, val);
+  load_subtile<IN>(io, sbase, n, full, key, val);
+  // the tile's output offset per digit, in flight while the keys are ranked
+  const uint32_t my_off = threadIdx.x < nd ? offs[(uint64_t)threadIdx.x * n_tiles + tile] : 0u;
   for (uint32_t e = threadIdx.x; e < kWaves * 256; e += kThreads) (&wcnt[0][0])[e] = 0;
   __syncthreads();
 #pragma unroll
@@ -176,7 +235,7 @@ __global__ void __launch_bounds__(kThreads)
   uint32_t off = block_excl_scan(tot_d, scan_sh, &total);
   if (threadIdx.x < nd) {
     tile_off[threadIdx.x] = off;
-    goff[threadIdx.x] = offs[(uint64_t)threadIdx.x * n_tiles + tile] - off;
+    goff[threadIdx.x] = my_off - off;
   }
   __syncthreads();
 #pragma unroll
@@ -191,11 +250,42 @@ __global__ void __launch_bounds__(kThreads)
   __syncthreads();
   const uint32_t tn = (uint32_t)min((uint64_t)kTile, n - tbase);
   for (uint32_t p = threadIdx.x; p < tn; p += kThreads) {
-    uint32_t k = sk[p];
-    uint32_t d = (k >> shift) & dmask;
-    uint32_t g = goff[d] + p;
-    kout[g] = k;
-    vout[g] = sv[p];
+    const uint32_t k = sk[p];
+    const uint32_t d = (k >> shift) & dmask;
+    const uint32_t g = goff[d] + p;
+    if (OUT == OUT_KV) {
+      io.kout[g] = k;
+      io.vout[g] = sv[p];
+    } else if (OUT == OUT_PACKED) {
+      io.lout[g] = (uint16_t)k;
+      io.wout[g] = ((k >> 16) << kIdBits) | sv[p];
+    } else {
+      io.vout[g] = sv[p];
+      // inside the tile's run of digit d the key's neighbours are its global
+      // neighbours; at the run's edges they lie in other tiles
+      const bool first = p == 0 || ((sk[p - 1] >> shift) & dmask) != d;
+      const bool last = p + 1 == tn || ((sk[p + 1] >> shift) & dmask) != d;
+      if (first || last) io.edge[g] = k;
+      if (!first && sk[p - 1] != k) io.start[k] = g;
+      if (!last && sk[p + 1] != k) io.end[k] = g + 1;
+    }
+  }
+}
+
+// After the last scatter: every (digit, tile) run's first and last item
+// decide their key's start and end when the item on their other side (the
+// neighbouring run's edge item, or nothing) holds another key.  `offs` are
+// the pass's scanned digit-major counts, so a run is [offs[e], offs[e + 1]).
+__global__ void __launch_bounds__(256)
+    k_run_edges(const uint32_t* __restrict__ offs, uint64_t n_runs, uint64_t n, const uint32_t* __restrict__ edge,
+                uint32_t* __restrict__ start, uint32_t* __restrict__ end) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_runs;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = offs[e], o1 = e + 1 < n_runs ? offs[e + 1] : (uint32_t)n;
+    if (o1 == o) continue;
+    const uint32_t kf = edge[o], kl = edge[o1 - 1];
+    if (o == 0 || edge[o - 1] != kf) start[kf] = o;
+    if (o1 == n || edge[o1] != kl) end[kl] = o1;
   }
 }
 
@@ -247,34 +337,53 @@ __global__ void __launch_bounds__(kThreads) k_scan_down(uint32_t* __restrict__ d
   }
 }
 
-typedef void (*UpFn)(const uint32_t*, uint64_t, int, uint32_t*, uint32_t);
-typedef void (*DownFn)(const uint32_t*, const uint32_t*, uint64_t, int, const uint32_t*, uint32_t, uint32_t*,
-                       uint32_t*);
-
-UpFn upsweep_fn(int bits) {
+template <typename T, bool HI>
+const void* upsweep_fn(int bits) {
   switch (bits) {
-    case 1: return k_upsweep<1>;
-    case 2: return k_upsweep<2>;
-    case 3: return k_upsweep<3>;
-    case 4: return k_upsweep<4>;
-    case 5: return k_upsweep<5>;
-    case 6: return k_upsweep<6>;
-    case 7: return k_upsweep<7>;
-    default: return k_upsweep<8>;
+    case 1: return (const void*)k_upsweep<1, T, HI>;
+    case 2: return (const void*)k_upsweep<2, T, HI>;
+    case 3: return (const void*)k_upsweep<3, T, HI>;
+    case 4: return (const void*)k_upsweep<4, T, HI>;
+    case 5: return (const void*)k_upsweep<5, T, HI>;
+    case 6: return (const void*)k_upsweep<6, T, HI>;
+    case 7: return (const void*)k_upsweep<7, T, HI>;
+    default: return (const void*)k_upsweep<8, T, HI>;
   }
 }
 
-DownFn downsweep_fn(int bits) {
+template <int IN, int OUT>
+const void* downsweep_fn(int bits) {
   switch (bits) {
-    case 1: return k_downsweep<1>;
-    case 2: return k_downsweep<2>;
-    case 3: return k_downsweep<3>;
-    case 4: return k_downsweep<4>;
-    case 5: return k_downsweep<5>;
-    case 6: return k_downsweep<6>;
-    case 7: return k_downsweep<7>;
-    default: return k_downsweep<8>;
+    case 1: return (const void*)k_downsweep<1, IN, OUT>;
+    case 2: return (const void*)k_downsweep<2, IN, OUT>;
+    case 3: return (const void*)k_downsweep<3, IN, OUT>;
+    case 4: return (const void*)k_downsweep<4, IN, OUT>;
+    case 5: return (const void*)k_downsweep<5, IN, OUT>;
+    case 6: return (const void*)k_downsweep<6, IN, OUT>;
+    case 7: return (const void*)k_downsweep<7, IN, OUT>;
+    default: return (const void*)k_downsweep<8, IN, OUT>;
   }
+}
+
+// One pass: digit counts, their scan, the scatter.
+template <typename T, bool HI>
+hipError_t sort_pass(const T* ukeys, const void* down, const ScatterIO& io, uint64_t n, int shift, int bits,
+                     uint32_t n_tiles, SortBuffers& b, hipStream_t st, PhaseTimer* timer) {
+  typedef void (*UpFn)(const T*, uint64_t, int, uint32_t*, uint32_t);
+  typedef void (*DownFn)(ScatterIO, uint64_t, int, const uint32_t*, uint32_t);
+  const UpFn up = (UpFn)upsweep_fn<T, HI>(bits);
+  const DownFn dn = (DownFn)down;
+  if (timer) timer->begin(PH_UPSWEEP, st);
+  hipLaunchKernelGGL(up, dim3(n_tiles), dim3(kThreads), 0, st, ukeys, n, shift, b.hist, n_tiles);
+  if (timer) timer->end(PH_UPSWEEP, st);
+  if (timer) timer->begin(PH_SCAN, st);
+  hipError_t e = exclusive_scan(b.hist, (uint64_t)n_tiles << bits, b.part, st);
+  if (timer) timer->end(PH_SCAN, st);
+  if (e != hipSuccess) return e;
+  if (timer) timer->begin(PH_DOWNSWEEP, st);
+  hipLaunchKernelGGL(dn, dim3(n_tiles), dim3(kThreads), 0, st, io, n, shift, (const uint32_t*)b.hist, n_tiles);
+  if (timer) timer->end(PH_DOWNSWEEP, st);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -305,23 +414,69 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
     dk = (p & 1) ? b.k1 : b.k0;
     dv = (p & 1) ? b.v1 : b.v0;
     if (n > 0) {
-      if (timer) timer->begin(PH_UPSWEEP, st);
-      hipLaunchKernelGGL(upsweep_fn(bits), dim3(n_tiles), dim3(kThreads), 0, st, sk, n, shift, b.hist, n_tiles);
-      if (timer) timer->end(PH_UPSWEEP, st);
-      if (timer) timer->begin(PH_SCAN, st);
-      hipError_t e = exclusive_scan(b.hist, (uint64_t)n_tiles << bits, b.part, st);
-      if (timer) timer->end(PH_SCAN, st);
+      ScatterIO io{};
+      io.kin = sk;
+      io.vin = sv;
+      io.kout = dk;
+      io.vout = dv;
+      const void* down = sv ? downsweep_fn<IN_KV, OUT_KV>(bits) : downsweep_fn<IN_KEYS, OUT_KV>(bits);
+      hipError_t e = sort_pass<uint32_t, false>(sk, down, io, n, shift, bits, n_tiles, b, st, timer);
       if (e != hipSuccess) return e;
-      if (timer) timer->begin(PH_DOWNSWEEP, st);
-      hipLaunchKernelGGL(downsweep_fn(bits), dim3(n_tiles), dim3(kThreads), 0, st, sk, sv, n, shift, b.hist, n_tiles,
-                         dk, dv);
-      if (timer) timer->end(PH_DOWNSWEEP, st);
     }
     sk = dk;
     sv = dv;
   }
   *keys_out = dk;
   *vals_out = dv;
+  return hipGetLastError();
+}
+
+bool packed_sort_ok(uint64_t n, int nbits) { return n <= (1ull << kIdBits) && nbits >= 1 && nbits <= 20; }
+
+hipError_t radix_sort_runs(const uint32_t* keys_in, uint64_t n, int nbits, SortBuffers& b, uint32_t* start,
+                           uint32_t* end, uint32_t** ids_out, hipStream_t st, PhaseTimer* timer) {
+  if (!packed_sort_ok(n, nbits)) return hipErrorInvalidValue;
+  const int passes = (nbits + 7) / 8;
+  const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+  uint16_t* lo[2] = {(uint16_t*)b.k0, (uint16_t*)b.k1};
+  uint32_t* w[2] = {b.v0, b.v1};
+  // the last pass writes the ids over the low halves of its own parity and
+  // the run-edge keys over its words, neither of which is its input
+  uint32_t* ids = ((passes - 1) & 1) ? b.k1 : b.k0;
+  uint32_t* edge = w[(passes - 1) & 1];
+  if (n > 0) {
+    for (int p = 0; p < passes; ++p) {
+      const int shift = p * 8, bits = min(8, nbits - shift);
+      const bool first = p == 0, last = p + 1 == passes;
+      ScatterIO io{};
+      io.kin = keys_in;
+      io.lin = lo[(p + 1) & 1];
+      io.win = w[(p + 1) & 1];
+      io.lout = lo[p & 1];
+      io.wout = w[p & 1];
+      io.vout = ids;
+      io.start = start;
+      io.end = end;
+      io.edge = edge;
+      const void* down = first ? (last ? downsweep_fn<IN_KEYS, OUT_IDS>(bits) : downsweep_fn<IN_KEYS, OUT_PACKED>(bits))
+                               : (last ? downsweep_fn<IN_PACKED, OUT_IDS>(bits) : downsweep_fn<IN_PACKED, OUT_PACKED>(bits));
+      hipError_t e;
+      if (first)
+        e = sort_pass<uint32_t, false>(keys_in, down, io, n, shift, bits, n_tiles, b, st, timer);
+      else if (shift + bits <= 16)
+        e = sort_pass<uint16_t, false>(io.lin, down, io, n, shift, bits, n_tiles, b, st, timer);
+      else
+        e = sort_pass<uint32_t, true>(io.win, down, io, n, shift, bits, n_tiles, b, st, timer);
+      if (e != hipSuccess) return e;
+    }
+    const int last_bits = nbits - 8 * (passes - 1);
+    const uint64_t n_runs = (uint64_t)n_tiles << last_bits;
+    if (timer) timer->begin(PH_BOUNDS, st);
+    hipLaunchKernelGGL(k_run_edges, dim3((uint32_t)std::min<uint64_t>((n_runs + 255) / 256, 65536)), dim3(256), 0, st,
+                       (const uint32_t*)b.hist, n_runs, n, (const uint32_t*)edge, start, end);
+    if (timer) timer->end(PH_BOUNDS, st);
+  }
+  *ids_out = ids;
   return hipGetLastError();
 }
 

@@ -97,7 +97,8 @@ __global__ void __launch_bounds__(kTkWaves * SL_WAVE)
   const uint32_t nc = tk_cells(s), ncp = tk_ncp(nc);
   const TkAcc a = tk_acc(lds32 + wave * 3 * ncp, ncp);
   for (uint32_t b = blockIdx.x * kTkWaves + wave; b < s.nb; b += gridDim.x * kTkWaves) {
-    const uint32_t s0 = start[b], e0 = end[b];
+    uint32_t s0, e0;
+    bucket_run(start, end, b, s0, e0);
     if (e0 - s0 > heavy_t) {
       if (lane == 0) {
         const uint32_t h = atomicAdd(heavy_n, 1u);
@@ -149,7 +150,8 @@ __global__ void __launch_bounds__(kTkChunkThreads)
   uint64_t base = 0;  // chunks of the buckets before h
   for (uint32_t h = 0; h < nh; ++h) {
     const uint32_t b = heavy_list[h];
-    const uint32_t s0 = start[b], e0 = end[b];
+    uint32_t s0, e0;
+    bucket_run(start, end, b, s0, e0);
     const uint32_t nch = (e0 - s0 + kTkChunk - 1) / kTkChunk;
     // this block's chunks of bucket h: global chunk numbers = blockIdx.x (mod grid)
     uint64_t j0 = (blockIdx.x + gridDim.x - (uint32_t)(base % gridDim.x)) % gridDim.x;
@@ -239,7 +241,11 @@ __global__ void __launch_bounds__(kTkChunkThreads)
                  : odd           ? make_uint2(top[3 * i + 1], 1u)
                                  : make_uint2(top[3 * i + 2], 0u);
     }
-    if (threadIdx.x == 0) tab.seen[(uint64_t)t * s.nb + b] = end[b] - start[b];
+    if (threadIdx.x == 0) {
+      uint32_t s0, e0;
+      bucket_run(start, end, b, s0, e0);
+      tab.seen[(uint64_t)t * s.nb + b] = e0 - s0;
+    }
   }
 }
 

@@ -94,10 +94,16 @@ def check_tables(api, idx, op, cs, ip, ix):
     assert len(bad) == 0, bad[:5]
 
 
+# bucket bits choose the sort's passes: 3 (one pass), 8 (one full pass), 10
+# and 12 (two), 17 and 20 (three, the last of 1 and 4 bits); 22 bits take the
+# general key-value sort and the separate scan for bucket runs
 @pytest.mark.parametrize("shape", [dict(), dict(L=16, log2_buckets=12, R=32), dict(K=2, L=5, log2_buckets=3, R=7),
                                    dict(hash_mode=1, L=6), dict(hash_mode=2, L=6), dict(R=1),
-                                   dict(R=130, log2_buckets=6)],
-                         ids=["base", "wide", "tiny-buckets", "mode1", "mode2", "R1", "R130"])
+                                   dict(R=130, log2_buckets=6), dict(L=4, log2_buckets=8),
+                                   dict(L=3, log2_buckets=17, R=4), dict(L=4, log2_buckets=20, R=8),
+                                   dict(L=2, log2_buckets=22, R=4)],
+                         ids=["base", "wide", "tiny-buckets", "mode1", "mode2", "R1", "R130", "B8", "B17", "B20",
+                              "B22-general-sort"])
 def test_build_parity(api, shape):
     gp, op = params_pair(api, **shape)
     _, (ip, ix) = rows_of(20000, seed=5)
