@@ -81,10 +81,10 @@ HBM_PEAK_GBS = 8000.0
 # bytes per launch of each phase; a row is used only while its source is the
 # one the counters were taken on.
 PHASE_SRC = {"validate": "hash.hip", "hash": "hash.hip", "sort_upsweep": "sort.hip", "sort_scan": "sort.hip",
-             "sort_downsweep": "sort.hip", "segment_bounds": "hash.hip", "select": "select.hip",
+             "sort_downsweep": "sort.hip", "segment_bounds": "sort.hip", "select": "select.hip",
              "heavy": "select.hip", "query": "query.hip"}
 PHASE_KERNEL = {"sort_downsweep": "k_downsweep", "sort_upsweep": "k_upsweep", "hash": "k_hash_rows",
-                "select": "k_select_light", "segment_bounds": "k_segment_bounds", "query": "k_query"}
+                "select": "k_select_light", "segment_bounds": "k_run_edges", "query": "k_query"}
 COUNTERS = os.path.join(ROOT, "profiles", "c1_hbm_counters.md")
 
 
