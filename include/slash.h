@@ -314,7 +314,10 @@ SLASH_API void slash_release_cache(void);
  * device batches as staging slots free up and launches them on one device
  * stream in submission order, so a query admitted in epoch e sees exactly
  * the inserts submitted before it; inserts queued back to back are applied
- * in one launch (each still closes its own epoch).  Batch slots (device and
+ * in one launch (each still closes its own epoch).  Inserts are prepared
+ * ahead in submission order (copied in, hashed and grouped on a second
+ * stream into per-slot scratch, up to four at a time), so only their table
+ * writes sit in the ordered stream.  Batch slots (device and
  * pinned host staging for one batch) are added while requests wait for one,
  * up to max_inflight, as long as the HBM budget and the device's free memory
  * (checked when a slot is added, leaving 1 GiB free) allow. */

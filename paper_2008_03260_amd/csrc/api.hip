@@ -646,11 +646,40 @@ slash_status slash::reserve_insert_scratch(slash_index* ix, uint64_t rows) {
 
 extern "C" slash_status slash_insert(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev,
                                      void* stream) {
-  return slash::insert_rows(ix, rows, flags, new_ids_dev, (hipStream_t)stream, InsertGate{});
+  return slash::insert_rows(ix, rows, flags, new_ids_dev, (hipStream_t)stream);
+}
+
+bool slash::insert_scratch_bytes(const slash_index* ix, uint32_t rows, size_t* keys_bytes, size_t* runs_bytes) {
+  if (!ix || !small_insert_ok(ix->shape, rows)) return false;
+  *keys_bytes = (size_t)rows * ix->shape.L * 4;
+  *runs_bytes = small_insert_scratch(ix->shape, rows);
+  return true;
+}
+
+slash_status slash::insert_prepare(slash_index* ix, slash_csr rows, const InsertScratch& sc, hipStream_t st,
+                                   uint32_t* first_id) {
+  if (!ix || !first_id) return fail(SLASH_E_INVAL, "NULL argument");
+  const uint64_t n = rows.n_rows;
+  if (n == 0 || n > sc.rows || !small_insert_ok(ix->shape, n))
+    return fail(SLASH_E_INVAL, "insert of %llu rows does not fit the scratch", (unsigned long long)n);
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->n_items + n > 0xFFFFFFFFull) return fail(SLASH_E_CAPACITY, "ids would exceed 0xFFFFFFFE");
+  const uint32_t first = (uint32_t)ix->n_items;
+  HIP_TRY(launch_hash_rows(ix->shape, ix->cv, rows, sc.keys, n, 0, st));
+  HIP_TRY(launch_insert_group(ix->shape, sc.keys, (uint32_t)n, first, sc.runs, st));
+  ix->n_items += n;
+  *first_id = first;
+  return SLASH_OK;
+}
+
+slash_status slash::insert_commit(slash_index* ix, const InsertScratch& sc, uint32_t n, hipStream_t st) {
+  if (!ix || n == 0 || n > sc.rows) return fail(SLASH_E_INVAL, "bad insert commit");
+  HIP_TRY(launch_insert_runs(ix->shape, ix->cv, sc.runs, n, tables(ix), st));
+  return SLASH_OK;
 }
 
 slash_status slash::insert_rows(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev,
-                                hipStream_t st, const InsertGate& gate) {
+                                hipStream_t st) {
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");
   const uint64_t n = rows.n_rows;
   if (n == 0) return SLASH_OK;
@@ -666,7 +695,7 @@ slash_status slash::insert_rows(slash_index* ix, slash_csr rows, uint32_t flags,
       return fail(SLASH_E_NOMEM, "insert scratch allocation failed");
     HIP_TRY(launch_hash_rows(s, ix->cv, rows, ix->ins_keys.as<uint32_t>(), n, 0, st));
     HIP_TRY(launch_insert_small(s, ix->cv, ix->ins_keys.as<uint32_t>(), (uint32_t)n, first, ix->ins_seg.p, tables(ix),
-                                st, gate));
+                                st));
     if (new_ids_dev) HIP_TRY(launch_iota_u32(new_ids_dev, first, n, st));
     ix->n_items += n;
     return SLASH_OK;
@@ -687,7 +716,7 @@ slash_status slash::insert_rows(slash_index* ix, slash_csr rows, uint32_t flags,
   int bits = (int)s.B + ceil_log2(s.L);
   HIP_TRY(radix_sort(ix->ins_keys.as<uint32_t>(), ix->ins_vals.as<uint32_t>(), items, bits, sb, &sk, &sv, st));
   HIP_TRY(launch_insert_merge(s, ix->cv, sk, sv, items, ix->ins_seg.as<uint32_t>(), ix->ins_part.as<uint32_t>(),
-                              tables(ix), st, gate));
+                              tables(ix), st));
   if (new_ids_dev) HIP_TRY(launch_iota_u32(new_ids_dev, first, n, st));
   ix->n_items += n;
   return SLASH_OK;

@@ -735,8 +735,8 @@ bool small_insert_ok(const Shape& s, uint64_t n) { return n >= 1 && n <= kSmallI
 // run records [L][n] (uint2) then run ids [L][n]
 size_t small_insert_scratch(const Shape& s, uint64_t n) { return (size_t)s.L * n * 12 + 64; }
 
-hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
-                               void* scratch, TablesView tab, hipStream_t st, const InsertGate& gate) {
+hipError_t launch_insert_group(const Shape& s, const uint32_t* keys, uint32_t n, uint32_t first_id, void* scratch,
+                               hipStream_t st) {
   if (n == 0 || n > kSmallInsert) return hipErrorInvalidValue;
   uint2* recs = (uint2*)scratch;
   uint32_t* items = (uint32_t*)(recs + (size_t)s.L * n);
@@ -747,28 +747,38 @@ hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_
           hipSuccess)
     return e;
   hipLaunchKernelGGL(k_insert_group, dim3(s.L), dim3(kGroupThreads), lds, st, keys, n, first_id, recs, items);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipStream_t wst = st;
-  if ((e = gate(st, &wst)) != hipSuccess) return e;
-  if (s.bucket) return launch_tk_runs(s, c, recs, items, n, tab, wst);
-  const uint64_t lanes = (uint64_t)s.L * n * 16;
-  const dim3 grid((uint32_t)((lanes + kMergeThreads - 1) / kMergeThreads));
-  if (s.R <= 16)
-    hipLaunchKernelGGL(k_insert_merge16<1>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
-  else if (s.R <= 32)
-    hipLaunchKernelGGL(k_insert_merge16<2>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
-  else if (s.R <= 64)
-    hipLaunchKernelGGL(k_insert_merge16<4>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
-  else if (s.R <= 128)
-    hipLaunchKernelGGL(k_insert_merge16<8>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
-  else
-    hipLaunchKernelGGL(k_insert_merge16<16>, grid, dim3(kMergeThreads), 0, wst, s, c, recs, items, n, tab);
   return hipGetLastError();
 }
 
+hipError_t launch_insert_runs(const Shape& s, const ConstView& c, void* scratch, uint32_t n, TablesView tab,
+                              hipStream_t st) {
+  if (n == 0 || n > kSmallInsert) return hipErrorInvalidValue;
+  uint2* recs = (uint2*)scratch;
+  uint32_t* items = (uint32_t*)(recs + (size_t)s.L * n);
+  if (s.bucket) return launch_tk_runs(s, c, recs, items, n, tab, st);
+  const uint64_t lanes = (uint64_t)s.L * n * 16;
+  const dim3 grid((uint32_t)((lanes + kMergeThreads - 1) / kMergeThreads));
+  if (s.R <= 16)
+    hipLaunchKernelGGL(k_insert_merge16<1>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else if (s.R <= 32)
+    hipLaunchKernelGGL(k_insert_merge16<2>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else if (s.R <= 64)
+    hipLaunchKernelGGL(k_insert_merge16<4>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else if (s.R <= 128)
+    hipLaunchKernelGGL(k_insert_merge16<8>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  else
+    hipLaunchKernelGGL(k_insert_merge16<16>, grid, dim3(kMergeThreads), 0, st, s, c, recs, items, n, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
+                               void* scratch, TablesView tab, hipStream_t st) {
+  hipError_t e = launch_insert_group(s, keys, n, first_id, scratch, st);
+  return e == hipSuccess ? launch_insert_runs(s, c, scratch, n, tab, st) : e;
+}
+
 hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys, const uint32_t* svals,
-                               uint64_t n, uint32_t* seg_scratch, uint32_t* part, TablesView tab, hipStream_t st,
-                               const InsertGate& gate) {
+                               uint64_t n, uint32_t* seg_scratch, uint32_t* part, TablesView tab, hipStream_t st) {
   if (n == 0) return hipSuccess;
   // seg_scratch: [0, n) flags -> segment numbers, [n, 2n) starts, [2n] count
   uint32_t* segno = seg_scratch;
@@ -779,11 +789,9 @@ hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_head_scatter, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, skeys, n, segno, seg_start,
                      nseg);
-  hipStream_t wst = st;
-  if ((e = gate(st, &wst)) != hipSuccess) return e;
-  if (s.bucket) return launch_tk_segments(s, c, skeys, svals, n, seg_start, nseg, tab, wst);
+  if (s.bucket) return launch_tk_segments(s, c, skeys, svals, n, seg_start, nseg, tab, st);
   size_t lds = (size_t)kSelWaves * wl_words(s.R) * 4;
-  hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, wst, s, c,
+  hipLaunchKernelGGL(k_insert_merge, dim3(grid_for(n, kSelWaves, 16384)), dim3(kSelWaves * SL_WAVE), lds, st, s, c,
                      skeys, svals, n, seg_start, nseg, tab);
   return hipGetLastError();
 }

@@ -14,10 +14,17 @@
 //     exactly the inserts submitted before it: an insert at the head of the
 //     FIFO (with the inserts queued right behind it, merged into one launch
 //     while they fit its staging) writes the tables after the batches before
-//     it and before the batches after it.  Its preparation (copying the rows
-//     in, hashing them, grouping them by bucket) runs on a second stream
-//     beside the query batches before it, after the previous insert's table
-//     writes (inserts share the index's insert scratch);
+//     it and before the batches after it;
+//   - an insert is prepared ahead, as soon as it is queued and an insert
+//     slot is free (inserts in FIFO order, so ids follow submission order):
+//     its rows are copied in, hashed and grouped by bucket into the slot's
+//     own scratch on a second stream, beside the query batches before it,
+//     and a one-thread kernel then writes the slot's sequence number to
+//     host-coherent memory.  When the insert reaches the head, the scheduler
+//     sees that word (it has usually long been written) and launches the
+//     table writes on the batch stream.  No event joins the two streams: a
+//     cross-stream event wait costs the launching thread about 20 us per
+//     insert on this runtime;
 //   - query results are written by the query kernel straight into pinned,
 //     host-coherent memory (no copy back);
 //   - slots are added while work is waiting, up to max_inflight, as long as
@@ -63,11 +70,11 @@ struct Request {
   std::vector<int32_t> idx;
   std::vector<int64_t> indptr;  // inserts
   double t_submit = 0;
+  int32_t prep = -1;  // inserts: the insert slot preparing it
 };
 
 struct Slot {
   hipEvent_t done = nullptr;  // everything the slot launched has finished
-  hipEvent_t prep = nullptr;  // inserts: the preparation kernels have finished
   bool busy = false;
   uint32_t kind = 0;
   uint64_t epoch = 0;  // queries: the epoch they see; inserts: the first request's epoch
@@ -83,6 +90,15 @@ struct Slot {
   uint32_t cap_q = 0;
   uint64_t cap_nnz = 0;
   uint32_t first_id = 0;
+  // inserts: the prepared rows, their bucket ids and runs, and the
+  // host-coherent word the preparation stream sets to prep_seq when done
+  uint32_t rows = 0;
+  size_t in_bytes = 0, idx_off = 0;
+  InsertScratch sc;
+  uint64_t* flag = nullptr;
+  uint64_t prep_seq = 0;
+  bool prep_failed = false;
+  bool uncommitted = false;  // prepared, table writes not launched yet (done is stale)
 };
 
 }  // namespace
@@ -99,8 +115,8 @@ struct slash_server {
   std::vector<Slot> ins;    // insert staging
   hipStream_t stream = nullptr;  // query batches and table writes, in FIFO order
   hipStream_t prep = nullptr;    // insert preparation
-  hipEvent_t last_insert = nullptr;  // table writes of the latest insert
-  bool have_insert = false;
+  uint64_t prep_seq = 0;         // preparations launched
+  size_t prep_scan = 0;          // FIFO entries from the head already looked at for preparation
   uint32_t cap_q = 0;
   uint64_t cap_nnz = 0, per_slot = 0;
   uint64_t epoch = 0;
@@ -121,10 +137,12 @@ namespace {
 void free_slot(Slot& s) {
   if (s.done) (void)hipEventSynchronize(s.done);
   if (s.done) (void)hipEventDestroy(s.done);
-  if (s.prep) (void)hipEventDestroy(s.prep);
   (void)hipFree(s.d_in);
+  (void)hipFree(s.sc.keys);
+  (void)hipFree(s.sc.runs);
   (void)hipHostFree(s.h_in);
   (void)hipHostFree(s.h_out);
+  (void)hipHostFree(s.flag);
   s = Slot();
 }
 
@@ -141,18 +159,35 @@ InLayout in_layout(uint64_t n, uint64_t nnz, bool with_k) {
 }
 
 // Device + pinned staging for up to cap_q queries / rows and cap_nnz indices
-// (query slots: plus host-coherent result memory the kernel writes).
-bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool with_out) {
+// (query slots: plus host-coherent result memory the kernel writes; insert
+// slots: plus insert scratch of keys_b + runs_b bytes and the
+// host-coherent preparation word).
+bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool with_out, size_t keys_b = 0,
+                size_t runs_b = 0) {
   s.cap_q = cap_q;
   s.cap_nnz = cap_nnz;
   const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
   if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
-  if (!with_out && hipEventCreateWithFlags(&s.prep, hipEventDisableTiming) != hipSuccess) return false;
   if (hipMalloc(&s.d_in, in_bytes) != hipSuccess) return false;
   if (hipHostMalloc(&s.h_in, in_bytes) != hipSuccess) return false;
   if (with_out && hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8, hipHostMallocCoherent) != hipSuccess)
     return false;
+  if (!with_out) {
+    if (hipMalloc(&s.sc.keys, keys_b) != hipSuccess || hipMalloc(&s.sc.runs, runs_b) != hipSuccess) return false;
+    if (hipHostMalloc(&s.flag, 64, hipHostMallocCoherent) != hipSuccess) return false;
+    *(volatile uint64_t*)s.flag = 0;
+    s.sc.rows = cap_q;
+  }
   return true;
+}
+
+// Sets the host-coherent word f to v; on a stream, after every kernel
+// launched on it before (kernels on one stream run in order).
+__global__ void k_set_flag(uint64_t* f, uint64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    __threadfence_system();
+    *(volatile uint64_t*)f = v;
+  }
 }
 
 __global__ void k_touch(int64_t* p) {
@@ -254,27 +289,13 @@ hipError_t launch_queries(slash_server* srv, Slot& s) {
   return hipEventRecord(s.done, st);
 }
 
-// The table writes of a served insert go to the batch stream, after the
-// insert's preparation on the preparation stream (its gate).
-hipError_t insert_gate(void* ctx, hipStream_t st, hipStream_t* write_st) {
-  Slot* s = (Slot*)((void**)ctx)[0];
-  slash_server* srv = (slash_server*)((void**)ctx)[1];
-  hipError_t e = hipEventRecord(s->prep, st);
-  if (e == hipSuccess) e = hipStreamWaitEvent(srv->stream, s->prep, 0);
-  *write_st = srv->stream;
-  return e;
-}
-
-// Apply the slot's inserts (one or more requests, their rows back to back):
-// copy, hash and group on the preparation stream after the previous insert's
-// table writes, then write the tables on the batch stream, after every batch
-// launched before and before every batch launched after.
-hipError_t launch_insert(slash_server* srv, Slot& s) {
+// Pack the FIFO's inserts [i, j) into insert slot s's staging (lock held).
+void pack_inserts(slash_server* srv, Slot& s, size_t i, size_t j) {
   uint32_t rows = 0;
   uint64_t nnz = 0;
-  for (const Request& r : s.reqs) {
-    rows += r.n_rows;
-    nnz += r.idx.size();
+  for (size_t x = i; x < j; ++x) {
+    rows += srv->pending[x].n_rows;
+    nnz += srv->pending[x].idx.size();
   }
   const InLayout l = in_layout(rows, nnz, false);
   int64_t* h_ip = (int64_t*)s.h_in;
@@ -282,26 +303,105 @@ hipError_t launch_insert(slash_server* srv, Slot& s) {
   uint32_t row = 0;
   uint64_t off = 0;
   h_ip[0] = 0;
-  for (const Request& r : s.reqs) {
-    for (uint32_t i = 0; i < r.n_rows; ++i) h_ip[row + i + 1] = (int64_t)off + r.indptr[i + 1];
+  for (size_t x = i; x < j; ++x) {
+    const Request& r = srv->pending[x];
+    for (uint32_t k = 0; k < r.n_rows; ++k) h_ip[row + k + 1] = (int64_t)off + r.indptr[k + 1];
     memcpy(h_ix + off, r.idx.data(), r.idx.size() * 4);
     off += r.idx.size();
     row += r.n_rows;
   }
+  s.rows = rows;
+  s.in_bytes = l.bytes;
+  s.idx_off = l.idx;
+}
+
+// Prepare insert slot s on the preparation stream (lock not held): copy,
+// hash, group into the slot's scratch (the ids are taken here), then set the
+// slot's word.
+hipError_t prepare_insert(slash_server* srv, Slot& s) {
   hipStream_t pst = srv->prep;
   hipError_t e;
-  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, pst)) != hipSuccess) return e;
-  if (srv->have_insert && (e = hipStreamWaitEvent(pst, srv->last_insert, 0)) != hipSuccess) return e;
-  s.first_id = (uint32_t)srv->next_id;
-  srv->next_id += rows;
-  slash_csr csr{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), rows};
-  void* ctx[2] = {&s, srv};
-  if (insert_rows(srv->ix, csr, SLASH_FLAG_TRUSTED, nullptr, pst, InsertGate{insert_gate, ctx}) != SLASH_OK)
-    return hipErrorLaunchFailure;
-  if ((e = hipEventRecord(s.done, srv->stream)) != hipSuccess) return e;
-  srv->last_insert = s.done;
-  srv->have_insert = true;
-  return hipSuccess;
+  if ((e = hipMemcpyAsync(s.d_in, s.h_in, s.in_bytes, hipMemcpyHostToDevice, pst)) != hipSuccess) return e;
+  slash_csr csr{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + s.idx_off), s.rows};
+  if (insert_prepare(srv->ix, csr, s.sc, pst, &s.first_id) != SLASH_OK) return hipErrorLaunchFailure;
+  s.prep_seq = ++srv->prep_seq;
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, pst, s.flag, s.prep_seq);
+  return hipGetLastError();
+}
+
+// A preparation that has not set its word after this long is taken as a
+// device failure.
+constexpr double kPrepTimeout = 10.0;
+
+// Commit prepared insert slot s on the batch stream (lock not held): wait
+// until its preparation has set the word, write the tables, record done.
+hipError_t commit_insert(slash_server* srv, Slot& s) {
+  if (s.prep_failed) return hipErrorLaunchFailure;
+  const volatile uint64_t* f = s.flag;
+  if (*f < s.prep_seq) {
+    const double t0 = now_s();
+    while (*f < s.prep_seq)
+      if (now_s() - t0 > kPrepTimeout) return hipErrorLaunchTimeOut;
+  }
+  if (insert_commit(srv->ix, s.sc, s.rows, srv->stream) != SLASH_OK) return hipErrorLaunchFailure;
+  return hipEventRecord(s.done, srv->stream);
+}
+
+// Remove the FIFO's head (lock held).
+void pop_head(slash_server* srv) {
+  srv->pending.pop_front();
+  if (srv->prep_scan) --srv->prep_scan;
+}
+
+// Prepare the queued inserts in FIFO order while insert slots are free; the
+// inserts queued right behind one share its slot while they fit its staging
+// (one launch, each request still its own epoch).  Lock held; released
+// around the launches.
+void prepare_ahead(slash_server* srv, std::unique_lock<std::mutex>& lk) {
+  size_t i = srv->prep_scan;
+  while (i < srv->pending.size()) {
+    if (srv->pending[i].kind != 1 || srv->pending[i].prep >= 0) {
+      ++i;
+      continue;
+    }
+    int32_t slot = -1;
+    for (size_t o = 0; o < srv->ins.size(); ++o)
+      if (!srv->ins[o].busy) {
+        slot = (int32_t)o;
+        break;
+      }
+    if (slot < 0) break;
+    Slot& s = srv->ins[slot];
+    size_t j = i;
+    uint32_t rows = 0;
+    uint64_t nnz = 0;
+    while (j < srv->pending.size() && srv->pending[j].kind == 1) {
+      Request& r = srv->pending[j];
+      if (j > i && (rows + r.n_rows > s.cap_q || nnz + r.idx.size() > s.cap_nnz)) break;
+      rows += r.n_rows;
+      nnz += r.idx.size();
+      r.prep = slot;
+      ++j;
+    }
+    pack_inserts(srv, s, i, j);
+    s.reqs.clear();
+    s.kind = 1;
+    s.busy = true;
+    s.uncommitted = true;
+    s.prep_failed = false;
+    srv->stats.batches++;
+    i = j;
+    srv->prep_scan = i;
+    lk.unlock();
+    const hipError_t e = prepare_insert(srv, s);
+    lk.lock();
+    if (e != hipSuccess) {
+      srv->dev_err = e;
+      s.prep_failed = true;
+    }
+    i = srv->prep_scan;
+  }
+  srv->prep_scan = i;
 }
 
 // Whether the queries at the head of the FIFO fill one batch, or an insert
@@ -355,7 +455,7 @@ void scheduler(slash_server* srv) {
     finished.clear();
     for (std::vector<Slot>* group : {&srv->slots, &srv->ins})
       for (Slot& s : *group)
-        if (s.busy) {
+        if (s.busy && !s.uncommitted) {
           const hipError_t q = hipEventQuery(s.done);
           if (q != hipErrorNotReady) finished.emplace_back(&s, q);
         }
@@ -365,41 +465,32 @@ void scheduler(slash_server* srv) {
       finish_slot(srv, *s, q == hipSuccess ? SLASH_OK : SLASH_E_DEVICE);
     }
     if (!finished.empty()) srv->cv.notify_all();
-    // 2. admit the head of the FIFO
+    // 2. prepare queued inserts, admit the head of the FIFO
     double wake_at = 0.0;
-    while (!srv->pending.empty()) {
+    for (;;) {
+      prepare_ahead(srv, lk);
+      if (srv->pending.empty()) break;
       Request& head = srv->pending.front();
       if (head.kind == 1) {
-        Slot* free_i = nullptr;
-        for (Slot& o : srv->ins)
-          if (!o.busy) {
-            free_i = &o;
-            break;
-          }
-        if (!free_i) break;
-        Slot& s = *free_i;
+        if (head.prep < 0) break;  // waits for an insert slot
+        const int32_t idx = head.prep;
+        Slot& s = srv->ins[idx];
         s.reqs.clear();
-        // this insert and the inserts right behind it, while they fit the
-        // staging: one launch, each request still its own epoch
-        uint32_t rows = 0;
-        uint64_t nnz = 0;
-        while (!srv->pending.empty() && srv->pending.front().kind == 1) {
-          Request& r = srv->pending.front();
-          if (!s.reqs.empty() && (rows + r.n_rows > s.cap_q || nnz + r.idx.size() > s.cap_nnz)) break;
-          rows += r.n_rows;
-          nnz += r.idx.size();
-          s.reqs.push_back(std::move(r));
-          srv->pending.pop_front();
+        while (!srv->pending.empty() && srv->pending.front().kind == 1 && srv->pending.front().prep == idx) {
+          s.reqs.push_back(std::move(srv->pending.front()));
+          pop_head(srv);
         }
-        s.kind = 1;
-        s.busy = true;
         s.epoch = srv->epoch + 1;
         srv->epoch += s.reqs.size();
-        srv->stats.batches++;
         lk.unlock();
-        hipError_t e = launch_insert(srv, s);
+        const hipError_t e = commit_insert(srv, s);
         lk.lock();
-        if (e != hipSuccess) srv->dev_err = e;
+        s.uncommitted = false;
+        if (e != hipSuccess) {
+          srv->dev_err = e;
+          finish_slot(srv, s, SLASH_E_DEVICE);
+          srv->cv.notify_all();
+        }
         continue;
       }
       Slot* free_s = nullptr;
@@ -429,7 +520,7 @@ void scheduler(slash_server* srv) {
         if (r.kind != 0 || nnz + r.idx.size() > s.cap_nnz) break;
         nnz += r.idx.size();
         s.reqs.push_back(std::move(r));
-        srv->pending.pop_front();
+        pop_head(srv);
       }
       s.kind = 0;
       s.busy = true;
@@ -502,7 +593,10 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   const uint32_t ins_rows = 4096;
   const uint64_t ins_nnz = cfg->max_insert_nnz ? cfg->max_insert_nnz
                                                : std::max<uint64_t>((uint64_t)ins_rows * 64, 8ull * cfg->max_query_nnz);
-  const uint64_t ins_bytes = in_layout(ins_rows, ins_nnz, false).bytes;
+  size_t keys_b = 0, runs_b = 0;
+  if (!insert_scratch_bytes(ix, ins_rows, &keys_b, &runs_b))
+    return fail(SLASH_E_UNSUPPORTED, "inserts of %u rows cannot be prepared ahead for this index", ins_rows);
+  const uint64_t ins_bytes = in_layout(ins_rows, ins_nnz, false).bytes + keys_b + runs_b;
   if (ins_bytes + srv->per_slot > cfg->hbm_budget_bytes) {
     delete srv;
     return fail(SLASH_E_NOMEM, "HBM budget %llu below one batch slot (%llu bytes)",
@@ -519,22 +613,16 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     return fail(SLASH_E_DEVICE, "stream creation failed");
   }
   srv->ins.emplace_back();
-  if (!alloc_slot(srv->ins[0], ins_rows, ins_nnz, km, false)) {
+  if (!alloc_slot(srv->ins[0], ins_rows, ins_nnz, km, false, keys_b, runs_b)) {
     free_server(srv);
     return fail(SLASH_E_NOMEM, "insert staging allocation failed");
   }
   srv->hbm_used = ins_bytes;
-  // the index's own scratch for the largest insert, so that no insert grows
-  // (and drains the device) while batches are in flight
-  if (slash_status rs = reserve_insert_scratch(ix, ins_rows); rs != SLASH_OK) {
-    free_server(srv);
-    return rs;
-  }
   // up to three more insert slots while the budget still leaves room for a
   // batch slot
   while (srv->ins.size() < kInsertSlots && srv->hbm_used + ins_bytes + srv->per_slot <= cfg->hbm_budget_bytes) {
     srv->ins.emplace_back();
-    if (!alloc_slot(srv->ins.back(), ins_rows, ins_nnz, km, false)) {
+    if (!alloc_slot(srv->ins.back(), ins_rows, ins_nnz, km, false, keys_b, runs_b)) {
       free_slot(srv->ins.back());
       srv->ins.pop_back();
       break;
@@ -551,7 +639,13 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   srv->hbm_used += srv->per_slot;
   srv->stats.peak_hbm_bytes = srv->hbm_used;
   bool warm = true;
-  for (Slot& o : srv->ins) warm = warm && warm_slot(srv->prep, o, false);
+  for (Slot& o : srv->ins) {
+    warm = warm && warm_slot(srv->prep, o, false);
+    if (warm) {
+      hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, srv->prep, o.flag, (uint64_t)0);
+      warm = hipGetLastError() == hipSuccess && hipStreamSynchronize(srv->prep) == hipSuccess;
+    }
+  }
   warm = warm && warm_slot(srv->stream, srv->slots[0], true);
   if (warm) {
     // one single-index query loads the query kernels

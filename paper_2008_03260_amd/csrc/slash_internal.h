@@ -226,33 +226,23 @@ hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const ui
                         FinalWork* finals, uint32_t* n_chunks, uint32_t* cand, TablesView tab, hipStream_t st);
 
 
-// A hook an insert calls on its stream `st` after the kernels that read only
-// the new rows and the insert scratch (hashing, grouping, sorting) and
-// before the first kernel that writes the tables.  It may enqueue waits and
-// may name another stream for the table-writing kernels (*write_st, preset
-// to st): a server runs the preparation beside its query batches and the
-// table writes in the order of its batches.  Returns the first error of what
-// it enqueued.
-struct InsertGate {
-  hipError_t (*fn)(void* ctx, hipStream_t st, hipStream_t* write_st) = nullptr;
-  void* ctx = nullptr;
-  hipError_t operator()(hipStream_t st, hipStream_t* write_st) const {
-    *write_st = st;
-    return fn ? fn(ctx, st, write_st) : hipSuccess;
-  }
-};
-
 // Small insert (n rows, keys [L][n] as written by launch_hash_rows without
-// combining): one block per table groups the (bucket, id) pairs in LDS, then
-// one kernel merges every touched bucket's run into its reservoir.
+// combining): one block per table groups the (bucket, id) pairs in LDS
+// (launch_insert_group: reads only the keys, writes only the scratch), then
+// one kernel merges every touched bucket's run into its reservoir
+// (launch_insert_runs: the only kernel that writes the tables).
 bool small_insert_ok(const Shape& s, uint64_t n);
 size_t small_insert_scratch(const Shape& s, uint64_t n);
+hipError_t launch_insert_group(const Shape& s, const uint32_t* keys, uint32_t n, uint32_t first_id, void* scratch,
+                               hipStream_t st);
+hipError_t launch_insert_runs(const Shape& s, const ConstView& c, void* scratch, uint32_t n, TablesView tab,
+                              hipStream_t st);
 hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
-                               void* scratch, TablesView tab, hipStream_t st, const InsertGate& gate = {});
+                               void* scratch, TablesView tab, hipStream_t st);
 // Insert merge: sorted combined keys (t*nb+b) with new ids -> merged reservoirs.
 hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys,
                                const uint32_t* svals, uint64_t n, uint32_t* seg_scratch,
-                               uint32_t* part, TablesView tab, hipStream_t st, const InsertGate& gate = {});
+                               uint32_t* part, TablesView tab, hipStream_t st);
 
 // Query kernels.
 struct QueryArgs {
@@ -306,12 +296,29 @@ hipError_t launch_tk_query(const Shape& s, const ConstView& c, const TablesView&
                            hipStream_t st);
 
 // Size the index's insert scratch for batches of up to `rows` rows now, so
-// that later inserts of at most that many rows allocate nothing and never
-// drain the device (a server calls this once at start).
+// that later inserts of at most that many rows allocate nothing.
 slash_status reserve_insert_scratch(slash_index* ix, uint64_t rows);
 
-// slash_insert with a gate before the table writes (see InsertGate).
-slash_status insert_rows(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev, hipStream_t st,
-                         const InsertGate& gate);
+// slash_insert's body (rows on `st`, in order after earlier work on it).
+slash_status insert_rows(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev, hipStream_t st);
+
+// A small insert split in two for a caller that prepares inserts beside
+// other work and orders the table writes itself (the server):
+// insert_prepare hashes and groups `rows` (trusted) into the caller's scratch
+// on `st` and takes the next ids (*first_id); insert_commit writes the tables
+// from that scratch on `st`, which the caller must order after the prepare's
+// kernels and after every query that must not see the rows.  Prepares take
+// ids in call order.  insert_scratch_bytes gives the scratch sizes for
+// inserts of up to `rows` rows, or returns false when such inserts cannot
+// take this path.
+struct InsertScratch {
+  uint32_t* keys = nullptr;  // [L][rows] bucket ids
+  void* runs = nullptr;      // run records and ids
+  uint32_t rows = 0;
+};
+bool insert_scratch_bytes(const slash_index* ix, uint32_t rows, size_t* keys_bytes, size_t* runs_bytes);
+slash_status insert_prepare(slash_index* ix, slash_csr rows, const InsertScratch& sc, hipStream_t st,
+                            uint32_t* first_id);
+slash_status insert_commit(slash_index* ix, const InsertScratch& sc, uint32_t n, hipStream_t st);
 
 }  // namespace slash
