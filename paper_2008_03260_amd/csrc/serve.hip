@@ -8,7 +8,8 @@
 //     for one batch each).  As soon as a slot is free it takes the longest
 //     run of queries at the head of the FIFO that fits the slot (continuous
 //     batching: no waiting for a full batch while the device has room),
-//     copies them in, runs slash_query and copies the results back;
+//     runs slash_query on them (a small batch is read in place from
+//     host-coherent memory, a larger one copied in first);
 //   - query batches and the table-writing kernels of inserts go to one
 //     device stream in FIFO order, so a query admitted in epoch e sees
 //     exactly the inserts submitted before it: an insert at the head of the
@@ -169,7 +170,9 @@ bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool 
   const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
   if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
   if (hipMalloc(&s.d_in, in_bytes) != hipSuccess) return false;
-  if (hipHostMalloc(&s.h_in, in_bytes) != hipSuccess) return false;
+  // query staging is host-coherent: small batches are read by the kernel in
+  // place (no stale lines when the slot is reused)
+  if (hipHostMalloc(&s.h_in, in_bytes, with_out ? hipHostMallocCoherent : 0u) != hipSuccess) return false;
   if (with_out && hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8, hipHostMallocCoherent) != hipSuccess)
     return false;
   if (!with_out) {
@@ -259,8 +262,14 @@ void finish_slot(slash_server* srv, Slot& s, int32_t status) {
   s.busy = false;
 }
 
+// Request bytes up to which a query batch is read by the kernel straight
+// from host-coherent memory: a copy would add a blit kernel and its launch
+// gap to the ordered stream, longer than the kernel's few reads over the
+// host link.
+constexpr size_t kZeroCopyBytes = size_t(64) << 10;
+
 // Launch a query batch on slot s (lock not held; reqs already moved in):
-// copy in, query, copy out, one event.
+// (copy in,) query with results written to host-coherent memory, one event.
 hipError_t launch_queries(slash_server* srv, Slot& s) {
   const uint32_t n = (uint32_t)s.reqs.size();
   const uint32_t km = srv->info.params.k_max;
@@ -281,9 +290,13 @@ hipError_t launch_queries(slash_server* srv, Slot& s) {
   }
   hipStream_t st = srv->stream;
   hipError_t e;
-  if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-  slash_csr q{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + l.idx), n};
-  slash_status rs = slash_query(srv->ix, q, (const uint32_t*)(s.d_in + l.k), 0, SLASH_FLAG_TRUSTED, s.h_out,
+  const char* in = s.h_in;
+  if (l.bytes > kZeroCopyBytes) {
+    if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    in = s.d_in;
+  }
+  slash_csr q{(const int64_t*)in, (const int32_t*)(in + l.idx), n};
+  slash_status rs = slash_query(srv->ix, q, (const uint32_t*)(in + l.k), 0, SLASH_FLAG_TRUSTED, s.h_out,
                                 s.h_out + (size_t)n * km, st);
   if (rs != SLASH_OK) return hipErrorLaunchFailure;
   return hipEventRecord(s.done, st);
