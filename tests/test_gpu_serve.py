@@ -265,3 +265,84 @@ def test_replay_open_loop(api, setup):
         qn += m
         i = j
     idx.close()
+
+
+@pytest.mark.parametrize("bucket", [0, 1])
+def test_burst_inserts_prepared_ahead(api, setup, bucket):
+    # every request submitted before the first poll, so the FIFO is long:
+    # inserts are prepared ahead (at most four insert slots at once, runs of
+    # back-to-back inserts sharing a slot) while the query batches before
+    # them run; each query equals the oracle on the rows inserted before it,
+    # and the ids of the inserts follow submission order
+    law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    if bucket:
+        params = api.Params.of(dim=1 << 20, K=4, L=16, log2_buckets=12, R=1, cm_rows=4, log2_cm_width=4, k_max=100,
+                               bucket=1, seed=synth.derive(31, synth.STREAM_INDEX))
+    rng = np.random.default_rng(7)
+    plan = []  # ("q", query index) or ("i", rows)
+    nq = len(qi) - 1
+    q = 0
+    for block in range(40):
+        for _ in range(int(rng.integers(0, 6))):
+            plan.append(("q", q % nq))
+            q += 1
+        for _ in range(block % 4):
+            plan.append(("i", int(rng.integers(1, 40))))
+    total_rows = sum(m for kind, m in plan if kind == "i")
+    iip, iix = law.rows(n0, total_rows)
+    idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=256 << 20, max_batch=16, max_inflight=4)
+    tickets = {}
+    row = 0
+    n_ins = 0
+    for kind, v in plan:
+        if kind == "q":
+            tickets[api.slash_serve_submit_query(srv, qx[qi[v]:qi[v + 1]], int(kq[v]))] = ("q", v, n_ins)
+        else:
+            sip = iip[row: row + v + 1] - iip[row]
+            six = iix[iip[row]: iip[row + v]]
+            n_ins += 1
+            tickets[api.slash_serve_submit_insert(srv, sip, six)] = ("i", (n0 + row, v), n_ins)
+            row += v
+    got = []
+    while len(got) < len(tickets):
+        got += api.slash_serve_poll(srv)
+    stats = api.slash_serve_stop(srv)
+    assert stats["inserts_done"] == n_ins and stats["rows_inserted"] == total_rows
+    # the oracle's tables after each insert, and its answers per epoch
+    op = oracle_params(params)
+    cs = oracle.constants(op)
+    answers = {}
+    queries_by_epoch = {}
+    for kind, v, e in tickets.values():
+        if kind == "q":
+            queries_by_epoch.setdefault(e, []).append(v)
+    epochs = sorted(queries_by_epoch)
+    # rebuild from the union for each epoch that has queries (inserts equal a
+    # bulk build on the union, for both bucket kinds)
+    rows_before = [0]
+    for kind, v in plan:
+        if kind == "i":
+            rows_before.append(rows_before[-1] + v)
+    uip = np.concatenate([ip[: n0 + 1], ip[n0] + iip[1:]])
+    uix = np.concatenate([ix[: ip[n0]], iix])
+    for e in epochs:
+        qs = sorted(set(queries_by_epoch[e]))
+        n_rows = n0 + rows_before[e]
+        sub_ip = np.concatenate([[0], np.cumsum([qi[v + 1] - qi[v] for v in qs])]).astype(np.int64)
+        sub_ix = np.concatenate([qx[qi[v]:qi[v + 1]] for v in qs])
+        sub_k = np.array([kq[v] for v in qs], dtype=np.uint32)
+        wi, ws = oracle_answers(params, uip, uix, n_rows, sub_ip, sub_ix, sub_k)
+        for r, v in enumerate(qs):
+            answers[(e, v)] = (wi[r], ws[r])
+    for c in got:
+        kind, v, e = tickets[c["ticket"]]
+        assert c["status"] == 0 and c["epoch"] == e
+        if kind == "i":
+            assert (c["first_id"], c["n_ids"]) == v
+            continue
+        k = int(kq[v])
+        ref_i, ref_s = answers[(e, v)]
+        assert (c["ids"] == ref_i[:k]).all() and (c["scores"] == ref_s[:k]).all(), (e, v)
+    assert idx.info()["n_items"] == n0 + total_rows
+    idx.close()
