@@ -149,8 +149,11 @@ typedef struct {
  * itself, and the build stops with E_INVAL after the hash pass when one is
  * outside.  Synchronises `stream` before returning (validation flags,
  * work-list sizes).  Errors: E_INVAL (params, rows, indices), E_NOMEM,
- * E_CAPACITY (n_rows > 0xFFFFFFFE), E_UNSUPPORTED, E_DEVICE.  *out is set
- * only on success. */
+ * E_CAPACITY (n_rows > 0xFFFFFFFE), E_UNSUPPORTED (among others: a shape no
+ * query kernel answers, i.e. more than 16384 reservoir slots L * R per query
+ * or a count-min / id set larger than LDS; slash_import_tables and
+ * slash_load refuse such shapes too), E_DEVICE.  *out is set only on
+ * success. */
 SLASH_API slash_status slash_build(const slash_params* params, slash_csr data, void* stream, slash_index** out);
 
 /* Insert rows (Section 3.1 streaming insert): ids n_items, n_items+1, ... in

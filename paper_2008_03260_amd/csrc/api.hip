@@ -239,6 +239,19 @@ static HostConsts derive_consts(const slash_params& p) {
   return h;
 }
 
+static Shape make_shape(const slash_params& p);
+
+// Whether a query form exists for the shape: Topkapi buckets need the fold
+// kernel's cells to fit; reservoir buckets need some work-group width whose
+// threads hold the L * R slots (at most 16 per thread, 16 waves) and whose
+// sketch or id set fits in LDS, with count-min or exact counting.
+static bool queryable(const Shape& s) {
+  if (s.bucket) return tk_supported(s);
+  for (uint32_t w : {16u, 8u, 4u, 2u, 1u})
+    if (query_supported(s, w, false) || query_supported(s, w, true)) return true;
+  return false;
+}
+
 static slash_status check_params(const slash_params* p) {
   if (!p) return fail(SLASH_E_INVAL, "params is NULL");
   if (p->dim == 0) return fail(SLASH_E_INVAL, "dim must be >= 1");
@@ -255,6 +268,12 @@ static slash_status check_params(const slash_params* p) {
     return fail(SLASH_E_UNSUPPORTED, "Topkapi buckets need log2_cm_width <= 8 and cm_rows * 2^log2_cm_width <= 256");
   if (((uint64_t)p->L << p->log2_buckets) > (1ull << 32)) return fail(SLASH_E_UNSUPPORTED, "L * 2^B must be <= 2^32");
   if ((uint64_t)p->L * p->R > 65535) return fail(SLASH_E_UNSUPPORTED, "L * R must be <= 65535");
+  // an index is built only if it can be queried
+  if (!queryable(make_shape(*p)))
+    return fail(SLASH_E_UNSUPPORTED,
+                p->bucket ? "Topkapi cells per bucket too many for the query kernel"
+                          : "no query form fits: L * R above 16384 slots, or the count-min (cm_rows x 2^log2_cm_width "
+                            "8-bit counters) too large for LDS");
   return SLASH_OK;
 }
 

@@ -42,6 +42,12 @@ def test_null_and_invalid_arguments_fail_before_device_work():
     bad = api.Params.of(dim=1 << 20, K=4, L=8, log2_buckets=10, R=300, cm_rows=2, log2_cm_width=8, k_max=10)
     assert L.slash_build(ctypes.byref(bad), api.CSR(None, None, 0), None, ctypes.byref(out)) == api.E_INVAL
     assert b"R must be" in L.slash_last_error()
+    # shapes no query kernel can answer are refused at build: more slots per
+    # query than 16 waves hold (16 per thread), a sketch larger than LDS
+    for kw in (dict(L=128, R=256, cm_rows=4, log2_cm_width=12), dict(L=32, R=64, cm_rows=16, log2_cm_width=16)):
+        bad = api.Params.of(dim=1 << 20, K=4, log2_buckets=10, k_max=10, **kw)
+        assert L.slash_build(ctypes.byref(bad), api.CSR(None, None, 0), None, ctypes.byref(out)) == api.E_UNSUPPORTED
+        assert b"no query form fits" in L.slash_last_error()
     # calls on a NULL index
     L.slash_free(None)  # a NULL index is ignored
     assert L.slash_query(None, api.CSR(None, None, 0), None, 1, 0, None, None, None) == api.E_INVAL
