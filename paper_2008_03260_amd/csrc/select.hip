@@ -239,19 +239,27 @@ __device__ __forceinline__ void select_small(uint32_t* lds, const uint32_t* __re
   }
   // compact the kept priorities (exactly min(n, R)) and sort them once; the
   // filler 0xFFFFFFFF may equal a kept priority, which changes nothing since
-  // the first `base` sorted values are the kept ones either way
-  uint32_t* kept = lds;
+  // the first `base` sorted values are the kept ones either way.  With one id
+  // per lane the kept priorities are sorted where they are.
   uint32_t base = 0;
+  uint32_t x;
+  if constexpr (kC == 1) {
+    const bool keep = id[0] != SL_EMPTY && pr[0] <= upper;
+    base = (uint32_t)__builtin_popcountll(ballot64(keep));
+    x = keep ? pr[0] : 0xFFFFFFFFu;
+  } else {
+    uint32_t* kept = lds;
 #pragma unroll
-  for (int c = 0; c < kC; ++c) {
-    const bool keep = id[c] != SL_EMPTY && pr[c] <= upper;
-    const uint64_t m = ballot64(keep);
-    const uint32_t pos = base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
-    if (keep && pos < SL_WAVE) kept[pos] = pr[c];
-    base += (uint32_t)__builtin_popcountll(m);
+    for (int c = 0; c < kC; ++c) {
+      const bool keep = id[c] != SL_EMPTY && pr[c] <= upper;
+      const uint64_t m = ballot64(keep);
+      const uint32_t pos = base + (uint32_t)__builtin_popcountll(m & lanemask_lt());
+      if (keep && pos < SL_WAVE) kept[pos] = pr[c];
+      base += (uint32_t)__builtin_popcountll(m);
+    }
+    wave_sync();
+    x = lane < min(base, (uint32_t)SL_WAVE) ? kept[lane] : 0xFFFFFFFFu;
   }
-  wave_sync();
-  uint32_t x = lane < min(base, (uint32_t)SL_WAVE) ? kept[lane] : 0xFFFFFFFFu;
   x = wave_sort32(x);
   if (lane < R) out[lane] = lane < base ? priority_inverse(x, key, im1, im2) : SL_EMPTY;
   wave_sync();
@@ -278,7 +286,13 @@ __global__ void __launch_bounds__(kSelWaves * SL_WAVE, 8)
     const uint32_t n = e0 - s0;
     uint32_t* out = tab.ids + ((uint64_t)t * s.nb + b) * s.R;
     if (n <= 8 * SL_WAVE && s.R <= SL_WAVE) {
-      if (n <= 4 * SL_WAVE)
+      // as many ids per lane as the bucket needs (most buckets hold at most
+      // two per lane)
+      if (n <= SL_WAVE)
+        select_small<1>(my, svals, s0, n, s.R, key, m1, m2, im1, im2, out);
+      else if (n <= 2 * SL_WAVE)
+        select_small<2>(my, svals, s0, n, s.R, key, m1, m2, im1, im2, out);
+      else if (n <= 4 * SL_WAVE)
         select_small<4>(my, svals, s0, n, s.R, key, m1, m2, im1, im2, out);
       else
         select_small<8>(my, svals, s0, n, s.R, key, m1, m2, im1, im2, out);

@@ -129,9 +129,9 @@ def test_build_heavy_buckets(api):
 def test_build_bucket_sizes_at_select_boundaries(api, R):
     # groups of identical rows fill one bucket per table with exactly n ids:
     # sizes on either side of every select path's limit (the register path
-    # for 256 and 512 ids, the streaming list, the chunked heavy path above
+    # for 64, 128, 256 and 512 ids, the streaming list, the chunked heavy path above
     # 16384 ids), with random rows around them
-    sizes = [1, 37, 63, 64, 65, 100, 255, 256, 257, 511, 512, 513, 16384, 16385]
+    sizes = [1, 37, 63, 64, 65, 100, 127, 128, 129, 255, 256, 257, 511, 512, 513, 16384, 16385]
     gp, op = params_pair(api, L=4, log2_buckets=14, R=R)
     _, (ip0, ix0) = rows_of(2000, seed=12)
     groups = []
