@@ -326,6 +326,8 @@ __global__ void __launch_bounds__(256)
                  uint32_t* __restrict__ n_chunks) {
   __shared__ uint32_t part[4];
   __shared__ uint32_t carry_sh;
+  // the 256 buckets of one round: first chunk, source offset and length
+  __shared__ uint32_t b_first[256], b_off[256], b_len[256];
   const uint32_t nh = *heavy_n, tid = threadIdx.x, lane = lane_id(), wave = tid / SL_WAVE;
   if (tid == 0) carry_sh = 0;
   __syncthreads();
@@ -345,18 +347,30 @@ __global__ void __launch_bounds__(256)
     }
     if (lane == SL_WAVE - 1) part[wave] = inc;
     __syncthreads();
-    uint32_t before = carry_sh;
+    const uint32_t carry = carry_sh;
+    uint32_t before = carry;
     for (uint32_t w = 0; w < wave; ++w) before += part[w];
     const uint32_t first = before + inc - nch;
-    if (i < nh) {
-      finals[i] = FinalWork{(uint64_t)first * R, nch * R, bucket, len, 0};
-      for (uint32_t c = 0; c < nch; ++c) {
-        const uint32_t o = c * chunk_len;
-        chunks[first + c] = ChunkWork{(uint64_t)off + o, min(chunk_len, len - o), first + c};
+    b_first[tid] = first;
+    b_off[tid] = off;
+    b_len[tid] = len;
+    if (i < nh) finals[i] = FinalWork{(uint64_t)first * R, nch * R, bucket, len, 0};
+    __syncthreads();
+    // the round's chunks, spread over the block: chunk j belongs to the last
+    // bucket whose first chunk is at most j (buckets without chunks share
+    // their successor's first and are skipped by the search)
+    const uint32_t total = b_first[255] + (b0 + 255 < nh ? (b_len[255] + chunk_len - 1) / chunk_len : 0u);
+    for (uint32_t j = carry + tid; j < total; j += 256) {
+      uint32_t lo = 0, hi = 255;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if (b_first[mid] <= j) lo = mid; else hi = mid - 1;
       }
+      const uint32_t o = (j - b_first[lo]) * chunk_len;
+      chunks[j] = ChunkWork{(uint64_t)b_off[lo] + o, min(chunk_len, b_len[lo] - o), j};
     }
     __syncthreads();
-    if (tid == 255) carry_sh = first + nch;
+    if (tid == 0) carry_sh = total;
     __syncthreads();
   }
   if (tid == 0) *n_chunks = carry_sh;
