@@ -396,7 +396,7 @@ def recall_operating_point(api, w, ip, ix, ins_ip, ins_ix, qi, qx, qi_h, qx_h, s
               "exact_warm_batched_queries_per_s": nq / (min(te) / 1e3),
               "batched_queries_per_s": nq / (tq[0] / 1e3), "warm_batched_queries_per_s": nq / (min(tq[1:]) / 1e3),
               "schedule": sched, "build_ms": build_ms,
-              "build_kernel_ms": sum(v["total_ms"] for v in prof.values()),
+              "build_kernel_ms_summed": sum(v["total_ms"] for v in prof.values()),
               "build_inserts_per_s": w["n"] / (build_ms / 1e3), "insert_4096_ms": ins_ms,
               "table_bytes": L * (1 << B) * (R + 1) * 4}
         log(f"operating point K={K} B={B} L={L} R={R} cm {pt['count_min']}: recall@10 {rec:.4f} "
@@ -707,10 +707,15 @@ def main():
     # per row bound), write the tables once (L * 2^B buckets of R ids and a
     # seen count)
     build_alg = 4 * nnz + 8 * (w["n"] + 1) + w["L"] * (1 << w["B"]) * (4 * w["R"] + 4)
-    # build phases, timed by the library with HIP events on the build stream
+    # build phases, timed by the library with HIP events on the stream each
+    # launch runs on; tables alternate between two streams, so launches of
+    # two tables overlap and their summed time exceeds the build's
     prof = prof_timed
     build_kernel_ms = sum(v["total_ms"] for v in prof.values())
-    build_gbs = build_alg / (build_kernel_ms / 1e3) / 1e9
+    # the whole build: HIP events on the bench stream around the synchronous
+    # slash_build call (every kernel of the build inside)
+    build_wall_ms = float(b_ms.mean())
+    build_gbs = build_alg / (build_wall_ms / 1e3) / 1e9
     dom = max((k for k in prof if prof[k]["launches"]), key=lambda k: prof[k]["total_ms"])
     d = prof[dom]
     dom_own_gbs = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9 if d["total_ms"] > 0 else 0.0
@@ -836,16 +841,18 @@ def main():
         "build_ms": float(b_ms.mean()),
         "insert_batch_rows_per_s": 4096 / (i_ms.mean() / 1e3),
         "batched_query_ms": float(q_ms.mean()),
-        "build_kernel_ms": build_kernel_ms,
+        "build_kernel_ms_summed": build_kernel_ms,
         "build_algorithmic_hbm_frac": build_alg / (b_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS,
         # the whole build (every kernel of one slash_build) against the
-        # build's algorithmic bytes: achieved = those bytes / summed kernel time
+        # build's algorithmic bytes: achieved = those bytes / the build's time
         "roofline": {"bound": "hbm", "achieved": build_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": build_gbs / HBM_PEAK_GBS, "traffic": counted_build_traffic(prof),
                      "kernel": "build: hash, radix sort, segment bounds, bottom-R select (all launches of one build)",
-                     "alg_bytes": build_alg, "kernel_ms": build_kernel_ms,
+                     "alg_bytes": build_alg, "build_ms": build_wall_ms, "kernel_ms_summed": build_kernel_ms,
                      "dominant_kernel": {
                          "kernel": dom_kernel, "phase": dom, "launches": d["launches"],
+                         # launches of two tables run at once (two streams)
+                         "tables_in_flight": 2,
                          "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
                          # the build's algorithmic bytes shared over this kernel's launches
                          "method_bytes_per_launch": build_alg / d["launches"],

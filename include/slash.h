@@ -148,7 +148,9 @@ typedef struct {
  * before any work; indices are checked against [0, dim) by the hash kernel
  * itself, and the build stops with E_INVAL after the hash pass when one is
  * outside.  Synchronises `stream` before returning (validation flags,
- * work-list sizes).  Errors: E_INVAL (params, rows, indices), E_NOMEM,
+ * work-list sizes; the tables are sorted and selected two at a time, on
+ * `stream` and on a second stream of the library's, each with its own
+ * scratch).  Errors: E_INVAL (params, rows, indices), E_NOMEM,
  * E_CAPACITY (n_rows > 0xFFFFFFFE), E_UNSUPPORTED (among others: a shape no
  * query kernel answers, i.e. more than 16384 reservoir slots L * R per query
  * or a count-min / id set larger than LDS; slash_import_tables and
@@ -273,7 +275,11 @@ SLASH_API slash_status slash_load(const char* path, void* stream, slash_index** 
 SLASH_API slash_status slash_index_info_get(const slash_index* index, slash_index_info* info);
 
 /* Per-phase timing of the build that made `index`, measured with HIP events
- * recorded on the build's stream around every launch of the phase.  Phases:
+ * recorded around every launch of the phase on the stream it ran on; the
+ * build runs its tables alternately on the caller's stream and on a second
+ * stream of its own (created once per device, kept until the process ends),
+ * so launches of two tables overlap and the phase totals of a build add up
+ * to more than its duration.  Phases:
  * validate, hash, sort_upsweep, sort_scan, sort_downsweep, segment_bounds,
  * select, heavy.  alg_bytes is the phase's algorithmic HBM traffic (bytes the
  * phase must read and write, counted once).  Writes up to max entries to out

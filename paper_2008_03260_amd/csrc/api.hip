@@ -177,6 +177,21 @@ struct DBuf {
   T* as() const { return (T*)p; }
 };
 
+// The build's second stream on a device (tables alternate between it and
+// the caller's stream): created on first use, default priority, kept until
+// the process ends.
+static hipStream_t build_stream(int device) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(device);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  streams[device] = st;
+  return st;
+}
+
 // Synchronises a stream when it goes out of scope.  Declared after the
 // scratch buffers of a call, it runs before they return to the cache, so no
 // block re-enters the cache while queued work may still use it (error paths
@@ -541,18 +556,30 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "table init: %s", hipGetErrorString(e)));
   }
   if (n > 0) {
-    DBuf keys, k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, hchunks, hfinals, hcount, hcand, tkh;
-    SyncOnExit drain{st};
+    // Tables alternate between the caller's stream and a second stream, each
+    // with its own sort and select scratch, so the phases of one table that
+    // leave most of the GPU idle (single-block planning and scans, launch
+    // gaps, the tail of a heavy bucket's merge) overlap another table's
+    // kernels.  The tables are independent; the host waits for both streams.
+    struct TableScratch {
+      DBuf k0, v0, k1, v1, hist, part, start, end, heavy, heavy_n, hchunks, hfinals, hcount, hcand, tkh;
+    };
+    DBuf keys;
+    TableScratch ts[2];
+    hipStream_t st2 = build_stream(ix->device);
+    if (!st2) return bail(fail(SLASH_E_DEVICE, "build stream creation failed"));
+    SyncOnExit drain{st}, drain2{st2};
     size_t hist_n = sort_hist_entries(n);
     size_t part_n = std::max(sort_part_entries(hist_n), sort_part_entries(n)) + 16;
     const size_t hcap = heavy_chunk_capacity(n, kHeavy);
-    if (!keys.get((size_t)s.L * n * 4) || !k0.get(n * 4) || !v0.get(n * 4) || !k1.get(n * 4) || !v1.get(n * 4) ||
-        !hist.get(hist_n * 4) || !part.get(part_n * 4) || !start.get((size_t)s.nb * 4) ||
-        !end.get((size_t)s.nb * 4) || !heavy.get((size_t)s.nb * 12) || !heavy_n.get(4) ||
-        !hchunks.get(hcap * sizeof(ChunkWork)) || !hfinals.get((n / kHeavy + 1) * sizeof(FinalWork)) ||
-        !hcount.get(4) || !hcand.get(hcap * s.R * 4) ||
-        (s.bucket && !tkh.get(tk_heavy_scratch_words(s, n / kHeavyTk + 1) * 4)))
-      return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
+    if (!keys.get((size_t)s.L * n * 4)) return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
+    for (TableScratch& x : ts)
+      if (!x.k0.get(n * 4) || !x.v0.get(n * 4) || !x.k1.get(n * 4) || !x.v1.get(n * 4) || !x.hist.get(hist_n * 4) ||
+          !x.part.get(part_n * 4) || !x.start.get((size_t)s.nb * 4) || !x.end.get((size_t)s.nb * 4) ||
+          !x.heavy.get((size_t)s.nb * 12) || !x.heavy_n.get(4) || !x.hchunks.get(hcap * sizeof(ChunkWork)) ||
+          !x.hfinals.get((n / kHeavy + 1) * sizeof(FinalWork)) || !x.hcount.get(4) ||
+          !x.hcand.get(hcap * s.R * 4) || (s.bucket && !x.tkh.get(tk_heavy_scratch_words(s, n / kHeavyTk + 1) * 4)))
+        return bail(fail(SLASH_E_NOMEM, "build scratch allocation failed"));
     // the hash kernel also checks every index against [0, dim) (flag bit 2)
     ConstView cvb = ix->cv;
     cvb.bad = ix->flag;
@@ -567,47 +594,52 @@ extern "C" slash_status slash_build(const slash_params* params, slash_csr data, 
       if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "hash: %s", hipGetErrorString(e)));
       if (f & 2u) return bail(fail(SLASH_E_INVAL, "a feature index is outside [0, dim)"));
     }
-    SortBuffers sb{k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), hist.as<uint32_t>(),
-                   part.as<uint32_t>()};
     // every table is enqueued back to back: heavy buckets are planned and
     // finished on the device, so the host never waits between tables
     // the packed sort (ids below 2^28, keys below 2^20) writes the bucket
     // runs itself; otherwise the sorted keys are scanned for them
     const bool packed = packed_sort_ok(n, (int)s.B);
     for (uint32_t t = 0; t < s.L; ++t) {
+      TableScratch& x = ts[t & 1];
+      const hipStream_t tst = (t & 1) ? st2 : st;
+      SortBuffers sb{x.k0.as<uint32_t>(), x.v0.as<uint32_t>(), x.k1.as<uint32_t>(), x.v1.as<uint32_t>(),
+                     x.hist.as<uint32_t>(), x.part.as<uint32_t>()};
+      DBuf &start = x.start, &end = x.end, &heavy = x.heavy, &heavy_n = x.heavy_n, &hchunks = x.hchunks,
+           &hfinals = x.hfinals, &hcount = x.hcount, &hcand = x.hcand, &tkh = x.tkh;
       uint32_t *sk = nullptr, *sv = nullptr;
       const uint32_t* tkeys = keys.as<uint32_t>() + (uint64_t)t * n;
-      e = launch_fill_u32(start.as<uint32_t>(), 0u, s.nb, st);
-      if (e == hipSuccess) e = launch_fill_u32(end.as<uint32_t>(), 0u, s.nb, st);
-      if (e == hipSuccess) e = launch_fill_u32(heavy_n.as<uint32_t>(), 0u, 1, st);
+      e = launch_fill_u32(start.as<uint32_t>(), 0u, s.nb, tst);
+      if (e == hipSuccess) e = launch_fill_u32(end.as<uint32_t>(), 0u, s.nb, tst);
+      if (e == hipSuccess) e = launch_fill_u32(heavy_n.as<uint32_t>(), 0u, 1, tst);
       if (e == hipSuccess && packed) {
-        e = radix_sort_runs(tkeys, n, (int)s.B, sb, start.as<uint32_t>(), end.as<uint32_t>(), &sv, st, &timer);
+        e = radix_sort_runs(tkeys, n, (int)s.B, sb, start.as<uint32_t>(), end.as<uint32_t>(), &sv, tst, &timer);
       } else if (e == hipSuccess) {
-        e = radix_sort(tkeys, nullptr, n, (int)s.B, sb, &sk, &sv, st, &timer);
-        timer.begin(PH_BOUNDS, st);
-        if (e == hipSuccess) e = launch_segment_bounds(sk, n, start.as<uint32_t>(), end.as<uint32_t>(), st);
-        timer.end(PH_BOUNDS, st);
+        e = radix_sort(tkeys, nullptr, n, (int)s.B, sb, &sk, &sv, tst, &timer);
+        timer.begin(PH_BOUNDS, tst);
+        if (e == hipSuccess) e = launch_segment_bounds(sk, n, start.as<uint32_t>(), end.as<uint32_t>(), tst);
+        timer.end(PH_BOUNDS, tst);
       }
-      timer.begin(PH_SELECT, st);
+      timer.begin(PH_SELECT, tst);
       if (e == hipSuccess && s.bucket)
         e = launch_tk_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavyTk,
-                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), tkh.as<uint32_t>(), st);
+                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), tkh.as<uint32_t>(), tst);
       else if (e == hipSuccess)
         e = launch_select_light(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix), kHeavy,
-                                heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), st);
-      timer.end(PH_SELECT, st);
-      timer.begin(PH_HEAVY, st);
+                                heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), tst);
+      timer.end(PH_SELECT, tst);
+      timer.begin(PH_HEAVY, tst);
       if (e == hipSuccess && s.bucket)
         e = launch_tk_heavy(s, ix->cv, t, sv, start.as<uint32_t>(), end.as<uint32_t>(), tables(ix),
-                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), n, tkh.as<uint32_t>(), st);
+                            heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), n, tkh.as<uint32_t>(), tst);
       else if (e == hipSuccess)
         e = launch_heavy(s, ix->cv, t, sv, n, heavy.as<uint32_t>(), heavy_n.as<uint32_t>(), kHeavy,
                          hchunks.as<ChunkWork>(), hfinals.as<FinalWork>(), hcount.as<uint32_t>(), hcand.as<uint32_t>(),
-                         tables(ix), st);
-      timer.end(PH_HEAVY, st);
+                         tables(ix), tst);
+      timer.end(PH_HEAVY, tst);
       if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build table %u: %s", t, hipGetErrorString(e)));
     }
     e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st2);
     if (e != hipSuccess) return bail(fail(SLASH_E_DEVICE, "build: %s", hipGetErrorString(e)));
   }
   HIP_TRY(hipStreamSynchronize(st));
