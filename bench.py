@@ -475,13 +475,17 @@ def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4,
                 "query_p99_us": float(np.percentile(ql, 99) * 1e6) if nq else None,
                 "insert_p50_us": float(np.percentile(il, 50) * 1e6) if len(il) else None,
                 "insert_p99_us": float(np.percentile(il, 99) * 1e6) if len(il) else None,
-                "batches": st["batches"], "peak_inflight": st["peak_inflight"]}
+                "batches": st["batches"], "peak_inflight": st["peak_inflight"],
+                # the scheduler thread's seconds in launch calls (and, of them,
+                # waiting for prepared inserts), per wall second
+                "scheduler_launch_frac": st["launch_s"] / wall, "scheduler_wait_frac": st["wait_s"] / wall}
 
     replay(min(rates), 0.2, seeds["query"] ^ 0x5A5A)
     for rate in rates:
         pt = replay(rate, seconds, seeds["query"] ^ int(rate))
         log(f"serve {rate:,.0f} req/s: {pt['queries_per_s']:,.0f} q/s, {pt['inserted_rows_per_s']:,.0f} rows/s inserted, "
-            f"query p50 {pt['query_p50_us']:.0f} us p99 {pt['query_p99_us']:.0f} us")
+            f"query p50 {pt['query_p50_us']:.0f} us p99 {pt['query_p99_us']:.0f} us; scheduler in launch calls "
+            f"{pt['scheduler_launch_frac']:.0%} (waiting {pt['scheduler_wait_frac']:.0%})")
         out.append(pt)
     return out
 

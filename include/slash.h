@@ -362,7 +362,9 @@ typedef struct {
 typedef struct {
   uint64_t queries_done, inserts_done, rows_inserted, batches, rejected_busy, rejected_nomem;
   uint64_t peak_inflight, peak_hbm_bytes;
-  double busy_s; /* seconds with device work in flight (host clock) */
+  double busy_s;   /* seconds with device work in flight (host clock) */
+  double launch_s; /* scheduler seconds in launch calls (query batches, insert preparations and commits) */
+  double wait_s;   /* of which waiting for a prepared insert's word before its commit */
 } slash_serve_stats;
 
 SLASH_API slash_status slash_serve_start(slash_index* index, const slash_serve_config* cfg, slash_server** out);

@@ -76,7 +76,7 @@ class Completion(C.Structure):
 class ServeStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("queries_done", "inserts_done", "rows_inserted", "batches",
                                           "rejected_busy", "rejected_nomem", "peak_inflight", "peak_hbm_bytes")] + \
-               [("busy_s", C.c_double)]
+               [("busy_s", C.c_double), ("launch_s", C.c_double), ("wait_s", C.c_double)]
 
 
 class Schedule(C.Structure):
@@ -349,7 +349,7 @@ def slash_serve_poll(srv, max_n: int = 1024) -> list:
 def slash_serve_stop(srv) -> dict:
     st = ServeStats()
     _check(lib().slash_serve_stop(srv, C.byref(st)), "slash_serve_stop")
-    return {f: (float(getattr(st, f)) if f == "busy_s" else int(getattr(st, f))) for f, _ in ServeStats._fields_}
+    return {f: (float(getattr(st, f)) if f.endswith("_s") else int(getattr(st, f))) for f, _ in ServeStats._fields_}
 
 
 def slash_serve_replay(srv, t_arrival, is_insert, ins_rows, q_indptr, q_indices, q_k, ins_indptr, ins_indices,

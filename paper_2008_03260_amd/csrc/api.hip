@@ -708,7 +708,7 @@ bool slash::insert_scratch_bytes(const slash_index* ix, uint32_t rows, size_t* k
 }
 
 slash_status slash::insert_prepare(slash_index* ix, slash_csr rows, const InsertScratch& sc, hipStream_t st,
-                                   uint32_t* first_id) {
+                                   uint32_t* first_id, const GroupSignal& sig) {
   if (!ix || !first_id) return fail(SLASH_E_INVAL, "NULL argument");
   const uint64_t n = rows.n_rows;
   if (n == 0 || n > sc.rows || !small_insert_ok(ix->shape, n))
@@ -717,7 +717,7 @@ slash_status slash::insert_prepare(slash_index* ix, slash_csr rows, const Insert
   if (ix->n_items + n > 0xFFFFFFFFull) return fail(SLASH_E_CAPACITY, "ids would exceed 0xFFFFFFFE");
   const uint32_t first = (uint32_t)ix->n_items;
   HIP_TRY(launch_hash_rows(ix->shape, ix->cv, rows, sc.keys, n, 0, st));
-  HIP_TRY(launch_insert_group(ix->shape, sc.keys, (uint32_t)n, first, sc.runs, st));
+  HIP_TRY(launch_insert_group(ix->shape, sc.keys, (uint32_t)n, first, sc.runs, st, sig));
   ix->n_items += n;
   *first_id = first;
   return SLASH_OK;

@@ -535,7 +535,7 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wsum, 
 
 __global__ void __launch_bounds__(kGroupThreads)
     k_insert_group(const uint32_t* __restrict__ keys, uint32_t n, uint32_t first_id, uint2* __restrict__ recs,
-                   uint32_t* __restrict__ items) {
+                   uint32_t* __restrict__ items, GroupSignal sig) {
   extern __shared__ uint32_t lds32[];
   const uint32_t t = blockIdx.x, tid = threadIdx.x;
   const uint32_t cl = group_cap_log2(n), cap = 1u << cl;
@@ -600,6 +600,20 @@ __global__ void __launch_bounds__(kGroupThreads)
   for (uint32_t j = 0; j < kGroupItems; ++j) {
     uint32_t i = tid + j * kGroupThreads;
     if (i < n) it[slot_cnt[slot[j]] + rank[j]] = first_id + i;
+  }
+  if (sig.flag) {
+    // the block's writes reach L2 at the barrier; the fence makes them
+    // visible device-wide before the block counts itself done; the last
+    // block resets the counter and sets the host-visible word
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      if (atomicAdd(sig.counter, 1u) == gridDim.x - 1) {
+        *sig.counter = 0;
+        __threadfence_system();
+        *(volatile uint64_t*)sig.flag = sig.value;
+      }
+    }
   }
 }
 
@@ -764,7 +778,7 @@ bool small_insert_ok(const Shape& s, uint64_t n) { return n >= 1 && n <= kSmallI
 size_t small_insert_scratch(const Shape& s, uint64_t n) { return (size_t)s.L * n * 12 + 64; }
 
 hipError_t launch_insert_group(const Shape& s, const uint32_t* keys, uint32_t n, uint32_t first_id, void* scratch,
-                               hipStream_t st) {
+                               hipStream_t st, const GroupSignal& sig) {
   if (n == 0 || n > kSmallInsert) return hipErrorInvalidValue;
   uint2* recs = (uint2*)scratch;
   uint32_t* items = (uint32_t*)(recs + (size_t)s.L * n);
@@ -774,7 +788,7 @@ hipError_t launch_insert_group(const Shape& s, const uint32_t* keys, uint32_t n,
       (e = hipFuncSetAttribute((const void*)k_insert_group, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
           hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_insert_group, dim3(s.L), dim3(kGroupThreads), lds, st, keys, n, first_id, recs, items);
+  hipLaunchKernelGGL(k_insert_group, dim3(s.L), dim3(kGroupThreads), lds, st, keys, n, first_id, recs, items, sig);
   return hipGetLastError();
 }
 

@@ -18,9 +18,10 @@
 //     it and before the batches after it;
 //   - an insert is prepared ahead, as soon as it is queued and an insert
 //     slot is free (inserts in FIFO order, so ids follow submission order):
-//     its rows are copied in, hashed and grouped by bucket into the slot's
-//     own scratch on a second stream, beside the query batches before it,
-//     and a one-thread kernel then writes the slot's sequence number to
+//     its rows are hashed (read in place from host-coherent staging up to
+//     1 MB, else copied in first) and grouped by bucket into the slot's own
+//     scratch on a second stream, beside the query batches before it, and
+//     the grouping kernel's last block writes the slot's sequence number to
 //     host-coherent memory.  When the insert reaches the head, the scheduler
 //     sees that word (it has usually long been written) and launches the
 //     table writes on the batch stream.  No event joins the two streams: a
@@ -96,6 +97,7 @@ struct Slot {
   uint32_t rows = 0;
   size_t in_bytes = 0, idx_off = 0;
   InsertScratch sc;
+  uint32_t* counter = nullptr;  // the grouping kernel's block counter (device)
   uint64_t* flag = nullptr;
   uint64_t prep_seq = 0;
   bool prep_failed = false;
@@ -141,6 +143,7 @@ void free_slot(Slot& s) {
   (void)hipFree(s.d_in);
   (void)hipFree(s.sc.keys);
   (void)hipFree(s.sc.runs);
+  (void)hipFree(s.counter);
   (void)hipHostFree(s.h_in);
   (void)hipHostFree(s.h_out);
   (void)hipHostFree(s.flag);
@@ -162,7 +165,7 @@ InLayout in_layout(uint64_t n, uint64_t nnz, bool with_k) {
 // Device + pinned staging for up to cap_q queries / rows and cap_nnz indices
 // (query slots: plus host-coherent result memory the kernel writes; insert
 // slots: plus insert scratch of keys_b + runs_b bytes and the
-// host-coherent preparation word).
+// host-coherent preparation word and the device counter that sets it).
 bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool with_out, size_t keys_b = 0,
                 size_t runs_b = 0) {
   s.cap_q = cap_q;
@@ -170,13 +173,14 @@ bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool 
   const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
   if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
   if (hipMalloc(&s.d_in, in_bytes) != hipSuccess) return false;
-  // query staging is host-coherent: small batches are read by the kernel in
-  // place (no stale lines when the slot is reused)
-  if (hipHostMalloc(&s.h_in, in_bytes, with_out ? hipHostMallocCoherent : 0u) != hipSuccess) return false;
+  // staging is host-coherent: small batches and inserts are read by the
+  // kernels in place (no stale lines when the slot is reused)
+  if (hipHostMalloc(&s.h_in, in_bytes, hipHostMallocCoherent) != hipSuccess) return false;
   if (with_out && hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8, hipHostMallocCoherent) != hipSuccess)
     return false;
   if (!with_out) {
     if (hipMalloc(&s.sc.keys, keys_b) != hipSuccess || hipMalloc(&s.sc.runs, runs_b) != hipSuccess) return false;
+    if (hipMalloc(&s.counter, 256) != hipSuccess || hipMemset(s.counter, 0, 256) != hipSuccess) return false;
     if (hipHostMalloc(&s.flag, 64, hipHostMallocCoherent) != hipSuccess) return false;
     *(volatile uint64_t*)s.flag = 0;
     s.sc.rows = cap_q;
@@ -184,14 +188,6 @@ bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool 
   return true;
 }
 
-// Sets the host-coherent word f to v; on a stream, after every kernel
-// launched on it before (kernels on one stream run in order).
-__global__ void k_set_flag(uint64_t* f, uint64_t v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    __threadfence_system();
-    *(volatile uint64_t*)f = v;
-  }
-}
 
 __global__ void k_touch(int64_t* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
@@ -328,18 +324,26 @@ void pack_inserts(slash_server* srv, Slot& s, size_t i, size_t j) {
   s.idx_off = l.idx;
 }
 
-// Prepare insert slot s on the preparation stream (lock not held): copy,
-// hash, group into the slot's scratch (the ids are taken here), then set the
-// slot's word.
+// Rows up to which an insert is hashed straight from host-coherent staging
+// (larger ones are copied in first).
+constexpr size_t kZeroCopyInsertBytes = size_t(1) << 20;
+
+// Prepare insert slot s on the preparation stream (lock not held): (copy,)
+// hash, group into the slot's scratch (the ids are taken here); the grouping
+// kernel's last block sets the slot's word.
 hipError_t prepare_insert(slash_server* srv, Slot& s) {
   hipStream_t pst = srv->prep;
   hipError_t e;
-  if ((e = hipMemcpyAsync(s.d_in, s.h_in, s.in_bytes, hipMemcpyHostToDevice, pst)) != hipSuccess) return e;
-  slash_csr csr{(const int64_t*)s.d_in, (const int32_t*)(s.d_in + s.idx_off), s.rows};
-  if (insert_prepare(srv->ix, csr, s.sc, pst, &s.first_id) != SLASH_OK) return hipErrorLaunchFailure;
+  const char* in = s.h_in;
+  if (s.in_bytes > kZeroCopyInsertBytes) {
+    if ((e = hipMemcpyAsync(s.d_in, s.h_in, s.in_bytes, hipMemcpyHostToDevice, pst)) != hipSuccess) return e;
+    in = s.d_in;
+  }
+  slash_csr csr{(const int64_t*)in, (const int32_t*)(in + s.idx_off), s.rows};
   s.prep_seq = ++srv->prep_seq;
-  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, pst, s.flag, s.prep_seq);
-  return hipGetLastError();
+  const GroupSignal sig{s.counter, s.flag, s.prep_seq};
+  if (insert_prepare(srv->ix, csr, s.sc, pst, &s.first_id, sig) != SLASH_OK) return hipErrorLaunchFailure;
+  return hipSuccess;
 }
 
 // A preparation that has not set its word after this long is taken as a
@@ -355,6 +359,7 @@ hipError_t commit_insert(slash_server* srv, Slot& s) {
     const double t0 = now_s();
     while (*f < s.prep_seq)
       if (now_s() - t0 > kPrepTimeout) return hipErrorLaunchTimeOut;
+    srv->stats.wait_s += now_s() - t0;
   }
   if (insert_commit(srv->ix, s.sc, s.rows, srv->stream) != SLASH_OK) return hipErrorLaunchFailure;
   return hipEventRecord(s.done, srv->stream);
@@ -406,7 +411,9 @@ void prepare_ahead(slash_server* srv, std::unique_lock<std::mutex>& lk) {
     i = j;
     srv->prep_scan = i;
     lk.unlock();
+    const double t0 = now_s();
     const hipError_t e = prepare_insert(srv, s);
+    srv->stats.launch_s += now_s() - t0;
     lk.lock();
     if (e != hipSuccess) {
       srv->dev_err = e;
@@ -496,7 +503,9 @@ void scheduler(slash_server* srv) {
         s.epoch = srv->epoch + 1;
         srv->epoch += s.reqs.size();
         lk.unlock();
+        const double t0 = now_s();
         const hipError_t e = commit_insert(srv, s);
+        srv->stats.launch_s += now_s() - t0;
         lk.lock();
         s.uncommitted = false;
         if (e != hipSuccess) {
@@ -540,7 +549,9 @@ void scheduler(slash_server* srv) {
       s.epoch = srv->epoch;
       srv->stats.batches++;
       lk.unlock();
+      const double t0 = now_s();
       hipError_t e = launch_queries(srv, s);
+      srv->stats.launch_s += now_s() - t0;
       lk.lock();
       if (e != hipSuccess) srv->dev_err = e;
       uint64_t inflight = 0;
@@ -652,13 +663,7 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   srv->hbm_used += srv->per_slot;
   srv->stats.peak_hbm_bytes = srv->hbm_used;
   bool warm = true;
-  for (Slot& o : srv->ins) {
-    warm = warm && warm_slot(srv->prep, o, false);
-    if (warm) {
-      hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, srv->prep, o.flag, (uint64_t)0);
-      warm = hipGetLastError() == hipSuccess && hipStreamSynchronize(srv->prep) == hipSuccess;
-    }
-  }
+  for (Slot& o : srv->ins) warm = warm && warm_slot(srv->prep, o, false);
   warm = warm && warm_slot(srv->stream, srv->slots[0], true);
   if (warm) {
     // one single-index query loads the query kernels

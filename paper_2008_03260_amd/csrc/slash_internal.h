@@ -233,8 +233,17 @@ hipError_t launch_heavy(const Shape& s, const ConstView& c, uint32_t t, const ui
 // (launch_insert_runs: the only kernel that writes the tables).
 bool small_insert_ok(const Shape& s, uint64_t n);
 size_t small_insert_scratch(const Shape& s, uint64_t n);
+// Optional completion signal of the grouping kernel: when flag is set, the
+// last block to finish sets *flag = value (host-visible) once every block's
+// writes are visible device-wide; counter is a device word that holds 0
+// before the launch (the last block returns it to 0).
+struct GroupSignal {
+  uint32_t* counter = nullptr;
+  uint64_t* flag = nullptr;
+  uint64_t value = 0;
+};
 hipError_t launch_insert_group(const Shape& s, const uint32_t* keys, uint32_t n, uint32_t first_id, void* scratch,
-                               hipStream_t st);
+                               hipStream_t st, const GroupSignal& sig = {});
 hipError_t launch_insert_runs(const Shape& s, const ConstView& c, void* scratch, uint32_t n, TablesView tab,
                               hipStream_t st);
 hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
@@ -311,6 +320,8 @@ slash_status insert_rows(slash_index* ix, slash_csr rows, uint32_t flags, uint32
 // ids in call order.  insert_scratch_bytes gives the scratch sizes for
 // inserts of up to `rows` rows, or returns false when such inserts cannot
 // take this path.
+// With sig.flag set, the grouping kernel sets *sig.flag = sig.value when the
+// prepare's kernels are done (see GroupSignal).
 struct InsertScratch {
   uint32_t* keys = nullptr;  // [L][rows] bucket ids
   void* runs = nullptr;      // run records and ids
@@ -318,7 +329,7 @@ struct InsertScratch {
 };
 bool insert_scratch_bytes(const slash_index* ix, uint32_t rows, size_t* keys_bytes, size_t* runs_bytes);
 slash_status insert_prepare(slash_index* ix, slash_csr rows, const InsertScratch& sc, hipStream_t st,
-                            uint32_t* first_id);
+                            uint32_t* first_id, const GroupSignal& sig = {});
 slash_status insert_commit(slash_index* ix, const InsertScratch& sc, uint32_t n, hipStream_t st);
 
 }  // namespace slash
