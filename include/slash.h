@@ -325,7 +325,7 @@ SLASH_API void slash_release_cache(void);
  * the inserts submitted before it; inserts queued back to back are applied
  * in one launch (each still closes its own epoch).  Inserts are prepared
  * ahead in submission order (copied in, hashed and grouped on a second
- * stream into per-slot scratch, up to four at a time), so only their table
+ * stream into per-slot scratch, up to eight at a time), so only their table
  * writes sit in the ordered stream.  Batch slots (device and
  * pinned host staging for one batch) are added while requests wait for one,
  * up to max_inflight, as long as the HBM budget and the device's free memory

@@ -60,7 +60,7 @@ double now_s() {
 
 // Insert staging slots a server keeps at most (inserts queued on the device
 // behind the one running).
-constexpr size_t kInsertSlots = 4;
+constexpr size_t kInsertSlots = 8;
 // Device memory a server leaves free when it adds a batch slot.
 constexpr uint64_t kFreeReserve = uint64_t(1) << 30;
 
@@ -642,7 +642,7 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     return fail(SLASH_E_NOMEM, "insert staging allocation failed");
   }
   srv->hbm_used = ins_bytes;
-  // up to three more insert slots while the budget still leaves room for a
+  // more insert slots (up to kInsertSlots) while the budget still leaves room for a
   // batch slot
   while (srv->ins.size() < kInsertSlots && srv->hbm_used + ins_bytes + srv->per_slot <= cfg->hbm_budget_bytes) {
     srv->ins.emplace_back();
