@@ -432,7 +432,7 @@ def recall_operating_point(api, w, ip, ix, ins_ip, ins_ix, qi, qx, qi_h, qx_h, s
     return {"found": False, "tried": tried}
 
 
-def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4, 1e5, 3e5, 1e6, 2e6)):
+def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4, 1e5, 3e5, 1e6, 2e6), fusion=0):
     """Open-loop Poisson arrivals against the continuous-batching server on
     the resident index: 90% queries (the batched mix), 10% inserts of 1-4096
     new rows.  Latency = completion - scheduled arrival.  Each rate offers
@@ -463,7 +463,7 @@ def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4,
             iip, iix = np.zeros(1, np.int64), np.zeros(0, np.int32)
         srv = api.slash_serve_start(h, hbm_budget_bytes=2 << 30, max_batch=2048, max_inflight=6,
                                     queue_capacity=1 << 22, max_query_nnz=w["max_nnz"],
-                                    max_insert_nnz=w.get("max_insert_nnz", 0))
+                                    max_insert_nnz=w.get("max_insert_nnz", 0), insert_fusion=fusion)
         t0 = time.perf_counter()
         lat, _ = api.slash_serve_replay(srv, t, ins, sz, q_ptr, q_idx, q_k, iip, iix)
         wall = time.perf_counter() - t0
@@ -478,14 +478,19 @@ def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4,
                 "batches": st["batches"], "peak_inflight": st["peak_inflight"],
                 # the scheduler thread's seconds in launch calls (and, of them,
                 # waiting for prepared inserts), per wall second
-                "scheduler_launch_frac": st["launch_s"] / wall, "scheduler_wait_frac": st["wait_s"] / wall}
+                "scheduler_launch_frac": st["launch_s"] / wall, "scheduler_wait_frac": st["wait_s"] / wall,
+                "scheduler_pack_frac": st["pack_s"] / wall,
+                # inserts served, and insert commits written by a query batch's launch
+                "inserts_done": st["inserts_done"], "fused_commits": st["fused_commits"]}
 
     replay(min(rates), 0.2, seeds["query"] ^ 0x5A5A)
     for rate in rates:
         pt = replay(rate, seconds, seeds["query"] ^ int(rate))
         log(f"serve {rate:,.0f} req/s: {pt['queries_per_s']:,.0f} q/s, {pt['inserted_rows_per_s']:,.0f} rows/s inserted, "
             f"query p50 {pt['query_p50_us']:.0f} us p99 {pt['query_p99_us']:.0f} us; scheduler in launch calls "
-            f"{pt['scheduler_launch_frac']:.0%} (waiting {pt['scheduler_wait_frac']:.0%})")
+            f"{pt['scheduler_launch_frac']:.0%} (waiting {pt['scheduler_wait_frac']:.0%}), copying requests "
+            f"{pt['scheduler_pack_frac']:.0%}; "
+            f"{pt['fused_commits']} of {pt['inserts_done']} inserts in query launches")
         out.append(pt)
     return out
 
@@ -505,6 +510,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="arrival window per serving rate (default: the workload's, 10 s for the 200M shard; "
                          "a point is capped at 400k requests)")
+    ap.add_argument("--serve-fusion", type=int, default=0, choices=(0, 1, 2),
+                    help="serving: 0 an insert already prepared is written by the query launch before it, "
+                         "1 never, 2 always")
     ap.add_argument("--serve-rates", default=None,
                     help="comma-separated offered request rates of the serving sweep (default: the workload's)")
     ap.add_argument("--mix-queries", type=int, default=1_000_000, help="queries of the batched mix")
@@ -689,7 +697,8 @@ def main():
         rates = w.get("serve_rates")
         if args.serve_rates:
             rates = tuple(float(x) for x in args.serve_rates.split(","))
-        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, secs, seeds, **({"rates": rates} if rates else {}))
+        serve = serve_sweep(api, h, law, w, mi_h, mx_h, mk, secs, seeds, fusion=args.serve_fusion,
+                            **({"rates": rates} if rates else {}))
 
     # the smallest index setting of the same shard with recall@10 >= 0.9
     op_point = None

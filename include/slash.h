@@ -326,7 +326,8 @@ SLASH_API void slash_release_cache(void);
  * in one launch (each still closes its own epoch).  Inserts are prepared
  * ahead in submission order (copied in, hashed and grouped on a second
  * stream into per-slot scratch, up to eight at a time), so only their table
- * writes sit in the ordered stream.  Batch slots (device and
+ * writes sit in the ordered stream, and those run inside the launch of the
+ * query batch before them when it is small (see insert_fusion).  Batch slots (device and
  * pinned host staging for one batch) are added while requests wait for one,
  * up to max_inflight, as long as the HBM budget and the device's free memory
  * (checked when a slot is added, leaving 1 GiB free) allow. */
@@ -342,6 +343,11 @@ typedef struct {
                                  query has waited this long */
   uint32_t max_query_nnz;     /* largest query row accepted */
   uint32_t max_insert_nnz;    /* indices one insert request may carry (0: max(4096 * 64, 8 * max_query_nnz)) */
+  uint32_t insert_fusion;     /* 0: a query batch of at most (compute units / 2) queries that is followed
+                                 by an insert already prepared also writes that insert's tables, in the
+                                 same launch, after every query of the batch has read them; 1: never;
+                                 2: always, waiting for the insert's preparation.  Results are the same */
+  uint32_t reserved;          /* 0 */
 } slash_serve_config;
 
 typedef struct {
@@ -365,6 +371,9 @@ typedef struct {
   double busy_s;   /* seconds with device work in flight (host clock) */
   double launch_s; /* scheduler seconds in launch calls (query batches, insert preparations and commits) */
   double wait_s;   /* of which waiting for a prepared insert's word before its commit */
+  double pack_s;   /* scheduler seconds copying request data into staging */
+  uint64_t fused_commits; /* insert commits (each of one or more merged inserts) whose table writes ran
+                             in a query batch's launch */
 } slash_serve_stats;
 
 SLASH_API slash_status slash_serve_start(slash_index* index, const slash_serve_config* cfg, slash_server** out);

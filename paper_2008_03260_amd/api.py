@@ -63,7 +63,7 @@ SERVE_MAX_K = 128
 class ServeConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_batch", C.c_uint32), ("max_inflight", C.c_uint32),
                 ("queue_capacity", C.c_uint32), ("max_wait_us", C.c_uint32), ("max_query_nnz", C.c_uint32),
-                ("max_insert_nnz", C.c_uint32)]
+                ("max_insert_nnz", C.c_uint32), ("insert_fusion", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Completion(C.Structure):
@@ -76,7 +76,8 @@ class Completion(C.Structure):
 class ServeStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("queries_done", "inserts_done", "rows_inserted", "batches",
                                           "rejected_busy", "rejected_nomem", "peak_inflight", "peak_hbm_bytes")] + \
-               [("busy_s", C.c_double), ("launch_s", C.c_double), ("wait_s", C.c_double)]
+               [("busy_s", C.c_double), ("launch_s", C.c_double), ("wait_s", C.c_double), ("pack_s", C.c_double),
+                ("fused_commits", C.c_uint64)]
 
 
 class Schedule(C.Structure):
@@ -309,9 +310,9 @@ def _np(a, dtype):
 
 
 def slash_serve_start(index, hbm_budget_bytes=1 << 30, max_batch=1024, max_inflight=4, queue_capacity=1 << 20,
-                      max_wait_us=0, max_query_nnz=4096, max_insert_nnz=0) -> C.c_void_p:
+                      max_wait_us=0, max_query_nnz=4096, max_insert_nnz=0, insert_fusion=0) -> C.c_void_p:
     cfg = ServeConfig(hbm_budget_bytes, max_batch, max_inflight, queue_capacity, max_wait_us, max_query_nnz,
-                      max_insert_nnz)
+                      max_insert_nnz, insert_fusion, 0)
     out = C.c_void_p()
     _check(lib().slash_serve_start(index, C.byref(cfg), C.byref(out)), "slash_serve_start")
     return out

@@ -729,6 +729,22 @@ slash_status slash::insert_commit(slash_index* ix, const InsertScratch& sc, uint
   return SLASH_OK;
 }
 
+bool slash::query_insert_ok(const slash_index* ix, uint64_t n_queries) {
+  // the same condition under which slash_query runs a batch with 16 waves
+  return ix && n_queries * 2 <= (uint64_t)ix->n_cu && query_insert_supported(ix->shape, n_queries);
+}
+
+slash_status slash::query_insert(slash_index* ix, slash_csr q, const uint32_t* kq, uint32_t* ids, uint32_t* scores,
+                                 const InsertScratch& sc, uint32_t n, FuseSync& fs, hipStream_t st) {
+  if (!ix || !kq || !ids || !scores || n == 0 || n > sc.rows) return fail(SLASH_E_INVAL, "bad fused query and insert");
+  if (!query_insert_ok(ix, q.n_rows)) return fail(SLASH_E_UNSUPPORTED, "no fused query and insert kernel fits");
+  QueryArgs a{q, kq, 0, 1, ids, scores, nullptr};
+  const hipError_t e = launch_query_insert(ix->shape, ix->cv, tables(ix), a, sc.runs, n, ix->n_cu, fs, st);
+  if (e == hipErrorNotSupported) return fail(SLASH_E_UNSUPPORTED, "no fused query and insert kernel fits");
+  HIP_TRY(e);
+  return SLASH_OK;
+}
+
 slash_status slash::insert_rows(slash_index* ix, slash_csr rows, uint32_t flags, uint32_t* new_ids_dev,
                                 hipStream_t st) {
   if (!ix) return fail(SLASH_E_INVAL, "index is NULL");

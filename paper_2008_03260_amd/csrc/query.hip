@@ -19,7 +19,10 @@
 //      by counting.  Results are written with stride k_max, padded with
 //      (EMPTY, 0).
 // The persistent form loops over queries taken from a device work counter.
+#include <array>
+
 #include "doph.h"
+#include "merge16.h"
 
 namespace slash {
 
@@ -143,9 +146,11 @@ __device__ __forceinline__ void hist_add(uint32_t* hist, bool part, uint32_t d) 
   if (part && lane_id() == (uint32_t)__builtin_ctzll(peers)) atomicAdd(&hist[d], (uint32_t)__builtin_popcountll(peers));
 }
 
+// `gathered`, when not null, is counted once the group's slots are all read
+// (a table writer may then start; see k_query_insert).
 template <int WAVES, int SPT, bool CL, bool EX>
 __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a, uint32_t q,
-                          uint32_t* lds, const QLayout& lay) {
+                          uint32_t* lds, const QLayout& lay, unsigned long long* gathered = nullptr) {
   constexpr uint32_t NT = WAVES * SL_WAVE;
   const uint32_t tid = threadIdx.x, wave = tid / SL_WAVE, lane = lane_id();
   uint32_t* bk = lds + lay.buckets;
@@ -222,6 +227,9 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       if (lane == 0) atomicAdd(&misc[7], live);
     }
     __syncthreads();
+    // every thread has used the ids it loaded (the live count above), so
+    // all of this query's table reads are done
+    if (gathered && tid == 0) atomicAdd(gathered, 1ull);
     // the counter sum and the 8-bit estimates are read in the same pass; the
     // estimates are redone below in the rare case the sum shows an overflow
     {
@@ -589,6 +597,85 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE, (query_min_waves<WAVES, SPT>(
   }
 }
 
+// A small query batch and the table writes of the insert queued right
+// behind it, in one launch of 16-wave work-groups (serving).  Every group
+// takes a ticket when it starts.  The first n tickets answer the batch's
+// queries, one each, and count themselves in sync[1] once all the slots they
+// read are in registers.  The later tickets apply the insert's run records
+// (sixteen lanes per record, the groups striding over the records), each
+// wave waiting first until all n queries have counted themselves.  So the
+// queries see the tables without the insert, and the next launch on the
+// stream sees them with it.  A group only waits for groups that took
+// earlier tickets: those are running and wait for nothing, so the wait ends;
+// it is bounded all the same, and a group that gives up sets *gave_up.  Both
+// counters only grow; the host passes the values they reach before this
+// launch and once its queries are counted.
+constexpr uint32_t kFusedWaves = 16;
+constexpr uint32_t kFusedSpinLimit = 1u << 20;  // polls: seconds at most, against microseconds needed
+
+struct FusedInsert {
+  const uint2* recs;      // [L][n_ins] run records of the prepared insert
+  const uint32_t* items;  // [L][n_ins] their new ids
+  uint32_t n_ins, merge_groups;
+  unsigned long long* sync;  // [0] tickets taken, [1] queries past their reads
+  unsigned long long ticket_base, gathered_target;
+  uint32_t* gave_up;  // host-coherent
+};
+
+template <int SPT, int E>
+__global__ void __launch_bounds__(kFusedWaves * SL_WAVE, (query_min_waves<kFusedWaves, SPT>()))
+    k_query_insert(Shape s, ConstView c, TablesView tab, QueryArgs a, FusedInsert f) {
+  constexpr uint32_t NT = kFusedWaves * SL_WAVE;
+  extern __shared__ uint32_t lds[];
+  const QLayout lay = q_layout(s, false);
+  if (threadIdx.x == 0) lds[lay.ticket] = (uint32_t)(atomicAdd(&f.sync[0], 1ull) - f.ticket_base);
+  __syncthreads();
+  const uint32_t ticket = lds[lay.ticket];
+  const uint32_t nq = (uint32_t)a.q.n_rows;
+  if (ticket < nq) {
+    const ConstView cl = stage_consts(s, c, lds + lay.cst, NT);
+    __syncthreads();
+    query_one<kFusedWaves, SPT, true, false>(s, cl, tab, a, ticket, lds, lay, &f.sync[1]);
+    return;
+  }
+  // table writers: each wave takes four records per pass and, before its
+  // first live record, waits for the batch's queries (lane 0 polls)
+  const uint64_t runs = (uint64_t)s.L * f.n_ins;
+  constexpr uint32_t per = NT / 16;  // records per group and pass
+  bool waited = false;
+  for (uint64_t r0 = (uint64_t)(ticket - nq) * per; r0 < runs; r0 += (uint64_t)f.merge_groups * per) {
+    const uint64_t run = r0 + threadIdx.x / 16;
+    const uint2 rec = run < runs ? f.recs[run] : make_uint2(0u, 0u);
+    const bool live = (rec.y >> 16) != 0;
+    if (__ballot(live) == 0) continue;
+    if (!waited) {
+      if (lane_id() == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&f.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < f.gathered_target) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins == kFusedSpinLimit) {
+            *(volatile uint32_t*)f.gave_up = 1u;
+            break;
+          }
+        }
+      }
+      waited = true;
+    }
+    if (live) {
+      const uint32_t t = (uint32_t)(run / f.n_ins);
+      merge_run16<E>(s, c, rec, t, f.items + (uint64_t)t * f.n_ins, tab);
+    }
+  }
+}
+
+// fused kernels by [log2 slots per thread][log2 entries per lane]
+template <int S>
+constexpr std::array<const void*, 4> kqi() {
+  return {(const void*)k_query_insert<S, 1>, (const void*)k_query_insert<S, 2>, (const void*)k_query_insert<S, 4>,
+          (const void*)k_query_insert<S, 8>};
+}
+const std::array<const void*, 4> kFused[5] = {kqi<1>(), kqi<2>(), kqi<4>(), kqi<8>(), kqi<16>()};
+
 struct KPair {
   const void* plain;
   const void* persistent;
@@ -724,6 +811,56 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
   e = hipLaunchKernel(k->persistent, dim3(grid), dim3(waves * SL_WAVE), args, lds, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
+}
+
+// Fused kernel for a batch of n queries and an insert (count-min queries,
+// constants in LDS, R <= 128), or nullptr.
+static const void* fused_kernel(const Shape& s, uint64_t n) {
+  if (n == 0 || n > (1u << 20) || s.bucket || s.R > 128 || !query_supported(s, kFusedWaves, false)) return nullptr;
+  if (!q_layout(s).cst_fit) return nullptr;
+  const uint32_t spt = (s.L * s.R + kFusedWaves * SL_WAVE - 1) / (kFusedWaves * SL_WAVE);
+  const uint32_t e = (s.R + 15) / 16;
+  return kFused[ilog2(spt < 1 ? 1 : spt)][ilog2(e)];
+}
+
+bool query_insert_supported(const Shape& s, uint64_t n_queries) { return fused_kernel(s, n_queries) != nullptr; }
+
+hipError_t launch_query_insert(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
+                               void* ins_scratch, uint32_t n_ins, int n_cu, FuseSync& fs, hipStream_t st) {
+  const void* k = fused_kernel(s, a.q.n_rows);
+  if (!k || a.exact || a.qbk || n_ins == 0 || !fs.dev || !fs.gave_up) return hipErrorNotSupported;
+  FusedInsert f;
+  if (!insert_run_arrays(s, ins_scratch, n_ins, &f.recs, &f.items)) return hipErrorNotSupported;
+  const size_t lds = query_lds_bytes(s, kFusedWaves, false);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const uint32_t nq = (uint32_t)a.q.n_rows;
+  const uint64_t runs = (uint64_t)s.L * n_ins;
+  constexpr uint32_t per = kFusedWaves * SL_WAVE / 16;
+  // one 16-wave group per CU beside the queries (what the kernel's
+  // registers allow); the groups stride over the records
+  const uint64_t want = (runs + per - 1) / per;
+  const uint64_t room = (uint64_t)std::max(n_cu - (int)std::min<uint32_t>(nq, 1u << 20), 64);
+  f.n_ins = n_ins;
+  f.merge_groups = (uint32_t)std::max<uint64_t>(1, std::min(want, room));
+  f.sync = fs.dev;
+  f.ticket_base = fs.tickets;
+  f.gathered_target = fs.gathered + nq;
+  f.gave_up = fs.gave_up;
+  Shape sh = s;
+  ConstView cv = c;
+  TablesView tv = tab;
+  QueryArgs qa = a;
+  void* args[] = {&sh, &cv, &tv, &qa, &f};
+  const uint32_t grid = nq + f.merge_groups;
+  hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(kFusedWaves * SL_WAVE), args, lds, st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  fs.tickets += grid;
+  fs.gathered += nq;
+  return hipSuccess;
 }
 
 void* persistent_query_kernel(const Shape& s, uint32_t waves, bool exact) {

@@ -27,6 +27,10 @@
 //     table writes on the batch stream.  No event joins the two streams: a
 //     cross-stream event wait costs the launching thread about 20 us per
 //     insert on this runtime;
+//   - a small query batch followed in the FIFO by an insert whose
+//     preparation is done writes that insert's tables in its own launch:
+//     the kernel's table writers start once every query of the batch has
+//     read its slots (one kernel and one launch gap less per insert);
 //   - query results are written by the query kernel straight into pinned,
 //     host-coherent memory (no copy back);
 //   - slots are added while work is waiting, up to max_inflight, as long as
@@ -35,7 +39,9 @@
 //   - with max_wait_us > 0, a batch that is neither full nor followed by an
 //     insert is held back until its oldest query has waited that long;
 //   - finished work is detected with one event per launch (polled without
-//     sleeping while work is in flight) and turned into completions.
+//     sleeping while work is in flight; every event is recorded on the batch
+//     stream, so they complete in launch order and only the oldest
+//     outstanding one is polled) and turned into completions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,7 +107,6 @@ struct Slot {
   uint64_t* flag = nullptr;
   uint64_t prep_seq = 0;
   bool prep_failed = false;
-  bool uncommitted = false;  // prepared, table writes not launched yet (done is stale)
 };
 
 }  // namespace
@@ -118,10 +123,14 @@ struct slash_server {
   std::vector<Slot> ins;    // insert staging
   hipStream_t stream = nullptr;  // query batches and table writes, in FIFO order
   hipStream_t prep = nullptr;    // insert preparation
+  FuseSync fuse;                 // counters of query launches that also write an insert
   uint64_t prep_seq = 0;         // preparations launched
   size_t prep_scan = 0;          // FIFO entries from the head already looked at for preparation
   uint32_t cap_q = 0;
   uint64_t cap_nnz = 0, per_slot = 0;
+  // slots with launched work, in launch order: (insert slot?, index); the
+  // scheduler thread's only
+  std::deque<std::pair<bool, uint32_t>> inflight;
   uint64_t epoch = 0;
   uint64_t next_ticket = 0;
   uint64_t next_id = 0;  // id of the next inserted row
@@ -264,9 +273,15 @@ void finish_slot(slash_server* srv, Slot& s, int32_t status) {
 // host link.
 constexpr size_t kZeroCopyBytes = size_t(64) << 10;
 
+hipError_t wait_prepared(slash_server* srv, const Slot& s);
+
 // Launch a query batch on slot s (lock not held; reqs already moved in):
 // (copy in,) query with results written to host-coherent memory, one event.
-hipError_t launch_queries(slash_server* srv, Slot& s) {
+// With `ins`, the prepared insert queued right behind the batch is committed
+// too, by the same kernel when one fits (*fused set), else by its own launch
+// after the batch's.
+hipError_t launch_queries(slash_server* srv, Slot& s, Slot* ins, bool* fused) {
+  const double t0 = now_s();
   const uint32_t n = (uint32_t)s.reqs.size();
   const uint32_t km = srv->info.params.k_max;
   uint64_t nnz = 0;
@@ -284,6 +299,7 @@ hipError_t launch_queries(slash_server* srv, Slot& s) {
     h_ip[q + 1] = (int64_t)off;
     h_k[q] = r.k;
   }
+  srv->stats.pack_s += now_s() - t0;
   hipStream_t st = srv->stream;
   hipError_t e;
   const char* in = s.h_in;
@@ -292,19 +308,36 @@ hipError_t launch_queries(slash_server* srv, Slot& s) {
     in = s.d_in;
   }
   slash_csr q{(const int64_t*)in, (const int32_t*)(in + l.idx), n};
+  *fused = false;
+  if (ins) {
+    if ((e = wait_prepared(srv, *ins)) != hipSuccess) return e;
+    const slash_status fs = query_insert(srv->ix, q, (const uint32_t*)(in + l.k), s.h_out, s.h_out + (size_t)n * km,
+                                         ins->sc, ins->rows, srv->fuse, st);
+    if (fs == SLASH_OK) {
+      *fused = true;
+      if ((e = hipEventRecord(s.done, st)) != hipSuccess) return e;
+      return hipEventRecord(ins->done, st);
+    }
+    if (fs != SLASH_E_UNSUPPORTED) return hipErrorLaunchFailure;
+  }
   slash_status rs = slash_query(srv->ix, q, (const uint32_t*)(in + l.k), 0, SLASH_FLAG_TRUSTED, s.h_out,
                                 s.h_out + (size_t)n * km, st);
   if (rs != SLASH_OK) return hipErrorLaunchFailure;
-  return hipEventRecord(s.done, st);
+  if ((e = hipEventRecord(s.done, st)) != hipSuccess) return e;
+  if (!ins) return hipSuccess;
+  if (insert_commit(srv->ix, ins->sc, ins->rows, st) != SLASH_OK) return hipErrorLaunchFailure;
+  return hipEventRecord(ins->done, st);
 }
 
-// Pack the FIFO's inserts [i, j) into insert slot s's staging (lock held).
-void pack_inserts(slash_server* srv, Slot& s, size_t i, size_t j) {
+// Pack inserts `rs` into insert slot s's staging.  Called without the lock:
+// the requests stay in the FIFO, whose other thread only appends (which
+// moves no element).
+void pack_inserts(Slot& s, const std::vector<const Request*>& rs) {
   uint32_t rows = 0;
   uint64_t nnz = 0;
-  for (size_t x = i; x < j; ++x) {
-    rows += srv->pending[x].n_rows;
-    nnz += srv->pending[x].idx.size();
+  for (const Request* r : rs) {
+    rows += r->n_rows;
+    nnz += r->idx.size();
   }
   const InLayout l = in_layout(rows, nnz, false);
   int64_t* h_ip = (int64_t*)s.h_in;
@@ -312,8 +345,8 @@ void pack_inserts(slash_server* srv, Slot& s, size_t i, size_t j) {
   uint32_t row = 0;
   uint64_t off = 0;
   h_ip[0] = 0;
-  for (size_t x = i; x < j; ++x) {
-    const Request& r = srv->pending[x];
+  for (const Request* rp : rs) {
+    const Request& r = *rp;
     for (uint32_t k = 0; k < r.n_rows; ++k) h_ip[row + k + 1] = (int64_t)off + r.indptr[k + 1];
     memcpy(h_ix + off, r.idx.data(), r.idx.size() * 4);
     off += r.idx.size();
@@ -350,9 +383,8 @@ hipError_t prepare_insert(slash_server* srv, Slot& s) {
 // device failure.
 constexpr double kPrepTimeout = 10.0;
 
-// Commit prepared insert slot s on the batch stream (lock not held): wait
-// until its preparation has set the word, write the tables, record done.
-hipError_t commit_insert(slash_server* srv, Slot& s) {
+// Wait (bounded) until insert slot s's preparation has set its word.
+hipError_t wait_prepared(slash_server* srv, const Slot& s) {
   if (s.prep_failed) return hipErrorLaunchFailure;
   const volatile uint64_t* f = s.flag;
   if (*f < s.prep_seq) {
@@ -361,6 +393,17 @@ hipError_t commit_insert(slash_server* srv, Slot& s) {
       if (now_s() - t0 > kPrepTimeout) return hipErrorLaunchTimeOut;
     srv->stats.wait_s += now_s() - t0;
   }
+  return hipSuccess;
+}
+
+// Whether insert slot s's preparation has set its word (no wait).
+bool is_prepared(const Slot& s) { return !s.prep_failed && *(const volatile uint64_t*)s.flag >= s.prep_seq; }
+
+// Commit prepared insert slot s on the batch stream (lock not held): wait
+// until its preparation has set the word, write the tables, record done.
+hipError_t commit_insert(slash_server* srv, Slot& s) {
+  hipError_t e = wait_prepared(srv, s);
+  if (e != hipSuccess) return e;
   if (insert_commit(srv->ix, s.sc, s.rows, srv->stream) != SLASH_OK) return hipErrorLaunchFailure;
   return hipEventRecord(s.done, srv->stream);
 }
@@ -371,11 +414,27 @@ void pop_head(slash_server* srv) {
   if (srv->prep_scan) --srv->prep_scan;
 }
 
+// Move the prepared inserts at the FIFO's head (those sharing the head's
+// insert slot) into that slot; each closes its own epoch.  Lock held.
+Slot& take_insert(slash_server* srv) {
+  const int32_t idx = srv->pending.front().prep;
+  Slot& s = srv->ins[idx];
+  s.reqs.clear();
+  while (!srv->pending.empty() && srv->pending.front().kind == 1 && srv->pending.front().prep == idx) {
+    s.reqs.push_back(std::move(srv->pending.front()));
+    pop_head(srv);
+  }
+  s.epoch = srv->epoch + 1;
+  srv->epoch += s.reqs.size();
+  return s;
+}
+
 // Prepare the queued inserts in FIFO order while insert slots are free; the
 // inserts queued right behind one share its slot while they fit its staging
 // (one launch, each request still its own epoch).  Lock held; released
 // around the launches.
 void prepare_ahead(slash_server* srv, std::unique_lock<std::mutex>& lk) {
+  std::vector<const Request*> rs;
   size_t i = srv->prep_scan;
   while (i < srv->pending.size()) {
     if (srv->pending[i].kind != 1 || srv->pending[i].prep >= 0) {
@@ -393,27 +452,30 @@ void prepare_ahead(slash_server* srv, std::unique_lock<std::mutex>& lk) {
     size_t j = i;
     uint32_t rows = 0;
     uint64_t nnz = 0;
+    rs.clear();
     while (j < srv->pending.size() && srv->pending[j].kind == 1) {
       Request& r = srv->pending[j];
       if (j > i && (rows + r.n_rows > s.cap_q || nnz + r.idx.size() > s.cap_nnz)) break;
       rows += r.n_rows;
       nnz += r.idx.size();
       r.prep = slot;
+      rs.push_back(&r);
       ++j;
     }
-    pack_inserts(srv, s, i, j);
     s.reqs.clear();
     s.kind = 1;
     s.busy = true;
-    s.uncommitted = true;
     s.prep_failed = false;
     srv->stats.batches++;
     i = j;
     srv->prep_scan = i;
     lk.unlock();
     const double t0 = now_s();
+    pack_inserts(s, rs);
+    const double t1 = now_s();
     const hipError_t e = prepare_insert(srv, s);
-    srv->stats.launch_s += now_s() - t0;
+    srv->stats.pack_s += t1 - t0;
+    srv->stats.launch_s += now_s() - t1;
     lk.lock();
     if (e != hipSuccess) {
       srv->dev_err = e;
@@ -466,6 +528,9 @@ void scheduler(slash_server* srv) {
   const uint32_t max_batch = srv->cfg.max_batch;
   const double max_wait = srv->cfg.max_wait_us * 1e-6;
   std::vector<std::pair<Slot*, hipError_t>> finished;
+  auto slot_of = [srv](const std::pair<bool, uint32_t>& f) -> Slot& {
+    return f.first ? srv->ins[f.second] : srv->slots[f.second];
+  };
   double busy_since = -1.0;
   std::unique_lock<std::mutex> lk(srv->mu);
   for (;;) {
@@ -473,16 +538,21 @@ void scheduler(slash_server* srv) {
     //    the events are queried without the lock.
     lk.unlock();
     finished.clear();
-    for (std::vector<Slot>* group : {&srv->slots, &srv->ins})
-      for (Slot& s : *group)
-        if (s.busy && !s.uncommitted) {
-          const hipError_t q = hipEventQuery(s.done);
-          if (q != hipErrorNotReady) finished.emplace_back(&s, q);
-        }
+    while (!srv->inflight.empty()) {
+      Slot& s = slot_of(srv->inflight.front());
+      const hipError_t q = hipEventQuery(s.done);
+      if (q == hipErrorNotReady) break;
+      finished.emplace_back(&s, q);
+      srv->inflight.pop_front();
+    }
     lk.lock();
+    // a fused launch whose table writer stopped waiting may have let queries
+    // see part of an insert: every result from then on is reported failed
+    const bool gave_up = *(const volatile uint32_t*)srv->fuse.gave_up != 0;
+    if (gave_up && srv->dev_err == hipSuccess) srv->dev_err = hipErrorLaunchTimeOut;
     for (auto& [s, q] : finished) {
       if (q != hipSuccess) srv->dev_err = q;
-      finish_slot(srv, *s, q == hipSuccess ? SLASH_OK : SLASH_E_DEVICE);
+      finish_slot(srv, *s, q == hipSuccess && !gave_up ? SLASH_OK : SLASH_E_DEVICE);
     }
     if (!finished.empty()) srv->cv.notify_all();
     // 2. prepare queued inserts, admit the head of the FIFO
@@ -493,25 +563,18 @@ void scheduler(slash_server* srv) {
       Request& head = srv->pending.front();
       if (head.kind == 1) {
         if (head.prep < 0) break;  // waits for an insert slot
-        const int32_t idx = head.prep;
-        Slot& s = srv->ins[idx];
-        s.reqs.clear();
-        while (!srv->pending.empty() && srv->pending.front().kind == 1 && srv->pending.front().prep == idx) {
-          s.reqs.push_back(std::move(srv->pending.front()));
-          pop_head(srv);
-        }
-        s.epoch = srv->epoch + 1;
-        srv->epoch += s.reqs.size();
+        Slot& s = take_insert(srv);
         lk.unlock();
         const double t0 = now_s();
         const hipError_t e = commit_insert(srv, s);
         srv->stats.launch_s += now_s() - t0;
         lk.lock();
-        s.uncommitted = false;
         if (e != hipSuccess) {
           srv->dev_err = e;
           finish_slot(srv, s, SLASH_E_DEVICE);
           srv->cv.notify_all();
+        } else {
+          srv->inflight.emplace_back(true, (uint32_t)(&s - srv->ins.data()));
         }
         continue;
       }
@@ -548,12 +611,32 @@ void scheduler(slash_server* srv) {
       s.busy = true;
       s.epoch = srv->epoch;
       srv->stats.batches++;
+      // the insert queued right behind the batch goes into the same launch
+      // when its preparation is done (or always, waiting for it, with
+      // insert_fusion 2)
+      Slot* ins = nullptr;
+      if (srv->cfg.insert_fusion != 1 && !srv->pending.empty() && srv->pending.front().kind == 1 &&
+          srv->pending.front().prep >= 0 && query_insert_ok(srv->ix, s.reqs.size())) {
+        Slot& is = srv->ins[srv->pending.front().prep];
+        if (!is.prep_failed && (srv->cfg.insert_fusion == 2 || is_prepared(is))) ins = &take_insert(srv);
+      }
       lk.unlock();
-      const double t0 = now_s();
-      hipError_t e = launch_queries(srv, s);
-      srv->stats.launch_s += now_s() - t0;
+      const double t0 = now_s(), p0 = srv->stats.pack_s;
+      bool fused = false;
+      hipError_t e = launch_queries(srv, s, ins, &fused);
+      srv->stats.launch_s += (now_s() - t0) - (srv->stats.pack_s - p0);
       lk.lock();
-      if (e != hipSuccess) srv->dev_err = e;
+      if (ins && fused) srv->stats.fused_commits++;
+      if (e != hipSuccess) {
+        // nothing of this launch can be trusted: fail its requests now
+        srv->dev_err = e;
+        finish_slot(srv, s, SLASH_E_DEVICE);
+        if (ins) finish_slot(srv, *ins, SLASH_E_DEVICE);
+        srv->cv.notify_all();
+      } else {
+        srv->inflight.emplace_back(false, (uint32_t)(&s - srv->slots.data()));
+        if (ins) srv->inflight.emplace_back(true, (uint32_t)(ins - srv->ins.data()));
+      }
       uint64_t inflight = 0;
       for (Slot& o : srv->slots) inflight += o.busy;
       srv->stats.peak_inflight = std::max(srv->stats.peak_inflight, inflight);
@@ -591,6 +674,8 @@ void free_server(slash_server* srv) {
       (void)hipStreamSynchronize(st);
       (void)hipStreamDestroy(st);
     }
+  (void)hipFree(srv->fuse.dev);
+  (void)hipHostFree(srv->fuse.gave_up);
   delete srv;
 }
 
@@ -600,6 +685,7 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   if (!ix || !cfg || !out) return fail(SLASH_E_INVAL, "NULL argument");
   if (cfg->max_batch == 0 || cfg->max_inflight == 0 || cfg->queue_capacity == 0 || cfg->max_query_nnz == 0)
     return fail(SLASH_E_INVAL, "max_batch, max_inflight, queue_capacity and max_query_nnz must be >= 1");
+  if (cfg->insert_fusion > 2) return fail(SLASH_E_INVAL, "insert_fusion must be 0, 1 or 2");
   slash_server* srv = new slash_server();
   srv->ix = ix;
   srv->cfg = *cfg;
@@ -636,6 +722,12 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
     free_server(srv);
     return fail(SLASH_E_DEVICE, "stream creation failed");
   }
+  if (hipMalloc(&srv->fuse.dev, 256) != hipSuccess || hipMemset(srv->fuse.dev, 0, 256) != hipSuccess ||
+      hipHostMalloc(&srv->fuse.gave_up, 64, hipHostMallocCoherent) != hipSuccess) {
+    free_server(srv);
+    return fail(SLASH_E_NOMEM, "fused-launch counters");
+  }
+  *(volatile uint32_t*)srv->fuse.gave_up = 0;
   srv->ins.emplace_back();
   if (!alloc_slot(srv->ins[0], ins_rows, ins_nnz, km, false, keys_b, runs_b)) {
     free_server(srv);

@@ -248,6 +248,9 @@ hipError_t launch_insert_runs(const Shape& s, const ConstView& c, void* scratch,
                               hipStream_t st);
 hipError_t launch_insert_small(const Shape& s, const ConstView& c, const uint32_t* keys, uint32_t n, uint32_t first_id,
                                void* scratch, TablesView tab, hipStream_t st);
+// The run records ([L][n] uint2) and ids ([L][n]) inside a small insert's
+// scratch; false when n does not take the small path.
+bool insert_run_arrays(const Shape& s, void* scratch, uint32_t n, const uint2** recs, const uint32_t** items);
 // Insert merge: sorted combined keys (t*nb+b) with new ids -> merged reservoirs.
 hipError_t launch_insert_merge(const Shape& s, const ConstView& c, const uint32_t* skeys,
                                const uint32_t* svals, uint64_t n, uint32_t* seg_scratch,
@@ -278,6 +281,22 @@ hipError_t launch_query_waves(const Shape& s, const ConstView& c, const TablesVi
                               uint32_t waves, hipStream_t st);
 hipError_t launch_query(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
                         hipStream_t st);
+// One launch that answers a small query batch (count-min, hashing in the
+// kernel) and then applies a prepared small insert's runs to the tables,
+// after every query of the batch has read them.  `dev` holds two device
+// words that start at zero and only grow; tickets/gathered are their values
+// after the last launch (updated here; launches using one FuseSync must be
+// ordered on one stream).  gave_up is a host-coherent word a launch sets when
+// its bounded wait ends without the queries' count.  hipErrorNotSupported
+// when the shape or batch has no fused kernel (then launch the two parts).
+struct FuseSync {
+  unsigned long long* dev = nullptr;
+  uint32_t* gave_up = nullptr;
+  unsigned long long tickets = 0, gathered = 0;
+};
+bool query_insert_supported(const Shape& s, uint64_t n_queries);
+hipError_t launch_query_insert(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
+                               void* ins_scratch, uint32_t n_ins, int n_cu, FuseSync& fs, hipStream_t st);
 hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const TablesView& tab,
                                    const QueryArgs& a, uint32_t waves, uint32_t per_ticket, uint32_t grid,
                                    uint32_t* ticket, hipStream_t st);
@@ -331,5 +350,11 @@ bool insert_scratch_bytes(const slash_index* ix, uint32_t rows, size_t* keys_byt
 slash_status insert_prepare(slash_index* ix, slash_csr rows, const InsertScratch& sc, hipStream_t st,
                             uint32_t* first_id, const GroupSignal& sig = {});
 slash_status insert_commit(slash_index* ix, const InsertScratch& sc, uint32_t n, hipStream_t st);
+// Query batch q (per-query k in kq, count-min) and the commit of prepared
+// insert sc (n rows) in one launch on `st` (see launch_query_insert).
+// SLASH_E_UNSUPPORTED when no fused kernel fits: nothing was launched.
+bool query_insert_ok(const slash_index* ix, uint64_t n_queries);
+slash_status query_insert(slash_index* ix, slash_csr q, const uint32_t* kq, uint32_t* ids, uint32_t* scores,
+                          const InsertScratch& sc, uint32_t n, FuseSync& fs, hipStream_t st);
 
 }  // namespace slash

@@ -54,9 +54,11 @@ def test_binding_struct_layouts_match_header(tmp_path):
         "slash_index_info": (api.IndexInfo, ["params", "n_items", "table_bytes", "n_buckets"]),
         "slash_schedule": (api.Schedule, ["waves_per_query", "groups_per_cu"]),
         "slash_phase_stat": (api.PhaseStat, ["name", "launches", "total_ms", "alg_bytes"]),
-        "slash_serve_config": (api.ServeConfig, ["hbm_budget_bytes", "max_batch", "max_query_nnz", "max_insert_nnz"]),
+        "slash_serve_config": (api.ServeConfig, ["hbm_budget_bytes", "max_batch", "max_query_nnz", "max_insert_nnz",
+                                                 "insert_fusion"]),
         "slash_completion": (api.Completion, ["ticket", "status", "ids", "scores", "t_submit_s", "t_done_s"]),
-        "slash_serve_stats": (api.ServeStats, ["queries_done", "peak_hbm_bytes", "busy_s", "wait_s"]),
+        "slash_serve_stats": (api.ServeStats, ["queries_done", "peak_hbm_bytes", "busy_s", "wait_s", "pack_s",
+                                               "fused_commits"]),
     }
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "slash.h"', "int main(void) {"]
     for cname, (_, fields) in checks.items():

@@ -267,13 +267,15 @@ def test_replay_open_loop(api, setup):
     idx.close()
 
 
-@pytest.mark.parametrize("bucket", [0, 1])
-def test_burst_inserts_prepared_ahead(api, setup, bucket):
+@pytest.mark.parametrize("bucket,fusion", [(0, 0), (0, 1), (0, 2), (1, 0)])
+def test_burst_inserts_prepared_ahead(api, setup, bucket, fusion):
     # every request submitted before the first poll, so the FIFO is long:
-    # inserts are prepared ahead (at most four insert slots at once, runs of
+    # inserts are prepared ahead (at most eight insert slots at once, runs of
     # back-to-back inserts sharing a slot) while the query batches before
     # them run; each query equals the oracle on the rows inserted before it,
-    # and the ids of the inserts follow submission order
+    # and the ids of the inserts follow submission order.  fusion 2 writes
+    # every insert that follows a query batch in that batch's launch (the
+    # queries must not see it), fusion 1 never does
     law, params, ip, ix, n0, n1, qi, qx, kq = setup
     if bucket:
         params = api.Params.of(dim=1 << 20, K=4, L=16, log2_buckets=12, R=1, cm_rows=4, log2_cm_width=4, k_max=100,
@@ -291,7 +293,8 @@ def test_burst_inserts_prepared_ahead(api, setup, bucket):
     total_rows = sum(m for kind, m in plan if kind == "i")
     iip, iix = law.rows(n0, total_rows)
     idx = api.Index(params, dev(ip[: n0 + 1]), dev(ix[: ip[n0]]))
-    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=256 << 20, max_batch=16, max_inflight=4)
+    srv = api.slash_serve_start(idx.handle, hbm_budget_bytes=256 << 20, max_batch=16, max_inflight=4,
+                                insert_fusion=fusion)
     tickets = {}
     row = 0
     n_ins = 0
@@ -309,6 +312,11 @@ def test_burst_inserts_prepared_ahead(api, setup, bucket):
         got += api.slash_serve_poll(srv)
     stats = api.slash_serve_stop(srv)
     assert stats["inserts_done"] == n_ins and stats["rows_inserted"] == total_rows
+    if fusion == 1 or bucket:
+        assert stats["fused_commits"] == 0
+    elif fusion == 2:
+        # an insert queued right behind a query batch (there are dozens)
+        assert stats["fused_commits"] >= 1, stats
     # the oracle's tables after each insert, and its answers per epoch
     op = oracle_params(params)
     cs = oracle.constants(op)
