@@ -137,6 +137,77 @@ __device__ __forceinline__ uint32_t hs_slot(uint32_t id, uint32_t log2_size) {
   return (id * 0x9E3779B1u) >> (32 - log2_size);
 }
 
+// The two quadratic passes over a few dozen collected keys (in LDS).  In
+// the 8- and 16-wave groups (one query at a time, latency) they run with
+// sixteen lanes per key: lane `sub` of a group visits keys sub, sub + 16,
+// ... and the group combines its lanes' results, so a key costs n / 16
+// dependent LDS reads instead of n.  The 1- to 4-wave groups (throughput:
+// other groups on the CU hide the reads) keep one thread per key, which
+// needs fewer registers.  Every thread of the block calls them with the
+// same n.
+
+// u[e] = c[e], or 0 when an earlier key equals it.
+template <uint32_t NT>
+__device__ __forceinline__ void drop_copies(const uint64_t* c, uint64_t* u, uint32_t n) {
+  if constexpr (NT < 512) {
+    for (uint32_t e = threadIdx.x; e < n; e += NT) {
+      const uint64_t x = c[e];
+      bool copy = false;
+      for (uint32_t j = 0; j < e; ++j) copy |= c[j] == x;
+      u[e] = copy ? 0ull : x;
+    }
+    return;
+  }
+  const uint32_t sub = threadIdx.x & 15u, grp = threadIdx.x >> 4;
+  for (uint32_t e0 = 0; e0 < n; e0 += NT / 16) {
+    const uint32_t e = e0 + grp;
+    const uint64_t x = e < n ? c[e] : 0ull;
+    const uint32_t lim = e < n ? e : 0u;
+    uint32_t copy = 0;
+    for (uint32_t j = sub; j < lim; j += 16) copy |= c[j] == x ? 1u : 0u;
+    copy |= __shfl_xor(copy, 1, 16);
+    copy |= __shfl_xor(copy, 2, 16);
+    copy |= __shfl_xor(copy, 4, 16);
+    copy |= __shfl_xor(copy, 8, 16);
+    if (e < n && sub == 0) u[e] = copy ? 0ull : x;
+  }
+}
+
+// Rank every nonzero key of u[0, n) (distinct) by the number of larger
+// keys and write the kk best in order: id = ~low half, score = high half.
+template <uint32_t NT>
+__device__ __forceinline__ void rank_write(const uint64_t* u, uint32_t n, uint32_t kk, uint32_t* oid, uint32_t* osc) {
+  if constexpr (NT < 512) {
+    for (uint32_t e = threadIdx.x; e < n; e += NT) {
+      const uint64_t x = u[e];
+      if (x == 0) continue;
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < n; ++j) r += u[j] > x ? 1u : 0u;
+      if (r < kk) {
+        oid[r] = ~(uint32_t)x;
+        osc[r] = (uint32_t)(x >> 32);
+      }
+    }
+    return;
+  }
+  const uint32_t sub = threadIdx.x & 15u, grp = threadIdx.x >> 4;
+  for (uint32_t e0 = 0; e0 < n; e0 += NT / 16) {
+    const uint32_t e = e0 + grp;
+    const uint64_t x = e < n ? u[e] : 0ull;
+    const uint32_t lim = e < n ? n : 0u;
+    uint32_t r = 0;
+    for (uint32_t j = sub; j < lim; j += 16) r += u[j] > x ? 1u : 0u;
+    r += __shfl_xor(r, 1, 16);
+    r += __shfl_xor(r, 2, 16);
+    r += __shfl_xor(r, 4, 16);
+    r += __shfl_xor(r, 8, 16);
+    if (sub == 0 && x != 0 && r < kk) {
+      oid[r] = ~(uint32_t)x;
+      osc[r] = (uint32_t)(x >> 32);
+    }
+  }
+}
+
 // Add one to hist[d] for every participating lane, one LDS atomic per
 // distinct digit of the wave.
 __device__ __forceinline__ void hist_add(uint32_t* hist, bool part, uint32_t d) {
@@ -390,23 +461,9 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       __syncthreads();
       const uint32_t ns = misc[10];
       if (ns <= lay.tie_cap) {
-        for (uint32_t e = tid; e < ns; e += NT) {
-          const uint64_t x = cbf[e];
-          bool copy = false;
-          for (uint32_t j = 0; j < e; ++j) copy |= cbf[j] == x;
-          uq[e] = copy ? 0ull : x;
-        }
+        drop_copies<NT>(cbf, uq, ns);
         __syncthreads();
-        for (uint32_t e = tid; e < ns; e += NT) {
-          const uint64_t x = uq[e];
-          if (x == 0) continue;
-          uint32_t r = 0;
-          for (uint32_t j = 0; j < ns; ++j) r += uq[j] > x ? 1u : 0u;
-          if (r < kq) {
-            oid[r] = ~(uint32_t)x;
-            osc[r] = (uint32_t)(x >> 32);
-          }
-        }
+        rank_write<NT>(uq, ns, kq, oid, osc);
         done = true;
       }
       __syncthreads();
@@ -477,6 +534,12 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     uint32_t remaining = kk;
     uint32_t cur = 0;
     const int top = misc[5] < 256u ? 32 : 40;
+    // 8- and 16-wave groups: every wave reads the histogram itself after one
+    // barrier per round.  The two buffers are then never cleared: a round's
+    // counts are its buffer's totals minus what the buffer held after its
+    // previous round, which every lane keeps for its four digits (sa: the
+    // buffer of this round, sb: the other; swapped every round).
+    uint32_t sa[4] = {0u, 0u, 0u, 0u}, sb[4] = {0u, 0u, 0u, 0u};
     for (int shift = top; shift >= 0; shift -= 8, cur ^= 1u) {
       uint32_t* H = hist + 256 * cur;
       const uint64_t hi_mask = ~0ull << (shift + 8);
@@ -486,32 +549,68 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
         hist_add(H, part, (uint32_t)(key[i] >> shift) & 255u);
       }
       __syncthreads();
-      if (wave == 0) {
-        // lane owns digits 4*lane .. 4*lane+3; sums over the digits above
-        uint32_t h0 = H[4 * lane], h1 = H[4 * lane + 1], h2 = H[4 * lane + 2], h3 = H[4 * lane + 3];
-        H[4 * lane] = 0;
-        H[4 * lane + 1] = 0;
-        H[4 * lane + 2] = 0;
-        H[4 * lane + 3] = 0;
-        uint32_t mine = h0 + h1 + h2 + h3;
+      uint32_t D = 0, cum = 0, cnt = 0;
+      if constexpr (NT >= 512) {
+        uint32_t hh[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t t = H[4 * lane + j];
+          hh[j] = t - sa[j];
+          sa[j] = sb[j];
+          sb[j] = t;
+        }
+        const uint32_t mine = hh[0] + hh[1] + hh[2] + hh[3];
         uint32_t v = mine;
         for (int o = 1; o < SL_WAVE; o <<= 1) {
           uint32_t y = __shfl_down(v, o, SL_WAVE);
           if (lane + o < SL_WAVE) v += y;
         }
-        uint32_t hh[4] = {h0, h1, h2, h3};
-        uint32_t cum = v - mine;
+        uint32_t c0 = v - mine, fd = 0, fc = 0, fh = 0;
+        bool found = false;
         for (int j = 3; j >= 0; --j) {
-          if (cum < remaining && remaining <= cum + hh[j]) {
-            misc[1] = 4 * lane + j;
-            misc[2] = cum;
-            misc[3] = hh[j];
+          if (c0 < remaining && remaining <= c0 + hh[j]) {
+            found = true;
+            fd = 4 * lane + j;
+            fc = c0;
+            fh = hh[j];
           }
-          cum += hh[j];
+          c0 += hh[j];
         }
+        const uint64_t fm = ballot64(found);
+        const int src = fm ? __builtin_ctzll(fm) : 0;
+        D = __shfl(fd, src, SL_WAVE);
+        cum = __shfl(fc, src, SL_WAVE);
+        cnt = __shfl(fh, src, SL_WAVE);
+      } else {
+        if (wave == 0) {
+          // lane owns digits 4*lane .. 4*lane+3; sums over the digits above
+          uint32_t h0 = H[4 * lane], h1 = H[4 * lane + 1], h2 = H[4 * lane + 2], h3 = H[4 * lane + 3];
+          H[4 * lane] = 0;
+          H[4 * lane + 1] = 0;
+          H[4 * lane + 2] = 0;
+          H[4 * lane + 3] = 0;
+          uint32_t mine = h0 + h1 + h2 + h3;
+          uint32_t v = mine;
+          for (int o = 1; o < SL_WAVE; o <<= 1) {
+            uint32_t y = __shfl_down(v, o, SL_WAVE);
+            if (lane + o < SL_WAVE) v += y;
+          }
+          uint32_t hh[4] = {h0, h1, h2, h3};
+          uint32_t c0 = v - mine;
+          for (int j = 3; j >= 0; --j) {
+            if (c0 < remaining && remaining <= c0 + hh[j]) {
+              misc[1] = 4 * lane + j;
+              misc[2] = c0;
+              misc[3] = hh[j];
+            }
+            c0 += hh[j];
+          }
+        }
+        __syncthreads();
+        D = misc[1];
+        cum = misc[2];
+        cnt = misc[3];
       }
-      __syncthreads();
-      uint32_t D = misc[1], cum = misc[2], cnt = misc[3];
       remaining -= cum;
       prefix |= (uint64_t)D << shift;
       if (remaining == cnt) break;  // the whole digit bin is selected
@@ -535,15 +634,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     }
   }
   __syncthreads();
-  for (uint32_t e = tid; e < n_c; e += NT) {
-    uint64_t x = cb[e];
-    uint32_t r = 0;
-    for (uint32_t j = 0; j < n_c; ++j) r += cb[j] > x ? 1u : 0u;
-    if (r < kk) {
-      oid[r] = ~(uint32_t)x;
-      osc[r] = (uint32_t)(x >> 32);
-    }
-  }
+  rank_write<NT>(cb, n_c, kk, oid, osc);
   }
   for (uint32_t e = kk + tid; e < s.k_max; e += NT) {
     oid[e] = SL_EMPTY;

@@ -305,13 +305,28 @@ def test_query_exact_variant(api, qsetup, k):
     assert int(ws.max()) <= op.L
 
 
-def test_query_small_batches(api, qsetup):
-    # batches too small to fill the GPU run each query with 16 waves
+@pytest.mark.parametrize("k", [10, 24])
+def test_query_small_batches(api, qsetup, k):
+    # batches too small to fill the GPU run each query with 16 waves; k = 24
+    # (above 16) takes the radix select
     idx, op, cs, oids, oseen, qi, qx = qsetup
-    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 10, k_max=24)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, k, k_max=24)
     for a, b in ((0, 1), (1, 4), (4, 37)):
-        gi, gs = idx.query(dev(qi[a: b + 1] - qi[a]), dev(qx[qi[a]: qi[b]]), 10)
+        gi, gs = idx.query(dev(qi[a: b + 1] - qi[a]), dev(qx[qi[a]: qi[b]]), k)
         assert (u32(gi) == wi[a:b]).all() and (u32(gs) == ws[a:b]).all()
+
+
+@pytest.mark.parametrize("waves", [8, 16])
+def test_query_wide_groups_large_k(api, qsetup, waves):
+    # 8- and 16-wave groups take their own forms of the radix select and of
+    # the final ranking; per-query k from 0 to k_max against the oracle
+    idx, op, cs, oids, oseen, qi, qx = qsetup
+    kq = np.random.default_rng(5).choice([0, 1, 10, 17, 24], size=len(qi) - 1).astype(np.uint32)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=24, kq=kq)
+    gi, gs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)),
+                               schedule=dict(waves_per_query=waves, queries_per_ticket=0))
+    torch.cuda.synchronize()
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
 
 
 def test_query_per_query_k(api, qsetup):
