@@ -327,10 +327,11 @@ SLASH_API void slash_release_cache(void);
  * ahead in submission order (copied in, hashed and grouped on a second
  * stream into per-slot scratch, up to eight at a time), so only their table
  * writes sit in the ordered stream, and those run inside the launch of the
- * query batch before them when it is small (see insert_fusion).  Batch slots (device and
- * pinned host staging for one batch) are added while requests wait for one,
- * up to max_inflight, as long as the HBM budget and the device's free memory
- * (checked when a slot is added, leaving 1 GiB free) allow. */
+ * query batch before them when it is small (see insert_fusion).  Batch
+ * slots (device and pinned host staging for one batch) are allocated at
+ * start, up to max_inflight, as far as the HBM budget and the device's free
+ * memory (leaving 1 GiB free) allow; one that did not fit then is added
+ * later, while requests wait for a slot, if memory has freed up. */
 #define SLASH_SERVE_MAX_K 128u /* largest k a served query may ask for */
 
 typedef struct {

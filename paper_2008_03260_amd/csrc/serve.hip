@@ -33,9 +33,9 @@
 //     read its slots (one kernel and one launch gap less per insert);
 //   - query results are written by the query kernel straight into pinned,
 //     host-coherent memory (no copy back);
-//   - slots are added while work is waiting, up to max_inflight, as long as
-//     the HBM budget and the device's free memory (checked when a slot is
-//     added) allow;
+//   - batch slots are allocated at start, up to max_inflight, as far as the
+//     HBM budget and the device's free memory allow (a slot that did not fit
+//     then is added later, while work is waiting, if memory has freed up);
 //   - with max_wait_us > 0, a batch that is neither full nor followed by an
 //     insert is held back until its oldest query has waited that long;
 //   - finished work is detected with one event per launch (polled without
@@ -757,6 +757,14 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   bool warm = true;
   for (Slot& o : srv->ins) warm = warm && warm_slot(srv->prep, o, false);
   warm = warm && warm_slot(srv->stream, srv->slots[0], true);
+  // the other batch slots now, as far as the budget and the free memory
+  // allow: a slot added while serving stalls the scheduler thread in the
+  // allocators for up to a millisecond
+  while (warm && srv->slots.size() < cfg->max_inflight) {
+    Slot* s = grow_slots(srv);
+    if (!s) break;
+    warm = warm_slot(srv->stream, *s, true);
+  }
   if (warm) {
     // one single-index query loads the query kernels
     Slot& q = srv->slots[0];
