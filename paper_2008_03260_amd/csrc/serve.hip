@@ -911,18 +911,35 @@ extern "C" slash_status slash_serve_replay(slash_server* srv, uint64_t n, const 
       submitted.store(i + 1, std::memory_order_release);
     }
   });
-  // map ticket -> request once tickets are known; poll completions
+  // poll completions; tickets are mapped to requests at the end.  Each
+  // completion is kept as a compact record (and its ids only when asked
+  // for), in storage sized up front: growing a vector of whole completions
+  // (1 KB each) reallocated hundreds of MB while serving, and the page
+  // faults and unmapping stalled the scheduler thread for milliseconds.
+  struct Done {
+    uint64_t ticket;
+    double t_done_s;
+    uint32_t k, kind;
+  };
   std::vector<slash_completion> buf(256);
   uint64_t got = 0;
-  std::vector<std::pair<uint64_t, uint64_t>> pending_done;  // (ticket, completion index in store)
-  std::vector<slash_completion> store;
+  std::vector<Done> store;
+  store.reserve(n);
+  std::vector<uint32_t> id_store;
+  if (out_ids) id_store.resize(n * (uint64_t)out_stride);
   slash_status rs = SLASH_OK;
   uint64_t expected = n;
   while (got < expected) {
     uint32_t m = 0;
     rs = slash_serve_poll(srv, buf.data(), (uint32_t)buf.size(), &m);
     if (rs != SLASH_OK) break;
-    for (uint32_t j = 0; j < m; ++j) store.push_back(buf[j]);
+    for (uint32_t j = 0; j < m && store.size() < n; ++j) {
+      const slash_completion& c = buf[j];
+      if (out_ids && c.kind == 0)
+        memcpy(id_store.data() + store.size() * (uint64_t)out_stride, c.ids,
+               std::min<uint32_t>(c.k, out_stride) * sizeof(uint32_t));
+      store.push_back(Done{c.ticket, c.t_done_s, c.k, c.kind});
+    }
     got += m;
     if (client_err.load() && submitted.load() == n) {
       uint64_t ok = 0;
@@ -938,13 +955,15 @@ extern "C" slash_status slash_serve_replay(slash_server* srv, uint64_t n, const 
   std::vector<int64_t> req_of(n + 1, -1);
   for (uint64_t i = 0; i < n; ++i)
     if (tickets[i] != ~0ull && tickets[i] - base < n) req_of[tickets[i] - base] = (int64_t)i;
-  for (const slash_completion& c : store) {
+  for (size_t x = 0; x < store.size(); ++x) {
+    const Done& c = store[x];
     if (c.ticket - base >= n) continue;
     int64_t i = req_of[c.ticket - base];
     if (i < 0) continue;
     lat[i] = c.t_done_s - (t0 + t_arr[i]);
     if (out_ids && c.kind == 0)
-      for (uint32_t j = 0; j < std::min<uint32_t>(c.k, out_stride); ++j) out_ids[(uint64_t)i * out_stride + j] = c.ids[j];
+      memcpy(out_ids + (uint64_t)i * out_stride, id_store.data() + x * (uint64_t)out_stride,
+             std::min<uint32_t>(c.k, out_stride) * sizeof(uint32_t));
   }
   for (uint64_t i = 0; i < n; ++i)
     if (tickets[i] == ~0ull) lat[i] = -1.0;
