@@ -345,9 +345,11 @@ typedef struct {
   uint32_t max_query_nnz;     /* largest query row accepted */
   uint32_t max_insert_nnz;    /* indices one insert request may carry (0: max(4096 * 64, 8 * max_query_nnz)) */
   uint32_t insert_fusion;     /* 0: a query batch of at most (compute units / 2) queries that is followed
-                                 by an insert already prepared also writes that insert's tables, in the
-                                 same launch, after every query of the batch has read them; 1: never;
-                                 2: always, waiting for the insert's preparation.  Results are the same */
+                                 by an insert already prepared shares a launch with that insert: the
+                                 batch reads its slots, the insert's tables are written after every
+                                 query of the batch has, and the batch is ranked in the next launch;
+                                 1: never; 2: always, waiting for the insert's preparation.  Results
+                                 are the same */
   uint32_t reserved;          /* 0 */
 } slash_serve_config;
 

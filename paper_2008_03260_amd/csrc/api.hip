@@ -729,18 +729,26 @@ slash_status slash::insert_commit(slash_index* ix, const InsertScratch& sc, uint
   return SLASH_OK;
 }
 
-bool slash::query_insert_ok(const slash_index* ix, uint64_t n_queries) {
-  // the same condition under which slash_query runs a batch with 16 waves
-  return ix && n_queries * 2 <= (uint64_t)ix->n_cu && query_insert_supported(ix->shape, n_queries);
+bool slash::serve_step_ok(const slash_index* ix, uint64_t n_queries) {
+  // one 16-wave work-group per query: the batches slash_query runs that way
+  return ix && n_queries * 2 <= (uint64_t)ix->n_cu && serve_step_supported(ix->shape);
 }
 
-slash_status slash::query_insert(slash_index* ix, slash_csr q, const uint32_t* kq, uint32_t* ids, uint32_t* scores,
-                                 const InsertScratch& sc, uint32_t n, FuseSync& fs, hipStream_t st) {
-  if (!ix || !kq || !ids || !scores || n == 0 || n > sc.rows) return fail(SLASH_E_INVAL, "bad fused query and insert");
-  if (!query_insert_ok(ix, q.n_rows)) return fail(SLASH_E_UNSUPPORTED, "no fused query and insert kernel fits");
-  QueryArgs a{q, kq, 0, 1, ids, scores, nullptr};
-  const hipError_t e = launch_query_insert(ix->shape, ix->cv, tables(ix), a, sc.runs, n, ix->n_cu, fs, st);
-  if (e == hipErrorNotSupported) return fail(SLASH_E_UNSUPPORTED, "no fused query and insert kernel fits");
+slash_status slash::serve_step(slash_index* ix, const ServeBatch& prev, const ServeBatch& cur, bool gather_only,
+                               const InsertScratch* sc, uint32_t n, FuseSync& fs, hipStream_t st) {
+  if (!ix || (n && (!sc || n > sc->rows))) return fail(SLASH_E_INVAL, "bad serving step");
+  for (const ServeBatch* b : {&prev, &cur})
+    if (b->q.n_rows && (!b->kq || !b->ids || !b->scores)) return fail(SLASH_E_INVAL, "bad serving step batch");
+  if (!serve_step_ok(ix, prev.q.n_rows) || !serve_step_ok(ix, cur.q.n_rows))
+    return fail(SLASH_E_UNSUPPORTED, "no serving step kernel fits");
+  QueryArgs pa{prev.q, prev.kq, 0, 1, prev.ids, prev.scores, nullptr};
+  pa.slot_ids = prev.slot_ids;
+  QueryArgs ca{cur.q, cur.kq, 0, 1, cur.ids, cur.scores, nullptr};
+  ca.slot_ids = cur.slot_ids;
+  const hipError_t e = launch_serve_step(ix->shape, ix->cv, tables(ix), pa, ca, gather_only, n ? sc->runs : nullptr, n,
+                                         ix->n_cu, fs, st);
+  if (e == hipErrorNotSupported) return fail(SLASH_E_UNSUPPORTED, "no serving step kernel fits");
+  if (e == hipErrorInvalidValue) return fail(SLASH_E_INVAL, "malformed serving step");
   HIP_TRY(e);
   return SLASH_OK;
 }

@@ -217,9 +217,13 @@ __device__ __forceinline__ void hist_add(uint32_t* hist, bool part, uint32_t d) 
   if (part && lane_id() == (uint32_t)__builtin_ctzll(peers)) atomicAdd(&hist[d], (uint32_t)__builtin_popcountll(peers));
 }
 
+// What a call of query_one does (serving splits a query in two launches):
+constexpr int kQueryFull = 0;       // hash, gather, count, rank
+constexpr int kQueryGather = 1;     // hash and gather, the slot ids to a.slot_ids[q][slot]
+constexpr int kQueryAggregate = 2;  // count and rank the slot ids a gather left in a.slot_ids
 // `gathered`, when not null, is counted once the group's slots are all read
-// (a table writer may then start; see k_query_insert).
-template <int WAVES, int SPT, bool CL, bool EX>
+// (a table writer may then start; see k_serve_step).
+template <int WAVES, int SPT, bool CL, bool EX, int MODE = kQueryFull>
 __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a, uint32_t q,
                           uint32_t* lds, const QLayout& lay, unsigned long long* gathered = nullptr) {
   constexpr uint32_t NT = WAVES * SL_WAVE;
@@ -238,7 +242,9 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   for (uint32_t e = tid; e < lay.cm_words; e += NT) cmw[e] = 0;
   for (uint32_t e = tid; e < 512; e += NT) hist[e] = 0;
   if (tid < 16) misc[tid] = 0;
-  if (a.qbk) {
+  if (MODE == kQueryAggregate) {
+    // the slots were read by the gather
+  } else if (a.qbk) {
     for (uint32_t t = tid; t < s.L; t += NT) bk[t] = a.qbk[(uint64_t)q * s.L + t];
   } else if (wave == 0) {
     const int64_t beg = a.q.indptr[q], end = a.q.indptr[q + 1];
@@ -262,10 +268,26 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     uint32_t sl = tid_q + i * NT;
     id[i] = SL_EMPTY;
     if (sl < slots) {
-      const uint32_t t = rpow ? sl >> rsh : sl / s.R;
-      const uint32_t j = sl - t * s.R;
-      id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
+      if constexpr (MODE == kQueryAggregate) {
+        id[i] = a.slot_ids[(uint64_t)q * slots + sl];
+      } else {
+        const uint32_t t = rpow ? sl >> rsh : sl / s.R;
+        const uint32_t j = sl - t * s.R;
+        id[i] = tab.ids[((uint64_t)t * s.nb + bk[t]) * s.R + j];
+      }
     }
+  }
+  if constexpr (MODE == kQueryGather) {
+    // the stores take the loaded ids, so once every thread has passed the
+    // barrier all of this query's table reads are done
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      const uint32_t sl = tid_q + i * NT;
+      if (sl < slots) a.slot_ids[(uint64_t)q * slots + sl] = id[i];
+    }
+    __syncthreads();
+    if (gathered && tid == 0) atomicAdd(gathered, 1ull);
+    return;
   }
   uint64_t key[SPT];
   uint32_t nrep = 0, emax = 0;
@@ -688,26 +710,35 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE, (query_min_waves<WAVES, SPT>(
   }
 }
 
-// A small query batch and the table writes of the insert queued right
-// behind it, in one launch of 16-wave work-groups (serving).  Every group
-// takes a ticket when it starts.  The first n tickets answer the batch's
-// queries, one each, and count themselves in sync[1] once all the slots they
-// read are in registers.  The later tickets apply the insert's run records
-// (sixteen lanes per record, the groups striding over the records), each
-// wave waiting first until all n queries have counted themselves.  So the
-// queries see the tables without the insert, and the next launch on the
-// stream sees them with it.  A group only waits for groups that took
-// earlier tickets: those are running and wait for nothing, so the wait ends;
-// it is bounded all the same, and a group that gives up sets *gave_up.  Both
-// counters only grow; the host passes the values they reach before this
-// launch and once its queries are counted.
+// One serving launch (16-wave work-groups).  Every group takes a ticket when
+// it starts; in ticket order the groups are:
+//   1. the second half of the previous batch's queries, one group each:
+//      count and rank the slot ids their gather left in prev.slot_ids (they
+//      read no table);
+//   2. this batch's queries, one group each, whole or (gather_only) only the
+//      first half (hash, read the slots, store their ids in cur.slot_ids);
+//      each counts itself in sync[1] once all its table reads are done;
+//   3. the table writers of the insert queued behind this batch (sixteen
+//      lanes per run record, the groups striding over the records); before
+//      its first live record each wave waits until every query of this
+//      batch has counted itself.
+// So this batch's queries see the tables without the insert, the next
+// launch on the stream sees them with it, and a batch whose insert follows
+// it is ranked in the next launch, beside the next batch's reads, instead of
+// holding the insert (and every later epoch) back until its slowest query
+// is ranked.  A group only waits for groups that took earlier tickets: those
+// are running and wait for nothing, so the wait ends; it is bounded all the
+// same, and a group that gives up sets *gave_up.  Both counters only grow;
+// the host passes their values before this launch.
 constexpr uint32_t kFusedWaves = 16;
 constexpr uint32_t kFusedSpinLimit = 1u << 20;  // polls: seconds at most, against microseconds needed
 
-struct FusedInsert {
+struct StepArgs {
+  QueryArgs prev, cur;
+  uint32_t gather_only;
+  uint32_t n_ins, merge_groups;
   const uint2* recs;      // [L][n_ins] run records of the prepared insert
   const uint32_t* items;  // [L][n_ins] their new ids
-  uint32_t n_ins, merge_groups;
   unsigned long long* sync;  // [0] tickets taken, [1] queries past their reads
   unsigned long long ticket_base, gathered_target;
   uint32_t* gave_up;  // host-coherent
@@ -715,37 +746,42 @@ struct FusedInsert {
 
 template <int SPT, int E>
 __global__ void __launch_bounds__(kFusedWaves * SL_WAVE, (query_min_waves<kFusedWaves, SPT>()))
-    k_query_insert(Shape s, ConstView c, TablesView tab, QueryArgs a, FusedInsert f) {
+    k_serve_step(Shape s, ConstView c, TablesView tab, StepArgs a) {
   constexpr uint32_t NT = kFusedWaves * SL_WAVE;
   extern __shared__ uint32_t lds[];
   const QLayout lay = q_layout(s, false);
-  if (threadIdx.x == 0) lds[lay.ticket] = (uint32_t)(atomicAdd(&f.sync[0], 1ull) - f.ticket_base);
+  if (threadIdx.x == 0) lds[lay.ticket] = (uint32_t)(atomicAdd(&a.sync[0], 1ull) - a.ticket_base);
   __syncthreads();
   const uint32_t ticket = lds[lay.ticket];
-  const uint32_t nq = (uint32_t)a.q.n_rows;
-  if (ticket < nq) {
+  const uint32_t np = (uint32_t)a.prev.q.n_rows, nc = (uint32_t)a.cur.q.n_rows;
+  if (ticket < np + nc) {
     const ConstView cl = stage_consts(s, c, lds + lay.cst, NT);
     __syncthreads();
-    query_one<kFusedWaves, SPT, true, false>(s, cl, tab, a, ticket, lds, lay, &f.sync[1]);
+    if (ticket < np)
+      query_one<kFusedWaves, SPT, true, false, kQueryAggregate>(s, cl, tab, a.prev, ticket, lds, lay);
+    else if (a.gather_only)
+      query_one<kFusedWaves, SPT, true, false, kQueryGather>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
+    else
+      query_one<kFusedWaves, SPT, true, false, kQueryFull>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
     return;
   }
   // table writers: each wave takes four records per pass and, before its
   // first live record, waits for the batch's queries (lane 0 polls)
-  const uint64_t runs = (uint64_t)s.L * f.n_ins;
+  const uint64_t runs = (uint64_t)s.L * a.n_ins;
   constexpr uint32_t per = NT / 16;  // records per group and pass
   bool waited = false;
-  for (uint64_t r0 = (uint64_t)(ticket - nq) * per; r0 < runs; r0 += (uint64_t)f.merge_groups * per) {
+  for (uint64_t r0 = (uint64_t)(ticket - np - nc) * per; r0 < runs; r0 += (uint64_t)a.merge_groups * per) {
     const uint64_t run = r0 + threadIdx.x / 16;
-    const uint2 rec = run < runs ? f.recs[run] : make_uint2(0u, 0u);
+    const uint2 rec = run < runs ? a.recs[run] : make_uint2(0u, 0u);
     const bool live = (rec.y >> 16) != 0;
     if (__ballot(live) == 0) continue;
     if (!waited) {
       if (lane_id() == 0) {
         uint32_t spins = 0;
-        while (__hip_atomic_load(&f.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < f.gathered_target) {
+        while (__hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.gathered_target) {
           __builtin_amdgcn_s_sleep(2);
           if (++spins == kFusedSpinLimit) {
-            *(volatile uint32_t*)f.gave_up = 1u;
+            *(volatile uint32_t*)a.gave_up = 1u;
             break;
           }
         }
@@ -753,17 +789,17 @@ __global__ void __launch_bounds__(kFusedWaves * SL_WAVE, (query_min_waves<kFused
       waited = true;
     }
     if (live) {
-      const uint32_t t = (uint32_t)(run / f.n_ins);
-      merge_run16<E>(s, c, rec, t, f.items + (uint64_t)t * f.n_ins, tab);
+      const uint32_t t = (uint32_t)(run / a.n_ins);
+      merge_run16<E>(s, c, rec, t, a.items + (uint64_t)t * a.n_ins, tab);
     }
   }
 }
 
-// fused kernels by [log2 slots per thread][log2 entries per lane]
+// serving-step kernels by [log2 slots per thread][log2 entries per lane]
 template <int S>
 constexpr std::array<const void*, 4> kqi() {
-  return {(const void*)k_query_insert<S, 1>, (const void*)k_query_insert<S, 2>, (const void*)k_query_insert<S, 4>,
-          (const void*)k_query_insert<S, 8>};
+  return {(const void*)k_serve_step<S, 1>, (const void*)k_serve_step<S, 2>, (const void*)k_serve_step<S, 4>,
+          (const void*)k_serve_step<S, 8>};
 }
 const std::array<const void*, 4> kFused[5] = {kqi<1>(), kqi<2>(), kqi<4>(), kqi<8>(), kqi<16>()};
 
@@ -904,53 +940,66 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
   return hipGetLastError();
 }
 
-// Fused kernel for a batch of n queries and an insert (count-min queries,
-// constants in LDS, R <= 128), or nullptr.
-static const void* fused_kernel(const Shape& s, uint64_t n) {
-  if (n == 0 || n > (1u << 20) || s.bucket || s.R > 128 || !query_supported(s, kFusedWaves, false)) return nullptr;
+// Serving-step kernel for this shape (count-min queries, constants in LDS,
+// R <= 128), or nullptr.
+static const void* step_kernel(const Shape& s) {
+  if (s.bucket || s.R > 128 || !query_supported(s, kFusedWaves, false)) return nullptr;
   if (!q_layout(s).cst_fit) return nullptr;
   const uint32_t spt = (s.L * s.R + kFusedWaves * SL_WAVE - 1) / (kFusedWaves * SL_WAVE);
   const uint32_t e = (s.R + 15) / 16;
   return kFused[ilog2(spt < 1 ? 1 : spt)][ilog2(e)];
 }
 
-bool query_insert_supported(const Shape& s, uint64_t n_queries) { return fused_kernel(s, n_queries) != nullptr; }
+bool serve_step_supported(const Shape& s) { return step_kernel(s) != nullptr; }
 
-hipError_t launch_query_insert(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
-                               void* ins_scratch, uint32_t n_ins, int n_cu, FuseSync& fs, hipStream_t st) {
-  const void* k = fused_kernel(s, a.q.n_rows);
-  if (!k || a.exact || a.qbk || n_ins == 0 || !fs.dev || !fs.gave_up) return hipErrorNotSupported;
-  FusedInsert f;
-  if (!insert_run_arrays(s, ins_scratch, n_ins, &f.recs, &f.items)) return hipErrorNotSupported;
+hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& prev,
+                             const QueryArgs& cur, bool gather_only, void* ins_scratch, uint32_t n_ins, int n_cu,
+                             FuseSync& fs, hipStream_t st) {
+  const void* k = step_kernel(s);
+  if (!k || !fs.dev || !fs.gave_up) return hipErrorNotSupported;
+  if (prev.exact || cur.exact || prev.qbk || cur.qbk || prev.q.n_rows > (1u << 20) || cur.q.n_rows > (1u << 20))
+    return hipErrorInvalidValue;
+  if ((prev.q.n_rows && !prev.slot_ids) || (gather_only && cur.q.n_rows && !cur.slot_ids)) return hipErrorInvalidValue;
+  StepArgs a;
+  a.prev = prev;
+  a.cur = cur;
+  a.gather_only = gather_only ? 1u : 0u;
+  a.n_ins = 0;
+  a.merge_groups = 0;
+  a.recs = nullptr;
+  a.items = nullptr;
+  const uint32_t np = (uint32_t)prev.q.n_rows, nc = (uint32_t)cur.q.n_rows;
+  if (n_ins) {
+    if (!insert_run_arrays(s, ins_scratch, n_ins, &a.recs, &a.items)) return hipErrorInvalidValue;
+    const uint64_t runs = (uint64_t)s.L * n_ins;
+    constexpr uint32_t per = kFusedWaves * SL_WAVE / 16;
+    // one 16-wave group per CU beside the queries (what the kernel's
+    // registers allow); the groups stride over the records
+    const uint64_t want = (runs + per - 1) / per;
+    const uint64_t room = (uint64_t)std::max(n_cu - (int)std::min<uint32_t>(np + nc, 1u << 20), 64);
+    a.n_ins = n_ins;
+    a.merge_groups = (uint32_t)std::max<uint64_t>(1, std::min(want, room));
+  }
+  const uint32_t grid = np + nc + a.merge_groups;
+  if (grid == 0) return hipSuccess;
   const size_t lds = query_lds_bytes(s, kFusedWaves, false);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const uint32_t nq = (uint32_t)a.q.n_rows;
-  const uint64_t runs = (uint64_t)s.L * n_ins;
-  constexpr uint32_t per = kFusedWaves * SL_WAVE / 16;
-  // one 16-wave group per CU beside the queries (what the kernel's
-  // registers allow); the groups stride over the records
-  const uint64_t want = (runs + per - 1) / per;
-  const uint64_t room = (uint64_t)std::max(n_cu - (int)std::min<uint32_t>(nq, 1u << 20), 64);
-  f.n_ins = n_ins;
-  f.merge_groups = (uint32_t)std::max<uint64_t>(1, std::min(want, room));
-  f.sync = fs.dev;
-  f.ticket_base = fs.tickets;
-  f.gathered_target = fs.gathered + nq;
-  f.gave_up = fs.gave_up;
+  a.sync = fs.dev;
+  a.ticket_base = fs.tickets;
+  a.gathered_target = fs.gathered + nc;
+  a.gave_up = fs.gave_up;
   Shape sh = s;
   ConstView cv = c;
   TablesView tv = tab;
-  QueryArgs qa = a;
-  void* args[] = {&sh, &cv, &tv, &qa, &f};
-  const uint32_t grid = nq + f.merge_groups;
+  void* args[] = {&sh, &cv, &tv, &a};
   hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(kFusedWaves * SL_WAVE), args, lds, st);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return e;
   fs.tickets += grid;
-  fs.gathered += nq;
+  fs.gathered += nc;
   return hipSuccess;
 }
 

@@ -28,9 +28,12 @@
 //     cross-stream event wait costs the launching thread about 20 us per
 //     insert on this runtime;
 //   - a small query batch followed in the FIFO by an insert whose
-//     preparation is done writes that insert's tables in its own launch:
-//     the kernel's table writers start once every query of the batch has
-//     read its slots (one kernel and one launch gap less per insert);
+//     preparation is done shares one launch with that insert: the batch's
+//     queries only gather their slots (ids kept in device memory) and the
+//     insert's table writers start once they have; the batch is ranked in
+//     the next launch, beside the next batch's gathers, or on its own when
+//     none follows soon.  So an epoch costs one launch of about a gather and
+//     an insert's writes, not a whole query's ranking as well;
 //   - query results are written by the query kernel straight into pinned,
 //     host-coherent memory (no copy back);
 //   - batch slots are allocated at start, up to max_inflight, as far as the
@@ -38,7 +41,8 @@
 //     then is added later, while work is waiting, if memory has freed up);
 //   - with max_wait_us > 0, a batch that is neither full nor followed by an
 //     insert is held back until its oldest query has waited that long;
-//   - finished work is detected with one event per launch (polled without
+//   - finished work is detected with one event per launch, recorded into
+//     one of the slots the launch finishes (polled without
 //     sleeping while work is in flight; every event is recorded on the batch
 //     stream, so they complete in launch order and only the oldest
 //     outstanding one is polled) and turned into completions.
@@ -107,6 +111,17 @@ struct Slot {
   uint64_t* flag = nullptr;
   uint64_t prep_seq = 0;
   bool prep_failed = false;
+  // query slots: the slot ids of a batch gathered in one launch and ranked
+  // in a later one ([n][L * R], device), and the batch as packed
+  uint32_t* slot_ids = nullptr;
+  ServeBatch batch;
+};
+
+// One launch on the batch stream and the slots it finishes: one event,
+// recorded into the first slot's.
+struct Launch {
+  uint32_t n = 0;
+  std::pair<bool, uint32_t> slot[3];  // (insert slot?, index)
 };
 
 }  // namespace
@@ -128,9 +143,10 @@ struct slash_server {
   size_t prep_scan = 0;          // FIFO entries from the head already looked at for preparation
   uint32_t cap_q = 0;
   uint64_t cap_nnz = 0, per_slot = 0;
-  // slots with launched work, in launch order: (insert slot?, index); the
-  // scheduler thread's only
-  std::deque<std::pair<bool, uint32_t>> inflight;
+  // launches in flight, in launch order (the scheduler thread's only)
+  std::deque<Launch> inflight;
+  int32_t gathered = -1;       // batch slot gathered and waiting to be ranked
+  size_t slot_ids_bytes = 0;   // per batch slot (0: batches are never split)
   uint64_t epoch = 0;
   uint64_t next_ticket = 0;
   uint64_t next_id = 0;  // id of the next inserted row
@@ -152,6 +168,7 @@ void free_slot(Slot& s) {
   (void)hipFree(s.d_in);
   (void)hipFree(s.sc.keys);
   (void)hipFree(s.sc.runs);
+  (void)hipFree(s.slot_ids);
   (void)hipFree(s.counter);
   (void)hipHostFree(s.h_in);
   (void)hipHostFree(s.h_out);
@@ -176,7 +193,7 @@ InLayout in_layout(uint64_t n, uint64_t nnz, bool with_k) {
 // slots: plus insert scratch of keys_b + runs_b bytes and the
 // host-coherent preparation word and the device counter that sets it).
 bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool with_out, size_t keys_b = 0,
-                size_t runs_b = 0) {
+                size_t runs_b = 0, size_t slot_ids_b = 0) {
   s.cap_q = cap_q;
   s.cap_nnz = cap_nnz;
   const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
@@ -187,6 +204,7 @@ bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool 
   if (hipHostMalloc(&s.h_in, in_bytes, hipHostMallocCoherent) != hipSuccess) return false;
   if (with_out && hipHostMalloc(&s.h_out, (size_t)cap_q * k_max * 8, hipHostMallocCoherent) != hipSuccess)
     return false;
+  if (slot_ids_b && hipMalloc(&s.slot_ids, slot_ids_b) != hipSuccess) return false;
   if (!with_out) {
     if (hipMalloc(&s.sc.keys, keys_b) != hipSuccess || hipMalloc(&s.sc.runs, runs_b) != hipSuccess) return false;
     if (hipMalloc(&s.counter, 256) != hipSuccess || hipMemset(s.counter, 0, 256) != hipSuccess) return false;
@@ -275,12 +293,11 @@ constexpr size_t kZeroCopyBytes = size_t(64) << 10;
 
 hipError_t wait_prepared(slash_server* srv, const Slot& s);
 
-// Launch a query batch on slot s (lock not held; reqs already moved in):
-// (copy in,) query with results written to host-coherent memory, one event.
-// With `ins`, the prepared insert queued right behind the batch is committed
-// too, by the same kernel when one fits (*fused set), else by its own launch
-// after the batch's.
-hipError_t launch_queries(slash_server* srv, Slot& s, Slot* ins, bool* fused) {
+// Pack query batch slot s's requests into its staging (lock not held) and
+// set s.batch: request data read by the kernels in place (host-coherent)
+// when small, else copied in on the batch stream; results to host-coherent
+// memory.
+hipError_t pack_queries(slash_server* srv, Slot& s) {
   const double t0 = now_s();
   const uint32_t n = (uint32_t)s.reqs.size();
   const uint32_t km = srv->info.params.k_max;
@@ -300,33 +317,49 @@ hipError_t launch_queries(slash_server* srv, Slot& s, Slot* ins, bool* fused) {
     h_k[q] = r.k;
   }
   srv->stats.pack_s += now_s() - t0;
-  hipStream_t st = srv->stream;
-  hipError_t e;
   const char* in = s.h_in;
   if (l.bytes > kZeroCopyBytes) {
-    if ((e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    const hipError_t e = hipMemcpyAsync(s.d_in, s.h_in, l.bytes, hipMemcpyHostToDevice, srv->stream);
+    if (e != hipSuccess) return e;
     in = s.d_in;
   }
-  slash_csr q{(const int64_t*)in, (const int32_t*)(in + l.idx), n};
+  s.batch.q = slash_csr{(const int64_t*)in, (const int32_t*)(in + l.idx), n};
+  s.batch.kq = (const uint32_t*)(in + l.k);
+  s.batch.ids = s.h_out;
+  s.batch.scores = s.h_out + (size_t)n * km;
+  s.batch.slot_ids = s.slot_ids;
+  return hipSuccess;
+}
+
+// One launch on the batch stream (lock not held): rank the gathered batch
+// `agg`, answer (or, with gather_only, gather) the batch `cur`, commit the
+// prepared insert `ins`; each may be null.  A serving-step kernel does all
+// of it when one fits, else `cur` runs as slash_query and `ins` as its own
+// commit (agg and gather_only need the step kernel).  One event, recorded
+// into ev_slot's.  *fused is set when cur and ins shared the kernel.
+hipError_t launch_step(slash_server* srv, Slot* agg, Slot* cur, bool gather_only, Slot* ins, Slot& ev_slot,
+                       bool* fused) {
+  hipStream_t st = srv->stream;
+  hipError_t e;
   *fused = false;
-  if (ins) {
-    if ((e = wait_prepared(srv, *ins)) != hipSuccess) return e;
-    const slash_status fs = query_insert(srv->ix, q, (const uint32_t*)(in + l.k), s.h_out, s.h_out + (size_t)n * km,
-                                         ins->sc, ins->rows, srv->fuse, st);
-    if (fs == SLASH_OK) {
-      *fused = true;
-      if ((e = hipEventRecord(s.done, st)) != hipSuccess) return e;
-      return hipEventRecord(ins->done, st);
-    }
-    if (fs != SLASH_E_UNSUPPORTED) return hipErrorLaunchFailure;
+  if (cur && (e = pack_queries(srv, *cur)) != hipSuccess) return e;
+  if (ins && (e = wait_prepared(srv, *ins)) != hipSuccess) return e;
+  const bool step = srv->slot_ids_bytes && (agg || gather_only || (cur && ins)) &&
+                    (!cur || serve_step_ok(srv->ix, cur->reqs.size()));
+  if (step) {
+    const ServeBatch none;
+    if (serve_step(srv->ix, agg ? agg->batch : none, cur ? cur->batch : none, gather_only, ins ? &ins->sc : nullptr,
+                   ins ? ins->rows : 0, srv->fuse, st) != SLASH_OK)
+      return hipErrorLaunchFailure;
+    *fused = cur && ins;
+  } else {
+    if (agg || gather_only) return hipErrorInvalidValue;
+    if (cur && slash_query(srv->ix, cur->batch.q, cur->batch.kq, 0, SLASH_FLAG_TRUSTED, cur->batch.ids,
+                           cur->batch.scores, st) != SLASH_OK)
+      return hipErrorLaunchFailure;
+    if (ins && insert_commit(srv->ix, ins->sc, ins->rows, st) != SLASH_OK) return hipErrorLaunchFailure;
   }
-  slash_status rs = slash_query(srv->ix, q, (const uint32_t*)(in + l.k), 0, SLASH_FLAG_TRUSTED, s.h_out,
-                                s.h_out + (size_t)n * km, st);
-  if (rs != SLASH_OK) return hipErrorLaunchFailure;
-  if ((e = hipEventRecord(s.done, st)) != hipSuccess) return e;
-  if (!ins) return hipSuccess;
-  if (insert_commit(srv->ix, ins->sc, ins->rows, st) != SLASH_OK) return hipErrorLaunchFailure;
-  return hipEventRecord(ins->done, st);
+  return hipEventRecord(ev_slot.done, st);
 }
 
 // Pack inserts `rs` into insert slot s's staging.  Called without the lock:
@@ -398,15 +431,6 @@ hipError_t wait_prepared(slash_server* srv, const Slot& s) {
 
 // Whether insert slot s's preparation has set its word (no wait).
 bool is_prepared(const Slot& s) { return !s.prep_failed && *(const volatile uint64_t*)s.flag >= s.prep_seq; }
-
-// Commit prepared insert slot s on the batch stream (lock not held): wait
-// until its preparation has set the word, write the tables, record done.
-hipError_t commit_insert(slash_server* srv, Slot& s) {
-  hipError_t e = wait_prepared(srv, s);
-  if (e != hipSuccess) return e;
-  if (insert_commit(srv->ix, s.sc, s.rows, srv->stream) != SLASH_OK) return hipErrorLaunchFailure;
-  return hipEventRecord(s.done, srv->stream);
-}
 
 // Remove the FIFO's head (lock held).
 void pop_head(slash_server* srv) {
@@ -509,7 +533,7 @@ Slot* grow_slots(slash_server* srv) {
   size_t free_b = 0, total_b = 0;
   Slot s;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b < srv->per_slot + kFreeReserve ||
-      !alloc_slot(s, srv->cap_q, srv->cap_nnz, srv->info.params.k_max, true)) {
+      !alloc_slot(s, srv->cap_q, srv->cap_nnz, srv->info.params.k_max, true, 0, 0, srv->slot_ids_bytes)) {
     free_slot(s);
     (void)hipGetLastError();
     srv->grow_retry_at = now_s() + 0.01;
@@ -521,6 +545,42 @@ Slot* grow_slots(slash_server* srv) {
   // references, and none across this call
   srv->slots.push_back(s);
   return &srv->slots.back();
+}
+
+// Launch one step (lock held; released around the launch) and track it:
+// the slots it finishes retire with its event; a batch gathered here
+// becomes the one waiting to be ranked.  On failure every slot involved is
+// failed at once.
+void run_step(slash_server* srv, std::unique_lock<std::mutex>& lk, Slot* agg, Slot* cur, bool gather_only,
+              Slot* ins) {
+  auto id_of = [srv](Slot* x) {
+    return x >= srv->ins.data() && x < srv->ins.data() + srv->ins.size()
+               ? std::make_pair(true, (uint32_t)(x - srv->ins.data()))
+               : std::make_pair(false, (uint32_t)(x - srv->slots.data()));
+  };
+  Launch ln;
+  Slot* done_with[3] = {ins, gather_only ? nullptr : cur, agg};
+  for (Slot* x : done_with)
+    if (x) ln.slot[ln.n++] = id_of(x);
+  Slot& ev_slot = ins ? *ins : (!gather_only && cur) ? *cur : *agg;
+  if (agg) srv->gathered = -1;
+  lk.unlock();
+  const double t0 = now_s(), p0 = srv->stats.pack_s;
+  bool fused = false;
+  const hipError_t e = launch_step(srv, agg, cur, gather_only, ins, ev_slot, &fused);
+  srv->stats.launch_s += (now_s() - t0) - (srv->stats.pack_s - p0);
+  lk.lock();
+  if (fused) srv->stats.fused_commits++;
+  if (e != hipSuccess) {
+    // nothing of this launch can be trusted: fail its requests now
+    srv->dev_err = e;
+    for (Slot* x : {agg, cur, ins})
+      if (x) finish_slot(srv, *x, SLASH_E_DEVICE);
+    srv->cv.notify_all();
+    return;
+  }
+  srv->inflight.push_back(ln);
+  if (gather_only) srv->gathered = id_of(cur).second;
 }
 
 void scheduler(slash_server* srv) {
@@ -539,15 +599,15 @@ void scheduler(slash_server* srv) {
     lk.unlock();
     finished.clear();
     while (!srv->inflight.empty()) {
-      Slot& s = slot_of(srv->inflight.front());
-      const hipError_t q = hipEventQuery(s.done);
+      const Launch& ln = srv->inflight.front();
+      const hipError_t q = hipEventQuery(slot_of(ln.slot[0]).done);
       if (q == hipErrorNotReady) break;
-      finished.emplace_back(&s, q);
+      for (uint32_t i = 0; i < ln.n; ++i) finished.emplace_back(&slot_of(ln.slot[i]), q);
       srv->inflight.pop_front();
     }
     lk.lock();
-    // a fused launch whose table writer stopped waiting may have let queries
-    // see part of an insert: every result from then on is reported failed
+    // a launch whose table writers stopped waiting may have let queries see
+    // part of an insert: every result from then on is reported failed
     const bool gave_up = *(const volatile uint32_t*)srv->fuse.gave_up != 0;
     if (gave_up && srv->dev_err == hipSuccess) srv->dev_err = hipErrorLaunchTimeOut;
     for (auto& [s, q] : finished) {
@@ -555,27 +615,21 @@ void scheduler(slash_server* srv) {
       finish_slot(srv, *s, q == hipSuccess && !gave_up ? SLASH_OK : SLASH_E_DEVICE);
     }
     if (!finished.empty()) srv->cv.notify_all();
-    // 2. prepare queued inserts, admit the head of the FIFO
+    // 2. prepare queued inserts, admit the head of the FIFO.  A batch whose
+    //    insert follows it is only gathered in the launch that writes the
+    //    insert and ranked in the next launch (or on its own, below, when
+    //    none follows soon), so the next epoch need not wait for its ranking.
     double wake_at = 0.0;
+    bool slot_wait = false;  // stopped for want of a batch slot
     for (;;) {
       prepare_ahead(srv, lk);
       if (srv->pending.empty()) break;
       Request& head = srv->pending.front();
+      Slot* agg = srv->gathered >= 0 ? &srv->slots[srv->gathered] : nullptr;
       if (head.kind == 1) {
         if (head.prep < 0) break;  // waits for an insert slot
         Slot& s = take_insert(srv);
-        lk.unlock();
-        const double t0 = now_s();
-        const hipError_t e = commit_insert(srv, s);
-        srv->stats.launch_s += now_s() - t0;
-        lk.lock();
-        if (e != hipSuccess) {
-          srv->dev_err = e;
-          finish_slot(srv, s, SLASH_E_DEVICE);
-          srv->cv.notify_all();
-        } else {
-          srv->inflight.emplace_back(true, (uint32_t)(&s - srv->ins.data()));
-        }
+        run_step(srv, lk, agg, nullptr, false, &s);
         continue;
       }
       Slot* free_s = nullptr;
@@ -588,7 +642,10 @@ void scheduler(slash_server* srv) {
         lk.unlock();
         free_s = grow_slots(srv);
         lk.lock();
-        if (!free_s) break;
+        if (!free_s) {
+          slot_wait = true;
+          break;
+        }
       }
       Slot& s = *free_s;
       if (max_wait > 0 && !srv->stopping) {
@@ -611,35 +668,34 @@ void scheduler(slash_server* srv) {
       s.busy = true;
       s.epoch = srv->epoch;
       srv->stats.batches++;
+      const bool small = srv->slot_ids_bytes && serve_step_ok(srv->ix, s.reqs.size());
       // the insert queued right behind the batch goes into the same launch
       // when its preparation is done (or always, waiting for it, with
       // insert_fusion 2)
       Slot* ins = nullptr;
-      if (srv->cfg.insert_fusion != 1 && !srv->pending.empty() && srv->pending.front().kind == 1 &&
-          srv->pending.front().prep >= 0 && query_insert_ok(srv->ix, s.reqs.size())) {
+      if (small && srv->cfg.insert_fusion != 1 && !srv->pending.empty() && srv->pending.front().kind == 1 &&
+          srv->pending.front().prep >= 0) {
         Slot& is = srv->ins[srv->pending.front().prep];
         if (!is.prep_failed && (srv->cfg.insert_fusion == 2 || is_prepared(is))) ins = &take_insert(srv);
       }
-      lk.unlock();
-      const double t0 = now_s(), p0 = srv->stats.pack_s;
-      bool fused = false;
-      hipError_t e = launch_queries(srv, s, ins, &fused);
-      srv->stats.launch_s += (now_s() - t0) - (srv->stats.pack_s - p0);
-      lk.lock();
-      if (ins && fused) srv->stats.fused_commits++;
-      if (e != hipSuccess) {
-        // nothing of this launch can be trusted: fail its requests now
-        srv->dev_err = e;
-        finish_slot(srv, s, SLASH_E_DEVICE);
-        if (ins) finish_slot(srv, *ins, SLASH_E_DEVICE);
-        srv->cv.notify_all();
-      } else {
-        srv->inflight.emplace_back(false, (uint32_t)(&s - srv->slots.data()));
-        if (ins) srv->inflight.emplace_back(true, (uint32_t)(ins - srv->ins.data()));
+      if (agg && !small) {
+        run_step(srv, lk, agg, nullptr, false, nullptr);  // rank the gathered batch first
+        agg = nullptr;
       }
+      run_step(srv, lk, agg, &s, ins != nullptr, ins);
       uint64_t inflight = 0;
       for (Slot& o : srv->slots) inflight += o.busy;
       srv->stats.peak_inflight = std::max(srv->stats.peak_inflight, inflight);
+    }
+    // a gathered batch is ranked on its own when no launch will carry it
+    // soon: nothing queued, the head held back or waiting for an insert
+    // slot, or no batch slot free and none but the gathered one busy (so
+    // none will free up)
+    if (srv->gathered >= 0) {
+      uint32_t others = 0;
+      for (const Slot& o : srv->slots) others += o.busy;
+      if (srv->pending.empty() || wake_at > 0 || !slot_wait || others <= 1)
+        run_step(srv, lk, &srv->slots[srv->gathered], nullptr, false, nullptr);
     }
     bool busy = false;
     for (Slot& s : srv->ins) busy |= s.busy;
@@ -698,6 +754,19 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   srv->cap_q = cfg->max_batch;
   srv->cap_nnz = std::max<uint64_t>((uint64_t)srv->cap_q * 64, cfg->max_query_nnz);
   srv->per_slot = slot_bytes(srv->cap_q, srv->cap_nnz);
+  // a batch small enough for the serving-step kernel can be split: gathered
+  // in the launch that writes the insert behind it, ranked in the next one;
+  // its slot ids wait in device memory
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, srv->device) != hipSuccess || n_cu < 1) {
+    delete srv;
+    return fail(SLASH_E_DEVICE, "device attributes");
+  }
+  if (serve_step_ok(ix, 1)) {
+    const uint64_t split_q = std::min<uint64_t>(srv->cap_q, (uint64_t)n_cu / 2);
+    srv->slot_ids_bytes = split_q * srv->info.params.L * srv->info.params.R * 4;
+    srv->per_slot += srv->slot_ids_bytes;
+  }
   // insert staging: 4096 rows of max_insert_nnz indices in total (default
   // the larger of 64 per row and 8 * max_query_nnz)
   const uint32_t ins_rows = 4096;
@@ -748,7 +817,7 @@ extern "C" slash_status slash_serve_start(slash_index* ix, const slash_serve_con
   // one batch slot now; more are added while work waits for them
   srv->slots.reserve(cfg->max_inflight);
   srv->slots.emplace_back();
-  if (!alloc_slot(srv->slots[0], srv->cap_q, srv->cap_nnz, km, true)) {
+  if (!alloc_slot(srv->slots[0], srv->cap_q, srv->cap_nnz, km, true, 0, 0, srv->slot_ids_bytes)) {
     free_server(srv);
     return fail(SLASH_E_NOMEM, "no batch slot fits the HBM budget");
   }

@@ -266,6 +266,7 @@ struct QueryArgs {
   uint32_t* out_scores;
   const uint32_t* qbk;  // bucket ids [n][L] hashed beforehand, or NULL (hash in the query kernel)
   uint32_t exact = 0;   // 1: rank by exact multiplicity instead of the count-min estimate
+  uint32_t* slot_ids = nullptr;  // serving: the gathered slot ids [n][L * R] between the two halves
 };
 // Kernel entry of the row-major hash kernel for this shape and its launch
 // geometry (for HIP graph nodes): (Shape, ConstView, slash_csr, uint32_t* out).
@@ -281,22 +282,25 @@ hipError_t launch_query_waves(const Shape& s, const ConstView& c, const TablesVi
                               uint32_t waves, hipStream_t st);
 hipError_t launch_query(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
                         hipStream_t st);
-// One launch that answers a small query batch (count-min, hashing in the
-// kernel) and then applies a prepared small insert's runs to the tables,
-// after every query of the batch has read them.  `dev` holds two device
-// words that start at zero and only grow; tickets/gathered are their values
-// after the last launch (updated here; launches using one FuseSync must be
-// ordered on one stream).  gave_up is a host-coherent word a launch sets when
-// its bounded wait ends without the queries' count.  hipErrorNotSupported
-// when the shape or batch has no fused kernel (then launch the two parts).
+// Serving: one launch that ranks the previous batch's queries from the
+// slot ids their gather stored (prev, may be empty), answers this batch's
+// queries whole or only gathers them (cur, may be empty; count-min, hashing
+// in the kernel), and then applies a prepared small insert's runs to the
+// tables (n_ins rows, none when 0) after every query of this batch has read
+// them.  `dev` holds two device words that start at zero and only grow;
+// tickets/gathered are their values after the last launch (updated here;
+// launches using one FuseSync must be ordered on one stream).  gave_up is a
+// host-coherent word a launch sets when its bounded wait ends without the
+// queries' count.  hipErrorNotSupported when the shape has no such kernel.
 struct FuseSync {
   unsigned long long* dev = nullptr;
   uint32_t* gave_up = nullptr;
   unsigned long long tickets = 0, gathered = 0;
 };
-bool query_insert_supported(const Shape& s, uint64_t n_queries);
-hipError_t launch_query_insert(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a,
-                               void* ins_scratch, uint32_t n_ins, int n_cu, FuseSync& fs, hipStream_t st);
+bool serve_step_supported(const Shape& s);
+hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& prev,
+                             const QueryArgs& cur, bool gather_only, void* ins_scratch, uint32_t n_ins, int n_cu,
+                             FuseSync& fs, hipStream_t st);
 hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const TablesView& tab,
                                    const QueryArgs& a, uint32_t waves, uint32_t per_ticket, uint32_t grid,
                                    uint32_t* ticket, hipStream_t st);
@@ -350,11 +354,21 @@ bool insert_scratch_bytes(const slash_index* ix, uint32_t rows, size_t* keys_byt
 slash_status insert_prepare(slash_index* ix, slash_csr rows, const InsertScratch& sc, hipStream_t st,
                             uint32_t* first_id, const GroupSignal& sig = {});
 slash_status insert_commit(slash_index* ix, const InsertScratch& sc, uint32_t n, hipStream_t st);
-// Query batch q (per-query k in kq, count-min) and the commit of prepared
-// insert sc (n rows) in one launch on `st` (see launch_query_insert).
-// SLASH_E_UNSUPPORTED when no fused kernel fits: nothing was launched.
-bool query_insert_ok(const slash_index* ix, uint64_t n_queries);
-slash_status query_insert(slash_index* ix, slash_csr q, const uint32_t* kq, uint32_t* ids, uint32_t* scores,
-                          const InsertScratch& sc, uint32_t n, FuseSync& fs, hipStream_t st);
+// One serving step on `st` (see launch_serve_step): rank the queries of
+// `prev` (their k in prev_kq, results to prev_ids/prev_scores, slot ids in
+// prev_slots; none when prev.n_rows == 0), answer or gather (into cur_slots)
+// the queries of `cur`, and commit the prepared insert sc (n rows; none when
+// n == 0).  SLASH_E_UNSUPPORTED when no step kernel fits: nothing was
+// launched.
+struct ServeBatch {
+  slash_csr q{};
+  const uint32_t* kq = nullptr;
+  uint32_t* ids = nullptr;
+  uint32_t* scores = nullptr;
+  uint32_t* slot_ids = nullptr;
+};
+bool serve_step_ok(const slash_index* ix, uint64_t n_queries);
+slash_status serve_step(slash_index* ix, const ServeBatch& prev, const ServeBatch& cur, bool gather_only,
+                        const InsertScratch* sc, uint32_t n, FuseSync& fs, hipStream_t st);
 
 }  // namespace slash
