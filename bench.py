@@ -435,14 +435,17 @@ def recall_operating_point(api, w, ip, ix, ins_ip, ins_ix, qi, qx, qi_h, qx_h, s
 def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4, 1e5, 3e5, 1e6, 2e6), fusion=0):
     """Open-loop Poisson arrivals against the continuous-batching server on
     the resident index: 90% queries (the batched mix), 10% inserts of 1-4096
-    new rows.  Latency = completion - scheduled arrival.  Each rate offers
-    `seconds` of arrivals, at most 400k requests.  An untimed 0.2 s window at
-    the lowest rate runs first (its inserts stay in the index)."""
+    new rows.  Latency = completion - scheduled arrival.  Each rate runs on a
+    fresh server: an untimed 0.05 s window at that rate, then `seconds` of
+    arrivals (at most 400k requests) timed; the server's counters cover both.
+    An untimed 0.2 s window at the lowest rate runs first (its inserts stay in
+    the index)."""
     import synth
     out = []
     next_row = w["n"] + 4096 * 64
 
-    def replay(rate, secs, seed):
+    def trace(rate, secs, seed):
+        # one Poisson trace: arrivals, the mix's queries, new rows to insert
         nonlocal next_row
         n = int(min(rate * secs, 400_000))
         t, ins, sz = synth.arrivals(seed, n, rate, 0.1, 1, 4096)
@@ -461,9 +464,18 @@ def serve_sweep(api, h, law, w, mi_h, mx_h, mk, seconds, seeds, rates=(1e4, 3e4,
             next_row += rows
         else:
             iip, iix = np.zeros(1, np.int64), np.zeros(0, np.int32)
+        return n, t, ins, sz, nq, q_ptr, q_idx, q_k, rows, iip, iix
+
+    def replay(rate, secs, seed, warm_secs=0.05):
+        # a fresh server per rate; an untimed window at the same rate first
+        # (a new server's first milliseconds are slower than its steady state)
         srv = api.slash_serve_start(h, hbm_budget_bytes=2 << 30, max_batch=2048, max_inflight=6,
                                     queue_capacity=1 << 22, max_query_nnz=w["max_nnz"],
                                     max_insert_nnz=w.get("max_insert_nnz", 0), insert_fusion=fusion)
+        if warm_secs:
+            _, t, ins, sz, _, q_ptr, q_idx, q_k, _, iip, iix = trace(rate, warm_secs, seed ^ 0x77)
+            api.slash_serve_replay(srv, t, ins, sz, q_ptr, q_idx, q_k, iip, iix)
+        n, t, ins, sz, nq, q_ptr, q_idx, q_k, rows, iip, iix = trace(rate, secs, seed)
         t0 = time.perf_counter()
         lat, _ = api.slash_serve_replay(srv, t, ins, sz, q_ptr, q_idx, q_k, iip, iix)
         wall = time.perf_counter() - t0

@@ -682,7 +682,10 @@ void scheduler(slash_server* srv) {
         run_step(srv, lk, agg, nullptr, false, nullptr);  // rank the gathered batch first
         agg = nullptr;
       }
-      run_step(srv, lk, agg, &s, ins != nullptr, ins);
+      // split the batch (gather now, rank in the next launch) only when more
+      // requests wait behind the insert, so that a launch will carry the
+      // ranking: else it would need a launch of its own
+      run_step(srv, lk, agg, &s, ins != nullptr && !srv->pending.empty(), ins);
       uint64_t inflight = 0;
       for (Slot& o : srv->slots) inflight += o.busy;
       srv->stats.peak_inflight = std::max(srv->stats.peak_inflight, inflight);
