@@ -377,6 +377,7 @@ typedef struct {
   double pack_s;   /* scheduler seconds copying request data into staging */
   uint64_t fused_commits; /* insert commits (each of one or more merged inserts) whose table writes ran
                              in a query batch's launch */
+  uint64_t split_batches; /* query batches gathered in one launch and ranked in a later one */
 } slash_serve_stats;
 
 SLASH_API slash_status slash_serve_start(slash_index* index, const slash_serve_config* cfg, slash_server** out);

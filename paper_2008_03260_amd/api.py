@@ -77,7 +77,7 @@ class ServeStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("queries_done", "inserts_done", "rows_inserted", "batches",
                                           "rejected_busy", "rejected_nomem", "peak_inflight", "peak_hbm_bytes")] + \
                [("busy_s", C.c_double), ("launch_s", C.c_double), ("wait_s", C.c_double), ("pack_s", C.c_double),
-                ("fused_commits", C.c_uint64)]
+                ("fused_commits", C.c_uint64), ("split_batches", C.c_uint64)]
 
 
 class Schedule(C.Structure):

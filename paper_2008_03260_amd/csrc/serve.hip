@@ -580,7 +580,10 @@ void run_step(slash_server* srv, std::unique_lock<std::mutex>& lk, Slot* agg, Sl
     return;
   }
   srv->inflight.push_back(ln);
-  if (gather_only) srv->gathered = id_of(cur).second;
+  if (gather_only) {
+    srv->gathered = id_of(cur).second;
+    srv->stats.split_batches++;
+  }
 }
 
 void scheduler(slash_server* srv) {

@@ -58,7 +58,7 @@ def test_binding_struct_layouts_match_header(tmp_path):
                                                  "insert_fusion"]),
         "slash_completion": (api.Completion, ["ticket", "status", "ids", "scores", "t_submit_s", "t_done_s"]),
         "slash_serve_stats": (api.ServeStats, ["queries_done", "peak_hbm_bytes", "busy_s", "wait_s", "pack_s",
-                                               "fused_commits"]),
+                                               "fused_commits", "split_batches"]),
     }
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "slash.h"', "int main(void) {"]
     for cname, (_, fields) in checks.items():

@@ -267,16 +267,23 @@ def test_replay_open_loop(api, setup):
     idx.close()
 
 
-@pytest.mark.parametrize("bucket,fusion", [(0, 0), (0, 1), (0, 2), (1, 0)])
-def test_burst_inserts_prepared_ahead(api, setup, bucket, fusion):
+@pytest.mark.parametrize("bucket,fusion,shape", [(0, 0, "small"), (0, 1, "small"), (0, 2, "small"), (1, 0, "small"),
+                                                 (0, 0, "headline"), (0, 2, "headline")])
+def test_burst_inserts_prepared_ahead(api, setup, bucket, fusion, shape):
     # every request submitted before the first poll, so the FIFO is long:
     # inserts are prepared ahead (at most eight insert slots at once, runs of
     # back-to-back inserts sharing a slot) while the query batches before
     # them run; each query equals the oracle on the rows inserted before it,
     # and the ids of the inserts follow submission order.  fusion 2 writes
     # every insert that follows a query batch in that batch's launch (the
-    # queries must not see it), fusion 1 never does
+    # queries must not see it), fusion 1 never does.  A batch whose insert
+    # has more requests queued behind it is only gathered in the insert's
+    # launch and ranked in the next one.  "headline": the 200M-point shard's
+    # table shape (L = 32, R = 64, count-min 4 x 4096) on 20k rows
     law, params, ip, ix, n0, n1, qi, qx, kq = setup
+    if shape == "headline":
+        params = api.Params.of(dim=1 << 20, K=4, L=32, log2_buckets=10, R=64, cm_rows=4, log2_cm_width=12,
+                               k_max=100, seed=synth.derive(31, synth.STREAM_INDEX))
     if bucket:
         params = api.Params.of(dim=1 << 20, K=4, L=16, log2_buckets=12, R=1, cm_rows=4, log2_cm_width=4, k_max=100,
                                bucket=1, seed=synth.derive(31, synth.STREAM_INDEX))
@@ -317,6 +324,9 @@ def test_burst_inserts_prepared_ahead(api, setup, bucket, fusion):
     elif fusion == 2:
         # an insert queued right behind a query batch (there are dozens)
         assert stats["fused_commits"] >= 1, stats
+        if shape == "headline":
+            # with requests queued behind the insert, the batch is split
+            assert stats["split_batches"] >= 1, stats
     # the oracle's tables after each insert, and its answers per epoch
     op = oracle_params(params)
     cs = oracle.constants(op)
