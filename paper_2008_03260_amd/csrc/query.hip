@@ -730,8 +730,8 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE, (query_min_waves<WAVES, SPT>(
 // are running and wait for nothing, so the wait ends; it is bounded all the
 // same, and a group that gives up sets *gave_up.  Both counters only grow;
 // the host passes their values before this launch.
-constexpr uint32_t kFusedWaves = 16;
-constexpr uint32_t kFusedSpinLimit = 1u << 20;  // polls: seconds at most, against microseconds needed
+constexpr uint32_t kStepWaves = 16;
+constexpr uint32_t kStepSpinLimit = 1u << 20;  // polls: seconds at most, against microseconds needed
 
 struct StepArgs {
   QueryArgs prev, cur;
@@ -745,9 +745,9 @@ struct StepArgs {
 };
 
 template <int SPT, int E>
-__global__ void __launch_bounds__(kFusedWaves * SL_WAVE, (query_min_waves<kFusedWaves, SPT>()))
+__global__ void __launch_bounds__(kStepWaves * SL_WAVE, (query_min_waves<kStepWaves, SPT>()))
     k_serve_step(Shape s, ConstView c, TablesView tab, StepArgs a) {
-  constexpr uint32_t NT = kFusedWaves * SL_WAVE;
+  constexpr uint32_t NT = kStepWaves * SL_WAVE;
   extern __shared__ uint32_t lds[];
   const QLayout lay = q_layout(s, false);
   if (threadIdx.x == 0) lds[lay.ticket] = (uint32_t)(atomicAdd(&a.sync[0], 1ull) - a.ticket_base);
@@ -758,11 +758,11 @@ __global__ void __launch_bounds__(kFusedWaves * SL_WAVE, (query_min_waves<kFused
     const ConstView cl = stage_consts(s, c, lds + lay.cst, NT);
     __syncthreads();
     if (ticket < np)
-      query_one<kFusedWaves, SPT, true, false, kQueryAggregate>(s, cl, tab, a.prev, ticket, lds, lay);
+      query_one<kStepWaves, SPT, true, false, kQueryAggregate>(s, cl, tab, a.prev, ticket, lds, lay);
     else if (a.gather_only)
-      query_one<kFusedWaves, SPT, true, false, kQueryGather>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
+      query_one<kStepWaves, SPT, true, false, kQueryGather>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
     else
-      query_one<kFusedWaves, SPT, true, false, kQueryFull>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
+      query_one<kStepWaves, SPT, true, false, kQueryFull>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
     return;
   }
   // table writers: each wave takes four records per pass and, before its
@@ -780,7 +780,7 @@ __global__ void __launch_bounds__(kFusedWaves * SL_WAVE, (query_min_waves<kFused
         uint32_t spins = 0;
         while (__hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.gathered_target) {
           __builtin_amdgcn_s_sleep(2);
-          if (++spins == kFusedSpinLimit) {
+          if (++spins == kStepSpinLimit) {
             *(volatile uint32_t*)a.gave_up = 1u;
             break;
           }
@@ -797,11 +797,11 @@ __global__ void __launch_bounds__(kFusedWaves * SL_WAVE, (query_min_waves<kFused
 
 // serving-step kernels by [log2 slots per thread][log2 entries per lane]
 template <int S>
-constexpr std::array<const void*, 4> kqi() {
+constexpr std::array<const void*, 4> kstep() {
   return {(const void*)k_serve_step<S, 1>, (const void*)k_serve_step<S, 2>, (const void*)k_serve_step<S, 4>,
           (const void*)k_serve_step<S, 8>};
 }
-const std::array<const void*, 4> kFused[5] = {kqi<1>(), kqi<2>(), kqi<4>(), kqi<8>(), kqi<16>()};
+const std::array<const void*, 4> kStepKernels[5] = {kstep<1>(), kstep<2>(), kstep<4>(), kstep<8>(), kstep<16>()};
 
 struct KPair {
   const void* plain;
@@ -943,11 +943,11 @@ hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const Tab
 // Serving-step kernel for this shape (count-min queries, constants in LDS,
 // R <= 128), or nullptr.
 static const void* step_kernel(const Shape& s) {
-  if (s.bucket || s.R > 128 || !query_supported(s, kFusedWaves, false)) return nullptr;
+  if (s.bucket || s.R > 128 || !query_supported(s, kStepWaves, false)) return nullptr;
   if (!q_layout(s).cst_fit) return nullptr;
-  const uint32_t spt = (s.L * s.R + kFusedWaves * SL_WAVE - 1) / (kFusedWaves * SL_WAVE);
+  const uint32_t spt = (s.L * s.R + kStepWaves * SL_WAVE - 1) / (kStepWaves * SL_WAVE);
   const uint32_t e = (s.R + 15) / 16;
-  return kFused[ilog2(spt < 1 ? 1 : spt)][ilog2(e)];
+  return kStepKernels[ilog2(spt < 1 ? 1 : spt)][ilog2(e)];
 }
 
 bool serve_step_supported(const Shape& s) { return step_kernel(s) != nullptr; }
@@ -972,7 +972,7 @@ hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesVie
   if (n_ins) {
     if (!insert_run_arrays(s, ins_scratch, n_ins, &a.recs, &a.items)) return hipErrorInvalidValue;
     const uint64_t runs = (uint64_t)s.L * n_ins;
-    constexpr uint32_t per = kFusedWaves * SL_WAVE / 16;
+    constexpr uint32_t per = kStepWaves * SL_WAVE / 16;
     // one 16-wave group per CU beside the queries (what the kernel's
     // registers allow); the groups stride over the records
     const uint64_t want = (runs + per - 1) / per;
@@ -982,7 +982,7 @@ hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesVie
   }
   const uint32_t grid = np + nc + a.merge_groups;
   if (grid == 0) return hipSuccess;
-  const size_t lds = query_lds_bytes(s, kFusedWaves, false);
+  const size_t lds = query_lds_bytes(s, kStepWaves, false);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -995,7 +995,7 @@ hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesVie
   ConstView cv = c;
   TablesView tv = tab;
   void* args[] = {&sh, &cv, &tv, &a};
-  hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(kFusedWaves * SL_WAVE), args, lds, st);
+  hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(kStepWaves * SL_WAVE), args, lds, st);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return e;
   fs.tickets += grid;
