@@ -537,6 +537,14 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       atomicAdd(&misc[0], v);
       atomicMax(&misc[5], m);
     }
+    if constexpr (NT >= 512) {
+      // the largest id among the representatives (the tie guess below)
+      uint32_t im = 0;
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) im = key[i] != 0 ? max(im, ~(uint32_t)key[i]) : im;
+      for (int o = 32; o > 0; o >>= 1) im = max(im, (uint32_t)__shfl_xor(im, o, SL_WAVE));
+      if (lane == 0) atomicMax(&misc[12], im);
+    }
   }
   __syncthreads();
   const uint32_t total = misc[0];
@@ -548,9 +556,17 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   //    ranked directly (ties on E are then ordered by id without more radix
   //    rounds); otherwise the select goes on through the id bytes until the
   //    keys >= thr are exactly the kk largest.
+  //    8- and 16-wave groups: when many keys tie on E (k = 100 against
+  //    about 2,000 ids of estimate 1), the remaining ones are the smallest
+  //    ids among the tied; ids are spread evenly below the largest one, so
+  //    one counting pass with a guessed id bound usually leaves between the
+  //    needed number and 256 keys, which are ranked directly; when it does
+  //    not, the radix rounds go on.
   uint64_t thr = 1;  // every representative (their keys are >= 2^32)
   uint32_t n_c = kk;  // keys collected for ranking
   uint64_t* cb = sel;  // where they are collected
+  bool guessed = false;
+  uint64_t guess_thr = 0;
   if (kk > 0 && kk < total) {
     uint64_t prefix = 0;
     uint32_t remaining = kk;
@@ -641,8 +657,35 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
         cb = (uint64_t*)(lds + lay.cm);
         break;
       }
+      if constexpr (NT >= 512) {
+        // room for collected keys: the count-min region, two words a key
+        const uint32_t cap = min((lay.hist - lay.cm) / 2, 256u);
+        const uint32_t above = kk - remaining;  // keys with estimate > E
+        if (shift == 32 && remaining < cnt && above + remaining < cap) {
+          const uint32_t E = (uint32_t)(prefix >> 32);
+          const uint32_t want = (remaining + (cap - above)) / 2;  // between what is needed and the room
+          const uint32_t idmax = misc[12];
+          const uint32_t X = (uint32_t)min<uint64_t>((uint64_t)idmax * want / cnt, idmax);
+          uint32_t c = 0;
+#pragma unroll
+          for (int i = 0; i < SPT; ++i)
+            c += (key[i] != 0 && (uint32_t)(key[i] >> 32) == E && ~(uint32_t)key[i] <= X) ? 1u : 0u;
+          for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, SL_WAVE);
+          if (lane == 0) atomicAdd(&misc[13], c);
+          __syncthreads();
+          const uint32_t ct = misc[13];
+          if (ct >= remaining && above + ct <= cap) {
+            // keys >= (E, ~X): those above E and the tied ids up to X
+            n_c = above + ct;
+            cb = (uint64_t*)(lds + lay.cm);
+            guessed = true;
+            guess_thr = ((uint64_t)E << 32) | (uint32_t)~X;
+            break;
+          }
+        }
+      }
     }
-    thr = prefix;
+    thr = guessed ? guess_thr : prefix;
   }
   // 5. collect the n_c keys >= thr, rank each among them by counting (keys
   //    are distinct), write the kk best in order
