@@ -537,7 +537,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       atomicAdd(&misc[0], v);
       atomicMax(&misc[5], m);
     }
-    if constexpr (NT >= 512) {
+    if constexpr (NT >= 1024) {
       // the largest id among the representatives (the tie guess below)
       uint32_t im = 0;
 #pragma unroll
@@ -556,12 +556,13 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   //    ranked directly (ties on E are then ordered by id without more radix
   //    rounds); otherwise the select goes on through the id bytes until the
   //    keys >= thr are exactly the kk largest.
-  //    8- and 16-wave groups: when many keys tie on E (k = 100 against
-  //    about 2,000 ids of estimate 1), the remaining ones are the smallest
-  //    ids among the tied; ids are spread evenly below the largest one, so
-  //    one counting pass with a guessed id bound usually leaves between the
-  //    needed number and 256 keys, which are ranked directly; when it does
-  //    not, the radix rounds go on.
+  //    16-wave groups (the latency form; in the 8-wave throughput form the
+  //    extra registers would cost a group per CU): when many keys tie on E
+  //    (k = 100 against about 2,000 ids of estimate 1), the remaining ones
+  //    are the smallest ids among the tied; ids are spread evenly below the
+  //    largest one, so one counting pass with a guessed id bound usually
+  //    leaves between the needed number and 256 keys, which are ranked
+  //    directly; when it does not, the radix rounds go on.
   uint64_t thr = 1;  // every representative (their keys are >= 2^32)
   uint32_t n_c = kk;  // keys collected for ranking
   uint64_t* cb = sel;  // where they are collected
@@ -657,7 +658,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
         cb = (uint64_t*)(lds + lay.cm);
         break;
       }
-      if constexpr (NT >= 512) {
+      if constexpr (NT >= 1024) {
         // room for collected keys: the count-min region, two words a key
         const uint32_t cap = min((lay.hist - lay.cm) / 2, 256u);
         const uint32_t above = kk - remaining;  // keys with estimate > E
