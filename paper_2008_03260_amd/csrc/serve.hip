@@ -146,6 +146,7 @@ struct slash_server {
   // launches in flight, in launch order (the scheduler thread's only)
   std::deque<Launch> inflight;
   int32_t gathered = -1;       // batch slot gathered and waiting to be ranked
+  double prep_wait_since = -1.0;  // the head insert's preparation was first found unfinished
   size_t slot_ids_bytes = 0;   // per batch slot (0: batches are never split)
   uint64_t epoch = 0;
   uint64_t next_ticket = 0;
@@ -623,7 +624,8 @@ void scheduler(slash_server* srv) {
     //    insert and ranked in the next launch (or on its own, below, when
     //    none follows soon), so the next epoch need not wait for its ranking.
     double wake_at = 0.0;
-    bool slot_wait = false;  // stopped for want of a batch slot
+    bool slot_wait = false;     // stopped for want of a batch slot
+    bool prep_blocked = false;  // stopped at an insert still being prepared
     for (;;) {
       prepare_ahead(srv, lk);
       if (srv->pending.empty()) break;
@@ -631,6 +633,23 @@ void scheduler(slash_server* srv) {
       Slot* agg = srv->gathered >= 0 ? &srv->slots[srv->gathered] : nullptr;
       if (head.kind == 1) {
         if (head.prep < 0) break;  // waits for an insert slot
+        Slot& is = srv->ins[head.prep];
+        if (!is.prep_failed && !is_prepared(is)) {
+          // its preparation is still running: poll it on the next rounds
+          // (finished work keeps being retired meanwhile); one that takes
+          // longer than kPrepTimeout is failed
+          const double t = now_s();
+          if (srv->prep_wait_since < 0) srv->prep_wait_since = t;
+          if (t - srv->prep_wait_since <= kPrepTimeout) {
+            prep_blocked = true;
+            break;
+          }
+          is.prep_failed = true;
+        }
+        if (srv->prep_wait_since >= 0) {
+          srv->stats.wait_s += now_s() - srv->prep_wait_since;
+          srv->prep_wait_since = -1.0;
+        }
         Slot& s = take_insert(srv);
         run_step(srv, lk, agg, nullptr, false, &s);
         continue;
@@ -700,7 +719,7 @@ void scheduler(slash_server* srv) {
     if (srv->gathered >= 0) {
       uint32_t others = 0;
       for (const Slot& o : srv->slots) others += o.busy;
-      if (srv->pending.empty() || wake_at > 0 || !slot_wait || others <= 1)
+      if (srv->pending.empty() || wake_at > 0 || (!slot_wait && !prep_blocked) || others <= 1)
         run_step(srv, lk, &srv->slots[srv->gathered], nullptr, false, nullptr);
     }
     bool busy = false;
