@@ -544,6 +544,17 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       for (int i = 0; i < SPT; ++i) im = key[i] != 0 ? max(im, ~(uint32_t)key[i]) : im;
       for (int o = 32; o > 0; o >>= 1) im = max(im, (uint32_t)__shfl_xor(im, o, SL_WAVE));
       if (lane == 0) atomicMax(&misc[12], im);
+      // the threshold select's first round (histogram buffer 0: the
+      // representatives' estimates, when all are below 256) is counted here:
+      // most estimates are 1 and take one atomic per wave, the others one each
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) {
+        const uint32_t e = (uint32_t)(key[i] >> 32);
+        const bool live = key[i] != 0;
+        const uint64_t b1 = ballot64(live && e == 1);
+        if (b1 && lane == (uint32_t)__builtin_ctzll(b1)) atomicAdd(&hist[1], (uint32_t)__builtin_popcountll(b1));
+        if (live && e != 1 && e < 256) atomicAdd(&hist[e], 1u);
+      }
     }
   }
   __syncthreads();
@@ -573,6 +584,13 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     uint32_t remaining = kk;
     uint32_t cur = 0;
     const int top = misc[5] < 256u ? 32 : 40;
+    // 16-wave groups: the round at bit 32 was counted with the distinct ids;
+    // when it is not the first round, its buffer starts cleared as usual
+    constexpr bool kPre = NT >= 1024;
+    if (kPre && top == 40) {
+      for (uint32_t e = tid; e < 256; e += NT) hist[e] = 0;
+      __syncthreads();
+    }
     // 8- and 16-wave groups: every wave reads the histogram itself after one
     // barrier per round.  The two buffers are then never cleared: a round's
     // counts are its buffer's totals minus what the buffer held after its
@@ -582,12 +600,14 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     for (int shift = top; shift >= 0; shift -= 8, cur ^= 1u) {
       uint32_t* H = hist + 256 * cur;
       const uint64_t hi_mask = ~0ull << (shift + 8);
+      if (!(kPre && top == 32 && shift == 32)) {
 #pragma unroll
-      for (int i = 0; i < SPT; ++i) {
-        bool part = key[i] != 0 && (key[i] & hi_mask) == (prefix & hi_mask);
-        hist_add(H, part, (uint32_t)(key[i] >> shift) & 255u);
+        for (int i = 0; i < SPT; ++i) {
+          bool part = key[i] != 0 && (key[i] & hi_mask) == (prefix & hi_mask);
+          hist_add(H, part, (uint32_t)(key[i] >> shift) & 255u);
+        }
+        __syncthreads();
       }
-      __syncthreads();
       uint32_t D = 0, cum = 0, cnt = 0;
       if constexpr (NT >= 512) {
         uint32_t hh[4];
