@@ -684,7 +684,10 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
         const uint32_t above = kk - remaining;  // keys with estimate > E
         if (shift == 32 && remaining < cnt && above + remaining < cap) {
           const uint32_t E = (uint32_t)(prefix >> 32);
-          const uint32_t want = (remaining + (cap - above)) / 2;  // between what is needed and the room
+          // a little over what is needed (the count found spreads by about
+          // its square root), within the room: fewer keys to rank
+          const uint32_t want = min((remaining + (cap - above)) / 2,
+                                    remaining + 4u + (uint32_t)(2.5f * sqrtf((float)remaining)));
           const uint32_t idmax = misc[12];
           const uint32_t X = (uint32_t)min<uint64_t>((uint64_t)idmax * want / cnt, idmax);
           uint32_t c = 0;
