@@ -689,7 +689,10 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
           const uint32_t want = min((remaining + (cap - above)) / 2,
                                     remaining + 4u + (uint32_t)(2.5f * sqrtf((float)remaining)));
           const uint32_t idmax = misc[12];
-          const uint32_t X = (uint32_t)min<uint64_t>((uint64_t)idmax * want / cnt, idmax);
+          // only a guess (the count below checks it exactly): float arithmetic
+          // instead of a 64-bit division
+          const float xf = fminf((float)idmax * ((float)want / (float)cnt), 4294967040.0f);  // below 2^32
+          const uint32_t X = min((uint32_t)xf, idmax);
           uint32_t c = 0;
 #pragma unroll
           for (int i = 0; i < SPT; ++i)
