@@ -302,15 +302,37 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     uint32_t est[SPT];
 #pragma unroll
     for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
+    // 16-wave groups (one group per CU, registers to spare): every slot's
+    // cells are kept, 16 bits each, when d <= 4 and d * w <= 65536, and the
+    // estimate pass reads them back instead of hashing again
+    constexpr bool kCache = NT >= 1024 && SPT <= 8;
+    const bool cache = kCache && s.d <= 4 && (s.d << s.lw) <= 65536u;
+    uint32_t gc[kCache ? 2 * SPT : 1];
     {
       uint32_t live = 0;
-      for (uint32_t r = 0; r < s.d; ++r) {
-        const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+      if (cache) {
 #pragma unroll
-        for (int i = 0; i < SPT; ++i) {
-          if (id[i] != SL_EMPTY) {
-            const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
-            atomicAdd(&cmw[g >> 2], 1u << ((g & 3u) * 8));
+        for (uint32_t r = 0; r < 4; ++r) {
+          if (r < s.d) {
+            const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+              const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+              if (r & 1) gc[(2 * i + r / 2) % (kCache ? 2 * SPT : 1)] |= g << 16;
+              else gc[(2 * i + r / 2) % (kCache ? 2 * SPT : 1)] = g;
+              if (id[i] != SL_EMPTY) atomicAdd(&cmw[g >> 2], 1u << ((g & 3u) * 8));
+            }
+          }
+        }
+      } else {
+        for (uint32_t r = 0; r < s.d; ++r) {
+          const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+#pragma unroll
+          for (int i = 0; i < SPT; ++i) {
+            if (id[i] != SL_EMPTY) {
+              const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+              atomicAdd(&cmw[g >> 2], 1u << ((g & 3u) * 8));
+            }
           }
         }
       }
@@ -330,12 +352,25 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       for (uint32_t e = tid; e < lay.cm_words; e += NT) sum = __builtin_amdgcn_sad_u8(cmw[e], 0u, sum);
       for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, SL_WAVE);
       if (lane == 0) atomicAdd(&misc[6], sum);
-      for (uint32_t r = 0; r < s.d; ++r) {
-        const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+      if (cache) {
 #pragma unroll
-        for (int i = 0; i < SPT; ++i) {
-          const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
-          est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
+        for (uint32_t r = 0; r < 4; ++r) {
+          if (r < s.d) {
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+              const uint32_t g = (gc[(2 * i + r / 2) % (kCache ? 2 * SPT : 1)] >> (16 * (r & 1))) & 0xFFFFu;
+              est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
+            }
+          }
+        }
+      } else {
+        for (uint32_t r = 0; r < s.d; ++r) {
+          const uint64_t ar = cld64<CL>(c.a_r, r), br = cld64<CL>(c.b_r, r);
+#pragma unroll
+          for (int i = 0; i < SPT; ++i) {
+            const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
+            est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
+          }
         }
       }
       // slots whose id may occur more than once (estimate >= 2)
