@@ -376,6 +376,28 @@ def test_query_counter_overflow_recount(api, lw):
     assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
 
 
+@pytest.mark.parametrize("waves", [8, 16])
+@pytest.mark.parametrize("lw", [0, 1], ids=["w1", "w2"])
+def test_query_wide_groups_estimates_above_255(api, waves, lw):
+    # every estimate above 255 (1 or 2 counters per row over 512
+    # occurrences) and k above the few-outputs bound: the radix select starts
+    # at the estimate's second byte, in the 16-wave form after clearing the
+    # histogram the distinct ids counted into
+    gp, op = params_pair(api, k_max=24, L=16, log2_buckets=3, R=32, cm_rows=2, log2_cm_width=lw)
+    law, (ip, ix) = rows_of(4000, seed=43)
+    idx = api.Index(gp, dev(ip), dev(ix))
+    cs = oracle.constants(op)
+    oids, oseen = oracle.build(op, cs, ip, ix)
+    qi, qx = ip[:33], ix[: ip[32]]
+    kq = np.random.default_rng(7).choice([20, 24], size=32).astype(np.uint32)
+    wi, ws = oracle.query(op, cs, oids, oseen, qi, qx, 0, k_max=24, kq=kq)
+    assert int(ws[:, 0].min()) > 255
+    gi, gs = idx.query_batched(dev(qi), dev(qx), 0, k_per_query=dev(kq.view(np.int32)),
+                               schedule=dict(waves_per_query=waves, queries_per_ticket=0))
+    torch.cuda.synchronize()
+    assert (u32(gi) == wi).all() and (u32(gs) == ws).all()
+
+
 @pytest.mark.parametrize("sched", [dict(waves_per_query=1, queries_per_ticket=1),
                                    dict(waves_per_query=2, queries_per_ticket=3),
                                    dict(waves_per_query=4, queries_per_ticket=8, groups_per_cu=1),
