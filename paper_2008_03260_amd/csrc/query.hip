@@ -307,7 +307,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     // estimate pass reads them back instead of hashing again
     constexpr bool kCache = NT >= 1024 && SPT <= 8;
     const bool cache = kCache && s.d <= 4 && (s.d << s.lw) <= 65536u;
-    uint32_t gc[kCache ? 2 * SPT : 1];
+    uint32_t gc[kCache ? 2 * SPT : 1];  // rows 0, 1 of slot i in gc[2i], rows 2, 3 in gc[2i + 1]
     {
       uint32_t live = 0;
       if (cache) {
@@ -318,8 +318,8 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
 #pragma unroll
             for (int i = 0; i < SPT; ++i) {
               const uint32_t g = (r << s.lw) + cm_hash(ar, br, id[i], s.lw);
-              if (r & 1) gc[(2 * i + r / 2) % (kCache ? 2 * SPT : 1)] |= g << 16;
-              else gc[(2 * i + r / 2) % (kCache ? 2 * SPT : 1)] = g;
+              uint32_t& w = gc[kCache ? 2 * i + r / 2 : 0];
+              w = (r & 1) ? w | (g << 16) : g;
               if (id[i] != SL_EMPTY) atomicAdd(&cmw[g >> 2], 1u << ((g & 3u) * 8));
             }
           }
@@ -358,7 +358,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
           if (r < s.d) {
 #pragma unroll
             for (int i = 0; i < SPT; ++i) {
-              const uint32_t g = (gc[(2 * i + r / 2) % (kCache ? 2 * SPT : 1)] >> (16 * (r & 1))) & 0xFFFFu;
+              const uint32_t g = (gc[kCache ? 2 * i + r / 2 : 0] >> (16 * (r & 1))) & 0xFFFFu;
               est[i] = min(est[i], (cmw[g >> 2] >> ((g & 3u) * 8)) & 255u);
             }
           }
@@ -579,9 +579,11 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       for (int i = 0; i < SPT; ++i) im = key[i] != 0 ? max(im, ~(uint32_t)key[i]) : im;
       for (int o = 32; o > 0; o >>= 1) im = max(im, (uint32_t)__shfl_xor(im, o, SL_WAVE));
       if (lane == 0) atomicMax(&misc[12], im);
-      // the threshold select's first round (histogram buffer 0: the
-      // representatives' estimates, when all are below 256) is counted here:
-      // most estimates are 1 and take one atomic per wave, the others one each
+      // the threshold select's first round is counted here (histogram
+      // buffer 0: the representatives' estimates below 256, which is that
+      // round's histogram when every estimate is; otherwise the select
+      // clears it): most estimates are 1 and take one atomic per wave, the
+      // others one each
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
         const uint32_t e = (uint32_t)(key[i] >> 32);
