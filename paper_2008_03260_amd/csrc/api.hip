@@ -746,7 +746,7 @@ slash_status slash::serve_step(slash_index* ix, const ServeBatch& prev, const Se
   QueryArgs ca{cur.q, cur.kq, 0, 1, cur.ids, cur.scores, nullptr};
   ca.slot_ids = cur.slot_ids;
   const hipError_t e = launch_serve_step(ix->shape, ix->cv, tables(ix), pa, ca, gather_only, n ? sc->runs : nullptr, n,
-                                         ix->n_cu, fs, st);
+                                         ix->n_cu, fs, st, cur.host_indptr);
   if (e == hipErrorNotSupported) return fail(SLASH_E_UNSUPPORTED, "no serving step kernel fits");
   if (e == hipErrorInvalidValue) return fail(SLASH_E_INVAL, "malformed serving step");
   HIP_TRY(e);

@@ -222,10 +222,12 @@ constexpr int kQueryFull = 0;       // hash, gather, count, rank
 constexpr int kQueryGather = 1;     // hash and gather, the slot ids to a.slot_ids[q][slot]
 constexpr int kQueryAggregate = 2;  // count and rank the slot ids a gather left in a.slot_ids
 // `gathered`, when not null, is counted once the group's slots are all read
-// (a table writer may then start; see k_serve_step).
+// (a table writer may then start; see k_serve_step).  qb, qe, when qb >= 0,
+// are query q's row offsets, read from a.q.indptr otherwise.
 template <int WAVES, int SPT, bool CL, bool EX, int MODE = kQueryFull>
 __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& a, uint32_t q,
-                          uint32_t* lds, const QLayout& lay, unsigned long long* gathered = nullptr) {
+                          uint32_t* lds, const QLayout& lay, unsigned long long* gathered = nullptr,
+                          int64_t qb = -1, int64_t qe = -1) {
   constexpr uint32_t NT = WAVES * SL_WAVE;
   const uint32_t tid = threadIdx.x, wave = tid / SL_WAVE, lane = lane_id();
   uint32_t* bk = lds + lay.buckets;
@@ -247,7 +249,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
   } else if (a.qbk) {
     for (uint32_t t = tid; t < s.L; t += NT) bk[t] = a.qbk[(uint64_t)q * s.L + t];
   } else if (wave == 0) {
-    const int64_t beg = a.q.indptr[q], end = a.q.indptr[q + 1];
+    const int64_t beg = qb >= 0 ? qb : a.q.indptr[q], end = qb >= 0 ? qe : a.q.indptr[q + 1];
     const uint32_t* h = doph_wave<CL>(s, c, a.q.indices + beg, (uint32_t)(end - beg), lds + lay.doph);
     for (uint32_t t = lane; t < s.L; t += SL_WAVE) bk[t] = table_bucket<CL>(s, c, h, t);
   }
@@ -302,10 +304,11 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     uint32_t est[SPT];
 #pragma unroll
     for (int i = 0; i < SPT; ++i) est[i] = 0xFFFFFFFFu;
-    // 16-wave groups (one group per CU, registers to spare): every slot's
-    // cells are kept, 16 bits each, when d <= 4 and d * w <= 65536, and the
-    // estimate pass reads them back instead of hashing again
-    constexpr bool kCache = NT >= 1024 && SPT <= 8;
+    // 16-wave groups with up to 4 slots a thread (one group per CU,
+    // registers to spare; 8 slots would spill in the serving step): every
+    // slot's cells are kept, 16 bits each, when d <= 4 and d * w <= 65536, and
+    // the estimate pass reads them back instead of hashing again
+    constexpr bool kCache = NT >= 1024 && SPT <= 4;
     const bool cache = kCache && s.d <= 4 && (s.d << s.lw) <= 65536u;
     uint32_t gc[kCache ? 2 * SPT : 1];  // rows 0, 1 of slot i in gc[2i], rows 2, 3 in gc[2i + 1]
     {
@@ -583,9 +586,10 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
       // buffer 0: the representatives' estimates below 256, which is that
       // round's histogram when every estimate is; otherwise the select
       // clears it): most estimates are 1 and take one atomic per wave, the
-      // others one each
+      // others one each.  Up to 4 slots a thread (with 8 the serving step
+      // would spill).
 #pragma unroll
-      for (int i = 0; i < SPT; ++i) {
+      for (int i = 0; i < (SPT <= 4 ? SPT : 0); ++i) {
         const uint32_t e = (uint32_t)(key[i] >> 32);
         const bool live = key[i] != 0;
         const uint64_t b1 = ballot64(live && e == 1);
@@ -623,7 +627,7 @@ __device__ void query_one(const Shape& s, const ConstView& c, const TablesView& 
     const int top = misc[5] < 256u ? 32 : 40;
     // 16-wave groups: the round at bit 32 was counted with the distinct ids;
     // when it is not the first round, its buffer starts cleared as usual
-    constexpr bool kPre = NT >= 1024;
+    constexpr bool kPre = NT >= 1024 && SPT <= 4;
     if (kPre && top == 40) {
       for (uint32_t e = tid; e < 256; e += NT) hist[e] = 0;
       __syncthreads();
@@ -840,8 +844,11 @@ __global__ void __launch_bounds__(WAVES * SL_WAVE, (query_min_waves<WAVES, SPT>(
 constexpr uint32_t kStepWaves = 16;
 constexpr uint32_t kStepSpinLimit = 1u << 20;  // polls: seconds at most, against microseconds needed
 
+constexpr uint32_t kStepBounds = 32;  // queries of cur whose row offsets come with the launch
 struct StepArgs {
   QueryArgs prev, cur;
+  uint32_t n_bounds;                  // cur.q's first n_bounds queries: offsets bounds[q], bounds[q + 1]
+  uint32_t bounds[kStepBounds + 1];
   uint32_t gather_only;
   uint32_t n_ins, merge_groups;
   const uint2* recs;      // [L][n_ins] run records of the prepared insert
@@ -866,10 +873,27 @@ __global__ void __launch_bounds__(kStepWaves * SL_WAVE, (query_min_waves<kStepWa
     __syncthreads();
     if (ticket < np)
       query_one<kStepWaves, SPT, true, false, kQueryAggregate>(s, cl, tab, a.prev, ticket, lds, lay);
-    else if (a.gather_only)
-      query_one<kStepWaves, SPT, true, false, kQueryGather>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
-    else
-      query_one<kStepWaves, SPT, true, false, kQueryFull>(s, cl, tab, a.cur, ticket - np, lds, lay, &a.sync[1]);
+    else {
+      // the query's row offsets from the launch when they came with it (no
+      // read of the host-coherent staging before its indices)
+      const uint32_t q = ticket - np;
+      int64_t qb = -1, qe = -1;
+      // up to 4 slots a thread (with more the kernel would spill)
+      if (SPT <= 4 && q < a.n_bounds) {
+        // constant offsets into the launch's arguments (a variable index
+        // would make the compiler copy them to scratch)
+#pragma unroll
+        for (uint32_t j = 0; j < kStepBounds; ++j)
+          if (j == q) {
+            qb = a.bounds[j];
+            qe = a.bounds[j + 1];
+          }
+      }
+      if (a.gather_only)
+        query_one<kStepWaves, SPT, true, false, kQueryGather>(s, cl, tab, a.cur, q, lds, lay, &a.sync[1], qb, qe);
+      else
+        query_one<kStepWaves, SPT, true, false, kQueryFull>(s, cl, tab, a.cur, q, lds, lay, &a.sync[1], qb, qe);
+    }
     return;
   }
   // table writers: each wave takes four records per pass and, before its
@@ -1061,7 +1085,7 @@ bool serve_step_supported(const Shape& s) { return step_kernel(s) != nullptr; }
 
 hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& prev,
                              const QueryArgs& cur, bool gather_only, void* ins_scratch, uint32_t n_ins, int n_cu,
-                             FuseSync& fs, hipStream_t st) {
+                             FuseSync& fs, hipStream_t st, const int64_t* cur_host_ip) {
   const void* k = step_kernel(s);
   if (!k || !fs.dev || !fs.gave_up) return hipErrorNotSupported;
   if (prev.exact || cur.exact || prev.qbk || cur.qbk || prev.q.n_rows > (1u << 20) || cur.q.n_rows > (1u << 20))
@@ -1071,6 +1095,11 @@ hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesVie
   a.prev = prev;
   a.cur = cur;
   a.gather_only = gather_only ? 1u : 0u;
+  a.n_bounds = 0;
+  if (cur_host_ip && cur.q.n_rows && cur_host_ip[cur.q.n_rows] <= 0xFFFFFFFFll) {
+    a.n_bounds = (uint32_t)std::min<uint64_t>(cur.q.n_rows, kStepBounds);
+    for (uint32_t q = 0; q <= a.n_bounds; ++q) a.bounds[q] = (uint32_t)cur_host_ip[q];
+  }
   a.n_ins = 0;
   a.merge_groups = 0;
   a.recs = nullptr;

@@ -331,6 +331,7 @@ hipError_t pack_queries(slash_server* srv, Slot& s) {
     in = s.d_in;
   }
   s.batch.q = slash_csr{(const int64_t*)in, (const int32_t*)(in + l.idx), n};
+  s.batch.host_indptr = h_ip;
   s.batch.kq = (const uint32_t*)(in + l.k);
   s.batch.ids = s.h_out;
   s.batch.scores = s.h_out + (size_t)n * km;

@@ -285,7 +285,9 @@ hipError_t launch_query(const Shape& s, const ConstView& c, const TablesView& ta
 // Serving: one launch that ranks the previous batch's queries from the
 // slot ids their gather stored (prev, may be empty), answers this batch's
 // queries whole or only gathers them (cur, may be empty; count-min, hashing
-// in the kernel), and then applies a prepared small insert's runs to the
+// in the kernel; cur_host_ip, when not null, is cur's row offsets in host
+// memory, whose first entries go in the launch so the kernel need not read
+// them), and then applies a prepared small insert's runs to the
 // tables (n_ins rows, none when 0) after every query of this batch has read
 // them.  `dev` holds two device words that start at zero and only grow;
 // tickets/gathered are their values after the last launch (updated here;
@@ -300,7 +302,7 @@ struct FuseSync {
 bool serve_step_supported(const Shape& s);
 hipError_t launch_serve_step(const Shape& s, const ConstView& c, const TablesView& tab, const QueryArgs& prev,
                              const QueryArgs& cur, bool gather_only, void* ins_scratch, uint32_t n_ins, int n_cu,
-                             FuseSync& fs, hipStream_t st);
+                             FuseSync& fs, hipStream_t st, const int64_t* cur_host_ip = nullptr);
 hipError_t launch_query_persistent(const Shape& s, const ConstView& c, const TablesView& tab,
                                    const QueryArgs& a, uint32_t waves, uint32_t per_ticket, uint32_t grid,
                                    uint32_t* ticket, hipStream_t st);
@@ -362,6 +364,7 @@ slash_status insert_commit(slash_index* ix, const InsertScratch& sc, uint32_t n,
 // launched.
 struct ServeBatch {
   slash_csr q{};
+  const int64_t* host_indptr = nullptr;  // q's row offsets in host memory (the first ones go in the launch)
   const uint32_t* kq = nullptr;
   uint32_t* ids = nullptr;
   uint32_t* scores = nullptr;
